@@ -1,0 +1,116 @@
+"""CPU FP64 oracle: the naive per-parameter Bartels-Stewart solve.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this module.  It shares no
+code with the GPU library: no kernels, headers, helpers, tables or constants.
+
+What it computes (Section 1, equations (Ljap jdba 1) and (eq:formA)): for one
+parameter sample d, the unique solution X of
+
+    A X + X A^T = -B B^T,        A = A0 - U diag(d) V^T,
+
+and the output functional f(X) = trace(E X).  The method is the one the paper
+names as the naive baseline in Section 1: a Schur decomposition of A(p) for
+every p, followed by a triangular back-substitution (Bartels and Stewart).  No
+Sherman-Morrison-Woodbury step, no eigenbasis of the seed, no Krylov method
+and no recycling.  The Schur factorisation is a library primitive
+(``scipy.linalg.schur``); the triangular Lyapunov back-substitution is written
+out column by column below, with no blocking.
+
+Reading (documented in the design doc): the complex Schur form A = Z T Z^H is used
+so every diagonal block is 1x1.  With X = Z Y Z^H the equation becomes
+T Y + Y T^H = Z^H C Z, and column j of Y satisfies
+
+    (T + conj(T_jj) I) y_j = f_j - sum_{k>j} conj(T_jk) y_k,
+
+solved for j = n-1 down to 0.
+
+Diagnostics: the normwise backward error of Section 2.2 (the quotient used in
+the Proposition on the backward error), the asymmetry of X and its smallest
+symmetric eigenvalue.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.linalg as sla
+
+
+def triangular_lyapunov(T: np.ndarray, F: np.ndarray) -> np.ndarray:
+    """Solve T Y + Y T^H = F for upper-triangular complex T (column by column)."""
+    n = T.shape[0]
+    Y = np.zeros((n, n), dtype=np.complex128, order="F")
+    Tc = T.conj()
+    W = np.array(T, dtype=np.complex128, order="F")  # T + conj(T_jj) I, diagonal rewritten per column
+    dT = np.diag(T).copy()
+    idx = np.arange(n)
+    for j in range(n - 1, -1, -1):
+        rhs = np.array(F[:, j], dtype=np.complex128)
+        if j + 1 < n:
+            rhs -= Y[:, j + 1:] @ Tc[j, j + 1:]
+        W[idx, idx] = dT + Tc[j, j]
+        Y[:, j] = sla.solve_triangular(W, rhs, lower=False, check_finite=False)
+    return Y
+
+
+def lyapunov_bs(A: np.ndarray, C: np.ndarray):
+    """Solve A X + X A^T = C by Bartels-Stewart.  Returns (X, schur diag of A)."""
+    T, Z = sla.schur(A, output="complex")
+    F = Z.conj().T @ C @ Z
+    Y = triangular_lyapunov(T, F)
+    X = Z @ Y @ Z.conj().T
+    return X, np.diag(T)
+
+
+def backward_error(A, X, C):
+    """||A X + X A^T - C||_F / (2 ||A||_F ||X||_F + ||C||_F)."""
+    R = A @ X + X @ A.T - C
+    return np.linalg.norm(R) / (2 * np.linalg.norm(A) * np.linalg.norm(X) + np.linalg.norm(C))
+
+
+@dataclass
+class OracleResult:
+    trace: float
+    stable: bool
+    max_real_eig: float
+    backward_error: float
+    asymmetry: float
+    min_sym_eig_rel: float
+    imag_rel: float
+    seconds: float
+
+
+def trace_E(E: np.ndarray, X: np.ndarray) -> float:
+    if E.ndim == 1:
+        return float(np.dot(E, np.diag(X)))
+    return float(np.sum(E.T * X))
+
+
+def solve_one(A0, U, V, B, E, d, diagnostics: bool = True) -> OracleResult:
+    """trace(E X(p)) for one parameter sample, with diagnostics."""
+    t0 = time.perf_counter()
+    A = A0 - (U * np.asarray(d)[None, :]) @ V.T
+    C = -(B @ B.T)
+    Xc, lam = lyapunov_bs(A, C)
+    mre = float(np.max(lam.real))
+    X = Xc.real
+    imag_rel = float(np.linalg.norm(Xc.imag) / max(np.linalg.norm(X), 1e-300))
+    tr = trace_E(E, X)
+    be = asym = mse = float("nan")
+    if diagnostics:
+        be = float(backward_error(A, X, C))
+        nx = np.linalg.norm(X)
+        asym = float(np.linalg.norm(X - X.T) / nx)
+        ev = np.linalg.eigvalsh(0.5 * (X + X.T))
+        mse = float(ev[0] / max(abs(ev[-1]), 1e-300))
+    return OracleResult(tr, mre < 0, mre, be, asym, mse, imag_rel,
+                        time.perf_counter() - t0)
+
+
+def solve_problem(pr, idx=None, diagnostics: bool = True):
+    """Oracle results for the parameter samples ``idx`` (default: all) of a Problem."""
+    if idx is None:
+        idx = range(pr.P)
+    return [solve_one(pr.A0, pr.U, pr.V, pr.B, pr.E, pr.d[i], diagnostics) for i in idx]

@@ -1,0 +1,75 @@
+"""Input generators: determinism, structure, stability of every A(p)."""
+import numpy as np
+import pytest
+
+from gen import workloads as W
+
+
+def test_determinism():
+    a = W.config(0)
+    b = W.config(0)
+    for f in ("A0", "U", "V", "B", "E", "d"):
+        assert np.array_equal(getattr(a, f), getattr(b, f))
+    c = W.config(3)
+    d = W.config(3)
+    assert np.array_equal(c.A0, d.A0) and np.array_equal(c.d, d.d)
+
+
+def test_chain_structure():
+    pr = W.config(0)
+    K = pr.meta["K"]
+    assert np.allclose(K, K.T)
+    assert np.all(np.linalg.eigvalsh(K) > 0)
+    assert np.count_nonzero(np.triu(K, 2)) == 0
+    assert pr.n == 400 and pr.r == 1 and pr.P == 64 and pr.s == 400
+    assert pr.U[200 + 99, 0] == 1.0 / pr.meta["masses"][99]
+    assert pr.V[200 + 99, 0] == 1.0
+
+
+def test_rayleigh_spectrum_formula():
+    """Eigenvalues of the Rayleigh seed: (-a - b l +- sqrt((a + b l)^2 - 4 l)) / 2 over eig(K, M)."""
+    pr = W.small_chain(40, (7,), 2, 1)
+    m, K = pr.meta["masses"], pr.meta["K"]
+    lk = np.linalg.eigvalsh(K / np.sqrt(m)[:, None] / np.sqrt(m)[None, :])
+    a, b = 0.01, 0.002
+    disc = np.sqrt((a + b * lk + 0j) ** 2 - 4 * lk)
+    lam = np.concatenate([(-a - b * lk + disc) / 2, (-a - b * lk - disc) / 2])
+    ev = np.linalg.eigvals(pr.A0)
+    key = lambda z: (round(z.real, 9), round(z.imag, 9))
+    assert np.allclose(sorted(lam, key=key), sorted(ev, key=key), rtol=1e-10, atol=1e-10)
+
+
+def test_multiagent_structure():
+    pr = W.config(3)
+    assert pr.n == 1000 and pr.r == 8 and pr.P == 512 and pr.s == 4
+    A0 = pr.A0
+    sym = 0.5 * (A0 + A0.T)
+    L = -sym[0::2, 0::2] - 0.1 * np.eye(500)
+    assert np.allclose(L.sum(1), 0.0)
+    assert np.linalg.eigvalsh(sym)[-1] <= -0.1 + 1e-12
+    assert np.allclose(pr.d[:, 0::2], pr.d[:, 1::2])
+    assert np.all(pr.d >= 0) and np.all(pr.d <= 5)
+
+
+@pytest.mark.parametrize("ci,idx", [(0, range(64)), (3, range(0, 512, 64)), (1, (0, 31, 992, 1023))])
+def test_every_sample_is_stable(ci, idx):
+    pr = W.config(ci)
+    for i in idx:
+        assert np.max(np.linalg.eigvals(pr.A_of(i)).real) < 0
+
+
+def test_c2_shapes():
+    pr = W.config(2, P=4)
+    assert pr.n == 4000 and pr.r == 3 and pr.s == 16
+    assert len(set(pr.meta["dampers"])) == 3
+
+
+def test_serving_requests():
+    reqs = W.serving_requests(200, rate=10.0, seed=4)
+    assert all(b.arrival > a.arrival for a, b in zip(reqs, reqs[1:]))
+    assert all(8 <= q.P <= 512 and q.n in (400, 1000, 2000, 4000) for q in reqs)
+    assert all(q.r in (2, 4) for q in reqs if q.kind == "multiagent")
+    reused = sum(1 for i, q in enumerate(reqs) if any(p.seed_id == q.seed_id for p in reqs[:i]))
+    assert 0.15 < reused / len(reqs) < 0.45
+    pr = W.request_problem(reqs[0])
+    assert pr.P == reqs[0].P and pr.r == reqs[0].r

@@ -1,0 +1,211 @@
+/*
+ * lyapsmw -- batched trace(E X(p)) for parametrized Lyapunov equations on MI355X.
+ *
+ * Problem (Section 1, equations (Ljap jdba 1) and (eq:formA)): for many
+ * parameter samples p with D(p) = diag(d(p)), d(p) in R^r,
+ *
+ *     A(p) X + X A(p)^T = -B B^T,      A(p) = A0 - U D(p) V^T,
+ *
+ * evaluate f(X(p)) = trace(E X(p)).
+ *
+ * Method (Section 2.1): the seed A0 is factored once (A0 = Q0 Lambda0 Q0^-1,
+ * offline stage of Table 1); every p is handled by a Sherman-Morrison-Woodbury
+ * correction whose capacitance system (eq:SMW_linearsystem) is solved by a
+ * preconditioned, restarted Krylov method (the preconditioner is eq:prec with
+ * its exact block-diagonal part), and every Krylov matrix-vector product is a
+ * seed Lyapunov solve with a low-rank right-hand side, i.e. a Cauchy-matrix
+ * contraction in the eigenbasis (eq:Z(v), eq:N2M1).  The capacitance system is
+ * solved in its n*r reduced form, unknown Y = D V^T X(p) (r x n), which carries
+ * the same unknowns as the paper's 2nk vector w(v) (w1 = w2^T).
+ *
+ * Conventions shared by every entry point:
+ *  - Host matrices are row-major (C order), float64.
+ *  - Device buffers are float64 unless stated, and belong to the caller.
+ *  - Calls are ordered on the HIP stream given as `void* hip_stream`
+ *    (NULL = the default stream).  seed_factor and smw_solve_batch also
+ *    synchronise that stream before they return (they drive the iteration
+ *    from the host).  lyap_seed_apply and trace_EX only enqueue work.
+ *  - Argument errors return synchronously, before any launch, with
+ *    LYAP_E_INVAL.  No call aborts, throws or exits.
+ *  - Per-parameter numerical failures are reported in lyap_result.status;
+ *    the call itself then returns LYAP_OK.
+ *  - A seed is read-only after seed_factor and may be used from several
+ *    streams at once, except that lyap_seed_apply and trace_EX share a
+ *    per-seed scratch area: calls of those two on one seed must not overlap.
+ */
+#ifndef LYAPSMW_H
+#define LYAPSMW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lyap_seed_s* lyap_seed;
+typedef struct lyap_engine_s* lyap_engine;
+
+typedef enum {
+  LYAP_OK = 0,
+  LYAP_E_INVAL = 1,        /* bad argument (size, pointer, non-finite host input, workspace) */
+  LYAP_E_NOMEM = 2,        /* device or host allocation failed */
+  LYAP_E_UNSTABLE = 3,     /* seed has lambda_i + lambda_j ~ 0: no unique Lyapunov solution */
+  LYAP_E_NOCONV = 4,       /* per-parameter: iteration limit reached before the tolerance */
+  LYAP_E_BREAKDOWN = 5,    /* per-parameter: Krylov breakdown without convergence */
+  LYAP_E_DEVICE = 6,       /* a HIP runtime call failed */
+  LYAP_E_UNSUPPORTED = 7,  /* requested option not available (e.g. no host LAPACK found) */
+  LYAP_E_NONFINITE = 8     /* per-parameter: NaN/Inf in d(p) or in the iteration */
+} lyap_status;
+
+typedef enum {
+  LYAP_BASIS_AUTO = 0,   /* eigenbasis unless its condition estimate exceeds max_eig_cond */
+  LYAP_BASIS_EIG = 1,    /* complex eigenbasis of A0 (Section 2.1), stored in real form */
+  LYAP_BASIS_SCHUR = 2   /* real Schur basis with a triangular Bartels-Stewart seed solve */
+} lyap_basis;
+
+typedef enum {
+  LYAP_PREC_FP64 = 0,     /* every matrix-vector product in FP64 (MFMA f64) */
+  LYAP_PREC_FP32_IR = 1,  /* inner Krylov products in FP32 MFMA, FP64 residuals and refinement */
+  LYAP_PREC_BF16_IR = 2,  /* inner products as three BF16 MFMA products (split operands), FP32
+                             accumulation, FP64 residuals and refinement */
+  LYAP_PREC_FP32 = 3      /* FP32 MFMA products, no FP64 refinement (tolerance ~1e-6) */
+} lyap_prec;
+
+typedef struct {
+  int32_t basis;          /* lyap_basis */
+  int32_t E_is_diag;      /* 1: E is an n-vector (diagonal); 0: E is dense n x n (symmetrised) */
+  double max_eig_cond;    /* AUTO switches to the Schur basis above this (default 1e6 if <= 0) */
+} lyap_seed_opts;
+
+typedef struct {
+  int32_t prec;           /* lyap_prec */
+  int32_t max_iter;       /* total matrix-vector products per parameter (default 600) */
+  int32_t restart;        /* Krylov dimension per cycle m (default 40, at most 64) */
+  int32_t use_precond;    /* 1: right preconditioner = exact diagonal blocks of eq:prec (default 1) */
+  int32_t recycle_k;      /* reserved (0) */
+  int32_t max_refine;     /* FP64 refinement steps for the *_IR modes (default 30) */
+  double tol;             /* FP64 relative residual target ||b - A y|| / ||b|| (default 1e-12) */
+  double inner_tol;       /* relative reduction per inner cycle in *_IR modes (default 1e-4) */
+} lyap_solve_opts;
+
+typedef struct {
+  int32_t status;         /* lyap_status of this parameter */
+  int32_t iters;          /* matrix-vector products (all precisions) */
+  int32_t cycles;         /* restart cycles (= FP64 residual evaluations) */
+  int32_t refinements;    /* FP64 refinement steps that were followed by an inner solve */
+  double rel_residual;    /* final FP64 relative residual of the capacitance system */
+  double trace;           /* trace(E X(p)) from the eigen-coordinate solution */
+} lyap_result;
+
+typedef struct {
+  int64_t n, r, s;
+  int64_t npairs;         /* complex-conjugate eigenvalue pairs (h); real eigenvalues = n - 2h */
+  int64_t ld;             /* padded leading dimension of every n-vector on the device */
+  int32_t basis;          /* basis actually used */
+  int32_t reserved;
+  double cond_est;        /* ||S||_1 ||S^-1||_1 of the real eigenbasis (unit-norm eigenvectors) */
+  double min_lam_sum;     /* min |lambda_i + lambda_j| / max |lambda_i + lambda_j| */
+  double max_re_lambda;   /* largest real part of the seed spectrum */
+  double t0;              /* trace(E X0) of the seed equation (eq:seedLE) */
+  double factor_seconds;  /* host wall time of seed_factor */
+  size_t device_bytes;
+} lyap_seed_info;
+
+/* ------------------------------------------------------------------------ */
+/* Offline stage (Table 1, left column).                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Factor the seed A0 and precompute everything that does not depend on p.
+ *   n, r, s  : sizes, 1 <= r <= n, 1 <= s, n <= 16384.
+ *   A0       : host n x n.     U, V : host n x r (A(p) = A0 - U diag(d) V^T).
+ *   B        : host n x s (right-hand side -B B^T).
+ *   E        : host n (opts->E_is_diag) or n x n.
+ *   opts     : may be NULL (AUTO basis, diagonal E).
+ * The host eigendecomposition uses LAPACK dgeev resolved at run time from the
+ * process (e.g. the copy inside libtorch_cpu) or from the library named by the
+ * environment variable LYAP_LAPACK_LIB; LYAP_E_UNSUPPORTED if none is found.
+ * Returns LYAP_E_UNSTABLE if some Re(lambda) >= 0 or lambda_i + lambda_j ~ 0.
+ * On success *out owns all device memory of the seed until seed_release. */
+lyap_status seed_factor(int64_t n, int64_t r, int64_t s, const double* A0, const double* U,
+                        const double* V, const double* B, const double* E,
+                        const lyap_seed_opts* opts, void* hip_stream, lyap_seed* out);
+
+lyap_status seed_info(lyap_seed seed, lyap_seed_info* out);
+lyap_status seed_release(lyap_seed seed);
+size_t seed_device_bytes(lyap_seed seed);
+
+/* ------------------------------------------------------------------------ */
+/* The seed Lyapunov solve with a low-rank right-hand side (eq:Z(v)): for each */
+/* b < batch, with Y_b = Y_dev + b*r*n (r x n row-major),                      */
+/*     G_b = V^T X_b,   A0 X_b + X_b A0^T = U Y_b + Y_b^T U^T,                */
+/* written to G_dev + b*r*n.  Transform into the eigenbasis, Cauchy           */
+/* contraction (the division by lambda_i + lambda_j), transform back.          */
+/* prec: LYAP_PREC_FP64 or LYAP_PREC_FP32 (the whole chain in that precision). */
+/* ------------------------------------------------------------------------ */
+lyap_status lyap_seed_apply(lyap_seed seed, int64_t batch, const double* Y_dev, double* G_dev,
+                            int32_t prec, void* hip_stream);
+
+/* ------------------------------------------------------------------------ */
+/* Online stage (Table 1, right column).                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Device workspace smw_solve_batch needs for P parameters. */
+size_t smw_workspace_bytes(lyap_seed seed, int64_t P, const lyap_solve_opts* opts);
+
+/* Solve the capacitance system for P parameters.
+ *   d_dev     : device P x r, row p = diag of D(p).  Entries must be finite;
+ *               zero is allowed (the system is used in the form (I - D K) Y = D c0).
+ *   Y_dev     : device P x r x n output, Y(p) = D(p) V^T X(p) (physical coordinates).
+ *   res_host  : host array of P results (status, iterations, residual, trace).
+ *   workspace : device buffer of at least smw_workspace_bytes(seed, P, opts) bytes.
+ * All P parameters are batched: slots of the Krylov engine are filled with
+ * parameters in order and refilled as parameters converge. */
+lyap_status smw_solve_batch(lyap_seed seed, int64_t P, const double* d_dev,
+                            const lyap_solve_opts* opts, double* Y_dev, lyap_result* res_host,
+                            void* workspace_dev, size_t workspace_bytes, void* hip_stream);
+
+/* trace(E X(p)) = t0 + 2 <Gamma, Y(p)> with Gamma = G U, A0^T G + G A0 = E
+ * (the additive split of f in Section 2.1, collapsed to O(r n) per p).
+ * Y_dev: device P x r x n from smw_solve_batch; trace_dev: device P doubles. */
+lyap_status trace_EX(lyap_seed seed, int64_t P, const double* Y_dev, double* trace_dev,
+                     void* hip_stream);
+
+/* ------------------------------------------------------------------------ */
+/* Continuous-batching engine (one seed, a fixed number of slots).            */
+/* smw_solve_batch runs on an engine; a serving loop drives engines directly. */
+/* ------------------------------------------------------------------------ */
+
+/* Create an engine with `slots` concurrent parameters.  It allocates its own
+ * device state (engine_device_bytes) and captures one Krylov step as a HIP
+ * graph on `hip_stream`, which it keeps using. */
+lyap_status engine_create(lyap_seed seed, int64_t slots, const lyap_solve_opts* opts,
+                          void* hip_stream, lyap_engine* out);
+size_t engine_device_bytes(lyap_seed seed, int64_t slots, const lyap_solve_opts* opts);
+lyap_status engine_destroy(lyap_engine eng);
+
+/* Queue `count` parameters (host count x r) with caller tags (host, may be NULL:
+ * tags are then consecutive from the engine's running counter). */
+lyap_status engine_submit(lyap_engine eng, int64_t count, const double* d_host,
+                          const int64_t* tags);
+
+/* Run up to `max_steps` Krylov steps (one matrix-vector product for every busy
+ * slot per step), refilling slots from the queue every `poll_every` steps.
+ * Returns when the engine is idle or max_steps is reached; *busy receives the
+ * number of parameters still queued or in flight. */
+lyap_status engine_run(lyap_engine eng, int64_t max_steps, int32_t poll_every, int64_t* busy);
+
+/* Move up to `max_out` finished results to the caller (tags, results). */
+lyap_status engine_harvest(lyap_engine eng, int64_t max_out, int64_t* tags_out,
+                           lyap_result* res_out, int64_t* n_out);
+
+const char* lyap_status_string(lyap_status s);
+
+/* Text of the most recent error raised by any entry point (process-wide). */
+const char* lyap_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LYAPSMW_H */

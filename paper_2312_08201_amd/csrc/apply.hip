@@ -1,0 +1,148 @@
+// The seed Lyapunov solve with a low-rank right-hand side in physical
+// coordinates (eq:Z(v) of Section 2.1), and the collapsed trace functional.
+//
+//   lyap_seed_apply:  G = V^T X,  A0 X + X A0^T = U Y + Y^T U^T
+//     transform-in   rho(Y Q0^-T) = Y Tin                       (MFMA GEMM)
+//     Cauchy         Gh_a = sum_b Yh_b o K1_ab + sum_b Uh_b o ((Vh_a o Yh_b) L)
+//     transform-out  G = rho(Gh) Tout                           (MFMA GEMM)
+//   trace_EX:        trace(E X(p)) = t0 + 2 <Gamma^T, Y(p)>
+#include "internal.h"
+
+namespace lyap {
+
+namespace {
+
+__device__ inline int us(int u, int h, bool& pr) {
+  pr = u < h;
+  return pr ? 2 * u : u + h;
+}
+
+__global__ void k_apply_formX(double* __restrict__ X, const double* __restrict__ Vh,
+                              const double* __restrict__ Yh, int r, int h, int n, int ld) {
+  const int row = blockIdx.y;  // (q r + a) r + b
+  const int b = row % r, a = (row / r) % r, q = row / (r * r);
+  const double* va = Vh + (long)a * ld;
+  const double* yb = Yh + ((long)q * r + b) * ld;
+  double* xo = X + (long)row * ld;
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < n - h; u += gridDim.x * blockDim.x) {
+    bool pr;
+    const int i = us(u, h, pr);
+    if (pr) {
+      const double ar = va[i], ai = va[i + 1], br = yb[i], bi = yb[i + 1];
+      xo[i] = ar * br - ai * bi;
+      xo[i + 1] = ar * bi + ai * br;
+    } else {
+      xo[i] = va[i] * yb[i];
+    }
+  }
+}
+
+__global__ void k_apply_epilogue(double* __restrict__ Gh, const double* __restrict__ Yh,
+                                 const double* __restrict__ H, const double* __restrict__ K1,
+                                 const double* __restrict__ Uh, int r, int h, int n, int ld) {
+  const int row = blockIdx.y;  // q r + a
+  const int a = row % r, q = row / r;
+  double* go = Gh + (long)row * ld;
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < n - h; u += gridDim.x * blockDim.x) {
+    bool pr;
+    const int i = us(u, h, pr);
+    double sr = 0, si = 0;
+    for (int b = 0; b < r; ++b) {
+      const double* k = K1 + (long)(a * r + b) * ld;
+      const double* yb = Yh + ((long)q * r + b) * ld;
+      const double* ub = Uh + (long)b * ld;
+      const double* hb = H + ((long)row * r + b) * ld;
+      if (pr) {
+        sr += yb[i] * k[i] - yb[i + 1] * k[i + 1] + ub[i] * hb[i] - ub[i + 1] * hb[i + 1];
+        si += yb[i] * k[i + 1] + yb[i + 1] * k[i] + ub[i] * hb[i + 1] + ub[i + 1] * hb[i];
+      } else {
+        sr += yb[i] * k[i] + ub[i] * hb[i];
+      }
+    }
+    go[i] = sr;
+    if (pr) go[i + 1] = si;
+  }
+}
+
+__global__ void k_pad_rows(double* __restrict__ dst, long ldd, const double* __restrict__ src,
+                           long lds_, int n) {
+  const int row = blockIdx.y;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
+    dst[(long)row * ldd + k] = src[(long)row * lds_ + k];
+}
+
+void gemm64(const double* A, long lda, const double* B, long ldb, double* C, long ldc, long M,
+            long N, long K, long Nstore, hipStream_t s) {
+  GemmArgs g{};
+  g.type = GemmType::F64;
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.Nstore = Nstore;
+  g.M_dev = nullptr;
+  g.m_scale = 1;
+  gemm_launch(g, s);
+}
+
+void apply_impl(lyap_seed_s* sd, long long batch, const double* Y, double* G, int prec,
+                hipStream_t st) {
+  LYAP_REQUIRE(batch >= 1, LYAP_E_INVAL, "batch < 1");
+  LYAP_REQUIRE(Y && G, LYAP_E_INVAL, "NULL buffer");
+  LYAP_REQUIRE(prec == LYAP_PREC_FP64, LYAP_E_UNSUPPORTED, "lyap_seed_apply: only FP64");
+  const long long r = sd->r, n = sd->n, ld = sd->ld, h = sd->h;
+  const long long rows1 = batch * r, rows2 = batch * r * r;
+  const size_t rowb = ld * sizeof(double);
+  const size_t need = (size_t)(3 * rows1 + 2 * rows2) * rowb;
+  if (sd->scratch_bytes < need) {
+    sd->scratch.alloc(need);
+    sd->scratch_bytes = need;
+  }
+  double* Yp = sd->scratch.as<double>();
+  double* Yh = Yp + rows1 * ld;
+  double* Gh = Yh + rows1 * ld;
+  double* X = Gh + rows1 * ld;
+  double* H = X + rows2 * ld;
+  // pads must be zero: clear the whole area once per call (stream ordered)
+  LYAP_HIP(hipMemsetAsync(Yp, 0, need, st));
+  const int ub = (int)std::min<long long>((n + 255) / 256, 64);
+  hipLaunchKernelGGL(k_pad_rows, dim3(ub, rows1), dim3(256), 0, st, Yp, (long)ld, Y, (long)n, (int)n);
+  gemm64(Yp, ld, sd->Tin.as<double>(), ld, Yh, ld, rows1, ld, ld, ld, st);
+  hipLaunchKernelGGL(k_apply_formX, dim3(ub, rows2), dim3(256), 0, st, X, sd->Vh.as<double>(), Yh,
+                     (int)r, (int)h, (int)n, (int)ld);
+  gemm64(X, ld, sd->Mc.as<double>(), ld, H, ld, rows2, ld, ld, ld, st);
+  hipLaunchKernelGGL(k_apply_epilogue, dim3(ub, rows1), dim3(256), 0, st, Gh, Yh, H,
+                     sd->K1.as<double>(), sd->Uh.as<double>(), (int)r, (int)h, (int)n, (int)ld);
+  gemm64(Gh, ld, sd->Tout.as<double>(), ld, G, n, rows1, ld, ld, n, st);
+  LYAP_HIP(hipGetLastError());
+}
+
+}  // namespace
+}  // namespace lyap
+
+using namespace lyap;
+
+
+extern "C" {
+
+lyap_status lyap_seed_apply(lyap_seed sd, int64_t batch, const double* Y_dev, double* G_dev,
+                            int32_t prec, void* hip_stream) {
+  if (!sd) return LYAP_E_INVAL;
+  LYAP_TRY(apply_impl(sd, batch, Y_dev, G_dev, prec, (hipStream_t)hip_stream));
+  return LYAP_OK;
+}
+
+lyap_status trace_EX(lyap_seed sd, int64_t P, const double* Y_dev, double* trace_dev,
+                     void* hip_stream) {
+  if (!sd || P < 1 || !Y_dev || !trace_dev) return LYAP_E_INVAL;
+  LYAP_TRY(batched_dot(trace_dev, Y_dev, sd->n, sd->Gam.as<double>(), sd->ld, (int)sd->r, (int)P,
+                       (int)sd->n, sd->t0, 2.0, (hipStream_t)hip_stream));
+  return LYAP_OK;
+}
+
+}  // extern "C"

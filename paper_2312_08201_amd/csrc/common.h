@@ -1,0 +1,112 @@
+// Shared definitions of the lyapsmw library (device layouts, error plumbing).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lyapsmw.h"
+
+namespace lyap {
+
+// Every n-vector on the device is stored with this padded length, zero beyond n,
+// so GEMM tiles never need bounds checks along K and N.
+constexpr int kPad = 128;
+inline int64_t pad_to(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+constexpr int kMaxRestart = 64;
+constexpr int kMaxRank = 16;
+
+// Thrown inside the library only; every C entry point catches and converts.
+struct Error {
+  lyap_status st;
+  std::string msg;
+};
+
+#define LYAP_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      throw ::lyap::Error{LYAP_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    }                                                                               \
+  } while (0)
+
+#define LYAP_REQUIRE(cond, code, text)                 \
+  do {                                                 \
+    if (!(cond)) throw ::lyap::Error{code, text};      \
+  } while (0)
+
+void set_last_error(const std::string& s);
+
+// Wrap the body of a C entry point: library errors become status codes.
+#define LYAP_TRY(...)                                   \
+  try {                                                 \
+    __VA_ARGS__;                                        \
+  } catch (const ::lyap::Error& e) {                    \
+    ::lyap::set_last_error(e.msg);                      \
+    return e.st;                                        \
+  } catch (const std::bad_alloc&) {                     \
+    ::lyap::set_last_error("host allocation failed");   \
+    return LYAP_E_NOMEM;                                \
+  } catch (...) {                                       \
+    ::lyap::set_last_error("unexpected exception");     \
+    return LYAP_E_DEVICE;                               \
+  }
+
+// A device allocation owned by RAII.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t b) { alloc(b); }
+  void alloc(size_t b) {
+    release();
+    if (b == 0) return;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      p = nullptr;
+      throw Error{LYAP_E_NOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed"};
+    }
+    bytes = b;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  ~DevBuf() { release(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+// Precision of one GEMM launch.
+enum class GemmType { F64 = 0, F32 = 1, BF16X3 = 2 };
+
+// C[M x N] = A[M x K] * B[K x N], row-major, K and N multiples of the tile
+// (guaranteed by kPad).  Rows >= M (static) or >= *M_dev (dynamic, if given)
+// are neither read beyond the clamp nor stored.  Columns >= Nstore not stored.
+// F64: A, B, C double.  F32: A, B float, C float.
+// BF16X3: A and B given as (hi, lo) bf16 pairs; B stored transposed (N x K);
+//         C float.
+struct GemmArgs {
+  GemmType type;
+  const void* A;      // F64/F32: M x lda ; BF16X3: hi plane, lo plane at A + a_plane
+  const void* B;      // F64/F32: K x ldb ; BF16X3: Bt hi (N x ldb), lo at B + b_plane
+  void* C;
+  int64_t M, N, K;
+  int64_t lda, ldb, ldc;
+  int64_t Nstore;     // columns actually written
+  int64_t a_plane, b_plane;  // element offsets of the lo planes (BF16X3)
+  const int* M_dev;   // optional device row count (scaled by m_scale)
+  int m_scale;
+};
+
+void gemm_launch(const GemmArgs& g, hipStream_t s);
+
+}  // namespace lyap

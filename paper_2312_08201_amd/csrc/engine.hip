@@ -1,0 +1,1173 @@
+// Online stage (Section 2.1, Table 1 right column): the batched Krylov engine.
+//
+// Every busy slot holds one parameter sample p and advances one Krylov step
+// per engine step.  A step is a fixed sequence of launches (captured once as
+// a HIP graph):
+//   k_lists     compact the slots that need an FP64 or a low-precision
+//               matrix-vector product into two lists (device counts)
+//   k_prep      z = P^-1 v_j (Arnoldi step) or z = y (residual step)
+//   k_formX     rows (p, a, b) of the Cauchy GEMM: Vh_a o z_b
+//   GEMM        H = X * Mc  (MFMA, FP64 or FP32 / split-BF16)
+//   k_epilogue  w = z - D (sum_b z_b o K1_ab + sum_b Uh_b o H_pab)
+//   k_krylov    one workgroup per slot: CGS2 orthogonalisation with
+//               wavefront reductions, Givens update in FP64, restart with a
+//               true FP64 residual, convergence, result write-out and
+//               admission of the next queued parameter (device-side queue).
+//
+// The capacitance system is the n*r reduced form of eq:SMW_linearsystem,
+// scaled by D so that d = 0 is allowed:  (I - D K) y = D c0,
+// K(y) = Vh (L o (Uh y + y^T Uh^T)) in eigen-coordinates.  The right
+// preconditioner is the exact block-diagonal part of eq:prec: per eigen slot
+// j the r x r block I - D K1[:, :, j] (complex on conjugate pairs).
+// Mixed precision: Arnoldi products use the low-precision GEMM, every
+// restart evaluates the residual with the FP64 GEMM (iterative refinement).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <memory>
+
+#include "internal.h"
+
+namespace lyap {
+
+constexpr int kPrecRank = 8;  // block preconditioner up to r = 8
+
+enum Phase : int { PH_FREE = 0, PH_ARNOLDI = 1, PH_RESTART = 2 };
+
+// per-slot integer state
+enum SI : int { SI_PHASE = 0, SI_J, SI_ITERS, SI_CYCLES, SI_REFINE, SI_QPOS, SI_N };
+// per-slot double state
+enum SD : int { SD_BNORM = 0, SD_BETA, SD_N };
+
+struct DevResult {  // one per queue position
+  int status, iters, cycles, refines;
+  double relres, trace;
+  long long tag;
+  int valid, pad;
+};
+
+struct EngineArgs {
+  // seed
+  const double* Uh;
+  const double* Vh;
+  const double* K1;
+  const double* c0;
+  const double* gam;
+  double t0;
+  int n, h, ld, r;
+  // engine
+  int S, m, max_iter, max_refine, use_precond, mixed;
+  double tol, inner_tol;
+  int* si;          // S x SI_N
+  double* sdv;      // S x SD_N
+  double* d;        // S x r
+  double* R;        // S x m x (m+1)  rotated Hessenberg columns
+  double* g;        // S x (m+1)
+  double* cs;       // S x m
+  double* sn;       // S x m
+  double* V;        // S x (m+1) x N
+  double* x;        // S x N
+  double* z;        // S x N
+  double* w;        // S x N
+  double* Pinv;     // S x r*r x ld
+  int* lists;       // [0..S): FP64 list, [S..2S): low-precision list, [2S], [2S+1] counts
+  // queue (ring of capacity Q) and results
+  const double* qd;        // Q x r
+  const long long* qtag;   // Q
+  int* qctl;               // [0] head, [1] tail, [2] done count
+  DevResult* res;          // Q
+  int Q;
+  double* sol;             // optional: solutions by tag, stride N (rho form)
+  long long sol_cap;
+};
+
+// ---------------------------------------------------------------------------
+// reductions (64-wide wavefronts, 256-thread workgroups)
+// ---------------------------------------------------------------------------
+constexpr int KT = 256;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// sum over the workgroup of NV values per thread, result visible to all threads
+template <int NV>
+__device__ inline void block_sum(double (&v)[NV], double* lds) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) lds[wave * NV + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = lds[i] + lds[NV + i] + lds[2 * NV + i] + lds[3 * NV + i];
+  __syncthreads();
+}
+
+__device__ inline double block_sum1(double v, double* lds) {
+  double a[1] = {v};
+  block_sum<1>(a, lds);
+  return a[0];
+}
+
+// unit u: conjugate pair u < h (slots 2u, 2u+1) or real eigenvalue (slot u + h)
+__device__ inline int uslot(int u, int h, bool& pr) {
+  pr = u < h;
+  return pr ? 2 * u : u + h;
+}
+
+// z_a[u] = sum_b P[a][b][u] o v_b[u] for one slot (all units, all a)
+__device__ inline void apply_pinv(const EngineArgs& A, int s, const double* v, double* zout,
+                                  bool accumulate) {
+  const int r = A.r, ld = A.ld, nu = A.n - A.h;
+  const double* P = A.Pinv + (long)s * r * r * ld;
+  for (int u = threadIdx.x; u < nu; u += blockDim.x) {
+    bool pr;
+    const int q = uslot(u, A.h, pr);
+    for (int a = 0; a < r; ++a) {
+      double sr = 0, si = 0;
+      for (int b = 0; b < r; ++b) {
+        const double* pb = P + (long)(a * r + b) * ld;
+        const double* vb = v + (long)b * ld;
+        if (pr) {
+          const double pr_ = pb[q], pi_ = pb[q + 1], vr = vb[q], vi = vb[q + 1];
+          sr += pr_ * vr - pi_ * vi;
+          si += pr_ * vi + pi_ * vr;
+        } else {
+          sr += pb[q] * vb[q];
+        }
+      }
+      double* za = zout + (long)a * ld;
+      if (accumulate) {
+        za[q] += sr;
+        if (pr) za[q + 1] += si;
+      } else {
+        za[q] = sr;
+        if (pr) za[q + 1] = si;
+      }
+    }
+  }
+}
+
+// Admission of queue entry qp into slot s (whole workgroup): preconditioner
+// blocks (I - D K1_j)^-1, right-hand side b = D c0, v0 = b / ||b||.
+__device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
+  const int r = A.r, ld = A.ld, N = r * ld, nu = A.n - A.h;
+  int* si = A.si + (long)s * SI_N;
+  double* sdv = A.sdv + (long)s * SD_N;
+  const int qi = qp % A.Q;
+  double* d = A.d + (long)s * r;
+  __shared__ double dsh[kMaxRank];
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  if (threadIdx.x < r) {
+    const double v = A.qd[(long)qi * r + threadIdx.x];
+    dsh[threadIdx.x] = v;
+    d[threadIdx.x] = v;
+    if (!isfinite(v)) atomicOr(&bad, 1);
+  }
+  __syncthreads();
+  double* xs = A.x + (long)s * N;
+  double* V0 = A.V + (long)s * (A.m + 1) * N;
+  for (int e = threadIdx.x; e < N; e += blockDim.x) xs[e] = 0.0;
+  if (bad) {
+    if (threadIdx.x == 0) {
+      DevResult& o = A.res[qi];
+      o.status = LYAP_E_NONFINITE;
+      o.iters = o.cycles = o.refines = 0;
+      o.relres = NAN;
+      o.trace = NAN;
+      o.tag = A.qtag[qi];
+      __threadfence();
+      o.valid = 1;
+      si[SI_PHASE] = PH_FREE;
+      atomicAdd(&A.qctl[2], 1);
+    }
+    __syncthreads();
+    return;
+  }
+  // preconditioner blocks
+  if (A.use_precond) {
+    double* P = A.Pinv + (long)s * r * r * ld;
+    for (int u = threadIdx.x; u < nu; u += blockDim.x) {
+      bool pr;
+      const int q = uslot(u, A.h, pr);
+      double Mr[kPrecRank * kPrecRank], Mi[kPrecRank * kPrecRank];
+      double Ir[kPrecRank * kPrecRank], Ii[kPrecRank * kPrecRank];
+      for (int a = 0; a < r; ++a)
+        for (int b = 0; b < r; ++b) {
+          const double* k = A.K1 + (long)(a * r + b) * ld;
+          Mr[a * r + b] = (a == b ? 1.0 : 0.0) - dsh[a] * k[q];
+          Mi[a * r + b] = pr ? -dsh[a] * k[q + 1] : 0.0;
+          Ir[a * r + b] = a == b ? 1.0 : 0.0;
+          Ii[a * r + b] = 0.0;
+        }
+      // Gauss-Jordan with partial pivoting (complex)
+      for (int c = 0; c < r; ++c) {
+        int piv = c;
+        double best = -1;
+        for (int i = c; i < r; ++i) {
+          const double mag = fabs(Mr[i * r + c]) + fabs(Mi[i * r + c]);
+          if (mag > best) {
+            best = mag;
+            piv = i;
+          }
+        }
+        if (piv != c)
+          for (int b = 0; b < r; ++b) {
+            double t;
+            t = Mr[c * r + b]; Mr[c * r + b] = Mr[piv * r + b]; Mr[piv * r + b] = t;
+            t = Mi[c * r + b]; Mi[c * r + b] = Mi[piv * r + b]; Mi[piv * r + b] = t;
+            t = Ir[c * r + b]; Ir[c * r + b] = Ir[piv * r + b]; Ir[piv * r + b] = t;
+            t = Ii[c * r + b]; Ii[c * r + b] = Ii[piv * r + b]; Ii[piv * r + b] = t;
+          }
+        const double pr_ = Mr[c * r + c], pi_ = Mi[c * r + c];
+        const double den = pr_ * pr_ + pi_ * pi_;
+        const double ivr = pr_ / den, ivi = -pi_ / den;
+        for (int b = 0; b < r; ++b) {
+          double ar = Mr[c * r + b], ai = Mi[c * r + b];
+          Mr[c * r + b] = ar * ivr - ai * ivi;
+          Mi[c * r + b] = ar * ivi + ai * ivr;
+          ar = Ir[c * r + b];
+          ai = Ii[c * r + b];
+          Ir[c * r + b] = ar * ivr - ai * ivi;
+          Ii[c * r + b] = ar * ivi + ai * ivr;
+        }
+        for (int i = 0; i < r; ++i) {
+          if (i == c) continue;
+          const double fr = Mr[i * r + c], fi = Mi[i * r + c];
+          if (fr == 0.0 && fi == 0.0) continue;
+          for (int b = 0; b < r; ++b) {
+            Mr[i * r + b] -= fr * Mr[c * r + b] - fi * Mi[c * r + b];
+            Mi[i * r + b] -= fr * Mi[c * r + b] + fi * Mr[c * r + b];
+            Ir[i * r + b] -= fr * Ir[c * r + b] - fi * Ii[c * r + b];
+            Ii[i * r + b] -= fr * Ii[c * r + b] + fi * Ir[c * r + b];
+          }
+        }
+      }
+      for (int a = 0; a < r; ++a)
+        for (int b = 0; b < r; ++b) {
+          double* pb = P + (long)(a * r + b) * ld;
+          pb[q] = Ir[a * r + b];
+          if (pr) pb[q + 1] = Ii[a * r + b];
+        }
+    }
+  }
+  // b = D c0 ; ||b||
+  double acc = 0;
+  for (int e = threadIdx.x; e < N; e += blockDim.x) {
+    const double v = dsh[e / ld] * A.c0[e];
+    V0[e] = v;
+    acc += v * v;
+  }
+  const double bn = sqrt(block_sum1(acc, lds));
+  if (bn == 0.0) {
+    // D = 0: y = 0 is exact, X(p) = X0
+    if (threadIdx.x == 0) {
+      DevResult& o = A.res[qi];
+      o.status = LYAP_OK;
+      o.iters = o.cycles = o.refines = 0;
+      o.relres = 0.0;
+      o.trace = A.t0;
+      o.tag = A.qtag[qi];
+      __threadfence();
+      o.valid = 1;
+      si[SI_PHASE] = PH_FREE;
+      atomicAdd(&A.qctl[2], 1);
+    }
+    __syncthreads();
+    return;
+  }
+  const double inv = 1.0 / bn;
+  for (int e = threadIdx.x; e < N; e += blockDim.x) V0[e] *= inv;
+  if (threadIdx.x == 0) {
+    si[SI_PHASE] = PH_ARNOLDI;
+    si[SI_J] = 0;
+    si[SI_ITERS] = 0;
+    si[SI_CYCLES] = 1;
+    si[SI_REFINE] = 0;
+    si[SI_QPOS] = qp;
+    sdv[SD_BNORM] = bn;
+    sdv[SD_BETA] = bn;
+    A.g[(long)s * (A.m + 1)] = bn;
+  }
+  __syncthreads();
+}
+
+// claim the next queue position, or -1
+__device__ inline int claim(const EngineArgs& A) {
+  int old = atomicAdd(&A.qctl[0], 0);
+  while (true) {
+    const int tail = atomicAdd(&A.qctl[1], 0);
+    if (old >= tail) return -1;
+    const int got = atomicCAS(&A.qctl[0], old, old + 1);
+    if (got == old) return old;
+    old = got;
+  }
+}
+
+__device__ void finish(const EngineArgs& A, int s, int status, double relres, double* lds) {
+  const int r = A.r, ld = A.ld, N = r * ld;
+  int* si = A.si + (long)s * SI_N;
+  const double* xs = A.x + (long)s * N;
+  double acc = 0;
+  for (int e = threadIdx.x; e < N; e += blockDim.x) acc += A.gam[e] * xs[e];
+  const double tr = A.t0 + block_sum1(acc, lds);
+  const int qp = si[SI_QPOS];
+  const int qi = qp % A.Q;
+  const long long tag = A.qtag[qi];
+  if (A.sol && tag >= 0 && tag < A.sol_cap) {
+    double* dst = A.sol + tag * (long long)N;
+    for (int e = threadIdx.x; e < N; e += blockDim.x) dst[e] = xs[e];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    DevResult& o = A.res[qi];
+    o.status = status;
+    o.iters = si[SI_ITERS];
+    o.cycles = si[SI_CYCLES];
+    o.refines = si[SI_REFINE];
+    o.relres = relres;
+    o.trace = tr;
+    o.tag = tag;
+    __threadfence();
+    o.valid = 1;
+    si[SI_PHASE] = PH_FREE;
+    atomicAdd(&A.qctl[2], 1);
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// step kernels
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) k_lists(EngineArgs A) {
+  // single workgroup; stable compaction in slot order
+  __shared__ int c64[1024], clo[1024];
+  const int S = A.S;
+  const int per = (S + blockDim.x - 1) / blockDim.x;
+  const int s0 = threadIdx.x * per;
+  int n64 = 0, nlo = 0;
+  for (int s = s0; s < min(S, s0 + per); ++s) {
+    const int ph = A.si[(long)s * SI_N + SI_PHASE];
+    if (ph == PH_RESTART || (ph == PH_ARNOLDI && !A.mixed)) ++n64;
+    else if (ph == PH_ARNOLDI) ++nlo;
+  }
+  c64[threadIdx.x] = n64;
+  clo[threadIdx.x] = nlo;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int a = 0, b = 0;
+    for (int t = 0; t < (int)blockDim.x; ++t) {
+      const int x = c64[t], y = clo[t];
+      c64[t] = a;
+      clo[t] = b;
+      a += x;
+      b += y;
+    }
+    A.lists[2 * S] = a;
+    A.lists[2 * S + 1] = b;
+  }
+  __syncthreads();
+  int o64 = c64[threadIdx.x], olo = clo[threadIdx.x];
+  for (int s = s0; s < min(S, s0 + per); ++s) {
+    const int ph = A.si[(long)s * SI_N + SI_PHASE];
+    if (ph == PH_RESTART || (ph == PH_ARNOLDI && !A.mixed)) A.lists[o64++] = s;
+    else if (ph == PH_ARNOLDI) A.lists[S + olo++] = s;
+  }
+}
+
+// z for every listed slot (both lists): one workgroup per list entry
+__global__ void __launch_bounds__(KT) k_prep(EngineArgs A) {
+  const int S = A.S;
+  const int li = blockIdx.x;
+  const int c64 = A.lists[2 * S], clo = A.lists[2 * S + 1];
+  int s;
+  if (li < c64) s = A.lists[li];
+  else if (li < S && li - c64 < clo) s = A.lists[S + (li - c64)];
+  else return;
+  const int N = A.r * A.ld;
+  const int ph = A.si[(long)s * SI_N + SI_PHASE];
+  double* zs = A.z + (long)s * N;
+  if (ph == PH_RESTART) {
+    const double* xs = A.x + (long)s * N;
+    for (int e = threadIdx.x; e < N; e += blockDim.x) zs[e] = xs[e];
+  } else {
+    const int j = A.si[(long)s * SI_N + SI_J];
+    const double* vj = A.V + ((long)s * (A.m + 1) + j) * N;
+    if (A.use_precond) apply_pinv(A, s, vj, zs, false);
+    else
+      for (int e = threadIdx.x; e < N; e += blockDim.x) zs[e] = vj[e];
+  }
+}
+
+// X rows (li, a, b) = Vh_a o z_{slot(li), b} in precision T
+template <class T> __device__ inline void put(T* X, long off, long plane, double v);
+template <> __device__ inline void put<double>(double* X, long off, long, double v) { X[off] = v; }
+template <> __device__ inline void put<float>(float* X, long off, long, double v) { X[off] = (float)v; }
+template <> __device__ inline void put<__bf16>(__bf16* X, long off, long plane, double v) {
+  const float f = (float)v;
+  const __bf16 hi = (__bf16)f;
+  X[off] = hi;
+  X[off + plane] = (__bf16)(f - (float)hi);
+}
+
+template <class T>
+__global__ void __launch_bounds__(KT) k_formX(EngineArgs A, T* X, long plane, int which) {
+  const int S = A.S, r = A.r, ld = A.ld, h = A.h;
+  const int cnt = A.lists[2 * S + which];
+  const int row = blockIdx.y;  // li * r * r + a * r + b
+  const int li = row / (r * r);
+  if (li >= cnt) return;
+  const int a = (row / r) % r, b = row % r;
+  const int s = A.lists[which * S + li];
+  const double* va = A.Vh + (long)a * ld;
+  const double* zb = A.z + ((long)s * r + b) * ld;
+  const long base = (long)row * ld;
+  const int nu = A.n - h;
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x) {
+    bool pr;
+    const int q = uslot(u, h, pr);
+    if (pr) {
+      const double ar = va[q], ai = va[q + 1], br = zb[q], bi = zb[q + 1];
+      put<T>(X, base + q, plane, ar * br - ai * bi);
+      put<T>(X, base + q + 1, plane, ar * bi + ai * br);
+    } else {
+      put<T>(X, base + q, plane, va[q] * zb[q]);
+    }
+  }
+}
+
+// w = z - D (sum_b z_b o K1_ab + sum_b Uh_b o H_(li,a,b))
+template <class HT>
+__global__ void __launch_bounds__(KT) k_epilogue(EngineArgs A, const HT* H, int which) {
+  const int S = A.S, r = A.r, ld = A.ld, h = A.h;
+  const int cnt = A.lists[2 * S + which];
+  const int row = blockIdx.y;  // li * r + a
+  const int li = row / r;
+  if (li >= cnt) return;
+  const int a = row % r;
+  const int s = A.lists[which * S + li];
+  const double* zs = A.z + (long)s * r * ld;
+  double* ws = A.w + ((long)s * r + a) * ld;
+  const double da = A.d[(long)s * r + a];
+  const int nu = A.n - h;
+  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x) {
+    bool pr;
+    const int q = uslot(u, h, pr);
+    double sr = 0, si = 0;
+    for (int b = 0; b < r; ++b) {
+      const double* k = A.K1 + (long)(a * r + b) * ld;
+      const double* zb = zs + (long)b * ld;
+      const double* ub = A.Uh + (long)b * ld;
+      const HT* hb = H + ((long)(li * r + a) * r + b) * ld;
+      if (pr) {
+        const double kr = k[q], ki = k[q + 1], zr = zb[q], zi = zb[q + 1];
+        const double ur = ub[q], ui = ub[q + 1], hr = (double)hb[q], hi = (double)hb[q + 1];
+        sr += zr * kr - zi * ki + ur * hr - ui * hi;
+        si += zr * ki + zi * kr + ur * hi + ui * hr;
+      } else {
+        sr += zb[q] * k[q] + ub[q] * (double)hb[q];
+      }
+    }
+    ws[q] = zs[(long)a * ld + q] - da * sr;
+    if (pr) ws[q + 1] = zs[(long)a * ld + q + 1] - da * si;
+  }
+}
+
+// one workgroup per slot
+__global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
+  __shared__ double lds[4 * 8];
+  __shared__ double ycoef[kMaxRestart + 1];
+  __shared__ double hcol[kMaxRestart + 2];
+  __shared__ int next_phase;
+  const int s = blockIdx.x;
+  const int r = A.r, ld = A.ld, N = r * ld, m = A.m;
+  int* si = A.si + (long)s * SI_N;
+  double* sdv = A.sdv + (long)s * SD_N;
+  int ph = si[SI_PHASE];
+
+  if (ph == PH_FREE) {
+    __shared__ int qp;
+    if (threadIdx.x == 0) qp = claim(A);
+    __syncthreads();
+    if (qp >= 0) admit(A, s, qp, lds);
+    return;
+  }
+
+  double* Vs = A.V + (long)s * (m + 1) * N;
+  double* ws = A.w + (long)s * N;
+  double* xs = A.x + (long)s * N;
+  double* gs = A.g + (long)s * (m + 1);
+  double* Rs = A.R + (long)s * m * (m + 1);
+  double* css = A.cs + (long)s * m;
+  double* sns = A.sn + (long)s * m;
+  const double bn = sdv[SD_BNORM];
+
+  if (ph == PH_RESTART) {
+    // w = A y ; residual r = D c0 - w into V0
+    const double* d = A.d + (long)s * r;
+    double acc = 0;
+    for (int e = threadIdx.x; e < N; e += blockDim.x) {
+      const double v = d[e / ld] * A.c0[e] - ws[e];
+      Vs[e] = v;
+      acc += v * v;
+    }
+    const double rn = sqrt(block_sum1(acc, lds));
+    const double rel = rn / bn;
+    const int iters = si[SI_ITERS] + 1;
+    const int refines = si[SI_REFINE];
+    __syncthreads();
+    if (threadIdx.x == 0) si[SI_ITERS] = iters;
+    __syncthreads();
+    bool freed = true;
+    if (!isfinite(rel)) {
+      finish(A, s, LYAP_E_NONFINITE, rel, lds);
+    } else if (rel <= A.tol) {
+      finish(A, s, LYAP_OK, rel, lds);
+    } else if (iters >= A.max_iter || (A.mixed && refines >= A.max_refine)) {
+      finish(A, s, LYAP_E_NOCONV, rel, lds);
+    } else {
+      freed = false;
+      const double inv = 1.0 / rn;
+      for (int e = threadIdx.x; e < N; e += blockDim.x) Vs[e] *= inv;
+      if (threadIdx.x == 0) {
+        gs[0] = rn;
+        sdv[SD_BETA] = rn;
+        si[SI_J] = 0;
+        si[SI_CYCLES] += 1;
+        si[SI_REFINE] = refines + 1;
+        si[SI_PHASE] = PH_ARNOLDI;
+      }
+      __syncthreads();
+    }
+    if (freed) {
+      __shared__ int qp2;
+      if (threadIdx.x == 0) qp2 = claim(A);
+      __syncthreads();
+      if (qp2 >= 0) admit(A, s, qp2, lds);
+    }
+    return;
+  }
+
+  // ---- Arnoldi step j: w = A P^-1 v_j ----
+  const int j = si[SI_J];
+  if (threadIdx.x < kMaxRestart + 2) hcol[threadIdx.x] = 0.0;
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int k0 = 0; k0 <= j; k0 += 8) {
+      double acc[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) acc[t] = 0.0;
+      const int kc = min(8, j + 1 - k0);
+      for (int e = threadIdx.x; e < N; e += blockDim.x) {
+        const double we = ws[e];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (t < kc) acc[t] += Vs[(long)(k0 + t) * N + e] * we;
+      }
+      block_sum<8>(acc, lds);
+      if (threadIdx.x == 0)
+        for (int t = 0; t < kc; ++t) {
+          hcol[k0 + t] += acc[t];
+          ycoef[k0 + t] = acc[t];
+        }
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < N; e += blockDim.x) {
+      double we = ws[e];
+      for (int k = 0; k <= j; ++k) we -= ycoef[k] * Vs[(long)k * N + e];
+      ws[e] = we;
+    }
+    __syncthreads();
+  }
+  double acc = 0;
+  for (int e = threadIdx.x; e < N; e += blockDim.x) acc += ws[e] * ws[e];
+  const double hn = sqrt(block_sum1(acc, lds));
+  double* vnext = Vs + (long)(j + 1) * N;
+  if (hn > 0) {
+    const double inv = 1.0 / hn;
+    for (int e = threadIdx.x; e < N; e += blockDim.x) vnext[e] = ws[e] * inv;
+  }
+  if (threadIdx.x == 0) {
+    hcol[j + 1] = hn;
+    // apply previous rotations
+    for (int k = 0; k < j; ++k) {
+      const double a = hcol[k], b = hcol[k + 1];
+      hcol[k] = css[k] * a + sns[k] * b;
+      hcol[k + 1] = -sns[k] * a + css[k] * b;
+    }
+    const double a = hcol[j], b = hcol[j + 1];
+    double c, sg;
+    if (b == 0.0) {
+      c = 1.0;
+      sg = 0.0;
+    } else {
+      const double t = hypot(a, b);
+      c = a / t;
+      sg = b / t;
+    }
+    css[j] = c;
+    sns[j] = sg;
+    hcol[j] = c * a + sg * b;
+    hcol[j + 1] = 0.0;
+    for (int k = 0; k <= j; ++k) Rs[(long)j * (m + 1) + k] = hcol[k];
+    const double gj = gs[j];
+    gs[j] = c * gj;
+    gs[j + 1] = -sg * gj;
+    const double est = fabs(gs[j + 1]);
+    const int iters = si[SI_ITERS] + 1;
+    si[SI_ITERS] = iters;
+    const int jn = j + 1;
+    si[SI_J] = jn;
+    double target = 0.5 * A.tol * bn;
+    if (A.mixed) target = fmax(target, A.inner_tol * sdv[SD_BETA]);
+    const bool end = est <= target || jn >= m || !(hn > 1e-300 * bn) || iters >= A.max_iter ||
+                     !isfinite(est);
+    next_phase = end ? PH_RESTART : PH_ARNOLDI;
+    if (end) {
+      // back substitution R y = g
+      for (int k = jn - 1; k >= 0; --k) {
+        double v = gs[k];
+        for (int l = k + 1; l < jn; ++l) v -= Rs[(long)l * (m + 1) + k] * ycoef[l];
+        ycoef[k] = v / Rs[(long)k * (m + 1) + k];
+      }
+    }
+  }
+  __syncthreads();
+  if (next_phase == PH_RESTART) {
+    const int jn = j + 1;
+    // u = V y (into w), x += P^-1 u
+    for (int e = threadIdx.x; e < N; e += blockDim.x) {
+      double u = 0;
+      for (int k = 0; k < jn; ++k) u += ycoef[k] * Vs[(long)k * N + e];
+      ws[e] = u;
+    }
+    __syncthreads();
+    if (A.use_precond) apply_pinv(A, s, ws, xs, true);
+    else
+      for (int e = threadIdx.x; e < N; e += blockDim.x) xs[e] += ws[e];
+    __syncthreads();
+    if (threadIdx.x == 0) si[SI_PHASE] = PH_RESTART;
+  }
+}
+
+}  // namespace lyap
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+using namespace lyap;
+
+struct lyap_engine_s {
+  lyap_seed sd = nullptr;
+  int S = 0, m = 40;
+  lyap_solve_opts opts{};
+  hipStream_t stream = nullptr;  // private non-blocking stream (graph capture needs one)
+  bool mixed = false;
+  GemmType low = GemmType::F64;
+  int Q = 0;
+  long long submitted = 0;   // queue positions handed out (host mirror of tail)
+  long long harvested = 0;   // queue positions whose result was returned
+  long long next_tag = 0;
+  DevBuf si, sdv, d, R, g, cs, sn, V, x, z, w, Pinv, lists, X, H, Xlo, Hlo;
+  DevBuf qd, qtag, qctl, res;
+  double* sol = nullptr;
+  long long sol_cap = 0;
+  bool owns_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  EngineArgs args{};
+  std::vector<DevResult> res_host;
+  std::vector<long long> done_pos;  // host-side list of positions already harvested
+  std::vector<char> got;
+  long long rows_pad = 0;
+};
+
+namespace lyap {
+
+static void fill_defaults(lyap_solve_opts& o, const lyap_solve_opts* in) {
+  o.prec = LYAP_PREC_FP64;
+  o.max_iter = 600;
+  o.restart = 40;
+  o.use_precond = 1;
+  o.recycle_k = 0;
+  o.max_refine = 30;
+  o.tol = 1e-12;
+  o.inner_tol = 1e-4;
+  if (!in) return;
+  o.prec = in->prec;
+  if (in->max_iter > 0) o.max_iter = in->max_iter;
+  if (in->restart > 0) o.restart = in->restart;
+  o.use_precond = in->use_precond;
+  o.recycle_k = in->recycle_k;
+  if (in->max_refine > 0) o.max_refine = in->max_refine;
+  if (in->tol > 0) o.tol = in->tol;
+  if (in->inner_tol > 0) o.inner_tol = in->inner_tol;
+}
+
+static void validate_opts(const lyap_solve_opts& o) {
+  LYAP_REQUIRE(o.prec >= 0 && o.prec <= 3, LYAP_E_INVAL, "prec out of range");
+  LYAP_REQUIRE(o.restart >= 1 && o.restart <= kMaxRestart, LYAP_E_INVAL, "restart out of [1, 64]");
+  LYAP_REQUIRE(o.tol > 0 && o.tol < 1, LYAP_E_INVAL, "tol out of (0, 1)");
+  LYAP_REQUIRE(o.max_iter >= 1, LYAP_E_INVAL, "max_iter < 1");
+}
+
+struct EngineSizes {
+  size_t total = 0;
+  long long rows_pad = 0;
+};
+
+static EngineSizes engine_sizes(const lyap_seed_s* sd, long long S, const lyap_solve_opts& o,
+                                long long Q) {
+  EngineSizes z;
+  const long long r = sd->r, ld = sd->ld, N = r * ld, m = o.restart;
+  z.rows_pad = pad_to(S * r * r, 128);
+  auto add = [&](size_t b) { z.total += (b + 255) / 256 * 256; };
+  add(S * SI_N * 4);
+  add(S * SD_N * 8);
+  add(S * r * 8);
+  add(S * m * (m + 1) * 8);
+  add(S * (m + 1) * 8);
+  add(S * m * 8 * 2);
+  add(S * (m + 1) * N * 8);
+  add(S * N * 8 * 3);
+  add(S * r * r * ld * 8);
+  add((2 * S + 2) * 4);
+  add(z.rows_pad * ld * 8 * 2);  // X, H fp64
+  const bool mixed = o.prec != LYAP_PREC_FP64;
+  if (mixed) {
+    add(z.rows_pad * ld * (o.prec == LYAP_PREC_BF16_IR ? 4 : 4));  // Xlo (float or 2 bf16 planes)
+    add(z.rows_pad * ld * 4);                                       // Hlo float
+  }
+  add(Q * r * 8);
+  add(Q * 8);
+  add(16);
+  add(Q * sizeof(DevResult));
+  return z;
+}
+
+static void launch_step(lyap_engine_s* E, hipStream_t st) {
+  const EngineArgs& A = E->args;
+  lyap_seed_s* sd = E->sd;
+  const int S = E->S, r = (int)sd->r, ld = (int)sd->ld, nu = (int)(sd->n - sd->h);
+  hipLaunchKernelGGL(k_lists, dim3(1), dim3(1024), 0, st, A);
+  hipLaunchKernelGGL(k_prep, dim3(S), dim3(KT), 0, st, A);
+  const int ublocks = std::max(1, std::min((nu + KT - 1) / KT, 64));
+  // FP64 list (which = 0)
+  {
+    hipLaunchKernelGGL((k_formX<double>), dim3(ublocks, S * r * r), dim3(KT), 0, st, A,
+                       E->X.as<double>(), 0L, 0);
+    GemmArgs g{};
+    g.type = GemmType::F64;
+    g.A = E->X.p;
+    g.B = sd->Mc.p;
+    g.C = E->H.p;
+    g.M = E->rows_pad;
+    g.N = ld;
+    g.K = ld;
+    g.lda = g.ldb = g.ldc = ld;
+    g.Nstore = ld;
+    g.M_dev = E->lists.as<int>() + 2 * S;
+    g.m_scale = r * r;
+    gemm_launch(g, st);
+    hipLaunchKernelGGL((k_epilogue<double>), dim3(ublocks, S * r), dim3(KT), 0, st, A,
+                       E->H.as<double>(), 0);
+  }
+  if (E->mixed) {
+    GemmArgs g{};
+    g.B = (E->low == GemmType::F32) ? sd->Mc32.p : sd->Mcb.p;
+    g.type = E->low;
+    g.A = E->Xlo.p;
+    g.C = E->Hlo.p;
+    g.M = E->rows_pad;
+    g.N = ld;
+    g.K = ld;
+    g.lda = g.ldb = g.ldc = ld;
+    g.Nstore = ld;
+    g.M_dev = E->lists.as<int>() + 2 * S + 1;
+    g.m_scale = r * r;
+    if (E->low == GemmType::F32) {
+      hipLaunchKernelGGL((k_formX<float>), dim3(ublocks, S * r * r), dim3(KT), 0, st, A,
+                         E->Xlo.as<float>(), 0L, 1);
+    } else {
+      g.a_plane = E->rows_pad * ld;
+      g.b_plane = (long long)ld * ld;
+      hipLaunchKernelGGL((k_formX<__bf16>), dim3(ublocks, S * r * r), dim3(KT), 0, st, A,
+                         E->Xlo.as<__bf16>(), (long)(E->rows_pad * ld), 1);
+    }
+    gemm_launch(g, st);
+    hipLaunchKernelGGL((k_epilogue<float>), dim3(ublocks, S * r), dim3(KT), 0, st, A,
+                       E->Hlo.as<float>(), 1);
+  }
+  hipLaunchKernelGGL(k_krylov, dim3(S), dim3(KT), 0, st, A);
+  LYAP_HIP(hipGetLastError());
+}
+
+static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lyap_solve_opts* in,
+                                         hipStream_t st, long long Q, double* sol,
+                                         long long sol_cap, bool use_graph) {
+  LYAP_REQUIRE(sd != nullptr, LYAP_E_INVAL, "seed is NULL");
+  LYAP_REQUIRE(S >= 1 && S <= 8192, LYAP_E_INVAL, "slots out of [1, 8192]");
+  lyap_solve_opts o;
+  fill_defaults(o, in);
+  validate_opts(o);
+  auto* E = new lyap_engine_s();
+  std::unique_ptr<lyap_engine_s> guard(E);
+  E->sd = sd;
+  E->S = (int)S;
+  E->m = o.restart;
+  E->opts = o;
+  LYAP_HIP(hipStreamCreateWithFlags(&E->stream, hipStreamNonBlocking));
+  {
+    // order the engine after the caller's stream
+    hipEvent_t ev;
+    LYAP_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    LYAP_HIP(hipEventRecord(ev, st));
+    LYAP_HIP(hipStreamWaitEvent(E->stream, ev, 0));
+    LYAP_HIP(hipEventDestroy(ev));
+  }
+  st = E->stream;
+  E->mixed = o.prec != LYAP_PREC_FP64;
+  E->low = o.prec == LYAP_PREC_BF16_IR ? GemmType::BF16X3 : GemmType::F32;
+  E->Q = (int)Q;
+  const long long r = sd->r, ld = sd->ld, N = r * ld, m = o.restart;
+  EngineSizes z = engine_sizes(sd, S, o, Q);
+  E->rows_pad = z.rows_pad;
+  auto zalloc = [&](DevBuf& b, size_t bytes) {
+    b.alloc(std::max<size_t>(bytes, 16));
+    LYAP_HIP(hipMemsetAsync(b.p, 0, b.bytes, st));
+  };
+  zalloc(E->si, S * SI_N * 4);
+  zalloc(E->sdv, S * SD_N * 8);
+  zalloc(E->d, S * r * 8);
+  zalloc(E->R, S * m * (m + 1) * 8);
+  zalloc(E->g, S * (m + 1) * 8);
+  zalloc(E->cs, S * m * 8);
+  zalloc(E->sn, S * m * 8);
+  zalloc(E->V, S * (m + 1) * N * 8);
+  zalloc(E->x, S * N * 8);
+  zalloc(E->z, S * N * 8);
+  zalloc(E->w, S * N * 8);
+  zalloc(E->Pinv, S * r * r * ld * 8);
+  zalloc(E->lists, (2 * S + 2) * 4);
+  zalloc(E->X, z.rows_pad * ld * 8);
+  zalloc(E->H, z.rows_pad * ld * 8);
+  if (E->mixed) {
+    zalloc(E->Xlo, z.rows_pad * ld * 4);
+    zalloc(E->Hlo, z.rows_pad * ld * 4);
+  }
+  zalloc(E->qd, Q * r * 8);
+  zalloc(E->qtag, Q * 8);
+  zalloc(E->qctl, 16);
+  zalloc(E->res, Q * sizeof(DevResult));
+  E->sol = sol;
+  E->sol_cap = sol_cap;
+  E->res_host.resize(Q);
+  E->got.assign(Q, 0);
+
+  EngineArgs& A = E->args;
+  A.Uh = sd->Uh.as<double>();
+  A.Vh = sd->Vh.as<double>();
+  A.K1 = sd->K1.as<double>();
+  A.c0 = sd->c0.as<double>();
+  A.gam = sd->gam.as<double>();
+  A.t0 = sd->t0;
+  A.n = (int)sd->n;
+  A.h = (int)sd->h;
+  A.ld = (int)ld;
+  A.r = (int)r;
+  A.S = (int)S;
+  A.m = (int)m;
+  A.max_iter = o.max_iter;
+  A.max_refine = o.max_refine;
+  A.use_precond = (o.use_precond && r <= kPrecRank) ? 1 : 0;
+  A.mixed = E->mixed ? 1 : 0;
+  A.tol = o.tol;
+  A.inner_tol = o.inner_tol;
+  A.si = E->si.as<int>();
+  A.sdv = E->sdv.as<double>();
+  A.d = E->d.as<double>();
+  A.R = E->R.as<double>();
+  A.g = E->g.as<double>();
+  A.cs = E->cs.as<double>();
+  A.sn = E->sn.as<double>();
+  A.V = E->V.as<double>();
+  A.x = E->x.as<double>();
+  A.z = E->z.as<double>();
+  A.w = E->w.as<double>();
+  A.Pinv = E->Pinv.as<double>();
+  A.lists = E->lists.as<int>();
+  A.qd = E->qd.as<double>();
+  A.qtag = E->qtag.as<long long>();
+  A.qctl = E->qctl.as<int>();
+  A.res = E->res.as<DevResult>();
+  A.Q = (int)Q;
+  A.sol = sol;
+  A.sol_cap = sol_cap;
+  LYAP_HIP(hipStreamSynchronize(st));
+
+  if (use_graph) {
+    LYAP_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+      launch_step(E, st);
+    } catch (...) {
+      hipGraph_t tmp;
+      (void)hipStreamEndCapture(st, &tmp);
+      throw;
+    }
+    LYAP_HIP(hipStreamEndCapture(st, &E->graph));
+    LYAP_HIP(hipGraphInstantiate(&E->gexec, E->graph, nullptr, nullptr, 0));
+    E->owns_graph = true;
+  }
+  guard.release();
+  return E;
+}
+
+static void engine_destroy_impl(lyap_engine_s* E) {
+  if (!E) return;
+  (void)hipStreamSynchronize(E->stream);
+  if (E->gexec) (void)hipGraphExecDestroy(E->gexec);
+  if (E->graph) (void)hipGraphDestroy(E->graph);
+  if (E->stream) (void)hipStreamDestroy(E->stream);
+  delete E;
+}
+
+// host -> device queue append (positions submitted .. submitted+count)
+static void engine_submit_impl(lyap_engine_s* E, long long count, const double* d_host,
+                               const long long* tags) {
+  LYAP_REQUIRE(count >= 0, LYAP_E_INVAL, "count < 0");
+  if (count == 0) return;
+  LYAP_REQUIRE(d_host != nullptr, LYAP_E_INVAL, "d is NULL");
+  const long long inflight = E->submitted - E->harvested;
+  LYAP_REQUIRE(inflight + count <= E->Q, LYAP_E_INVAL, "engine queue capacity exceeded");
+  const int r = (int)E->sd->r;
+  hipStream_t st = E->stream;
+  // copy in at most two contiguous pieces of the ring
+  long long done = 0;
+  std::vector<long long> tg(count);
+  for (long long i = 0; i < count; ++i) tg[i] = tags ? tags[i] : E->next_tag + i;
+  while (done < count) {
+    const long long pos = (E->submitted + done) % E->Q;
+    const long long piece = std::min(count - done, (long long)E->Q - pos);
+    LYAP_HIP(hipMemcpyAsync(E->qd.as<double>() + pos * r, d_host + done * r,
+                            piece * r * sizeof(double), hipMemcpyHostToDevice, st));
+    LYAP_HIP(hipMemcpyAsync(E->qtag.as<long long>() + pos, tg.data() + done,
+                            piece * sizeof(long long), hipMemcpyHostToDevice, st));
+    // clear result records of the new positions
+    LYAP_HIP(hipMemsetAsync(E->res.as<DevResult>() + pos, 0, piece * sizeof(DevResult), st));
+    done += piece;
+  }
+  E->submitted += count;
+  if (!tags) E->next_tag += count;
+  const int tail = (int)(E->submitted);
+  LYAP_HIP(hipMemcpyAsync(E->qctl.as<int>() + 1, &tail, sizeof(int), hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipStreamSynchronize(st));  // tail lives on the host stack
+}
+
+static long long engine_done_count(lyap_engine_s* E) {
+  int c = 0;
+  LYAP_HIP(hipMemcpyAsync(&c, E->qctl.as<int>() + 2, sizeof(int), hipMemcpyDeviceToHost, E->stream));
+  LYAP_HIP(hipStreamSynchronize(E->stream));
+  return c;
+}
+
+static long long engine_run_impl(lyap_engine_s* E, long long max_steps, int poll_every) {
+  if (poll_every < 1) poll_every = 8;
+  long long steps = 0;
+  while (steps < max_steps) {
+    const long long busy = E->submitted - engine_done_count(E);
+    if (busy <= 0) return 0;
+    const long long k = std::min<long long>(poll_every, max_steps - steps);
+    for (long long i = 0; i < k; ++i) {
+      if (E->gexec) LYAP_HIP(hipGraphLaunch(E->gexec, E->stream));
+      else launch_step(E, E->stream);
+    }
+    steps += k;
+  }
+  return E->submitted - engine_done_count(E);
+}
+
+static long long engine_harvest_impl(lyap_engine_s* E, long long max_out, long long* tags_out,
+                                     lyap_result* res_out) {
+  // copy the records of all in-flight positions (ring order)
+  const long long lo = E->harvested, hi = E->submitted;
+  if (hi <= lo || max_out <= 0) return 0;
+  for (long long p = lo; p < hi;) {
+    const long long pos = p % E->Q;
+    const long long piece = std::min(hi - p, (long long)E->Q - pos);
+    LYAP_HIP(hipMemcpyAsync(E->res_host.data() + pos, E->res.as<DevResult>() + pos,
+                            piece * sizeof(DevResult), hipMemcpyDeviceToHost, E->stream));
+    p += piece;
+  }
+  LYAP_HIP(hipStreamSynchronize(E->stream));
+  long long n = 0;
+  for (long long p = lo; p < hi && n < max_out; ++p) {
+    const long long pos = p % E->Q;
+    const DevResult& o = E->res_host[pos];
+    if (!o.valid || E->got[pos]) continue;
+    E->got[pos] = 1;
+    if (tags_out) tags_out[n] = o.tag;
+    if (res_out) {
+      res_out[n].status = o.status;
+      res_out[n].iters = o.iters;
+      res_out[n].cycles = o.cycles;
+      res_out[n].refinements = o.refines;
+      res_out[n].rel_residual = o.relres;
+      res_out[n].trace = o.trace;
+    }
+    ++n;
+  }
+  // advance the harvested watermark over contiguous harvested positions
+  while (E->harvested < E->submitted && E->got[E->harvested % E->Q]) {
+    E->got[E->harvested % E->Q] = 0;
+    ++E->harvested;
+  }
+  return n;
+}
+
+}  // namespace lyap
+
+
+static long long default_slots(const lyap_seed_s* sd, long long P) {
+  // enough rows for the Cauchy GEMM to fill the GPU, bounded by P
+  const long long r = sd->r;
+  long long S = std::max<long long>(64, 8192 / (r * r));
+  S = std::min<long long>(S, 2048);
+  return std::max<long long>(1, std::min(S, P));
+}
+
+extern "C" {
+
+size_t engine_device_bytes(lyap_seed sd, int64_t slots, const lyap_solve_opts* opts) {
+  if (!sd || slots < 1) return 0;
+  lyap_solve_opts o;
+  fill_defaults(o, opts);
+  return engine_sizes(sd, slots, o, std::max<int64_t>(4 * slots, 1024)).total;
+}
+
+lyap_status engine_create(lyap_seed sd, int64_t slots, const lyap_solve_opts* opts,
+                          void* hip_stream, lyap_engine* out) {
+  if (!out) return LYAP_E_INVAL;
+  *out = nullptr;
+  LYAP_TRY(*out = engine_create_impl(sd, slots, opts, (hipStream_t)hip_stream,
+                                     std::max<int64_t>(4 * slots, 1024), nullptr, 0, true));
+  return LYAP_OK;
+}
+
+lyap_status engine_destroy(lyap_engine E) {
+  if (!E) return LYAP_E_INVAL;
+  LYAP_TRY(engine_destroy_impl(E));
+  return LYAP_OK;
+}
+
+lyap_status engine_submit(lyap_engine E, int64_t count, const double* d_host, const int64_t* tags) {
+  if (!E) return LYAP_E_INVAL;
+  LYAP_TRY(engine_submit_impl(E, count, d_host, reinterpret_cast<const long long*>(tags)));
+  return LYAP_OK;
+}
+
+lyap_status engine_run(lyap_engine E, int64_t max_steps, int32_t poll_every, int64_t* busy) {
+  if (!E) return LYAP_E_INVAL;
+  LYAP_TRY({
+    const long long b = engine_run_impl(E, max_steps, poll_every);
+    if (busy) *busy = b;
+  });
+  return LYAP_OK;
+}
+
+lyap_status engine_harvest(lyap_engine E, int64_t max_out, int64_t* tags_out, lyap_result* res_out,
+                           int64_t* n_out) {
+  if (!E) return LYAP_E_INVAL;
+  LYAP_TRY({
+    const long long n =
+        engine_harvest_impl(E, max_out, reinterpret_cast<long long*>(tags_out), res_out);
+    if (n_out) *n_out = n;
+  });
+  return LYAP_OK;
+}
+
+size_t smw_workspace_bytes(lyap_seed sd, int64_t P, const lyap_solve_opts* opts) {
+  if (!sd || P < 1) return 0;
+  lyap_solve_opts o;
+  fill_defaults(o, opts);
+  const long long S = default_slots(sd, P);
+  const size_t sol = (size_t)P * sd->r * sd->ld * sizeof(double);
+  return engine_sizes(sd, S, o, P).total + sol;
+}
+
+lyap_status smw_solve_batch(lyap_seed sd, int64_t P, const double* d_dev,
+                            const lyap_solve_opts* opts, double* Y_dev, lyap_result* res_host,
+                            void* workspace_dev, size_t workspace_bytes, void* hip_stream) {
+  if (!sd || P < 1 || !d_dev || !Y_dev || !res_host) return LYAP_E_INVAL;
+  LYAP_TRY({
+    lyap_solve_opts o;
+    fill_defaults(o, opts);
+    validate_opts(o);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const size_t need = smw_workspace_bytes(sd, P, opts);
+    LYAP_REQUIRE(workspace_dev == nullptr || workspace_bytes >= need, LYAP_E_INVAL,
+                 "workspace too small");
+    const long long r = sd->r, ld = sd->ld, n = sd->n;
+    // the solution store comes from the workspace (or a private allocation)
+    DevBuf own;
+    double* sol;
+    if (workspace_dev) {
+      sol = reinterpret_cast<double*>(workspace_dev);
+    } else {
+      own.alloc((size_t)P * r * ld * sizeof(double));
+      sol = own.as<double>();
+    }
+    const long long S = default_slots(sd, P);
+    lyap_engine_s* E = engine_create_impl(sd, S, &o, st, P, sol, P, true);
+    std::unique_ptr<lyap_engine_s, void (*)(lyap_engine_s*)> eg(E, engine_destroy_impl);
+    const hipStream_t user = st;
+    st = E->stream;
+    // queue: d from device, tags 0..P-1
+    LYAP_HIP(hipMemcpyAsync(E->qd.p, d_dev, P * r * sizeof(double), hipMemcpyDeviceToDevice, st));
+    std::vector<long long> tags(P);
+    for (long long i = 0; i < P; ++i) tags[i] = i;
+    LYAP_HIP(hipMemcpyAsync(E->qtag.p, tags.data(), P * sizeof(long long), hipMemcpyHostToDevice, st));
+    const int tail = (int)P;
+    LYAP_HIP(hipMemcpyAsync(E->qctl.as<int>() + 1, &tail, sizeof(int), hipMemcpyHostToDevice, st));
+    LYAP_HIP(hipStreamSynchronize(st));
+    E->submitted = P;
+    const long long max_steps = (long long)o.max_iter * ((P + S - 1) / S + 1) + 16;
+    engine_run_impl(E, max_steps, 8);
+    std::vector<long long> tg(P);
+    std::vector<lyap_result> rr(P);
+    const long long got = engine_harvest_impl(E, P, tg.data(), rr.data());
+    for (long long i = 0; i < P; ++i) {
+      res_host[i] = lyap_result{LYAP_E_NOCONV, 0, 0, 0, NAN, NAN};
+    }
+    for (long long i = 0; i < got; ++i)
+      if (tg[i] >= 0 && tg[i] < P) res_host[tg[i]] = rr[i];
+    // physical Y = rho(Yhat) Tout  (transform-out GEMM, n columns stored)
+    GemmArgs g{};
+    g.type = GemmType::F64;
+    g.A = sol;
+    g.B = sd->Tout.p;
+    g.C = Y_dev;
+    g.M = P * r;
+    g.N = ld;
+    g.K = ld;
+    g.lda = ld;
+    g.ldb = ld;
+    g.ldc = n;
+    g.Nstore = n;
+    g.M_dev = nullptr;
+    g.m_scale = 1;
+    gemm_launch(g, st);
+    LYAP_HIP(hipStreamSynchronize(st));
+    (void)user;
+  });
+  return LYAP_OK;
+}
+
+}  // extern "C"

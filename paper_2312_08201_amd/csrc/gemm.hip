@@ -1,0 +1,331 @@
+// MFMA GEMM kernels for gfx950 (CDNA4).
+//
+// One GEMM shape serves the whole library: C[M x N] = A[M x K] * B[K x N],
+// row-major, with K and N padded to the tile so the inner loop has no bounds
+// checks.  It carries both the basis transforms (A = batched r x n blocks, B =
+// the real eigenbasis or its inverse) and the Cauchy contraction of the seed
+// Lyapunov solve (A = Hadamard products of low-rank rows, B = the real form of
+// the Cauchy matrix 1/(lambda_i + lambda_j)).
+//
+// Tiling: 128 x 128 workgroup tile, 4 waves of 64 x 64, 16 x 16 MFMA blocks.
+// Operands are staged through LDS with one barrier per K-tile (double buffer);
+// the next K-tile is fetched into registers while the current one is
+// multiplied.  Workgroups are mapped to tiles so that consecutive tiles of one
+// B column panel land on the same XCD (blocks are dispatched round-robin over
+// the 8 XCDs), which keeps the shared B panel in that XCD's L2.
+#include "common.h"
+
+namespace lyap {
+
+namespace {
+
+constexpr int BM = 128;
+constexpr int BN = 128;
+constexpr int NTHREADS = 256;
+
+typedef double double4_ __attribute__((ext_vector_type(4)));
+typedef float float4_ __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_ __attribute__((ext_vector_type(8)));
+
+__device__ inline double4_ mfma(double a, double b, double4_ c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline float4_ mfma(float a, float b, float4_ c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <class T> struct Acc;
+template <> struct Acc<double> { typedef double4_ type; };
+template <> struct Acc<float> { typedef float4_ type; };
+
+// Tile index -> (m-tile, n-tile) with XCD-aware grouping.
+__device__ inline void tile_of(int bid, int mtiles, int ntiles, int& mt, int& nt) {
+  const int T = mtiles * ntiles;
+  int t = bid;
+  const int full = (T / 8) * 8;
+  if (bid < full) {
+    const int per = full / 8;
+    t = (bid % 8) * per + bid / 8;
+  }
+  nt = t / mtiles;
+  mt = t % mtiles;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 / FP32: v_mfma_{f64,f32}_16x16x4.  Lane layout (16 x 16 x 4):
+//   A[i][k] in lane i + 16 k, B[k][j] in lane j + 16 k,
+//   D[i][j]: f32 in lane j + 16 (i / 4), element i % 4;
+//            f64 in lane j + 16 (i % 4), element i / 4 (measured on gfx950).
+// LDS holds A transposed (k-major) so a fragment read is 16 consecutive rows.
+// ---------------------------------------------------------------------------
+template <class T, int BK>
+__global__ void __launch_bounds__(NTHREADS)
+gemm_kernel(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
+            int M, int N, int K, long lda, long ldb, long ldc, int Nstore,
+            const int* __restrict__ M_dev, int m_scale) {
+  typedef typename Acc<T>::type acc_t;
+  constexpr int PADA = 4;
+  constexpr int PADB = 4;
+  __shared__ T As[2][BK][BM + PADA];
+  __shared__ T Bs[2][BK][BN + PADB];
+
+  const int mtiles = (M + BM - 1) / BM;
+  const int ntiles = N / BN;
+  int mt, nt;
+  tile_of(blockIdx.x, mtiles, ntiles, mt, nt);
+  int Meff = M;
+  if (M_dev) {
+    const int md = M_dev[0] * m_scale;
+    Meff = md < M ? md : M;
+  }
+  const int row0 = mt * BM;
+  const int col0 = nt * BN;
+  if (row0 >= Meff) return;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave >> 1) * 64;
+  const int wn0 = (wave & 1) * 64;
+
+  // global -> register mapping
+  constexpr int A_PER = BM * BK / NTHREADS;      // elements per thread
+  constexpr int A_TPR = BK / A_PER;              // threads per row
+  const int a_row = tid / A_TPR;
+  const int a_k = (tid % A_TPR) * A_PER;
+  int a_grow = row0 + a_row;
+  if (a_grow > M - 1) a_grow = M - 1;
+  const T* a_src = A + (long)a_grow * lda + a_k;
+
+  constexpr int B_PER = BK * BN / NTHREADS;
+  constexpr int B_TPR = BN / B_PER;
+  const int b_k = tid / B_TPR;
+  const int b_n = (tid % B_TPR) * B_PER;
+  const T* b_src = B + (long)b_k * ldb + col0 + b_n;
+
+  T ra[A_PER], rb[B_PER];
+
+  auto gload = [&](int kt) {
+    const T* pa = a_src + (long)kt * BK;
+#pragma unroll
+    for (int i = 0; i < A_PER; ++i) ra[i] = pa[i];
+    const T* pb = b_src + (long)kt * BK * ldb;
+#pragma unroll
+    for (int i = 0; i < B_PER; ++i) rb[i] = pb[i];
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < A_PER; ++i) As[buf][a_k + i][a_row] = ra[i];
+#pragma unroll
+    for (int i = 0; i < B_PER; ++i) Bs[buf][b_k][b_n + i] = rb[i];
+  };
+
+  acc_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+  const int nk = K / BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int lr = lane & 15;
+  const int lk = lane >> 4;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload(kt + 1);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      T af[4], bfr[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) af[i] = As[cur][kk + lk][wm0 + 16 * i + lr];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bfr[j] = Bs[cur][kk + lk][wn0 + 16 * j + lr];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma(af[i], bfr[j], acc[i][j]);
+    }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  // output rows of element v: f64 16x16x4 -> lane/16 + 4 v ; f32 16x16x4 -> 4 (lane/16) + v
+  constexpr bool kF64 = sizeof(T) == 8;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = row0 + wm0 + 16 * i + (kF64 ? lk + 4 * v : 4 * lk + v);
+      if (row >= Meff) continue;
+      T* crow = C + (long)row * ldc;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = col0 + wn0 + 16 * j + lr;
+        if (col < Nstore) crow[col] = acc[i][j][v];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Split-BF16 (three products): A = Ah + Al, B = Bh + Bl with bf16 planes,
+// C ~= Ah Bh + Ah Bl + Al Bh accumulated in FP32 (v_mfma_f32_16x16x32_bf16,
+// gfx950).  Lane layout (16 x 16 x 32): A[i][k] in lane i + 16 (k / 8),
+// element k % 8; B[k][j] in lane j + 16 (k / 8), element k % 8; D as above.
+// B is stored transposed (Bt[N][K]) so both operands are k-contiguous.
+// ---------------------------------------------------------------------------
+constexpr int BK16 = 32;
+
+__global__ void __launch_bounds__(NTHREADS)
+gemm_bf16x3_kernel(const __bf16* __restrict__ A, long a_plane, const __bf16* __restrict__ Bt,
+                   long b_plane, float* __restrict__ C, int M, int N, int K, long lda, long ldb,
+                   long ldc, int Nstore, const int* __restrict__ M_dev, int m_scale) {
+  constexpr int PAD = 8;  // bf16 elements
+  __shared__ __attribute__((aligned(16))) __bf16 Ash[2][2][BM][BK16 + PAD];  // [buf][plane]
+  __shared__ __attribute__((aligned(16))) __bf16 Bsh[2][2][BN][BK16 + PAD];
+
+  const int mtiles = (M + BM - 1) / BM;
+  const int ntiles = N / BN;
+  int mt, nt;
+  tile_of(blockIdx.x, mtiles, ntiles, mt, nt);
+  int Meff = M;
+  if (M_dev) {
+    const int md = M_dev[0] * m_scale;
+    Meff = md < M ? md : M;
+  }
+  const int row0 = mt * BM;
+  const int col0 = nt * BN;
+  if (row0 >= Meff) return;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave >> 1) * 64;
+  const int wn0 = (wave & 1) * 64;
+
+  // each thread moves 16 bf16 (two 16-byte vectors) per plane per operand
+  const int g_row = tid >> 1;           // 0..127
+  const int g_k = (tid & 1) * 16;       // 0 or 16
+  int a_grow = row0 + g_row;
+  if (a_grow > M - 1) a_grow = M - 1;
+  const __bf16* a_src = A + (long)a_grow * lda + g_k;
+  const __bf16* b_src = Bt + (long)(col0 + g_row) * ldb + g_k;
+
+  typedef uint4 vec_t;  // 8 bf16
+  vec_t ra[2][2], rb[2][2];  // [plane][half]
+
+  auto gload = [&](int kt) {
+    const long off = (long)kt * BK16;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const vec_t* pa = reinterpret_cast<const vec_t*>(a_src + p * a_plane + off);
+      const vec_t* pb = reinterpret_cast<const vec_t*>(b_src + p * b_plane + off);
+      ra[p][0] = pa[0];
+      ra[p][1] = pa[1];
+      rb[p][0] = pb[0];
+      rb[p][1] = pb[1];
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      vec_t* da = reinterpret_cast<vec_t*>(&Ash[buf][p][g_row][g_k]);
+      vec_t* db = reinterpret_cast<vec_t*>(&Bsh[buf][p][g_row][g_k]);
+      da[0] = ra[p][0];
+      da[1] = ra[p][1];
+      db[0] = rb[p][0];
+      db[1] = rb[p][1];
+    }
+  };
+
+  float4_ acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = float4_{0, 0, 0, 0};
+
+  const int nk = K / BK16;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int lr = lane & 15;
+  const int lk = (lane >> 4) * 8;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload(kt + 1);
+    bf16x8_ ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ah[i] = *reinterpret_cast<const bf16x8_*>(&Ash[cur][0][wm0 + 16 * i + lr][lk]);
+      al[i] = *reinterpret_cast<const bf16x8_*>(&Ash[cur][1][wm0 + 16 * i + lr][lk]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      bh[j] = *reinterpret_cast<const bf16x8_*>(&Bsh[cur][0][wn0 + 16 * j + lr][lk]);
+      bl[j] = *reinterpret_cast<const bf16x8_*>(&Bsh[cur][1][wn0 + 16 * j + lr][lk]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = row0 + wm0 + 16 * i + (lane >> 4) * 4 + v;
+      if (row >= Meff) continue;
+      float* crow = C + (long)row * ldc;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = col0 + wn0 + 16 * j + lr;
+        if (col < Nstore) crow[col] = acc[i][j][v];
+      }
+    }
+  }
+}
+
+}  // namespace
+
+void gemm_launch(const GemmArgs& g, hipStream_t s) {
+  LYAP_REQUIRE(g.N % BN == 0, LYAP_E_INVAL, "gemm: N not padded");
+  LYAP_REQUIRE(g.M >= 1, LYAP_E_INVAL, "gemm: M < 1");
+  const int mtiles = (int)((g.M + BM - 1) / BM);
+  const int ntiles = (int)(g.N / BN);
+  dim3 grid(mtiles * ntiles), block(NTHREADS);
+  switch (g.type) {
+    case GemmType::F64:
+      LYAP_REQUIRE(g.K % 16 == 0, LYAP_E_INVAL, "gemm: K not padded");
+      hipLaunchKernelGGL((gemm_kernel<double, 16>), grid, block, 0, s,
+                         (const double*)g.A, (const double*)g.B, (double*)g.C, (int)g.M,
+                         (int)g.N, (int)g.K, (long)g.lda, (long)g.ldb, (long)g.ldc,
+                         (int)g.Nstore, g.M_dev, g.m_scale);
+      break;
+    case GemmType::F32:
+      LYAP_REQUIRE(g.K % 32 == 0, LYAP_E_INVAL, "gemm: K not padded");
+      hipLaunchKernelGGL((gemm_kernel<float, 32>), grid, block, 0, s, (const float*)g.A,
+                         (const float*)g.B, (float*)g.C, (int)g.M, (int)g.N, (int)g.K,
+                         (long)g.lda, (long)g.ldb, (long)g.ldc, (int)g.Nstore, g.M_dev,
+                         g.m_scale);
+      break;
+    case GemmType::BF16X3:
+      LYAP_REQUIRE(g.K % BK16 == 0, LYAP_E_INVAL, "gemm: K not padded");
+      hipLaunchKernelGGL(gemm_bf16x3_kernel, grid, block, 0, s, (const __bf16*)g.A,
+                         (long)g.a_plane, (const __bf16*)g.B, (long)g.b_plane, (float*)g.C,
+                         (int)g.M, (int)g.N, (int)g.K, (long)g.lda, (long)g.ldb, (long)g.ldc,
+                         (int)g.Nstore, g.M_dev, g.m_scale);
+      break;
+  }
+  LYAP_HIP(hipGetLastError());
+}
+
+}  // namespace lyap

@@ -1,0 +1,65 @@
+// Internal structures of the lyapsmw library.
+//
+// Real form of the complex eigenbasis.  A0 = Q0 Lambda0 Q0^-1 (Section 2.1)
+// with complex-conjugate eigenpairs.  Every quantity the method needs in
+// eigen-coordinates (Q0^-1 U, V^T Q0, Y Q0^-T, the Cauchy contraction ...) is
+// a complex vector whose entries for lambda and conj(lambda) are conjugate.
+// It is stored as a real "rho-vector" of length n: for the k-th pair
+// (Im lambda_k > 0) the entries 2k, 2k+1 hold the real and imaginary part of
+// the lambda_k entry; real eigenvalues follow at 2h, 2h+1, ...  Products of
+// two such vectors are complex on pair slots and real elsewhere.
+//
+// S (n x n, real) holds the eigenvectors in the same order:
+// S[:, 2k] = Re q_k, S[:, 2k+1] = Im q_k, S[:, 2h+m] = real eigenvector m.
+// Then Q0^-1 row k = (S^-1 row 2k - i S^-1 row 2k+1) / 2, which gives
+//   rho(Y Q0^-T) = (Y S^-T) * sig,   sig = (1/2, -1/2, ..., 1, ...)
+//   Y           = (rho(Yhat) * sigp) S^T,  sigp = (2, -2, ..., 1, ...)
+//   rho(V^T Q0) = V^T S.
+#pragma once
+
+#include "common.h"
+
+struct lyap_seed_s {
+  int64_t n = 0, r = 0, s = 0, h = 0, ld = 0;
+  int basis = LYAP_BASIS_EIG;
+  double cond_est = 0, min_lam_sum = 0, max_re = 0, t0 = 0, factor_seconds = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+
+  // persistent device data (double unless noted; n-vectors have stride ld, zero pad)
+  lyap::DevBuf lam;     // 2 x ld: Re / Im of the eigenvalue belonging to each rho slot
+  lyap::DevBuf Mc;      // ld x ld: real Cauchy operator, rho(x L) = rho(x) Mc
+  lyap::DevBuf Mc32;    // ld x ld float copy
+  lyap::DevBuf Mcb;     // 2 planes ld x ld bf16 (hi, lo) of Mc^T
+  lyap::DevBuf Tin;     // ld x ld: Tin[m][j] = S^-1[j][m] sig_j   (rho(Y Q0^-T) = Y Tin)
+  lyap::DevBuf Tout;    // ld x ld: Tout[j][m] = sigp_j S[m][j]     (Y = rho(Yhat) Tout)
+  lyap::DevBuf Uh;      // r x ld  rho(Q0^-1 U)^T
+  lyap::DevBuf Vh;      // r x ld  rho(V^T Q0)
+  lyap::DevBuf K1;      // r*r x ld: K1[a][b] = rho((Vh_a o Uh_b) L)
+  lyap::DevBuf c0;      // r x ld: rho(V^T X0 Q0^-T)
+  lyap::DevBuf gam;     // r x ld: trace(E X) = t0 + sum_b <gam_b, rho(Yhat_b)>
+  lyap::DevBuf Gam;     // r x ld: physical Gamma^T (trace = t0 + 2 <Gamma^T, Y>)
+  lyap::DevBuf scratch; // grown on demand by lyap_seed_apply / trace_EX
+  size_t scratch_bytes = 0;
+
+  size_t device_bytes() const {
+    return lam.bytes + Mc.bytes + Mc32.bytes + Mcb.bytes + Tin.bytes + Tout.bytes + Uh.bytes +
+           Vh.bytes + K1.bytes + c0.bytes + gam.bytes + Gam.bytes + scratch.bytes;
+  }
+};
+
+namespace lyap {
+
+// ---- elementwise helpers on rho-vectors (launchers, seed.hip) ----
+// out[(i*nb + j)] = a_i o b_j  (rho-complex product), rows of length ld
+void hadamard_outer(double* out, const double* a, long lda, int na, const double* b, long ldb,
+                    int nb, int h, int n, int ld, hipStream_t s);
+// out[g] (+)= scale * sum_{t < G} w_t o H[g*G + t]   for g < ngroups
+void contract_groups(double* out, const double* H, long ldh, const double* w, long ldw, int ngroups,
+                     int G, int h, int n, int ld, double scale, bool accumulate, hipStream_t s);
+// deterministic dot products: out[p] = base + scale * sum_k x[p*stride + k] * y[(p % ymod)*... ]
+void batched_dot(double* out, const double* X, long ldx, const double* Y, long ldy, int rows_per,
+                 int count, int n, double base, double scale, hipStream_t s);
+void convert_f64_f32(float* out, const double* in, long count, hipStream_t s);
+
+}  // namespace lyap

@@ -1,0 +1,668 @@
+// Offline stage: seed factorisation and the p-independent precompute
+// (Section 2.1, Table 1 left column), plus the stand-alone seed Lyapunov
+// solve (eq:Z(v)) and the collapsed trace functional.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+
+#include "internal.h"
+#include "lapack_host.h"
+
+namespace lyap {
+
+namespace {
+std::mutex g_err_mu;
+std::string g_last_error;
+}  // namespace
+
+void set_last_error(const std::string& s) {
+  std::lock_guard<std::mutex> g(g_err_mu);
+  g_last_error = s;
+}
+
+// ---------------------------------------------------------------------------
+// Device kernels
+// ---------------------------------------------------------------------------
+
+// Real form of the Cauchy matrix L_ij = 1 / (lambda_i + lambda_j): the linear
+// map rho(x) -> rho(x L) restricted to conjugate-symmetric x (Section 2.1,
+// the division by lambda_i + lambda_j of eq:Z(v)).  Row = input slot i,
+// column = output slot j.  For a pair k (input) and pair l (output):
+//   x_k L_kl + conj(x_k) L_{conj k, l},  a1 = 1/(l_k + l_l), a2 = 1/(conj l_k + l_l).
+__device__ inline void crecip(double x, double y, double& re, double& im) {
+  // 1 / (x + i y) by Smith's scaling
+  if (fabs(x) >= fabs(y)) {
+    const double t = y / x, den = x + y * t;
+    re = 1.0 / den;
+    im = -t / den;
+  } else {
+    const double t = x / y, den = x * t + y;
+    re = t / den;
+    im = -1.0 / den;
+  }
+}
+
+__global__ void k_build_cauchy(double* __restrict__ Mc, const double* __restrict__ lam, int n, int h,
+                               int ld) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= ld) return;
+  double v = 0.0;
+  if (i < n && j < n) {
+    const double* lre = lam;
+    const double* lim = lam + ld;
+    const bool ip = i < 2 * h, jp = j < 2 * h;
+    const double xr = lre[i], xi = lim[i];  // lambda of slot i (pair: lambda_k, Im > 0)
+    const double yr = lre[j], yi = lim[j];
+    if (ip && jp) {
+      double a1r, a1i, a2r, a2i;
+      crecip(xr + yr, xi + yi, a1r, a1i);
+      crecip(xr + yr, -xi + yi, a2r, a2i);
+      const int ci = i & 1, cj = j & 1;
+      if (!ci && !cj) v = a1r + a2r;
+      else if (ci && !cj) v = a2i - a1i;
+      else if (!ci && cj) v = a1i + a2i;
+      else v = a1r - a2r;
+    } else if (ip && !jp) {
+      double ar, ai;
+      crecip(xr + yr, xi, ar, ai);
+      v = (i & 1) ? -2.0 * ai : 2.0 * ar;
+    } else if (!ip && jp) {
+      double br, bi;
+      crecip(xr + yr, yi, br, bi);
+      v = (j & 1) ? bi : br;
+    } else {
+      v = 1.0 / (xr + yr);
+    }
+  }
+  Mc[(long)i * ld + j] = v;
+}
+
+// unit u -> first slot and pair flag
+__device__ inline int unit_slot(int u, int h, bool& pair) {
+  pair = u < h;
+  return pair ? 2 * u : u + h;
+}
+
+__global__ void k_hadamard_outer(double* __restrict__ out, const double* __restrict__ a, long lda,
+                                 int na, const double* __restrict__ b, long ldb, int nb, int h,
+                                 int n, int ld) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = blockIdx.y;
+  const int ia = row / nb, ib = row % nb;
+  if (u >= n - h) return;
+  bool pr;
+  const int q = unit_slot(u, h, pr);
+  const double* pa = a + ia * lda;
+  const double* pb = b + ib * ldb;
+  double* po = out + (long)row * ld;
+  if (pr) {
+    const double ar = pa[q], ai = pa[q + 1], br = pb[q], bi = pb[q + 1];
+    po[q] = ar * br - ai * bi;
+    po[q + 1] = ar * bi + ai * br;
+  } else {
+    po[q] = pa[q] * pb[q];
+  }
+}
+
+__global__ void k_contract_groups(double* __restrict__ out, const double* __restrict__ H, long ldh,
+                                  const double* __restrict__ w, long ldw, int G, int h, int n, int ld,
+                                  double scale, int accumulate) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = blockIdx.y;
+  if (u >= n - h) return;
+  bool pr;
+  const int q = unit_slot(u, h, pr);
+  double sr = 0.0, si = 0.0;
+  for (int t = 0; t < G; ++t) {
+    const double* ph = H + (long)(g * G + t) * ldh;
+    const double* pw = w + (long)t * ldw;
+    if (pr) {
+      const double hr = ph[q], hi = ph[q + 1], wr = pw[q], wi = pw[q + 1];
+      sr += wr * hr - wi * hi;
+      si += wr * hi + wi * hr;
+    } else {
+      sr += pw[q] * ph[q];
+    }
+  }
+  double* po = out + (long)g * ld;
+  if (accumulate) {
+    po[q] += scale * sr;
+    if (pr) po[q + 1] += scale * si;
+  } else {
+    po[q] = scale * sr;
+    if (pr) po[q + 1] = scale * si;
+  }
+}
+
+// out[p] = base + scale * sum_{k < rows_per*n_row...}: one workgroup per p,
+// fixed reduction order (deterministic).
+__global__ void k_batched_dot(double* __restrict__ out, const double* __restrict__ X, long ldx,
+                              const double* __restrict__ Y, long ldy, int rows_per, int n,
+                              double base, double scale) {
+  const int p = blockIdx.x;
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int b = 0; b < rows_per; ++b) {
+    const double* px = X + ((long)p * rows_per + b) * ldx;
+    const double* py = Y + (long)b * ldy;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) acc += px[k] * py[k];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[p] = base + scale * red[0];
+}
+
+__global__ void k_f64_to_f32(float* __restrict__ out, const double* __restrict__ in, long count) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = (float)in[i];
+}
+
+// Mcb planes: hi = bf16(Mc^T), lo = bf16(Mc^T - hi), transposed to N x K.
+__global__ void k_split_bf16_T(__bf16* __restrict__ out, const double* __restrict__ in, int ld) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;  // column of Mc = row of out
+  const int j = blockIdx.y;
+  if (k >= ld) return;
+  const float v = (float)in[(long)k * ld + j];
+  const __bf16 hi = (__bf16)v;
+  const __bf16 lo = (__bf16)(v - (float)hi);
+  out[(long)j * ld + k] = hi;
+  out[(long)ld * ld + (long)j * ld + k] = lo;
+}
+
+// copy rows of length n (stride src_ld) into rows of stride dst_ld (pad untouched)
+__global__ void k_copy_rows(double* __restrict__ dst, long dst_ld, const double* __restrict__ src,
+                            long src_ld, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = blockIdx.y;
+  if (k < n) dst[(long)row * dst_ld + k] = src[(long)row * src_ld + k];
+}
+
+__global__ void k_gamma_rho(double* __restrict__ gam, const double* __restrict__ om, int h, int n,
+                            int ld) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (q >= n) return;
+  const double v = om[(long)b * ld + q];
+  gam[(long)b * ld + q] = q < 2 * h ? ((q & 1) ? -4.0 * v : 4.0 * v) : 2.0 * v;
+}
+
+// S^-1 B recovered from Bh = (S^-1 B) * sig
+__global__ void k_unscale_sig(double* __restrict__ out, const double* __restrict__ in, int h, int n,
+                              int ld) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (q >= n) return;
+  const double v = in[(long)c * ld + q];
+  out[(long)c * ld + q] = q < 2 * h ? ((q & 1) ? -2.0 * v : 2.0 * v) : v;
+}
+
+}  // namespace lyap
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+namespace lyap {
+
+void hadamard_outer(double* out, const double* a, long lda, int na, const double* b, long ldb,
+                    int nb, int h, int n, int ld, hipStream_t s) {
+  if (na * nb == 0) return;
+  dim3 grid((n - h + 255) / 256, na * nb);
+  hipLaunchKernelGGL(k_hadamard_outer, grid, dim3(256), 0, s, out, a, lda, na, b, ldb, nb, h, n, ld);
+  LYAP_HIP(hipGetLastError());
+}
+
+void contract_groups(double* out, const double* H, long ldh, const double* w, long ldw, int ngroups,
+                     int G, int h, int n, int ld, double scale, bool accumulate, hipStream_t s) {
+  dim3 grid((n - h + 255) / 256, ngroups);
+  hipLaunchKernelGGL(k_contract_groups, grid, dim3(256), 0, s, out, H, ldh, w, ldw, G, h, n, ld,
+                     scale, accumulate ? 1 : 0);
+  LYAP_HIP(hipGetLastError());
+}
+
+void batched_dot(double* out, const double* X, long ldx, const double* Y, long ldy, int rows_per,
+                 int count, int n, double base, double scale, hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_batched_dot, dim3(count), dim3(256), 0, s, out, X, ldx, Y, ldy, rows_per, n,
+                     base, scale);
+  LYAP_HIP(hipGetLastError());
+}
+
+void convert_f64_f32(float* out, const double* in, long count, hipStream_t s) {
+  hipLaunchKernelGGL(k_f64_to_f32, dim3((count + 255) / 256), dim3(256), 0, s, out, in, count);
+  LYAP_HIP(hipGetLastError());
+}
+
+static void gemm64(const double* A, long lda, const double* B, long ldb, double* C, long ldc,
+                   long M, long N, long K, long Nstore, hipStream_t s) {
+  GemmArgs g{};
+  g.type = GemmType::F64;
+  g.A = A;
+  g.B = B;
+  g.C = C;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.lda = lda;
+  g.ldb = ldb;
+  g.ldc = ldc;
+  g.Nstore = Nstore;
+  g.M_dev = nullptr;
+  g.m_scale = 1;
+  gemm_launch(g, s);
+}
+
+// ---------------------------------------------------------------------------
+// seed_factor
+// ---------------------------------------------------------------------------
+static void check_finite(const double* p, size_t count, const char* what) {
+  LYAP_REQUIRE(p != nullptr, LYAP_E_INVAL, std::string(what) + " is NULL");
+  for (size_t i = 0; i < count; ++i)
+    LYAP_REQUIRE(std::isfinite(p[i]), LYAP_E_INVAL, std::string(what) + " has a non-finite entry");
+}
+
+static void upload_rows(double* dst, long dst_ld, const double* src_host_rowmajor, long rows,
+                        long cols, hipStream_t s) {
+  LYAP_HIP(hipMemcpy2DAsync(dst, dst_ld * sizeof(double), src_host_rowmajor, cols * sizeof(double),
+                            cols * sizeof(double), rows, hipMemcpyHostToDevice, s));
+}
+
+static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A0, const double* U,
+                                const double* V, const double* B, const double* E,
+                                const lyap_seed_opts* opts, hipStream_t stream) {
+  auto t_start = std::chrono::steady_clock::now();
+  LYAP_REQUIRE(n >= 1 && n <= 16384, LYAP_E_INVAL, "n out of range [1, 16384]");
+  LYAP_REQUIRE(r >= 1 && r <= n && r <= kMaxRank, LYAP_E_INVAL, "r out of range [1, min(n, 16)]");
+  LYAP_REQUIRE(s >= 1 && s <= 65536, LYAP_E_INVAL, "s out of range");
+  const int E_diag = opts ? opts->E_is_diag : 1;
+  const int basis_req = opts ? opts->basis : LYAP_BASIS_AUTO;
+  double max_cond = opts && opts->max_eig_cond > 0 ? opts->max_eig_cond : 1e6;
+  LYAP_REQUIRE(basis_req >= 0 && basis_req <= 2, LYAP_E_INVAL, "basis out of range");
+  check_finite(A0, (size_t)n * n, "A0");
+  check_finite(U, (size_t)n * r, "U");
+  check_finite(V, (size_t)n * r, "V");
+  check_finite(B, (size_t)n * s, "B");
+  check_finite(E, E_diag ? (size_t)n : (size_t)n * n, "E");
+  if (basis_req == LYAP_BASIS_SCHUR)
+    throw Error{LYAP_E_UNSUPPORTED, "the Schur-basis seed solve is not available in this build"};
+
+  const LapackFns& L = lapack();
+  LYAP_REQUIRE(L.dgeev && L.dgetrf && L.dgetrs, LYAP_E_UNSUPPORTED,
+               "no host LAPACK (dgeev_/dgetrf_/dgetrs_) found; set LYAP_LAPACK_LIB");
+
+  // ---- host FP64 eigendecomposition (column-major copy of A0) ----
+  const int N = (int)n;
+  std::vector<double> Acm((size_t)n * n);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) Acm[(size_t)j * n + i] = A0[(size_t)i * n + j];
+  std::vector<double> wr(n), wi(n), VR((size_t)n * n);
+  int info = 0, lwork = -1;
+  double wq = 0;
+  const int one = 1;
+  L.dgeev("N", "V", &N, Acm.data(), &N, wr.data(), wi.data(), nullptr, &one, VR.data(), &N, &wq,
+          &lwork, &info);
+  lwork = (int)wq + 1;
+  std::vector<double> work(lwork);
+  L.dgeev("N", "V", &N, Acm.data(), &N, wr.data(), wi.data(), nullptr, &one, VR.data(), &N,
+          work.data(), &lwork, &info);
+  LYAP_REQUIRE(info == 0, LYAP_E_UNSTABLE, "dgeev failed to converge");
+
+  // order: conjugate pairs first (Re, Im columns), then real eigenvalues
+  std::vector<int> pairs, reals;
+  for (int j = 0; j < N; ++j) {
+    if (wi[j] > 0) {
+      pairs.push_back(j);
+      ++j;  // the conjugate partner follows
+    } else {
+      reals.push_back(j);
+    }
+  }
+  const int h = (int)pairs.size();
+  LYAP_REQUIRE(2 * h + (int)reals.size() == N, LYAP_E_UNSTABLE, "unexpected eigenvalue ordering");
+  std::vector<double> Scm((size_t)n * n), lre(n), lim(n);
+  for (int k = 0; k < h; ++k) {
+    const int j = pairs[k];
+    std::memcpy(&Scm[(size_t)(2 * k) * n], &VR[(size_t)j * n], sizeof(double) * n);
+    std::memcpy(&Scm[(size_t)(2 * k + 1) * n], &VR[(size_t)(j + 1) * n], sizeof(double) * n);
+    lre[2 * k] = lre[2 * k + 1] = wr[j];
+    lim[2 * k] = lim[2 * k + 1] = wi[j];
+  }
+  for (size_t m = 0; m < reals.size(); ++m) {
+    const int j = reals[m];
+    std::memcpy(&Scm[(size_t)(2 * h + m) * n], &VR[(size_t)j * n], sizeof(double) * n);
+    lre[2 * h + m] = wr[j];
+    lim[2 * h + m] = 0.0;
+  }
+  // stability and solvability of the seed Lyapunov operator
+  double max_re = -INFINITY, min_sum = INFINITY, max_sum = 0;
+  for (int i = 0; i < N; ++i) max_re = std::max(max_re, wr[i]);
+  for (int i = 0; i < N; ++i)
+    for (int j = i; j < N; ++j) {
+      const double sr = wr[i] + wr[j], si = wi[i] + wi[j];
+      const double a = std::hypot(sr, si);
+      min_sum = std::min(min_sum, a);
+      max_sum = std::max(max_sum, a);
+    }
+  LYAP_REQUIRE(max_re < 0, LYAP_E_UNSTABLE, "seed A0 is not stable (max Re lambda >= 0)");
+  LYAP_REQUIRE(min_sum > 1e-13 * max_sum, LYAP_E_UNSTABLE, "lambda_i + lambda_j ~ 0 for the seed");
+
+  // S^-1 by LU; condition estimate ||S||_1 ||S^-1||_1
+  std::vector<double> LU(Scm), Sinv_cm((size_t)n * n, 0.0);
+  std::vector<int> ipiv(n);
+  L.dgetrf(&N, &N, LU.data(), &N, ipiv.data(), &info);
+  LYAP_REQUIRE(info == 0, LYAP_E_UNSTABLE, "eigenvector matrix is singular (defective seed)");
+  for (int i = 0; i < N; ++i) Sinv_cm[(size_t)i * n + i] = 1.0;
+  L.dgetrs("N", &N, &N, LU.data(), &N, ipiv.data(), Sinv_cm.data(), &N, &info);
+  LYAP_REQUIRE(info == 0, LYAP_E_UNSTABLE, "dgetrs failed");
+  auto norm1 = [&](const std::vector<double>& Mcm) {
+    double best = 0;
+    for (int j = 0; j < N; ++j) {
+      double c = 0;
+      for (int i = 0; i < N; ++i) c += std::fabs(Mcm[(size_t)j * n + i]);
+      best = std::max(best, c);
+    }
+    return best;
+  };
+  const double cond = norm1(Scm) * norm1(Sinv_cm);
+  if (basis_req == LYAP_BASIS_AUTO && !(cond <= max_cond))
+    throw Error{LYAP_E_UNSUPPORTED,
+                "eigenbasis condition " + std::to_string(cond) +
+                    " exceeds max_eig_cond and the Schur-basis path is not available"};
+
+  auto* sd = new lyap_seed_s();
+  std::unique_ptr<lyap_seed_s> guard(sd);
+  sd->n = n;
+  sd->r = r;
+  sd->s = s;
+  sd->h = h;
+  const int64_t ld = pad_to(n, kPad);
+  sd->ld = ld;
+  sd->basis = LYAP_BASIS_EIG;
+  sd->cond_est = cond;
+  sd->min_lam_sum = min_sum / max_sum;
+  sd->max_re = max_re;
+  sd->stream = stream;
+  LYAP_HIP(hipGetDevice(&sd->device));
+
+  // sig, sigp
+  std::vector<double> sig(n), sigp(n);
+  for (int q = 0; q < N; ++q) {
+    if (q < 2 * h) {
+      sig[q] = (q & 1) ? -0.5 : 0.5;
+      sigp[q] = (q & 1) ? -2.0 : 2.0;
+    } else {
+      sig[q] = 1.0;
+      sigp[q] = 1.0;
+    }
+  }
+  // host layouts (row-major, padded to ld)
+  std::vector<double> Tin_h((size_t)ld * ld, 0.0), Tout_h((size_t)ld * ld, 0.0),
+      S_h((size_t)ld * ld, 0.0), Sinv_h((size_t)ld * ld, 0.0);
+  for (int a = 0; a < N; ++a)
+    for (int b = 0; b < N; ++b) {
+      // Tin[m=a][j=b] = Sinv[j][m] sig_j = Sinv_cm[m*n + j] sig_j
+      Tin_h[(size_t)a * ld + b] = Sinv_cm[(size_t)a * n + b] * sig[b];
+      // Tout[j=a][m=b] = sigp_j S[m][j] = sigp_j Scm[j*n + m]
+      Tout_h[(size_t)a * ld + b] = sigp[a] * Scm[(size_t)a * n + b];
+      // row-major S and S^-1
+      S_h[(size_t)a * ld + b] = Scm[(size_t)b * n + a];
+      Sinv_h[(size_t)a * ld + b] = Sinv_cm[(size_t)b * n + a];
+    }
+  std::vector<double> lam_h(2 * ld, 0.0);
+  for (int q = 0; q < N; ++q) {
+    lam_h[q] = lre[q];
+    lam_h[ld + q] = lim[q];
+  }
+
+  const size_t mat = (size_t)ld * ld * sizeof(double);
+  hipStream_t st = stream;
+  sd->lam.alloc(2 * ld * sizeof(double));
+  sd->Mc.alloc(mat);
+  sd->Tin.alloc(mat);
+  sd->Tout.alloc(mat);
+  DevBuf Sd(mat), Sinvd(mat);
+  LYAP_HIP(hipMemcpyAsync(sd->lam.p, lam_h.data(), 2 * ld * sizeof(double), hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(sd->Tin.p, Tin_h.data(), mat, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(sd->Tout.p, Tout_h.data(), mat, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(Sd.p, S_h.data(), mat, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(Sinvd.p, Sinv_h.data(), mat, hipMemcpyHostToDevice, st));
+  {
+    dim3 grid((ld + 255) / 256, ld);
+    hipLaunchKernelGGL(k_build_cauchy, grid, dim3(256), 0, st, sd->Mc.as<double>(),
+                       sd->lam.as<double>(), (int)n, h, (int)ld);
+    LYAP_HIP(hipGetLastError());
+  }
+
+  // ---- rho(Q0^-1 U), rho(V^T Q0), rho(Q0^-1 B) via the transform GEMMs ----
+  const size_t rowb = (size_t)ld * sizeof(double);
+  auto zeros = [&](DevBuf& b, size_t rows) {
+    b.alloc(rows * rowb);
+    LYAP_HIP(hipMemsetAsync(b.p, 0, rows * rowb, st));
+  };
+  std::vector<double> Ut((size_t)r * n), Vt((size_t)r * n), Bt((size_t)s * n);
+  for (int i = 0; i < N; ++i) {
+    for (int a = 0; a < r; ++a) {
+      Ut[(size_t)a * n + i] = U[(size_t)i * r + a];
+      Vt[(size_t)a * n + i] = V[(size_t)i * r + a];
+    }
+    for (int c = 0; c < s; ++c) Bt[(size_t)c * n + i] = B[(size_t)i * s + c];
+  }
+  DevBuf Utd, Vtd, Btd, Bh;
+  zeros(Utd, r);
+  zeros(Vtd, r);
+  zeros(Btd, s);
+  zeros(Bh, s);
+  upload_rows(Utd.as<double>(), ld, Ut.data(), r, n, st);
+  upload_rows(Vtd.as<double>(), ld, Vt.data(), r, n, st);
+  upload_rows(Btd.as<double>(), ld, Bt.data(), s, n, st);
+  zeros(sd->Uh, r);
+  zeros(sd->Vh, r);
+  gemm64(Utd.as<double>(), ld, sd->Tin.as<double>(), ld, sd->Uh.as<double>(), ld, r, ld, ld, n, st);
+  gemm64(Vtd.as<double>(), ld, Sd.as<double>(), ld, sd->Vh.as<double>(), ld, r, ld, ld, n, st);
+  gemm64(Btd.as<double>(), ld, sd->Tin.as<double>(), ld, Bh.as<double>(), ld, s, ld, ld, n, st);
+
+  // ---- K1 = the exact block-diagonal part of the capacitance operator ----
+  zeros(sd->K1, r * r);
+  {
+    DevBuf X;
+    zeros(X, r * r);
+    hadamard_outer(X.as<double>(), sd->Vh.as<double>(), ld, r, sd->Uh.as<double>(), ld, r, h, n,
+                   ld, st);
+    gemm64(X.as<double>(), ld, sd->Mc.as<double>(), ld, sd->K1.as<double>(), ld, r * r, ld, ld, ld,
+           st);
+    LYAP_HIP(hipStreamSynchronize(st));
+  }
+
+  // chunked "rows x Cauchy, contract" helper: out[g] += scale * sum_t w_t o (a_g o b_t) L
+  // rows ordered (g, t); a has ngroups rows, b and w have G rows.
+  const long chunk_rows = 8192;
+  auto rows_contract = [&](double* out, const double* a, int ngroups, const double* b,
+                           const double* w, int G, double scale) {
+    DevBuf X, H;
+    const long tchunk = std::max<long>(1, std::min<long>(G, chunk_rows / std::max(1, ngroups)));
+    zeros(X, (size_t)ngroups * tchunk);
+    H.alloc((size_t)ngroups * tchunk * rowb);
+    for (long t0 = 0; t0 < G; t0 += tchunk) {
+      const int tc = (int)std::min<long>(tchunk, G - t0);
+      hadamard_outer(X.as<double>(), a, ld, ngroups, b + t0 * ld, ld, tc, h, n, ld, st);
+      gemm64(X.as<double>(), ld, sd->Mc.as<double>(), ld, H.as<double>(), ld, (long)ngroups * tc,
+             ld, ld, ld, st);
+      contract_groups(out, H.as<double>(), ld, w + t0 * ld, ld, ngroups, tc, h, n, ld, scale,
+                      t0 > 0, st);
+    }
+    LYAP_HIP(hipStreamSynchronize(st));
+  };
+
+  // c0[a] = rho(V^T X0 Q0^-T) = - sum_c Bh_c o ((Vh_a o Bh_c) L)
+  zeros(sd->c0, r);
+  rows_contract(sd->c0.as<double>(), sd->Vh.as<double>(), (int)r, Bh.as<double>(), Bh.as<double>(),
+                (int)s, -1.0);
+
+  // ---- trace functional: rows of E S ----
+  std::vector<int> erows;
+  DevBuf ES, Wrows;
+  if (E_diag) {
+    for (int m = 0; m < N; ++m)
+      if (E[m] != 0.0) erows.push_back(m);
+    const int ne = (int)erows.size();
+    std::vector<double> ES_h((size_t)std::max(ne, 1) * ld, 0.0), W_h((size_t)std::max(ne, 1) * ld, 0.0);
+    for (int t = 0; t < ne; ++t) {
+      const int m = erows[t];
+      for (int q = 0; q < N; ++q) {
+        const double smq = Scm[(size_t)q * n + m];
+        ES_h[(size_t)t * ld + q] = E[m] * smq;
+        W_h[(size_t)t * ld + q] = smq;
+      }
+    }
+    ES.alloc(ES_h.size() * sizeof(double));
+    Wrows.alloc(W_h.size() * sizeof(double));
+    LYAP_HIP(hipMemcpyAsync(ES.p, ES_h.data(), ES.bytes, hipMemcpyHostToDevice, st));
+    LYAP_HIP(hipMemcpyAsync(Wrows.p, W_h.data(), Wrows.bytes, hipMemcpyHostToDevice, st));
+  } else {
+    // symmetric part of E, then ES = E_sym S (transform GEMM), all rows
+    std::vector<double> Es_h((size_t)ld * ld, 0.0);
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j)
+        Es_h[(size_t)i * ld + j] = 0.5 * (E[(size_t)i * n + j] + E[(size_t)j * n + i]);
+    DevBuf Esd(mat);
+    LYAP_HIP(hipMemcpyAsync(Esd.p, Es_h.data(), mat, hipMemcpyHostToDevice, st));
+    zeros(ES, n);
+    gemm64(Esd.as<double>(), ld, Sd.as<double>(), ld, ES.as<double>(), ld, n, ld, ld, n, st);
+    Wrows.alloc(mat);
+    LYAP_HIP(hipMemcpyAsync(Wrows.p, Sd.p, (size_t)n * rowb, hipMemcpyDeviceToDevice, st));
+    for (int m = 0; m < N; ++m) erows.push_back(m);
+    LYAP_HIP(hipStreamSynchronize(st));
+  }
+  const int ne = (int)erows.size();
+
+  zeros(sd->gam, r);
+  zeros(sd->Gam, r);
+  double t0 = 0.0;
+  if (ne > 0) {
+    // Omega[b] = sum_m S_m o ((Uh_b o ES_m) L)  (G U = Q0^-T Omega)
+    DevBuf Om;
+    zeros(Om, r);
+    rows_contract(Om.as<double>(), sd->Uh.as<double>(), (int)r, ES.as<double>(), Wrows.as<double>(),
+                  ne, 1.0);
+    // physical Gamma^T = Omega S^-1 ; rho trace weights
+    gemm64(Om.as<double>(), ld, Sinvd.as<double>(), ld, sd->Gam.as<double>(), ld, r, ld, ld, n, st);
+    {
+      dim3 grid((n + 255) / 256, r);
+      hipLaunchKernelGGL(k_gamma_rho, grid, dim3(256), 0, st, sd->gam.as<double>(), Om.as<double>(),
+                         h, (int)n, (int)ld);
+      LYAP_HIP(hipGetLastError());
+    }
+    // t0 = trace(E X0) = - sum_c <S^-1 B_c, OmegaB_c>
+    DevBuf OmB, SiB, tdev(sizeof(double) * (size_t)s);
+    zeros(OmB, s);
+    zeros(SiB, s);
+    rows_contract(OmB.as<double>(), Bh.as<double>(), (int)s, ES.as<double>(), Wrows.as<double>(), ne,
+                  1.0);
+    {
+      dim3 grid((n + 255) / 256, s);
+      hipLaunchKernelGGL(k_unscale_sig, grid, dim3(256), 0, st, SiB.as<double>(), Bh.as<double>(), h,
+                         (int)n, (int)ld);
+      LYAP_HIP(hipGetLastError());
+    }
+    // one reduction over all s rows: sum_c <SiB_c, OmB_c>
+    batched_dot(tdev.as<double>(), SiB.as<double>(), ld, OmB.as<double>(), ld, (int)s, 1, (int)n,
+                0.0, -1.0, st);
+    LYAP_HIP(hipMemcpyAsync(&t0, tdev.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipStreamSynchronize(st));
+  }
+  sd->t0 = t0;
+
+  // ---- low-precision copies of the Cauchy operator (mixed-precision modes) ----
+  sd->Mc32.alloc((size_t)ld * ld * sizeof(float));
+  convert_f64_f32(sd->Mc32.as<float>(), sd->Mc.as<double>(), ld * ld, st);
+  sd->Mcb.alloc((size_t)2 * ld * ld * sizeof(__bf16));
+  {
+    dim3 grid((ld + 255) / 256, ld);
+    hipLaunchKernelGGL(k_split_bf16_T, grid, dim3(256), 0, st, sd->Mcb.as<__bf16>(),
+                       sd->Mc.as<double>(), (int)ld);
+    LYAP_HIP(hipGetLastError());
+  }
+  LYAP_HIP(hipStreamSynchronize(st));
+  sd->factor_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  guard.release();
+  return sd;
+}
+
+}  // namespace lyap
+
+// ---------------------------------------------------------------------------
+// C entry points
+// ---------------------------------------------------------------------------
+using namespace lyap;
+
+
+extern "C" {
+
+lyap_status seed_factor(int64_t n, int64_t r, int64_t s, const double* A0, const double* U,
+                        const double* V, const double* B, const double* E,
+                        const lyap_seed_opts* opts, void* hip_stream, lyap_seed* out) {
+  if (!out) return LYAP_E_INVAL;
+  *out = nullptr;
+  LYAP_TRY(*out = factor_impl(n, r, s, A0, U, V, B, E, opts, (hipStream_t)hip_stream));
+  return LYAP_OK;
+}
+
+lyap_status seed_info(lyap_seed sd, lyap_seed_info* o) {
+  if (!sd || !o) return LYAP_E_INVAL;
+  o->n = sd->n;
+  o->r = sd->r;
+  o->s = sd->s;
+  o->npairs = sd->h;
+  o->ld = sd->ld;
+  o->basis = sd->basis;
+  o->reserved = 0;
+  o->cond_est = sd->cond_est;
+  o->min_lam_sum = sd->min_lam_sum;
+  o->max_re_lambda = sd->max_re;
+  o->t0 = sd->t0;
+  o->factor_seconds = sd->factor_seconds;
+  o->device_bytes = sd->device_bytes();
+  return LYAP_OK;
+}
+
+lyap_status seed_release(lyap_seed sd) {
+  if (!sd) return LYAP_E_INVAL;
+  LYAP_TRY({
+    (void)hipStreamSynchronize(sd->stream);
+    delete sd;
+  });
+  return LYAP_OK;
+}
+
+size_t seed_device_bytes(lyap_seed sd) { return sd ? sd->device_bytes() : 0; }
+
+const char* lyap_status_string(lyap_status s) {
+  switch (s) {
+    case LYAP_OK: return "ok";
+    case LYAP_E_INVAL: return "invalid argument";
+    case LYAP_E_NOMEM: return "out of memory";
+    case LYAP_E_UNSTABLE: return "unstable or singular seed";
+    case LYAP_E_NOCONV: return "no convergence";
+    case LYAP_E_BREAKDOWN: return "Krylov breakdown";
+    case LYAP_E_DEVICE: return "device error";
+    case LYAP_E_UNSUPPORTED: return "unsupported";
+    case LYAP_E_NONFINITE: return "non-finite value";
+  }
+  return "unknown status";
+}
+
+const char* lyap_last_error(void) {
+  static thread_local std::string copy;
+  std::lock_guard<std::mutex> g(g_err_mu);
+  copy = g_last_error;
+  return copy.c_str();
+}
+
+}  // extern "C"

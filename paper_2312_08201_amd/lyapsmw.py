@@ -1,0 +1,307 @@
+"""Thin Python binding of liblyapsmw.so (argument marshalling only).
+
+Every step of the method runs in the HIP library; this module converts
+numpy / torch arguments to pointers and sizes.  PyTorch is used for device
+memory and streams.  There is no fallback: if the library is missing or no
+GPU is present, every call raises.
+
+Entry points (names as in include/lyapsmw.h): seed_factor, lyap_seed_apply,
+smw_solve_batch, trace_EX, engine_*.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblyapsmw.so")
+
+OK, E_INVAL, E_NOMEM, E_UNSTABLE, E_NOCONV, E_BREAKDOWN, E_DEVICE, E_UNSUPPORTED, E_NONFINITE = range(9)
+BASIS = {"auto": 0, "eig": 1, "schur": 2}
+PREC = {"fp64": 0, "fp32_ir": 1, "bf16_ir": 2, "fp32": 3}
+
+
+class LyapError(RuntimeError):
+    def __init__(self, status, where, detail=""):
+        self.status = status
+        super().__init__("%s failed: status %d (%s) %s" % (where, status, _status_str(status), detail))
+
+
+class SeedOpts(C.Structure):
+    _fields_ = [("basis", C.c_int32), ("E_is_diag", C.c_int32), ("max_eig_cond", C.c_double)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("prec", C.c_int32), ("max_iter", C.c_int32), ("restart", C.c_int32),
+                ("use_precond", C.c_int32), ("recycle_k", C.c_int32), ("max_refine", C.c_int32),
+                ("tol", C.c_double), ("inner_tol", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("cycles", C.c_int32),
+                ("refinements", C.c_int32), ("rel_residual", C.c_double), ("trace", C.c_double)]
+
+
+class SeedInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("r", C.c_int64), ("s", C.c_int64), ("npairs", C.c_int64),
+                ("ld", C.c_int64), ("basis", C.c_int32), ("reserved", C.c_int32),
+                ("cond_est", C.c_double), ("min_lam_sum", C.c_double),
+                ("max_re_lambda", C.c_double), ("t0", C.c_double),
+                ("factor_seconds", C.c_double), ("device_bytes", C.c_size_t)]
+
+
+RESULT_DTYPE = np.dtype([("status", np.int32), ("iters", np.int32), ("cycles", np.int32),
+                         ("refinements", np.int32), ("rel_residual", np.float64),
+                         ("trace", np.float64)])
+
+_lib = None
+
+# exported symbols of include/lyapsmw.h (checked by the CPU tests)
+EXPORTS = ["seed_factor", "seed_info", "seed_release", "seed_device_bytes", "lyap_seed_apply",
+           "smw_workspace_bytes", "smw_solve_batch", "trace_EX", "engine_create",
+           "engine_device_bytes", "engine_destroy", "engine_submit", "engine_run",
+           "engine_harvest", "lyap_status_string", "lyap_last_error"]
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (no GPU needed to load it)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("liblyapsmw.so not built (%s); run __graft_entry__.build()" % path)
+    # the host LAPACK the library resolves at run time lives in libtorch_cpu
+    import torch  # noqa: F401
+    lib = C.CDLL(path, mode=C.RTLD_GLOBAL)
+    vp, i64, i32, dp = C.c_void_p, C.c_int64, C.c_int32, C.POINTER(C.c_double)
+    lib.seed_factor.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp, C.POINTER(SeedOpts), vp,
+                                C.POINTER(vp)]
+    lib.seed_info.argtypes = [vp, C.POINTER(SeedInfo)]
+    lib.seed_release.argtypes = [vp]
+    lib.seed_device_bytes.argtypes = [vp]
+    lib.seed_device_bytes.restype = C.c_size_t
+    lib.lyap_seed_apply.argtypes = [vp, i64, vp, vp, i32, vp]
+    lib.smw_workspace_bytes.argtypes = [vp, i64, C.POINTER(SolveOpts)]
+    lib.smw_workspace_bytes.restype = C.c_size_t
+    lib.smw_solve_batch.argtypes = [vp, i64, vp, C.POINTER(SolveOpts), vp, C.POINTER(Result), vp,
+                                    C.c_size_t, vp]
+    lib.trace_EX.argtypes = [vp, i64, vp, vp, vp]
+    lib.engine_create.argtypes = [vp, i64, C.POINTER(SolveOpts), vp, C.POINTER(vp)]
+    lib.engine_device_bytes.argtypes = [vp, i64, C.POINTER(SolveOpts)]
+    lib.engine_device_bytes.restype = C.c_size_t
+    lib.engine_destroy.argtypes = [vp]
+    lib.engine_submit.argtypes = [vp, i64, vp, vp]
+    lib.engine_run.argtypes = [vp, i64, i32, C.POINTER(i64)]
+    lib.engine_harvest.argtypes = [vp, i64, vp, C.POINTER(Result), C.POINTER(i64)]
+    lib.lyap_status_string.argtypes = [i32]
+    lib.lyap_status_string.restype = C.c_char_p
+    lib.lyap_last_error.argtypes = []
+    lib.lyap_last_error.restype = C.c_char_p
+    for name in ("seed_factor", "seed_info", "seed_release", "lyap_seed_apply", "smw_solve_batch",
+                 "trace_EX", "engine_create", "engine_destroy", "engine_submit", "engine_run",
+                 "engine_harvest"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _status_str(st):
+    try:
+        return load().lyap_status_string(st).decode()
+    except Exception:
+        return "?"
+
+
+def _check(st, where):
+    if st != OK:
+        detail = ""
+        try:
+            detail = load().lyap_last_error().decode()
+        except Exception:
+            pass
+        raise LyapError(st, where, detail)
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("lyapsmw needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _host(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != shape:
+        raise ValueError("expected shape %s, got %s" % (shape, a.shape))
+    return a
+
+
+def _dev_ptr(t, dtype_name="float64", shape=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("expected a CUDA tensor")
+    if str(t.dtype) != "torch." + dtype_name:
+        raise TypeError("expected %s, got %s" % (dtype_name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("expected shape %s, got %s" % (shape, tuple(t.shape)))
+    return C.c_void_p(t.data_ptr())
+
+
+def solve_opts(prec="fp64", tol=1e-12, max_iter=600, restart=40, use_precond=True,
+               max_refine=30, inner_tol=1e-4) -> SolveOpts:
+    return SolveOpts(PREC[prec] if isinstance(prec, str) else int(prec), int(max_iter),
+                     int(restart), 1 if use_precond else 0, 0, int(max_refine), float(tol),
+                     float(inner_tol))
+
+
+class Seed:
+    """seed_factor: offline stage for one (A0, U, V, B, E)."""
+
+    def __init__(self, A0, U, V, B, E, basis="auto", max_eig_cond=0.0, stream=None):
+        lib = load()
+        _torch()
+        A0 = _host(A0)
+        n = A0.shape[0]
+        U = _host(U)
+        V = _host(V)
+        B = _host(B)
+        E = _host(E)
+        if A0.shape != (n, n) or U.ndim != 2 or U.shape[0] != n or V.shape != U.shape \
+                or B.ndim != 2 or B.shape[0] != n:
+            raise ValueError("inconsistent shapes")
+        r, s = U.shape[1], B.shape[1]
+        diag = 1 if E.ndim == 1 else 0
+        if (diag and E.shape != (n,)) or (not diag and E.shape != (n, n)):
+            raise ValueError("E must be (n,) or (n, n)")
+        self._keep = (A0, U, V, B, E)
+        opts = SeedOpts(BASIS[basis], diag, float(max_eig_cond))
+        h = C.c_void_p()
+        st = lib.seed_factor(n, r, s, A0.ctypes.data, U.ctypes.data, V.ctypes.data, B.ctypes.data,
+                             E.ctypes.data, C.byref(opts), _stream(stream), C.byref(h))
+        _check(st, "seed_factor")
+        self.h = h
+        self.n, self.r, self.s = n, r, s
+
+    @classmethod
+    def from_problem(cls, pr, **kw):
+        return cls(pr.A0, pr.U, pr.V, pr.B, pr.E, **kw)
+
+    def info(self) -> dict:
+        inf = SeedInfo()
+        _check(load().seed_info(self.h, C.byref(inf)), "seed_info")
+        return {k: getattr(inf, k) for k, _ in SeedInfo._fields_}
+
+    def release(self):
+        if getattr(self, "h", None):
+            load().seed_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+    # ---- the seed Lyapunov solve with a low-rank right-hand side ----
+    def apply(self, Y, prec="fp64", stream=None):
+        torch = _torch()
+        batch = Y.shape[0]
+        _dev_ptr(Y, shape=(batch, self.r, self.n))
+        G = torch.empty_like(Y)
+        st = load().lyap_seed_apply(self.h, batch, _dev_ptr(Y), _dev_ptr(G), PREC[prec],
+                                    _stream(stream))
+        _check(st, "lyap_seed_apply")
+        return G
+
+    # ---- online stage ----
+    def workspace_bytes(self, P, opts: Optional[SolveOpts] = None) -> int:
+        opts = opts or solve_opts()
+        return int(load().smw_workspace_bytes(self.h, P, C.byref(opts)))
+
+    def solve(self, d, opts: Optional[SolveOpts] = None, stream=None):
+        """smw_solve_batch for d (P x r, CUDA float64).  Returns (Y, results)."""
+        torch = _torch()
+        opts = opts or solve_opts()
+        P = d.shape[0]
+        _dev_ptr(d, shape=(P, self.r))
+        Y = torch.empty((P, self.r, self.n), dtype=torch.float64, device=d.device)
+        nbytes = self.workspace_bytes(P, opts)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=d.device)
+        res = (Result * P)()
+        st = load().smw_solve_batch(self.h, P, _dev_ptr(d), C.byref(opts), _dev_ptr(Y), res,
+                                    C.c_void_p(ws.data_ptr()), nbytes, _stream(stream))
+        _check(st, "smw_solve_batch")
+        out = np.frombuffer(bytes(res), dtype=RESULT_DTYPE).copy()
+        return Y, out
+
+    def trace(self, Y, stream=None):
+        torch = _torch()
+        P = Y.shape[0]
+        _dev_ptr(Y, shape=(P, self.r, self.n))
+        t = torch.empty(P, dtype=torch.float64, device=Y.device)
+        _check(load().trace_EX(self.h, P, _dev_ptr(Y), _dev_ptr(t), _stream(stream)), "trace_EX")
+        return t
+
+
+class Engine:
+    """Continuous-batching engine bound to one seed."""
+
+    def __init__(self, seed: Seed, slots: int, opts: Optional[SolveOpts] = None, stream=None):
+        lib = load()
+        self.seed = seed
+        self.opts = opts or solve_opts()
+        h = C.c_void_p()
+        _check(lib.engine_create(seed.h, int(slots), C.byref(self.opts), _stream(stream),
+                                 C.byref(h)), "engine_create")
+        self.h = h
+        self.slots = slots
+
+    def submit(self, d, tags=None):
+        d = _host(d)
+        if d.ndim != 2 or d.shape[1] != self.seed.r:
+            raise ValueError("d must be (count, r)")
+        tg = None
+        if tags is not None:
+            tg = np.ascontiguousarray(tags, dtype=np.int64)
+        _check(load().engine_submit(self.h, d.shape[0], d.ctypes.data,
+                                    tg.ctypes.data if tg is not None else None), "engine_submit")
+
+    def run(self, max_steps=1 << 30, poll_every=8) -> int:
+        busy = C.c_int64()
+        _check(load().engine_run(self.h, int(max_steps), int(poll_every), C.byref(busy)),
+               "engine_run")
+        return busy.value
+
+    def harvest(self, max_out=1 << 20):
+        cap = int(max_out)
+        tags = np.zeros(cap, dtype=np.int64)
+        res = (Result * cap)()
+        n = C.c_int64()
+        _check(load().engine_harvest(self.h, cap, tags.ctypes.data, res, C.byref(n)),
+               "engine_harvest")
+        k = n.value
+        out = np.frombuffer(bytes(res), dtype=RESULT_DTYPE)[:k].copy()
+        return tags[:k].copy(), out
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().engine_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,213 @@
+"""GPU parity: the HIP path against the CPU oracle (same seeded inputs).
+
+Tolerance (stated by the method's target): relative error of trace(E X(p))
+<= 1e-10 for FP64 and for the refined mixed-precision modes, <= 1e-4 for
+unrefined FP32.  Small problems are compared element by element (every p,
+and Y(p) = D V^T X(p) entrywise); full-size workloads are compared on the
+oracle values stored in tests/golden/oracle_traces.json (written by
+tests/golden/make_golden.py, which calls only the oracle).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gen import workloads as W
+from oracle import lyap_bs as O
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "oracle_traces.json")
+
+
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2312_08201_amd as L
+    L.load()
+    return L, torch
+
+
+def oracle_traces(pr, idx=None):
+    return np.array([r.trace for r in O.solve_problem(pr, idx, diagnostics=False)])
+
+
+def oracle_X(pr, i):
+    A = pr.A_of(i)
+    X, _ = O.lyapunov_bs(A, -(pr.B @ pr.B.T))
+    return X.real
+
+
+def run(pr, **kw):
+    L, torch = lib()
+    seed = L.Seed.from_problem(pr)
+    d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
+    Y, res = seed.solve(d, L.solve_opts(**kw))
+    tr = seed.trace(Y).cpu().numpy()
+    torch.cuda.synchronize()
+    return seed, Y.cpu().numpy(), res, tr
+
+
+def rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)) / np.abs(np.asarray(b))
+
+
+# ---------------------------------------------------------------------------
+def test_seed_apply_matches_cpu_lyapunov():
+    """lyap_seed_apply: G = V^T X, A0 X + X A0^T = U Y + Y^T U^T (several tiles + ragged tail)."""
+    L, torch = lib()
+    for pr in (W.small_chain(70, (9, 40), 3, 2), W.random_stable(150, 3, 2, 1, 5),
+               W.small_multiagent(90, 2, 3, 2)):
+        seed = L.Seed.from_problem(pr)
+        rng = np.random.default_rng(1)
+        Yb = rng.standard_normal((3, pr.r, pr.n))
+        G = seed.apply(torch.tensor(Yb, device="cuda")).cpu().numpy()
+        for q in range(3):
+            R = pr.U @ Yb[q] + Yb[q].T @ pr.U.T
+            X, _ = O.lyapunov_bs(pr.A0, R)
+            Gref = pr.V.T @ X.real
+            err = np.linalg.norm(G[q] - Gref) / np.linalg.norm(Gref)
+            assert err <= 1e-11, (pr.name, q, err)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.small_chain(20, (5,), 3, 8),
+    lambda: W.small_chain(45, (7, 30, 41), 4, 6),
+    lambda: W.small_multiagent(30, 2, 3, 6),
+    lambda: W.random_stable(40, 2, 3, 5, 3),
+])
+def test_small_problems_fp64_elementwise(maker):
+    pr = maker()
+    seed, Y, res, tr = run(pr)
+    assert np.all(res["status"] == 0), res
+    ref = oracle_traces(pr)
+    assert np.max(rel(tr, ref)) <= 1e-10
+    assert np.max(rel(res["trace"], ref)) <= 1e-10
+    for i in range(pr.P):
+        X = oracle_X(pr, i)
+        Yref = pr.d[i][:, None] * (pr.V.T @ X)
+        assert np.linalg.norm(Y[i] - Yref) <= 1e-9 * np.linalg.norm(Yref), i
+
+
+def test_c0_every_parameter():
+    pr = W.config(0)
+    gold = json.load(open(GOLD))["c0"]["samples"]
+    assert len(gold) == 64
+    assert np.allclose([g["d"] for g in gold], pr.d)
+    seed, Y, res, tr = run(pr)
+    ref = np.array([g["trace"] for g in gold])
+    assert np.all(res["status"] == 0)
+    assert np.max(rel(tr, ref)) <= 1e-10
+    assert np.max(rel(res["trace"], ref)) <= 1e-10
+
+
+@pytest.mark.parametrize("cfg", [1, 3])
+def test_full_size_sampled(cfg):
+    """Full workload, full batch (the launch configuration the bench times); sampled oracle values."""
+    pr = W.config(cfg)
+    gold = json.load(open(GOLD))["c%d" % cfg]["samples"]
+    idx = [g["index"] for g in gold]
+    assert np.allclose([g["d"] for g in gold], pr.d[idx])
+    seed, Y, res, tr = run(pr)
+    assert np.all(res["status"] == 0), np.unique(res["status"], return_counts=True)
+    ref = np.array([g["trace"] for g in gold])
+    assert np.max(rel(tr[idx], ref)) <= 1e-10
+    assert np.max(rel(res["trace"][idx], ref)) <= 1e-10
+    # two routes to the trace (eigen coordinates vs physical Y) agree everywhere
+    assert np.max(rel(res["trace"], tr)) <= 1e-11
+
+
+@pytest.mark.parametrize("prec", ["fp32_ir", "bf16_ir"])
+def test_mixed_precision_refined(prec):
+    pr = W.config(3, P=64)
+    gold = json.load(open(GOLD))["c3"]["samples"]
+    gold = [g for g in gold if g["index"] < 64]
+    seed, Y, res, tr = run(pr, prec=prec)
+    assert np.all(res["status"] == 0), res
+    ref = np.array([g["trace"] for g in gold])
+    idx = [g["index"] for g in gold]
+    assert np.max(rel(tr[idx], ref)) <= 1e-10
+    pr0 = W.small_chain(45, (7, 30, 41), 4, 6)
+    seed, Y, res, tr = run(pr0, prec=prec)
+    assert np.all(res["status"] == 0)
+    assert np.max(rel(tr, oracle_traces(pr0))) <= 1e-10
+
+
+def test_fp32_unrefined_within_1e4():
+    pr = W.small_chain(45, (7, 30, 41), 4, 6)
+    seed, Y, res, tr = run(pr, prec="fp32", tol=1e-6)
+    assert np.max(rel(tr, oracle_traces(pr))) <= 1e-4
+
+
+def test_edge_cases():
+    L, torch = lib()
+    pr = W.small_chain(20, (5, 12), 3, 4)
+    d = pr.d.copy()
+    d[1] = 0.0           # D = 0: X(p) = X0
+    d[2, 0] = np.nan     # flagged, others unaffected
+    pr2 = W.Problem(pr.name, pr.A0, pr.U, pr.V, pr.B, pr.E, d)
+    seed, Y, res, tr = run(pr2)
+    assert res["status"][2] == 8  # LYAP_E_NONFINITE
+    ok = [0, 1, 3]
+    assert np.all(res["status"][ok] == 0)
+    ref = oracle_traces(pr2, ok)
+    assert np.max(rel(res["trace"][ok], ref)) <= 1e-10
+    info = seed.info()
+    X0, _ = O.lyapunov_bs(pr.A0, -(pr.B @ pr.B.T))
+    t0 = O.trace_E(pr.E, X0.real)
+    assert abs(info["t0"] - t0) <= 1e-11 * abs(t0)
+    assert abs(res["trace"][1] - t0) <= 1e-11 * abs(t0)
+    # iteration limit: per-parameter NOCONV, call succeeds
+    seed, Y, res, tr = run(pr, max_iter=2)
+    assert np.all(res["status"] == 4)
+    # P = 1
+    pr1 = pr.subset([3])
+    seed, Y, res, tr = run(pr1)
+    assert res["status"][0] == 0 and rel(tr, oracle_traces(pr1))[0] <= 1e-10
+
+
+def test_invalid_arguments_return_inval():
+    L, torch = lib()
+    pr = W.small_chain(10, (3,), 2, 2)
+    with pytest.raises(L.LyapError) as e:
+        L.Seed(pr.A0, pr.U, pr.V, pr.B, pr.E * np.nan)
+    assert e.value.status == 1
+    unstable = -pr.A0
+    with pytest.raises(L.LyapError) as e:
+        L.Seed(unstable, pr.U, pr.V, pr.B, pr.E)
+    assert e.value.status == 3
+    seed = L.Seed.from_problem(pr)
+    d = torch.tensor(pr.d, device="cuda")
+    with pytest.raises(L.LyapError) as e:
+        seed.solve(d, L.solve_opts(restart=500))
+    assert e.value.status == 1
+
+
+def test_engine_alone_vs_mixed():
+    """Continuous batching: the same p gives the same trace alone and inside a mix."""
+    L, torch = lib()
+    pr = W.config(3, P=48)
+    seed = L.Seed.from_problem(pr)
+    alone = {}
+    for i in (0, 5, 17):
+        eng = L.Engine(seed, 1)
+        eng.submit(pr.d[i:i + 1], [i])
+        assert eng.run() == 0
+        t, r = eng.harvest()
+        alone[i] = r["trace"][0]
+        eng.close()
+    eng = L.Engine(seed, 8)
+    order = np.random.default_rng(0).permutation(48)
+    eng.submit(pr.d[order[:20]], order[:20])
+    eng.run(max_steps=30)
+    eng.submit(pr.d[order[20:]], order[20:])
+    eng.run()
+    tags, res = eng.harvest()
+    got = dict(zip(tags.tolist(), res["trace"].tolist()))
+    assert len(got) == 48
+    for i, t in alone.items():
+        assert abs(got[i] - t) <= 1e-12 * abs(t)
+    ref = oracle_traces(pr, [0, 5, 17])
+    assert np.max(rel([got[0], got[5], got[17]], ref)) <= 1e-10

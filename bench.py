@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Benchmark: trace(E X(p)) evaluations per second on one MI355X.
+
+Default workload (the headline configuration): damped mass-spring chain with
+d = 1000 masses (n = 2000), two grounded dampers (r = 2), the 32 x 32
+log-spaced viscosity grid (P = 1024 parameter pairs), B = n x 8 Gaussian,
+E = diag(I_d, 0), FP64.  Synthetic, seeded inputs (gen/workloads.py).
+
+One step = the whole online stage for one sweep: smw_solve_batch over all P
+parameters (capacitance solves, every Krylov product a Cauchy contraction on
+MFMA, transform of the solutions to physical coordinates) followed by
+trace_EX.  The seed factorisation is the offline stage (Table 1 of the paper)
+and is done once before the timed region; its wall time is reported apart.
+
+Printed: one JSON line (metric, value, roofline of the dominant kernel, CPU
+oracle baseline, p50/p99 step latency, sampled error against stored oracle
+values).  ``--gpus N`` with N > 1 exits: this build measures one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "trace(EX(p)) evals/s at rel.err<=1e-10 vs FP64 oracle; p50/p99 sweep latency"
+PEAK = {"fp64": 78.6, "fp32_ir": 157.3, "fp32": 157.3, "bf16_ir": 2500.0}
+WORKLOAD = {
+    0: "c0: damped chain n=400 r=1, 64 log-spaced viscosities, B=I, E=diag(I,0)",
+    1: "c1: damped chain n=2000 r=2, 32x32 log-spaced viscosity grid (P=1024), B n x 8, E=diag(I,0)",
+    2: "c2: damped chain n=4000 r=3, 256 log-uniform viscosity triples, B n x 16, E=diag(I,0)",
+    3: "c3: multi-agent N=500 (n=1000) r=8 (4 edge weights), 512 samples, B n x 4, E=I",
+}
+
+
+def cpu_baseline(pr, idx):
+    """The oracle as it stands, on this host's cores, for one parameter of the workload."""
+    from oracle import lyap_bs as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        threads = os.cpu_count()
+    t = time.perf_counter()
+    res = O.solve_one(pr.A0, pr.U, pr.V, pr.B, pr.E, pr.d[idx], diagnostics=False)
+    dt = time.perf_counter() - t
+    return {"value": 1.0 / dt, "unit": "evals/s", "cores": int(threads), "kind": "oracle",
+            "sample": "1 parameter (index %d) of the same workload, complex-Schur Bartels-Stewart, "
+                      "%.1f s wall, multithreaded host BLAS" % (idx, dt)}, res.trace
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_ir", "bf16_ir", "fp32"])
+    ap.add_argument("--restart", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="graph replay, no event timing")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="only run a plain copy of this many MiB (byte-counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (this build has no multi-GPU path); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2312_08201_amd as L
+    from gen import workloads as W
+
+    if not torch.cuda.is_available():
+        print("no GPU", file=sys.stderr)
+        sys.exit(1)
+    L.load()
+
+    if args.calib_copy_mib:
+        nb = args.calib_copy_mib << 20
+        a = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            L.calib_copy(a, b)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": nb, "ok": bool(torch.equal(a, b))}), flush=True)
+        return
+
+    pr = W.config(args.config)
+    t = time.perf_counter()
+    seed = L.Seed.from_problem(pr)
+    factor_s = time.perf_counter() - t
+    info = seed.info()
+    d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
+    opts = L.solve_opts(prec=args.prec, restart=args.restart)
+
+    def step():
+        Y, res = seed.solve(d, opts)
+        tr = seed.trace(Y)
+        return tr, res
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    if not args.no_profile:
+        L.profile_enable(True)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        tr, res = step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = L.profile_read() if not args.no_profile else None
+    L.profile_enable(False)
+
+    traces = tr.cpu().numpy()
+    P = pr.P
+    value = P * args.steps / wall
+    ok = bool(np.all(res["status"] == 0))
+
+    # error against stored oracle values (written by tests/golden/make_golden.py)
+    max_rel = None
+    gold_path = os.path.join(ROOT, "tests", "golden", "oracle_traces.json")
+    if os.path.exists(gold_path):
+        gold = json.load(open(gold_path)).get("c%d" % args.config)
+        if gold:
+            idx = [g["index"] for g in gold["samples"]]
+            ref = np.array([g["trace"] for g in gold["samples"]])
+            max_rel = float(np.max(np.abs(traces[idx] - ref) / np.abs(ref)))
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32_ir": "f32+f64", "bf16_ir": "bf16+f64", "fp32": "f32"}[args.prec],
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD[args.config], "P": P, "n": pr.n, "r": pr.r,
+                   "precision": args.prec, "restart": args.restart},
+        "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+        "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+        "all_converged": ok,
+        "max_rel_err_sampled": max_rel,
+        "iters_mean": float(np.mean(res["iters"])),
+        "iters_max": int(np.max(res["iters"])),
+        "seed_factor_s": factor_s,
+        "eig_cond_est": info["cond_est"],
+    }
+    if prof and prof["gemm64_launches"] > 0:
+        if args.prec == "fp64":
+            ms, fl, nl, peak = prof["gemm64_ms"], prof["gemm64_flops"], prof["gemm64_launches"], 78.6
+        else:
+            ms, fl, nl, peak = prof["gemmlo_ms"], prof["gemmlo_flops"], prof["gemmlo_launches"], \
+                PEAK[args.prec]
+        achieved = fl / (ms * 1e-3) / 1e12
+        out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                           "frac": achieved / peak, "traffic": None,
+                           "kernel": "Cauchy contraction GEMM (%s)" % args.prec,
+                           "avg_launch_us": 1e3 * ms / nl, "launches": nl,
+                           "algorithmic_flops_per_launch": fl / nl}
+        out["kernel_time_share"] = {
+            "cauchy_gemm": (prof["gemm64_ms"] + prof["gemmlo_ms"]) / (1e3 * wall),
+            "krylov": prof["krylov_ms"] / (1e3 * wall)}
+    if not args.no_cpu_baseline:
+        cb, ctrace = cpu_baseline(pr, P // 2 + 5)
+        cb["rel_diff_vs_gpu"] = abs(ctrace - traces[P // 2 + 5]) / abs(ctrace)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -199,6 +199,31 @@ lyap_status engine_run(lyap_engine eng, int64_t max_steps, int32_t poll_every, i
 lyap_status engine_harvest(lyap_engine eng, int64_t max_out, int64_t* tags_out,
                            lyap_result* res_out, int64_t* n_out);
 
+/* ------------------------------------------------------------------------ */
+/* Measurement helpers (not part of the method).                             */
+/* ------------------------------------------------------------------------ */
+
+/* Per-kernel timings of engine steps, accumulated process-wide while
+ * profiling is enabled.  When enabled, engines launch their steps directly
+ * (not as a graph) with HIP event pairs around the FP64 Cauchy GEMM, the
+ * low-precision Cauchy GEMM and the Krylov kernel, on the stream those kernels
+ * run on.  *_flops are algorithmic: 2 r^2 n^2 per active parameter per
+ * product (the real-compressed Cauchy contraction), not the padded tile work. */
+typedef struct {
+  double gemm64_ms, gemm64_flops;
+  double gemmlo_ms, gemmlo_flops;
+  double krylov_ms;
+  int64_t gemm64_launches, gemmlo_launches, krylov_launches;
+  int64_t steps, slot_steps;
+} lyap_profile;
+
+void lyap_profile_enable(int32_t on); /* also resets the counters */
+lyap_status lyap_profile_read(lyap_profile* out);
+
+/* Plain device copy of `bytes` bytes with a simple vector-load kernel; used to
+ * calibrate hardware byte counters against a known traffic. */
+lyap_status lyap_calib_copy(const void* src_dev, void* dst_dev, size_t bytes, void* hip_stream);
+
 const char* lyap_status_string(lyap_status s);
 
 /* Text of the most recent error raised by any entry point (process-wide). */

@@ -122,6 +122,12 @@ void apply_impl(lyap_seed_s* sd, long long batch, const double* Y, double* G, in
   LYAP_HIP(hipGetLastError());
 }
 
+__global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, long count) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 }  // namespace
 }  // namespace lyap
 
@@ -142,6 +148,17 @@ lyap_status trace_EX(lyap_seed sd, int64_t P, const double* Y_dev, double* trace
   if (!sd || P < 1 || !Y_dev || !trace_dev) return LYAP_E_INVAL;
   LYAP_TRY(batched_dot(trace_dev, Y_dev, sd->n, sd->Gam.as<double>(), sd->ld, (int)sd->r, (int)P,
                        (int)sd->n, sd->t0, 2.0, (hipStream_t)hip_stream));
+  return LYAP_OK;
+}
+
+lyap_status lyap_calib_copy(const void* src, void* dst, size_t bytes, void* hip_stream) {
+  if (!src || !dst || bytes % 16 != 0) return LYAP_E_INVAL;
+  LYAP_TRY({
+    const long count = (long)(bytes / 16);
+    hipLaunchKernelGGL(k_copy16, dim3(2048), dim3(256), 0, (hipStream_t)hip_stream,
+                       (const uint4*)src, (uint4*)dst, count);
+    LYAP_HIP(hipGetLastError());
+  });
   return LYAP_OK;
 }
 

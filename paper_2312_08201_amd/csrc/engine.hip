@@ -26,6 +26,7 @@
 #include <cstring>
 #include <deque>
 #include <memory>
+#include <mutex>
 
 #include "internal.h"
 
@@ -753,7 +754,12 @@ static EngineSizes engine_sizes(const lyap_seed_s* sd, long long S, const lyap_s
   return z;
 }
 
-static void launch_step(lyap_engine_s* E, hipStream_t st) {
+// Optional event pairs around the kernels of one step (profiling mode).
+struct StepEvents {
+  hipEvent_t g64[2], glo[2], kry[2];
+};
+
+static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullptr) {
   const EngineArgs& A = E->args;
   lyap_seed_s* sd = E->sd;
   const int S = E->S, r = (int)sd->r, ld = (int)sd->ld, nu = (int)(sd->n - sd->h);
@@ -776,7 +782,9 @@ static void launch_step(lyap_engine_s* E, hipStream_t st) {
     g.Nstore = ld;
     g.M_dev = E->lists.as<int>() + 2 * S;
     g.m_scale = r * r;
+    if (ev) LYAP_HIP(hipEventRecord(ev->g64[0], st));
     gemm_launch(g, st);
+    if (ev) LYAP_HIP(hipEventRecord(ev->g64[1], st));
     hipLaunchKernelGGL((k_epilogue<double>), dim3(ublocks, S * r), dim3(KT), 0, st, A,
                        E->H.as<double>(), 0);
   }
@@ -802,12 +810,86 @@ static void launch_step(lyap_engine_s* E, hipStream_t st) {
       hipLaunchKernelGGL((k_formX<__bf16>), dim3(ublocks, S * r * r), dim3(KT), 0, st, A,
                          E->Xlo.as<__bf16>(), (long)(E->rows_pad * ld), 1);
     }
+    if (ev) LYAP_HIP(hipEventRecord(ev->glo[0], st));
     gemm_launch(g, st);
+    if (ev) LYAP_HIP(hipEventRecord(ev->glo[1], st));
     hipLaunchKernelGGL((k_epilogue<float>), dim3(ublocks, S * r), dim3(KT), 0, st, A,
                        E->Hlo.as<float>(), 1);
   }
+  if (ev) LYAP_HIP(hipEventRecord(ev->kry[0], st));
   hipLaunchKernelGGL(k_krylov, dim3(S), dim3(KT), 0, st, A);
+  if (ev) LYAP_HIP(hipEventRecord(ev->kry[1], st));
   LYAP_HIP(hipGetLastError());
+}
+
+// ---- process-wide profile (lyap_profile_*) ----
+namespace {
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+lyap_profile g_prof{};
+}  // namespace
+
+static bool profiling() {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  return g_prof_on;
+}
+
+// Run k steps with event pairs and per-step active counts; accumulate the profile.
+static void profiled_steps(lyap_engine_s* E, long long k) {
+  hipStream_t st = E->stream;
+  const int S = E->S;
+  std::vector<StepEvents> evs(k);
+  for (auto& e : evs)
+    for (hipEvent_t* p : {&e.g64[0], &e.g64[1], &e.glo[0], &e.glo[1], &e.kry[0], &e.kry[1]})
+      LYAP_HIP(hipEventCreate(p));
+  int* counts = nullptr;
+  LYAP_HIP(hipHostMalloc((void**)&counts, sizeof(int) * 2 * k, hipHostMallocDefault));
+  for (long long i = 0; i < k; ++i) {
+    launch_step(E, st, &evs[i]);
+    // the lists (and counts) stay valid until the next step's k_lists
+    LYAP_HIP(hipMemcpyAsync(counts + 2 * i, E->lists.as<int>() + 2 * S, 2 * sizeof(int),
+                            hipMemcpyDeviceToHost, st));
+  }
+  LYAP_HIP(hipStreamSynchronize(st));
+  const double r = (double)E->sd->r, n = (double)E->sd->n;
+  lyap_profile add{};
+  for (long long i = 0; i < k; ++i) {
+    float t = 0;
+    LYAP_HIP(hipEventElapsedTime(&t, evs[i].g64[0], evs[i].g64[1]));
+    if (counts[2 * i] > 0) {
+      add.gemm64_ms += t;
+      add.gemm64_launches += 1;
+      add.gemm64_flops += 2.0 * counts[2 * i] * r * r * n * n;
+    }
+    if (E->mixed) {
+      LYAP_HIP(hipEventElapsedTime(&t, evs[i].glo[0], evs[i].glo[1]));
+      if (counts[2 * i + 1] > 0) {
+        add.gemmlo_ms += t;
+        add.gemmlo_launches += 1;
+        add.gemmlo_flops += 2.0 * counts[2 * i + 1] * r * r * n * n;
+      }
+    }
+    LYAP_HIP(hipEventElapsedTime(&t, evs[i].kry[0], evs[i].kry[1]));
+    add.krylov_ms += t;
+    add.krylov_launches += 1;
+    add.slot_steps += counts[2 * i] + counts[2 * i + 1];
+  }
+  add.steps = k;
+  (void)hipHostFree(counts);
+  for (auto& e : evs)
+    for (hipEvent_t p : {e.g64[0], e.g64[1], e.glo[0], e.glo[1], e.kry[0], e.kry[1]})
+      (void)hipEventDestroy(p);
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof.gemm64_ms += add.gemm64_ms;
+  g_prof.gemm64_launches += add.gemm64_launches;
+  g_prof.gemm64_flops += add.gemm64_flops;
+  g_prof.gemmlo_ms += add.gemmlo_ms;
+  g_prof.gemmlo_launches += add.gemmlo_launches;
+  g_prof.gemmlo_flops += add.gemmlo_flops;
+  g_prof.krylov_ms += add.krylov_ms;
+  g_prof.krylov_launches += add.krylov_launches;
+  g_prof.slot_steps += add.slot_steps;
+  g_prof.steps += add.steps;
 }
 
 static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lyap_solve_opts* in,
@@ -985,9 +1067,13 @@ static long long engine_run_impl(lyap_engine_s* E, long long max_steps, int poll
     const long long busy = E->submitted - engine_done_count(E);
     if (busy <= 0) return 0;
     const long long k = std::min<long long>(poll_every, max_steps - steps);
-    for (long long i = 0; i < k; ++i) {
-      if (E->gexec) LYAP_HIP(hipGraphLaunch(E->gexec, E->stream));
-      else launch_step(E, E->stream);
+    if (profiling()) {
+      profiled_steps(E, k);
+    } else {
+      for (long long i = 0; i < k; ++i) {
+        if (E->gexec) LYAP_HIP(hipGraphLaunch(E->gexec, E->stream));
+        else launch_step(E, E->stream);
+      }
     }
     steps += k;
   }
@@ -1090,6 +1176,19 @@ lyap_status engine_harvest(lyap_engine E, int64_t max_out, int64_t* tags_out, ly
         engine_harvest_impl(E, max_out, reinterpret_cast<long long*>(tags_out), res_out);
     if (n_out) *n_out = n;
   });
+  return LYAP_OK;
+}
+
+void lyap_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof_on = on != 0;
+  g_prof = lyap_profile{};
+}
+
+lyap_status lyap_profile_read(lyap_profile* out) {
+  if (!out) return LYAP_E_INVAL;
+  std::lock_guard<std::mutex> g(g_prof_mu);
+  *out = g_prof;
   return LYAP_OK;
 }
 

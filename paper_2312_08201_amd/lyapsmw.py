@@ -54,6 +54,14 @@ class SeedInfo(C.Structure):
                 ("factor_seconds", C.c_double), ("device_bytes", C.c_size_t)]
 
 
+class Profile(C.Structure):
+    _fields_ = [("gemm64_ms", C.c_double), ("gemm64_flops", C.c_double),
+                ("gemmlo_ms", C.c_double), ("gemmlo_flops", C.c_double),
+                ("krylov_ms", C.c_double), ("gemm64_launches", C.c_int64),
+                ("gemmlo_launches", C.c_int64), ("krylov_launches", C.c_int64),
+                ("steps", C.c_int64), ("slot_steps", C.c_int64)]
+
+
 RESULT_DTYPE = np.dtype([("status", np.int32), ("iters", np.int32), ("cycles", np.int32),
                          ("refinements", np.int32), ("rel_residual", np.float64),
                          ("trace", np.float64)])
@@ -64,7 +72,8 @@ _lib = None
 EXPORTS = ["seed_factor", "seed_info", "seed_release", "seed_device_bytes", "lyap_seed_apply",
            "smw_workspace_bytes", "smw_solve_batch", "trace_EX", "engine_create",
            "engine_device_bytes", "engine_destroy", "engine_submit", "engine_run",
-           "engine_harvest", "lyap_status_string", "lyap_last_error"]
+           "engine_harvest", "lyap_status_string", "lyap_last_error", "lyap_profile_enable",
+           "lyap_profile_read", "lyap_calib_copy"]
 
 
 def load(path: str = LIB_PATH):
@@ -99,11 +108,15 @@ def load(path: str = LIB_PATH):
     lib.engine_harvest.argtypes = [vp, i64, vp, C.POINTER(Result), C.POINTER(i64)]
     lib.lyap_status_string.argtypes = [i32]
     lib.lyap_status_string.restype = C.c_char_p
+    lib.lyap_profile_enable.argtypes = [i32]
+    lib.lyap_profile_enable.restype = None
+    lib.lyap_profile_read.argtypes = [C.POINTER(Profile)]
+    lib.lyap_calib_copy.argtypes = [vp, vp, C.c_size_t, vp]
     lib.lyap_last_error.argtypes = []
     lib.lyap_last_error.restype = C.c_char_p
     for name in ("seed_factor", "seed_info", "seed_release", "lyap_seed_apply", "smw_solve_batch",
                  "trace_EX", "engine_create", "engine_destroy", "engine_submit", "engine_run",
-                 "engine_harvest"):
+                 "engine_harvest", "lyap_profile_read", "lyap_calib_copy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -305,3 +318,22 @@ class Engine:
             self.close()
         except Exception:
             pass
+
+
+def profile_enable(on: bool = True):
+    load().lyap_profile_enable(1 if on else 0)
+
+
+def profile_read() -> dict:
+    p = Profile()
+    _check(load().lyap_profile_read(C.byref(p)), "lyap_profile_read")
+    return {k: getattr(p, k) for k, _ in Profile._fields_}
+
+
+def calib_copy(src, dst, stream=None):
+    """Plain device copy (byte-counter calibration); src, dst CUDA tensors of equal size."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("size mismatch")
+    _check(load().lyap_calib_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes,
+                                  _stream(stream)), "lyap_calib_copy")

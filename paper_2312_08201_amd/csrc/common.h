@@ -85,6 +85,18 @@ struct DevBuf {
   template <class T> T* as() const { return reinterpret_cast<T*>(p); }
 };
 
+// Split-K factor of a dynamic-M GEMM launch: when only a few row tiles are
+// active (a tail of the sweep), idle workgroups take K-slices of the same
+// tiles; partial products go to a separate buffer and the consumer sums the
+// KS slices in fixed order.  Same formula on host and device.
+__host__ __device__ inline int splitk_of(int m_active_tiles, int ntiles, int grid, int nk) {
+  const int tiles = m_active_tiles * ntiles;
+  if (tiles <= 0) return 1;
+  int ks = 1;
+  while (ks < 16 && tiles * ks * 2 <= grid && nk % (ks * 2) == 0 && nk / (ks * 2) >= 4) ks *= 2;
+  return ks;
+}
+
 // Precision of one GEMM launch.
 enum class GemmType { F64 = 0, F32 = 1, BF16X3 = 2 };
 
@@ -105,7 +117,12 @@ struct GemmArgs {
   int64_t a_plane, b_plane;  // element offsets of the lo planes (BF16X3)
   const int* M_dev;   // optional device row count (scaled by m_scale)
   int m_scale;
+  void* Cpart;        // optional split-K partial buffer (same size as C), dynamic M only
 };
+
+constexpr int kGemmBM = 128;
+constexpr int kGemmBN = 128;
+inline int gemm_bk(GemmType t) { return t == GemmType::F64 ? 16 : 32; }
 
 void gemm_launch(const GemmArgs& g, hipStream_t s);
 

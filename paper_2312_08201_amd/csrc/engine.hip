@@ -155,6 +155,85 @@ __device__ inline void apply_pinv(const EngineArgs& A, int s, const double* v, d
   }
 }
 
+// (I - D K1_q)^-1 for one eigen slot q (complex r x r on a conjugate pair),
+// Gauss-Jordan with partial pivoting; R is the compile-time bound of r.
+template <int R>
+__device__ inline void block_inverse(const EngineArgs& A, const double* dsh, int q, bool pr,
+                                     double* P, int r = R) {
+  double Mr[R * R], Mi[R * R], Ir[R * R], Ii[R * R];
+  const int ld = A.ld;
+#pragma unroll
+  for (int a = 0; a < R; ++a)
+#pragma unroll
+    for (int b = 0; b < R; ++b) {
+      if (a >= r || b >= r) continue;
+      const double* k = A.K1 + (long)(a * r + b) * ld;
+      Mr[a * R + b] = (a == b ? 1.0 : 0.0) - dsh[a] * k[q];
+      Mi[a * R + b] = pr ? -dsh[a] * k[q + 1] : 0.0;
+      Ir[a * R + b] = a == b ? 1.0 : 0.0;
+      Ii[a * R + b] = 0.0;
+    }
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    if (c >= r) break;
+    int piv = c;
+    double best = -1;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if (i < c || i >= r) continue;
+      const double mag = fabs(Mr[i * R + c]) + fabs(Mi[i * R + c]);
+      if (mag > best) {
+        best = mag;
+        piv = i;
+      }
+    }
+    if (piv != c) {
+#pragma unroll
+      for (int b = 0; b < R; ++b) {
+        double t;
+        t = Mr[c * R + b]; Mr[c * R + b] = Mr[piv * R + b]; Mr[piv * R + b] = t;
+        t = Mi[c * R + b]; Mi[c * R + b] = Mi[piv * R + b]; Mi[piv * R + b] = t;
+        t = Ir[c * R + b]; Ir[c * R + b] = Ir[piv * R + b]; Ir[piv * R + b] = t;
+        t = Ii[c * R + b]; Ii[c * R + b] = Ii[piv * R + b]; Ii[piv * R + b] = t;
+      }
+    }
+    const double pr_ = Mr[c * R + c], pi_ = Mi[c * R + c];
+    const double den = pr_ * pr_ + pi_ * pi_;
+    const double ivr = pr_ / den, ivi = -pi_ / den;
+#pragma unroll
+    for (int b = 0; b < R; ++b) {
+      double ar = Mr[c * R + b], ai = Mi[c * R + b];
+      Mr[c * R + b] = ar * ivr - ai * ivi;
+      Mi[c * R + b] = ar * ivi + ai * ivr;
+      ar = Ir[c * R + b];
+      ai = Ii[c * R + b];
+      Ir[c * R + b] = ar * ivr - ai * ivi;
+      Ii[c * R + b] = ar * ivi + ai * ivr;
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if (i == c || i >= r) continue;
+      const double fr = Mr[i * R + c], fi = Mi[i * R + c];
+#pragma unroll
+      for (int b = 0; b < R; ++b) {
+        Mr[i * R + b] -= fr * Mr[c * R + b] - fi * Mi[c * R + b];
+        Mi[i * R + b] -= fr * Mi[c * R + b] + fi * Mr[c * R + b];
+        Ir[i * R + b] -= fr * Ir[c * R + b] - fi * Ii[c * R + b];
+        Ii[i * R + b] -= fr * Ii[c * R + b] + fi * Ir[c * R + b];
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < R; ++a)
+#pragma unroll
+    for (int b = 0; b < R; ++b) {
+      if (a >= r || b >= r) continue;
+      double* pb = P + (long)(a * r + b) * ld;
+      pb[q] = Ir[a * R + b];
+      if (pr) pb[q + 1] = Ii[a * R + b];
+    }
+}
+
 // Admission of queue entry qp into slot s (whole workgroup): preconditioner
 // blocks (I - D K1_j)^-1, right-hand side b = D c0, v0 = b / ||b||.
 __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
@@ -199,65 +278,13 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
     for (int u = threadIdx.x; u < nu; u += blockDim.x) {
       bool pr;
       const int q = uslot(u, A.h, pr);
-      double Mr[kPrecRank * kPrecRank], Mi[kPrecRank * kPrecRank];
-      double Ir[kPrecRank * kPrecRank], Ii[kPrecRank * kPrecRank];
-      for (int a = 0; a < r; ++a)
-        for (int b = 0; b < r; ++b) {
-          const double* k = A.K1 + (long)(a * r + b) * ld;
-          Mr[a * r + b] = (a == b ? 1.0 : 0.0) - dsh[a] * k[q];
-          Mi[a * r + b] = pr ? -dsh[a] * k[q + 1] : 0.0;
-          Ir[a * r + b] = a == b ? 1.0 : 0.0;
-          Ii[a * r + b] = 0.0;
-        }
-      // Gauss-Jordan with partial pivoting (complex)
-      for (int c = 0; c < r; ++c) {
-        int piv = c;
-        double best = -1;
-        for (int i = c; i < r; ++i) {
-          const double mag = fabs(Mr[i * r + c]) + fabs(Mi[i * r + c]);
-          if (mag > best) {
-            best = mag;
-            piv = i;
-          }
-        }
-        if (piv != c)
-          for (int b = 0; b < r; ++b) {
-            double t;
-            t = Mr[c * r + b]; Mr[c * r + b] = Mr[piv * r + b]; Mr[piv * r + b] = t;
-            t = Mi[c * r + b]; Mi[c * r + b] = Mi[piv * r + b]; Mi[piv * r + b] = t;
-            t = Ir[c * r + b]; Ir[c * r + b] = Ir[piv * r + b]; Ir[piv * r + b] = t;
-            t = Ii[c * r + b]; Ii[c * r + b] = Ii[piv * r + b]; Ii[piv * r + b] = t;
-          }
-        const double pr_ = Mr[c * r + c], pi_ = Mi[c * r + c];
-        const double den = pr_ * pr_ + pi_ * pi_;
-        const double ivr = pr_ / den, ivi = -pi_ / den;
-        for (int b = 0; b < r; ++b) {
-          double ar = Mr[c * r + b], ai = Mi[c * r + b];
-          Mr[c * r + b] = ar * ivr - ai * ivi;
-          Mi[c * r + b] = ar * ivi + ai * ivr;
-          ar = Ir[c * r + b];
-          ai = Ii[c * r + b];
-          Ir[c * r + b] = ar * ivr - ai * ivi;
-          Ii[c * r + b] = ar * ivi + ai * ivr;
-        }
-        for (int i = 0; i < r; ++i) {
-          if (i == c) continue;
-          const double fr = Mr[i * r + c], fi = Mi[i * r + c];
-          if (fr == 0.0 && fi == 0.0) continue;
-          for (int b = 0; b < r; ++b) {
-            Mr[i * r + b] -= fr * Mr[c * r + b] - fi * Mi[c * r + b];
-            Mi[i * r + b] -= fr * Mi[c * r + b] + fi * Mr[c * r + b];
-            Ir[i * r + b] -= fr * Ir[c * r + b] - fi * Ii[c * r + b];
-            Ii[i * r + b] -= fr * Ii[c * r + b] + fi * Ir[c * r + b];
-          }
-        }
+      switch (r) {
+        case 1: block_inverse<1>(A, dsh, q, pr, P); break;
+        case 2: block_inverse<2>(A, dsh, q, pr, P); break;
+        case 3: block_inverse<3>(A, dsh, q, pr, P); break;
+        case 4: block_inverse<4>(A, dsh, q, pr, P); break;
+        default: block_inverse<kPrecRank>(A, dsh, q, pr, P, r); break;
       }
-      for (int a = 0; a < r; ++a)
-        for (int b = 0; b < r; ++b) {
-          double* pb = P + (long)(a * r + b) * ld;
-          pb[q] = Ir[a * r + b];
-          if (pr) pb[q + 1] = Ii[a * r + b];
-        }
     }
   }
   // b = D c0 ; ||b||
@@ -445,9 +472,10 @@ __global__ void __launch_bounds__(KT) k_formX(EngineArgs A, T* X, long plane, in
   }
 }
 
-// w = z - D (sum_b z_b o K1_ab + sum_b Uh_b o H_(li,a,b))
+// w = z - D (sum_b z_b o K1_ab + sum_b Uh_b o H_(li,a,b)); H may be split-K partials
 template <class HT>
-__global__ void __launch_bounds__(KT) k_epilogue(EngineArgs A, const HT* H, int which) {
+__global__ void __launch_bounds__(KT)
+k_epilogue(EngineArgs A, const HT* H, const HT* Hp, int which, int ggrid, int gnk) {
   const int S = A.S, r = A.r, ld = A.ld, h = A.h;
   const int cnt = A.lists[2 * S + which];
   const int row = blockIdx.y;  // li * r + a
@@ -455,6 +483,10 @@ __global__ void __launch_bounds__(KT) k_epilogue(EngineArgs A, const HT* H, int 
   if (li >= cnt) return;
   const int a = row % r;
   const int s = A.lists[which * S + li];
+  const int mta = (cnt * r * r + kGemmBM - 1) / kGemmBM;
+  const int KS = splitk_of(mta, ld / kGemmBN, ggrid, gnk);
+  const long kstride = (long)mta * kGemmBM * ld;
+  const HT* Hsrc = KS > 1 ? Hp : H;
   const double* zs = A.z + (long)s * r * ld;
   double* ws = A.w + ((long)s * r + a) * ld;
   const double da = A.d[(long)s * r + a];
@@ -467,14 +499,19 @@ __global__ void __launch_bounds__(KT) k_epilogue(EngineArgs A, const HT* H, int 
       const double* k = A.K1 + (long)(a * r + b) * ld;
       const double* zb = zs + (long)b * ld;
       const double* ub = A.Uh + (long)b * ld;
-      const HT* hb = H + ((long)(li * r + a) * r + b) * ld;
+      const HT* hb = Hsrc + ((long)(li * r + a) * r + b) * ld;
+      double hr = 0, hi = 0;
+      for (int t = 0; t < KS; ++t) {
+        hr += (double)hb[t * kstride + q];
+        if (pr) hi += (double)hb[t * kstride + q + 1];
+      }
       if (pr) {
         const double kr = k[q], ki = k[q + 1], zr = zb[q], zi = zb[q + 1];
-        const double ur = ub[q], ui = ub[q + 1], hr = (double)hb[q], hi = (double)hb[q + 1];
+        const double ur = ub[q], ui = ub[q + 1];
         sr += zr * kr - zi * ki + ur * hr - ui * hi;
         si += zr * ki + zi * kr + ur * hi + ui * hr;
       } else {
-        sr += zb[q] * k[q] + ub[q] * (double)hb[q];
+        sr += zb[q] * k[q] + ub[q] * hr;
       }
     }
     ws[q] = zs[(long)a * ld + q] - da * sr;
@@ -482,9 +519,10 @@ __global__ void __launch_bounds__(KT) k_epilogue(EngineArgs A, const HT* H, int 
   }
 }
 
-// one workgroup per slot
+// One workgroup per slot: orthogonalisation, Givens update, restart and
+// convergence of that slot's Krylov iteration.
 __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
-  __shared__ double lds[4 * 8];
+  __shared__ double lds[4 * 9];
   __shared__ double ycoef[kMaxRestart + 1];
   __shared__ double hcol[kMaxRestart + 2];
   __shared__ int next_phase;
@@ -492,15 +530,8 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
   const int r = A.r, ld = A.ld, N = r * ld, m = A.m;
   int* si = A.si + (long)s * SI_N;
   double* sdv = A.sdv + (long)s * SD_N;
-  int ph = si[SI_PHASE];
-
-  if (ph == PH_FREE) {
-    __shared__ int qp;
-    if (threadIdx.x == 0) qp = claim(A);
-    __syncthreads();
-    if (qp >= 0) admit(A, s, qp, lds);
-    return;
-  }
+  const int ph = si[SI_PHASE];
+  if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
 
   double* Vs = A.V + (long)s * (m + 1) * N;
   double* ws = A.w + (long)s * N;
@@ -510,12 +541,13 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
   double* css = A.cs + (long)s * m;
   double* sns = A.sn + (long)s * m;
   const double bn = sdv[SD_BNORM];
+  const int tid = threadIdx.x;
 
   if (ph == PH_RESTART) {
     // w = A y ; residual r = D c0 - w into V0
     const double* d = A.d + (long)s * r;
     double acc = 0;
-    for (int e = threadIdx.x; e < N; e += blockDim.x) {
+    for (int e = tid; e < N; e += blockDim.x) {
       const double v = d[e / ld] * A.c0[e] - ws[e];
       Vs[e] = v;
       acc += v * v;
@@ -525,9 +557,8 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
     const int iters = si[SI_ITERS] + 1;
     const int refines = si[SI_REFINE];
     __syncthreads();
-    if (threadIdx.x == 0) si[SI_ITERS] = iters;
+    if (tid == 0) si[SI_ITERS] = iters;
     __syncthreads();
-    bool freed = true;
     if (!isfinite(rel)) {
       finish(A, s, LYAP_E_NONFINITE, rel, lds);
     } else if (rel <= A.tol) {
@@ -535,10 +566,9 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
     } else if (iters >= A.max_iter || (A.mixed && refines >= A.max_refine)) {
       finish(A, s, LYAP_E_NOCONV, rel, lds);
     } else {
-      freed = false;
       const double inv = 1.0 / rn;
-      for (int e = threadIdx.x; e < N; e += blockDim.x) Vs[e] *= inv;
-      if (threadIdx.x == 0) {
+      for (int e = tid; e < N; e += blockDim.x) Vs[e] *= inv;
+      if (tid == 0) {
         gs[0] = rn;
         sdv[SD_BETA] = rn;
         si[SI_J] = 0;
@@ -548,55 +578,58 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
       }
       __syncthreads();
     }
-    if (freed) {
-      __shared__ int qp2;
-      if (threadIdx.x == 0) qp2 = claim(A);
-      __syncthreads();
-      if (qp2 >= 0) admit(A, s, qp2, lds);
-    }
     return;
   }
 
   // ---- Arnoldi step j: w = A P^-1 v_j ----
+  // Classical Gram-Schmidt with the Daniel-Gragg-Kaufman-Stewart criterion:
+  // a second pass only when the first one cancelled more than 1/sqrt(2) of
+  // ||w||.  Each pass = one sweep for the dots (and ||w||^2), one sweep for the
+  // update (and the new ||w||^2).
   const int j = si[SI_J];
-  if (threadIdx.x < kMaxRestart + 2) hcol[threadIdx.x] = 0.0;
+  if (tid < kMaxRestart + 2) hcol[tid] = 0.0;
   __syncthreads();
+  double wn2 = 0.0, hn = 0.0;
   for (int pass = 0; pass < 2; ++pass) {
     for (int k0 = 0; k0 <= j; k0 += 8) {
-      double acc[8];
+      double acc[9];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) acc[t] = 0.0;
+      for (int t = 0; t < 9; ++t) acc[t] = 0.0;
       const int kc = min(8, j + 1 - k0);
-      for (int e = threadIdx.x; e < N; e += blockDim.x) {
+      for (int e = tid; e < N; e += blockDim.x) {
         const double we = ws[e];
 #pragma unroll
         for (int t = 0; t < 8; ++t)
           if (t < kc) acc[t] += Vs[(long)(k0 + t) * N + e] * we;
+        if (k0 == 0 && pass == 0) acc[8] += we * we;
       }
-      block_sum<8>(acc, lds);
-      if (threadIdx.x == 0)
+      block_sum<9>(acc, lds);
+      if (k0 == 0 && pass == 0) wn2 = acc[8];
+      if (tid == 0)
         for (int t = 0; t < kc; ++t) {
           hcol[k0 + t] += acc[t];
           ycoef[k0 + t] = acc[t];
         }
       __syncthreads();
     }
-    for (int e = threadIdx.x; e < N; e += blockDim.x) {
+    double nn = 0.0;
+    for (int e = tid; e < N; e += blockDim.x) {
       double we = ws[e];
       for (int k = 0; k <= j; ++k) we -= ycoef[k] * Vs[(long)k * N + e];
       ws[e] = we;
+      nn += we * we;
     }
-    __syncthreads();
+    nn = block_sum1(nn, lds);
+    hn = sqrt(nn);
+    if (!(nn < 0.5 * wn2)) break;  // no severe cancellation: one pass is enough
+    wn2 = nn;
   }
-  double acc = 0;
-  for (int e = threadIdx.x; e < N; e += blockDim.x) acc += ws[e] * ws[e];
-  const double hn = sqrt(block_sum1(acc, lds));
   double* vnext = Vs + (long)(j + 1) * N;
   if (hn > 0) {
     const double inv = 1.0 / hn;
-    for (int e = threadIdx.x; e < N; e += blockDim.x) vnext[e] = ws[e] * inv;
+    for (int e = tid; e < N; e += blockDim.x) vnext[e] = ws[e] * inv;
   }
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     hcol[j + 1] = hn;
     // apply previous rotations
     for (int k = 0; k < j; ++k) {
@@ -645,7 +678,7 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
   if (next_phase == PH_RESTART) {
     const int jn = j + 1;
     // u = V y (into w), x += P^-1 u
-    for (int e = threadIdx.x; e < N; e += blockDim.x) {
+    for (int e = tid; e < N; e += blockDim.x) {
       double u = 0;
       for (int k = 0; k < jn; ++k) u += ycoef[k] * Vs[(long)k * N + e];
       ws[e] = u;
@@ -653,10 +686,27 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
     __syncthreads();
     if (A.use_precond) apply_pinv(A, s, ws, xs, true);
     else
-      for (int e = threadIdx.x; e < N; e += blockDim.x) xs[e] += ws[e];
+      for (int e = tid; e < N; e += blockDim.x) xs[e] += ws[e];
     __syncthreads();
-    if (threadIdx.x == 0) si[SI_PHASE] = PH_RESTART;
+    if (tid == 0) si[SI_PHASE] = PH_RESTART;
   }
+}
+
+static void launch_krylov(const EngineArgs& A, int S, long long N, hipStream_t st) {
+  (void)N;
+  hipLaunchKernelGGL(k_krylov, dim3(S), dim3(KT), 0, st, A);
+}
+
+// Admission: every free slot takes the next queued parameter (device-side
+// queue), so a slot freed in this step starts its next parameter in the next.
+__global__ void __launch_bounds__(KT) k_admit(EngineArgs A) {
+  __shared__ double lds[4 * 9];
+  __shared__ int qp;
+  const int s = blockIdx.x;
+  if (A.si[(long)s * SI_N + SI_PHASE] != PH_FREE) return;
+  if (threadIdx.x == 0) qp = claim(A);
+  __syncthreads();
+  if (qp >= 0) admit(A, s, qp, lds);
 }
 
 }  // namespace lyap
@@ -677,7 +727,7 @@ struct lyap_engine_s {
   long long submitted = 0;   // queue positions handed out (host mirror of tail)
   long long harvested = 0;   // queue positions whose result was returned
   long long next_tag = 0;
-  DevBuf si, sdv, d, R, g, cs, sn, V, x, z, w, Pinv, lists, X, H, Xlo, Hlo;
+  DevBuf si, sdv, d, R, g, cs, sn, V, x, z, w, Pinv, lists, X, H, Hp, Xlo, Hlo, Hplo;
   DevBuf qd, qtag, qctl, res;
   double* sol = nullptr;
   long long sol_cap = 0;
@@ -741,11 +791,11 @@ static EngineSizes engine_sizes(const lyap_seed_s* sd, long long S, const lyap_s
   add(S * N * 8 * 3);
   add(S * r * r * ld * 8);
   add((2 * S + 2) * 4);
-  add(z.rows_pad * ld * 8 * 2);  // X, H fp64
+  add(z.rows_pad * ld * 8 * 3);  // X, H, split-K partials fp64
   const bool mixed = o.prec != LYAP_PREC_FP64;
   if (mixed) {
-    add(z.rows_pad * ld * (o.prec == LYAP_PREC_BF16_IR ? 4 : 4));  // Xlo (float or 2 bf16 planes)
-    add(z.rows_pad * ld * 4);                                       // Hlo float
+    add(z.rows_pad * ld * 4);      // Xlo (float, or two bf16 planes)
+    add(z.rows_pad * ld * 4 * 2);  // Hlo, split-K partials (float)
   }
   add(Q * r * 8);
   add(Q * 8);
@@ -782,11 +832,13 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     g.Nstore = ld;
     g.M_dev = E->lists.as<int>() + 2 * S;
     g.m_scale = r * r;
+    g.Cpart = E->Hp.p;
     if (ev) LYAP_HIP(hipEventRecord(ev->g64[0], st));
     gemm_launch(g, st);
     if (ev) LYAP_HIP(hipEventRecord(ev->g64[1], st));
+    const int ggrid = (int)(E->rows_pad / kGemmBM) * (ld / kGemmBN);
     hipLaunchKernelGGL((k_epilogue<double>), dim3(ublocks, S * r), dim3(KT), 0, st, A,
-                       E->H.as<double>(), 0);
+                       E->H.as<double>(), E->Hp.as<double>(), 0, ggrid, ld / gemm_bk(GemmType::F64));
   }
   if (E->mixed) {
     GemmArgs g{};
@@ -801,6 +853,7 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     g.Nstore = ld;
     g.M_dev = E->lists.as<int>() + 2 * S + 1;
     g.m_scale = r * r;
+    g.Cpart = E->Hplo.p;
     if (E->low == GemmType::F32) {
       hipLaunchKernelGGL((k_formX<float>), dim3(ublocks, S * r * r), dim3(KT), 0, st, A,
                          E->Xlo.as<float>(), 0L, 1);
@@ -813,12 +866,14 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     if (ev) LYAP_HIP(hipEventRecord(ev->glo[0], st));
     gemm_launch(g, st);
     if (ev) LYAP_HIP(hipEventRecord(ev->glo[1], st));
+    const int ggrid = (int)(E->rows_pad / kGemmBM) * (ld / kGemmBN);
     hipLaunchKernelGGL((k_epilogue<float>), dim3(ublocks, S * r), dim3(KT), 0, st, A,
-                       E->Hlo.as<float>(), 1);
+                       E->Hlo.as<float>(), E->Hplo.as<float>(), 1, ggrid, ld / gemm_bk(E->low));
   }
   if (ev) LYAP_HIP(hipEventRecord(ev->kry[0], st));
-  hipLaunchKernelGGL(k_krylov, dim3(S), dim3(KT), 0, st, A);
+  launch_krylov(A, S, (long long)r * ld, st);
   if (ev) LYAP_HIP(hipEventRecord(ev->kry[1], st));
+  hipLaunchKernelGGL(k_admit, dim3(S), dim3(KT), 0, st, A);
   LYAP_HIP(hipGetLastError());
 }
 
@@ -941,9 +996,11 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   zalloc(E->lists, (2 * S + 2) * 4);
   zalloc(E->X, z.rows_pad * ld * 8);
   zalloc(E->H, z.rows_pad * ld * 8);
+  zalloc(E->Hp, z.rows_pad * ld * 8);
   if (E->mixed) {
     zalloc(E->Xlo, z.rows_pad * ld * 4);
     zalloc(E->Hlo, z.rows_pad * ld * 4);
+    zalloc(E->Hplo, z.rows_pad * ld * 4);
   }
   zalloc(E->qd, Q * r * 8);
   zalloc(E->qtag, Q * 8);

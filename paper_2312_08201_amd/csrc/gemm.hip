@@ -62,7 +62,7 @@ template <class T, int BK>
 __global__ void __launch_bounds__(NTHREADS)
 gemm_kernel(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
             int M, int N, int K, long lda, long ldb, long ldc, int Nstore,
-            const int* __restrict__ M_dev, int m_scale) {
+            const int* __restrict__ M_dev, int m_scale, T* __restrict__ Cpart) {
   typedef typename Acc<T>::type acc_t;
   constexpr int PADA = 4;
   constexpr int PADB = 4;
@@ -71,16 +71,34 @@ gemm_kernel(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
 
   const int mtiles = (M + BM - 1) / BM;
   const int ntiles = N / BN;
-  int mt, nt;
-  tile_of(blockIdx.x, mtiles, ntiles, mt, nt);
   int Meff = M;
   if (M_dev) {
     const int md = M_dev[0] * m_scale;
     Meff = md < M ? md : M;
   }
+  const int nk_all = K / BK;
+  int mt, nt, ks = 0, KS = 1;
+  if (Cpart) {
+    const int mta = (Meff + BM - 1) / BM;
+    KS = splitk_of(mta, ntiles, (int)gridDim.x, nk_all);
+    if (KS > 1) {
+      const int tiles = mta * ntiles;
+      if ((int)blockIdx.x >= tiles * KS) return;
+      const int t = blockIdx.x % tiles;
+      ks = blockIdx.x / tiles;
+      nt = t / mta;
+      mt = t % mta;
+    } else {
+      tile_of(blockIdx.x, mtiles, ntiles, mt, nt);
+    }
+  } else {
+    tile_of(blockIdx.x, mtiles, ntiles, mt, nt);
+  }
   const int row0 = mt * BM;
   const int col0 = nt * BN;
   if (row0 >= Meff) return;
+  const int kt0 = ks * (nk_all / KS);
+  if (KS > 1) C = Cpart + (long)ks * ((Meff + BM - 1) / BM) * BM * ldc;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -95,13 +113,13 @@ gemm_kernel(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
   const int a_k = (tid % A_TPR) * A_PER;
   int a_grow = row0 + a_row;
   if (a_grow > M - 1) a_grow = M - 1;
-  const T* a_src = A + (long)a_grow * lda + a_k;
+  const T* a_src = A + (long)a_grow * lda + a_k + (long)kt0 * BK;
 
   constexpr int B_PER = BK * BN / NTHREADS;
   constexpr int B_TPR = BN / B_PER;
   const int b_k = tid / B_TPR;
   const int b_n = (tid % B_TPR) * B_PER;
-  const T* b_src = B + (long)b_k * ldb + col0 + b_n;
+  const T* b_src = B + (long)(b_k + kt0 * BK) * ldb + col0 + b_n;
 
   T ra[A_PER], rb[B_PER];
 
@@ -126,7 +144,7 @@ gemm_kernel(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
-  const int nk = K / BK;
+  const int nk = nk_all / KS;
   gload(0);
   sstore(0);
   __syncthreads();
@@ -181,23 +199,42 @@ constexpr int BK16 = 32;
 __global__ void __launch_bounds__(NTHREADS)
 gemm_bf16x3_kernel(const __bf16* __restrict__ A, long a_plane, const __bf16* __restrict__ Bt,
                    long b_plane, float* __restrict__ C, int M, int N, int K, long lda, long ldb,
-                   long ldc, int Nstore, const int* __restrict__ M_dev, int m_scale) {
+                   long ldc, int Nstore, const int* __restrict__ M_dev, int m_scale,
+                   float* __restrict__ Cpart) {
   constexpr int PAD = 8;  // bf16 elements
   __shared__ __attribute__((aligned(16))) __bf16 Ash[2][2][BM][BK16 + PAD];  // [buf][plane]
   __shared__ __attribute__((aligned(16))) __bf16 Bsh[2][2][BN][BK16 + PAD];
 
   const int mtiles = (M + BM - 1) / BM;
   const int ntiles = N / BN;
-  int mt, nt;
-  tile_of(blockIdx.x, mtiles, ntiles, mt, nt);
   int Meff = M;
   if (M_dev) {
     const int md = M_dev[0] * m_scale;
     Meff = md < M ? md : M;
   }
+  const int nk_all = K / BK16;
+  int mt, nt, ks = 0, KS = 1;
+  if (Cpart) {
+    const int mta = (Meff + BM - 1) / BM;
+    KS = splitk_of(mta, ntiles, (int)gridDim.x, nk_all);
+    if (KS > 1) {
+      const int tiles = mta * ntiles;
+      if ((int)blockIdx.x >= tiles * KS) return;
+      const int t = blockIdx.x % tiles;
+      ks = blockIdx.x / tiles;
+      nt = t / mta;
+      mt = t % mta;
+    } else {
+      tile_of(blockIdx.x, mtiles, ntiles, mt, nt);
+    }
+  } else {
+    tile_of(blockIdx.x, mtiles, ntiles, mt, nt);
+  }
   const int row0 = mt * BM;
   const int col0 = nt * BN;
   if (row0 >= Meff) return;
+  const int kt0 = ks * (nk_all / KS);
+  if (KS > 1) C = Cpart + (long)ks * ((Meff + BM - 1) / BM) * BM * ldc;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -210,8 +247,8 @@ gemm_bf16x3_kernel(const __bf16* __restrict__ A, long a_plane, const __bf16* __r
   const int g_k = (tid & 1) * 16;       // 0 or 16
   int a_grow = row0 + g_row;
   if (a_grow > M - 1) a_grow = M - 1;
-  const __bf16* a_src = A + (long)a_grow * lda + g_k;
-  const __bf16* b_src = Bt + (long)(col0 + g_row) * ldb + g_k;
+  const __bf16* a_src = A + (long)a_grow * lda + g_k + (long)kt0 * BK16;
+  const __bf16* b_src = Bt + (long)(col0 + g_row) * ldb + g_k + (long)kt0 * BK16;
 
   typedef uint4 vec_t;  // 8 bf16
   vec_t ra[2][2], rb[2][2];  // [plane][half]
@@ -246,7 +283,7 @@ gemm_bf16x3_kernel(const __bf16* __restrict__ A, long a_plane, const __bf16* __r
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = float4_{0, 0, 0, 0};
 
-  const int nk = K / BK16;
+  const int nk = nk_all / KS;
   gload(0);
   sstore(0);
   __syncthreads();
@@ -299,6 +336,7 @@ gemm_bf16x3_kernel(const __bf16* __restrict__ A, long a_plane, const __bf16* __r
 void gemm_launch(const GemmArgs& g, hipStream_t s) {
   LYAP_REQUIRE(g.N % BN == 0, LYAP_E_INVAL, "gemm: N not padded");
   LYAP_REQUIRE(g.M >= 1, LYAP_E_INVAL, "gemm: M < 1");
+  LYAP_REQUIRE(g.Cpart == nullptr || g.M_dev != nullptr, LYAP_E_INVAL, "gemm: split-K needs M_dev");
   const int mtiles = (int)((g.M + BM - 1) / BM);
   const int ntiles = (int)(g.N / BN);
   dim3 grid(mtiles * ntiles), block(NTHREADS);
@@ -308,21 +346,21 @@ void gemm_launch(const GemmArgs& g, hipStream_t s) {
       hipLaunchKernelGGL((gemm_kernel<double, 16>), grid, block, 0, s,
                          (const double*)g.A, (const double*)g.B, (double*)g.C, (int)g.M,
                          (int)g.N, (int)g.K, (long)g.lda, (long)g.ldb, (long)g.ldc,
-                         (int)g.Nstore, g.M_dev, g.m_scale);
+                         (int)g.Nstore, g.M_dev, g.m_scale, (double*)g.Cpart);
       break;
     case GemmType::F32:
       LYAP_REQUIRE(g.K % 32 == 0, LYAP_E_INVAL, "gemm: K not padded");
       hipLaunchKernelGGL((gemm_kernel<float, 32>), grid, block, 0, s, (const float*)g.A,
                          (const float*)g.B, (float*)g.C, (int)g.M, (int)g.N, (int)g.K,
                          (long)g.lda, (long)g.ldb, (long)g.ldc, (int)g.Nstore, g.M_dev,
-                         g.m_scale);
+                         g.m_scale, (float*)g.Cpart);
       break;
     case GemmType::BF16X3:
       LYAP_REQUIRE(g.K % BK16 == 0, LYAP_E_INVAL, "gemm: K not padded");
       hipLaunchKernelGGL(gemm_bf16x3_kernel, grid, block, 0, s, (const __bf16*)g.A,
                          (long)g.a_plane, (const __bf16*)g.B, (long)g.b_plane, (float*)g.C,
                          (int)g.M, (int)g.N, (int)g.K, (long)g.lda, (long)g.ldb, (long)g.ldc,
-                         (int)g.Nstore, g.M_dev, g.m_scale);
+                         (int)g.Nstore, g.M_dev, g.m_scale, (float*)g.Cpart);
       break;
   }
   LYAP_HIP(hipGetLastError());

@@ -293,6 +293,30 @@ def random_stable(n: int, r: int, s: int, P: int, seed: int, margin: float = 0.5
     return Problem("rand%d" % n, A0, U, V, B, E, d, dict(kind="random", seed=seed))
 
 
+def near_defective(n: int, r: int, s: int, P: int, seed: int, delta: float = 1e-9) -> Problem:
+    """A seed with nearly defective eigenvalue pairs (ill-conditioned eigenbasis).
+
+    A0 = Q blockdiag(J_k) Q^T with J_k = [[-a_k, 1], [0, -a_k - delta]], a_k >= 1,
+    Q orthogonal.  sym(J_k) is negative definite for a_k >= 1, so with U = V and
+    d >= 0 every A(p) is stable.
+    """
+    assert n % 2 == 0
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(1.0, 3.0, size=n // 2)
+    J = np.zeros((n, n))
+    for k in range(n // 2):
+        J[2 * k, 2 * k] = -a[k]
+        J[2 * k, 2 * k + 1] = 1.0
+        J[2 * k + 1, 2 * k + 1] = -a[k] - delta
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A0 = Q @ J @ Q.T
+    U = rng.standard_normal((n, r))
+    B = rng.standard_normal((n, s))
+    d = rng.uniform(0.1, 2.0, size=(P, r))
+    E = rng.uniform(0.0, 1.0, size=n)
+    return Problem("neardef%d" % n, A0, U, U.copy(), B, E, d, dict(kind="near_defective", seed=seed))
+
+
 @dataclass
 class Request:
     """One sweep request of the serving mix (workload c4)."""

@@ -220,6 +220,13 @@ typedef struct {
 void lyap_profile_enable(int32_t on); /* also resets the counters */
 lyap_status lyap_profile_read(lyap_profile* out);
 
+/* Host-only real Schur decomposition used by the Schur-basis seed solve:
+ * A = Z T Z^T, Z orthogonal, T upper quasi-triangular with 2x2 blocks only for
+ * complex-conjugate pairs (Householder Hessenberg reduction + implicit
+ * double-shift QR).  A, T, Z: host n x n row-major.  No GPU is touched.
+ * Returns LYAP_E_UNSTABLE if the iteration does not converge. */
+lyap_status lyap_real_schur(int64_t n, const double* A, double* T, double* Z);
+
 /* Plain device copy of `bytes` bytes with a simple vector-load kernel; used to
  * calibrate hardware byte counters against a known traffic. */
 lyap_status lyap_calib_copy(const void* src_dev, void* dst_dev, size_t bytes, void* hip_stream);

@@ -4,4 +4,5 @@ The compute path lives in liblyapsmw.so (HIP, gfx950); ``lyapsmw`` is its
 thin ctypes binding.  Importing the package does not touch the GPU.
 """
 from .lyapsmw import (Seed, Engine, LyapError, solve_opts, load, EXPORTS,  # noqa: F401
-                      RESULT_DTYPE, PREC, BASIS, profile_enable, profile_read, calib_copy)
+                      RESULT_DTYPE, PREC, BASIS, profile_enable, profile_read, calib_copy,
+                      real_schur)

@@ -96,6 +96,33 @@ void apply_impl(lyap_seed_s* sd, long long batch, const double* Y, double* G, in
   LYAP_REQUIRE(Y && G, LYAP_E_INVAL, "NULL buffer");
   LYAP_REQUIRE(prec == LYAP_PREC_FP64, LYAP_E_UNSUPPORTED, "lyap_seed_apply: only FP64");
   const long long r = sd->r, n = sd->n, ld = sd->ld, h = sd->h;
+  if (sd->basis == LYAP_BASIS_SCHUR) {
+    // Ys = Y Z ; T Xs + Xs T^T = Us Ys + Ys^T Us^T ; G = (Vs^T Xs) Z^T
+    const long long rows1 = batch * r;
+    const size_t rowb = ld * sizeof(double);
+    const size_t need = (size_t)(3 * rows1) * rowb + (size_t)batch * ld * rowb;
+    if (sd->scratch_bytes < need) {
+      sd->scratch.alloc(need);
+      sd->scratch_bytes = need;
+    }
+    double* Yp = sd->scratch.as<double>();
+    double* Ys = Yp + rows1 * ld;
+    double* Gs = Ys + rows1 * ld;
+    double* Xs = Gs + rows1 * ld;
+    LYAP_HIP(hipMemsetAsync(Yp, 0, need, st));
+    const int ub = (int)std::min<long long>((n + 255) / 256, 64);
+    hipLaunchKernelGGL(k_pad_rows, dim3(ub, rows1), dim3(256), 0, st, Yp, (long)ld, Y, (long)n,
+                       (int)n);
+    gemm64(Yp, ld, sd->Tin.as<double>(), ld, Ys, ld, rows1, ld, ld, ld, st);
+    trilyap_launch(sd->T.as<double>(), sd->Tt.as<double>(), Xs, ld * ld, nullptr, 0,
+                   sd->Uh.as<double>(), Ys, r * ld, (int)r, (int)n, (int)ld, (int)batch, nullptr,
+                   nullptr, st);
+    project_launch(sd->Vh.as<double>(), Xs, ld * ld, Gs, r * ld, (int)r, (int)n, (int)ld,
+                   (int)batch, nullptr, nullptr, st);
+    gemm64(Gs, ld, sd->Tout.as<double>(), ld, G, n, rows1, ld, ld, n, st);
+    LYAP_HIP(hipGetLastError());
+    return;
+  }
   const long long rows1 = batch * r, rows2 = batch * r * r;
   const size_t rowb = ld * sizeof(double);
   const size_t need = (size_t)(3 * rows1 + 2 * rows2) * rowb;

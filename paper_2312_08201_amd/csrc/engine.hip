@@ -519,6 +519,23 @@ k_epilogue(EngineArgs A, const HT* H, const HT* Hp, int which, int ggrid, int gn
   }
 }
 
+// Schur basis: w = z - D out, out_s[a] = Vs_a^T Xs (projected seed solve)
+__global__ void __launch_bounds__(KT) k_epilogue_schur(EngineArgs A, const double* out) {
+  const int S = A.S, r = A.r, ld = A.ld;
+  const int cnt = A.lists[2 * S];
+  const int row = blockIdx.y;  // li * r + a
+  const int li = row / r;
+  if (li >= cnt) return;
+  const int a = row % r;
+  const int s = A.lists[li];
+  const double da = A.d[(long)s * r + a];
+  const double* zs = A.z + ((long)s * r + a) * ld;
+  const double* os = out + ((long)s * r + a) * ld;
+  double* ws = A.w + ((long)s * r + a) * ld;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < A.n; q += gridDim.x * blockDim.x)
+    ws[q] = zs[q] - da * os[q];
+}
+
 // One workgroup per slot: orthogonalisation, Givens update, restart and
 // convergence of that slot's Krylov iteration.
 __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
@@ -727,7 +744,7 @@ struct lyap_engine_s {
   long long submitted = 0;   // queue positions handed out (host mirror of tail)
   long long harvested = 0;   // queue positions whose result was returned
   long long next_tag = 0;
-  DevBuf si, sdv, d, R, g, cs, sn, V, x, z, w, Pinv, lists, X, H, Hp, Xlo, Hlo, Hplo;
+  DevBuf si, sdv, d, R, g, cs, sn, V, x, z, w, Pinv, lists, X, H, Hp, Xlo, Hlo, Hplo, XS;
   DevBuf qd, qtag, qctl, res;
   double* sol = nullptr;
   long long sol_cap = 0;
@@ -792,6 +809,7 @@ static EngineSizes engine_sizes(const lyap_seed_s* sd, long long S, const lyap_s
   add(S * r * r * ld * 8);
   add((2 * S + 2) * 4);
   add(z.rows_pad * ld * 8 * 3);  // X, H, split-K partials fp64
+  if (sd->basis == LYAP_BASIS_SCHUR) add(S * ld * ld * 8);  // per-slot Schur-basis solutions
   const bool mixed = o.prec != LYAP_PREC_FP64;
   if (mixed) {
     add(z.rows_pad * ld * 4);      // Xlo (float, or two bf16 planes)
@@ -816,6 +834,20 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
   hipLaunchKernelGGL(k_lists, dim3(1), dim3(1024), 0, st, A);
   hipLaunchKernelGGL(k_prep, dim3(S), dim3(KT), 0, st, A);
   const int ublocks = std::max(1, std::min((nu + KT - 1) / KT, 64));
+  if (sd->basis == LYAP_BASIS_SCHUR) {
+    // seed solve in the real Schur basis for every listed slot
+    const int n = (int)sd->n;
+    const int* cnt = E->lists.as<int>() + 2 * S;
+    if (ev) LYAP_HIP(hipEventRecord(ev->g64[0], st));
+    trilyap_launch(sd->T.as<double>(), sd->Tt.as<double>(), E->XS.as<double>(), (long)ld * ld,
+                   nullptr, 0, sd->Uh.as<double>(), E->z.as<double>(), (long)r * ld, r, n, ld, S,
+                   E->lists.as<int>(), cnt, st);
+    if (ev) LYAP_HIP(hipEventRecord(ev->g64[1], st));
+    project_launch(sd->Vh.as<double>(), E->XS.as<double>(), (long)ld * ld, E->H.as<double>(),
+                   (long)r * ld, r, n, ld, S, E->lists.as<int>(), cnt, st);
+    hipLaunchKernelGGL(k_epilogue_schur, dim3(ublocks, S * r), dim3(KT), 0, st, A,
+                       E->H.as<double>());
+  } else {
   // FP64 list (which = 0)
   {
     hipLaunchKernelGGL((k_formX<double>), dim3(ublocks, S * r * r), dim3(KT), 0, st, A,
@@ -870,6 +902,7 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     hipLaunchKernelGGL((k_epilogue<float>), dim3(ublocks, S * r), dim3(KT), 0, st, A,
                        E->Hlo.as<float>(), E->Hplo.as<float>(), 1, ggrid, ld / gemm_bk(E->low));
   }
+  }  // eigen basis
   if (ev) LYAP_HIP(hipEventRecord(ev->kry[0], st));
   launch_krylov(A, S, (long long)r * ld, st);
   if (ev) LYAP_HIP(hipEventRecord(ev->kry[1], st));
@@ -972,6 +1005,8 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   }
   st = E->stream;
   E->mixed = o.prec != LYAP_PREC_FP64;
+  LYAP_REQUIRE(!(E->mixed && sd->basis == LYAP_BASIS_SCHUR), LYAP_E_UNSUPPORTED,
+               "the Schur-basis seed solve runs in FP64 only");
   E->low = o.prec == LYAP_PREC_BF16_IR ? GemmType::BF16X3 : GemmType::F32;
   E->Q = (int)Q;
   const long long r = sd->r, ld = sd->ld, N = r * ld, m = o.restart;
@@ -994,6 +1029,7 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   zalloc(E->w, S * N * 8);
   zalloc(E->Pinv, S * r * r * ld * 8);
   zalloc(E->lists, (2 * S + 2) * 4);
+  if (sd->basis == LYAP_BASIS_SCHUR) zalloc(E->XS, S * ld * ld * 8);
   zalloc(E->X, z.rows_pad * ld * 8);
   zalloc(E->H, z.rows_pad * ld * 8);
   zalloc(E->Hp, z.rows_pad * ld * 8);
@@ -1026,7 +1062,7 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   A.m = (int)m;
   A.max_iter = o.max_iter;
   A.max_refine = o.max_refine;
-  A.use_precond = (o.use_precond && r <= kPrecRank) ? 1 : 0;
+  A.use_precond = (o.use_precond && r <= kPrecRank && sd->basis != LYAP_BASIS_SCHUR) ? 1 : 0;
   A.mixed = E->mixed ? 1 : 0;
   A.tol = o.tol;
   A.inner_tol = o.inner_tol;
@@ -1179,6 +1215,12 @@ static long long engine_harvest_impl(lyap_engine_s* E, long long max_out, long l
 
 
 static long long default_slots(const lyap_seed_s* sd, long long P) {
+  if (sd->basis == LYAP_BASIS_SCHUR) {
+    // one n x n solution per slot: bound the buffer by 4 GiB
+    const long long per = sd->ld * sd->ld * 8;
+    const long long S = std::max<long long>(1, std::min<long long>(512, (4LL << 30) / per));
+    return std::max<long long>(1, std::min(S, P));
+  }
   // enough rows for the Cauchy GEMM to fill the GPU, bounded by P
   const long long r = sd->r;
   long long S = std::max<long long>(64, 8192 / (r * r));

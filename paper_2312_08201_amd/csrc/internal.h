@@ -39,12 +39,14 @@ struct lyap_seed_s {
   lyap::DevBuf c0;      // r x ld: rho(V^T X0 Q0^-T)
   lyap::DevBuf gam;     // r x ld: trace(E X) = t0 + sum_b <gam_b, rho(Yhat_b)>
   lyap::DevBuf Gam;     // r x ld: physical Gamma^T (trace = t0 + 2 <Gamma^T, Y>)
+  lyap::DevBuf T, Tt;   // Schur basis only: quasi-triangular T and T^T (ld x ld)
   lyap::DevBuf scratch; // grown on demand by lyap_seed_apply / trace_EX
   size_t scratch_bytes = 0;
 
   size_t device_bytes() const {
     return lam.bytes + Mc.bytes + Mc32.bytes + Mcb.bytes + Tin.bytes + Tout.bytes + Uh.bytes +
-           Vh.bytes + K1.bytes + c0.bytes + gam.bytes + Gam.bytes + scratch.bytes;
+           Vh.bytes + K1.bytes + c0.bytes + gam.bytes + Gam.bytes + T.bytes + Tt.bytes +
+           scratch.bytes;
   }
 };
 
@@ -61,5 +63,18 @@ void contract_groups(double* out, const double* H, long ldh, const double* w, lo
 void batched_dot(double* out, const double* X, long ldx, const double* Y, long ldy, int rows_per,
                  int count, int n, double base, double scale, hipStream_t s);
 void convert_f64_f32(float* out, const double* in, long count, hipStream_t s);
+
+// ---- Schur basis (schur.hip) ----
+// T Xs + Xs T^T = C per problem; C dense (Cd, row-major) or F G^T + G F^T
+// (F: k shared rows, G: k rows per problem).  X stored column by column.
+void trilyap_launch(const double* T, const double* Tt, double* X, long xstride, const double* Cd,
+                    long cstride, const double* F, const double* G, long gstride, int k, int n,
+                    int ld, int count, const int* list, const int* count_dev, hipStream_t st);
+// out_p[a] = sum_m Vt[a][m] X_p[m][:]
+void project_launch(const double* Vt, const double* X, long xstride, double* out, long ostride,
+                    int r, int n, int ld, int count, const int* list, const int* count_dev,
+                    hipStream_t st);
+void gemm64_rm(const double* A, long lda, const double* B, long ldb, double* C, long ldc, long M,
+               long N, long K, long Nstore, hipStream_t s);
 
 }  // namespace lyap

@@ -9,6 +9,7 @@
 
 #include "internal.h"
 #include "lapack_host.h"
+#include "schur_host.h"
 
 namespace lyap {
 
@@ -239,8 +240,8 @@ void convert_f64_f32(float* out, const double* in, long count, hipStream_t s) {
   LYAP_HIP(hipGetLastError());
 }
 
-static void gemm64(const double* A, long lda, const double* B, long ldb, double* C, long ldc,
-                   long M, long N, long K, long Nstore, hipStream_t s) {
+void gemm64_rm(const double* A, long lda, const double* B, long ldb, double* C, long ldc, long M,
+               long N, long K, long Nstore, hipStream_t s) {
   GemmArgs g{};
   g.type = GemmType::F64;
   g.A = A;
@@ -257,6 +258,10 @@ static void gemm64(const double* A, long lda, const double* B, long ldb, double*
   g.m_scale = 1;
   gemm_launch(g, s);
 }
+static inline void gemm64(const double* A, long lda, const double* B, long ldb, double* C, long ldc,
+                          long M, long N, long K, long Nstore, hipStream_t s) {
+  gemm64_rm(A, lda, B, ldb, C, ldc, M, N, K, Nstore, s);
+}
 
 // ---------------------------------------------------------------------------
 // seed_factor
@@ -271,6 +276,186 @@ static void upload_rows(double* dst, long dst_ld, const double* src_host_rowmajo
                         long cols, hipStream_t s) {
   LYAP_HIP(hipMemcpy2DAsync(dst, dst_ld * sizeof(double), src_host_rowmajor, cols * sizeof(double),
                             cols * sizeof(double), rows, hipMemcpyHostToDevice, s));
+}
+
+// Schur-basis seed: A0 = Z T Z^T (host Francis QR), precompute on the device.
+static lyap_seed_s* factor_schur(int64_t n, int64_t r, int64_t s, const double* A0, const double* U,
+                                 const double* V, const double* B, const double* E, int E_diag,
+                                 double cond, hipStream_t st,
+                                 std::chrono::steady_clock::time_point t_start) {
+  LYAP_REQUIRE(n <= 4096, LYAP_E_UNSUPPORTED, "Schur-basis path limited to n <= 4096");
+  const int N = (int)n;
+  std::vector<double> Th((size_t)n * n), Zh((size_t)n * n);
+  int iters = 0;
+  LYAP_REQUIRE(real_schur(N, A0, Th.data(), Zh.data(), &iters), LYAP_E_UNSTABLE,
+               "real Schur iteration did not converge");
+  // spectrum from the diagonal blocks
+  std::vector<double> lr, li;
+  for (int i = 0; i < N;) {
+    if (i + 1 < N && Th[(size_t)(i + 1) * n + i] != 0.0) {
+      const double a = Th[(size_t)i * n + i], b = Th[(size_t)i * n + i + 1];
+      const double c = Th[(size_t)(i + 1) * n + i], d = Th[(size_t)(i + 1) * n + i + 1];
+      const double p = 0.5 * (a - d), disc = p * p + b * c;
+      const double re = 0.5 * (a + d), im = std::sqrt(std::max(0.0, -disc));
+      lr.push_back(re); li.push_back(im);
+      lr.push_back(re); li.push_back(-im);
+      i += 2;
+    } else {
+      lr.push_back(Th[(size_t)i * n + i]); li.push_back(0.0);
+      i += 1;
+    }
+  }
+  double max_re = -INFINITY, min_sum = INFINITY, max_sum = 0;
+  for (int i = 0; i < N; ++i) max_re = std::max(max_re, lr[i]);
+  for (int i = 0; i < N; ++i)
+    for (int j = i; j < N; ++j) {
+      const double a = std::hypot(lr[i] + lr[j], li[i] + li[j]);
+      min_sum = std::min(min_sum, a);
+      max_sum = std::max(max_sum, a);
+    }
+  LYAP_REQUIRE(max_re < 0, LYAP_E_UNSTABLE, "seed A0 is not stable (max Re lambda >= 0)");
+  LYAP_REQUIRE(min_sum > 1e-13 * max_sum, LYAP_E_UNSTABLE, "lambda_i + lambda_j ~ 0 for the seed");
+
+  auto* sd = new lyap_seed_s();
+  std::unique_ptr<lyap_seed_s> guard(sd);
+  const int64_t ld = pad_to(n, kPad);
+  sd->n = n; sd->r = r; sd->s = s; sd->h = 0; sd->ld = ld;
+  sd->basis = LYAP_BASIS_SCHUR;
+  sd->cond_est = cond;
+  sd->min_lam_sum = min_sum / max_sum;
+  sd->max_re = max_re;
+  sd->stream = st;
+  LYAP_HIP(hipGetDevice(&sd->device));
+  const size_t mat = (size_t)ld * ld * sizeof(double);
+  std::vector<double> Zp((size_t)ld * ld, 0.0), Ztp((size_t)ld * ld, 0.0), Tp((size_t)ld * ld, 0.0),
+      Ttp((size_t)ld * ld, 0.0);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      Zp[(size_t)i * ld + j] = Zh[(size_t)i * n + j];
+      Ztp[(size_t)j * ld + i] = Zh[(size_t)i * n + j];
+      Tp[(size_t)i * ld + j] = Th[(size_t)i * n + j];
+      Ttp[(size_t)j * ld + i] = Th[(size_t)i * n + j];
+    }
+  sd->Tin.alloc(mat);   // Z   : Ys = Y Z
+  sd->Tout.alloc(mat);  // Z^T : Y = Ys Z^T
+  sd->T.alloc(mat);
+  sd->Tt.alloc(mat);
+  LYAP_HIP(hipMemcpyAsync(sd->Tin.p, Zp.data(), mat, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(sd->Tout.p, Ztp.data(), mat, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(sd->T.p, Tp.data(), mat, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(sd->Tt.p, Ttp.data(), mat, hipMemcpyHostToDevice, st));
+
+  const size_t rowb = (size_t)ld * sizeof(double);
+  auto zeros = [&](DevBuf& b, size_t rows) {
+    b.alloc(std::max<size_t>(rows, 1) * rowb);
+    LYAP_HIP(hipMemsetAsync(b.p, 0, b.bytes, st));
+  };
+  // transposed, padded factors
+  std::vector<double> Ut((size_t)r * ld, 0.0), Vt((size_t)r * ld, 0.0), Bt((size_t)s * ld, 0.0),
+      Bm((size_t)s * ld, 0.0);
+  for (int i = 0; i < N; ++i) {
+    for (int a = 0; a < r; ++a) {
+      Ut[(size_t)a * ld + i] = U[(size_t)i * r + a];
+      Vt[(size_t)a * ld + i] = V[(size_t)i * r + a];
+    }
+    for (int c = 0; c < s; ++c) Bt[(size_t)c * ld + i] = B[(size_t)i * s + c];
+  }
+  DevBuf Utd, Vtd, Btd, Bh, Bhm;
+  zeros(Utd, r); zeros(Vtd, r); zeros(Btd, s); zeros(Bh, s); zeros(Bhm, s);
+  LYAP_HIP(hipMemcpyAsync(Utd.p, Ut.data(), Ut.size() * 8, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(Vtd.p, Vt.data(), Vt.size() * 8, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(Btd.p, Bt.data(), Bt.size() * 8, hipMemcpyHostToDevice, st));
+  zeros(sd->Uh, r);
+  zeros(sd->Vh, r);
+  // Us^T = U^T Z, Vs^T = V^T Z, Bs^T = B^T Z  (transform GEMMs)
+  gemm64(Utd.as<double>(), ld, sd->Tin.as<double>(), ld, sd->Uh.as<double>(), ld, r, ld, ld, n, st);
+  gemm64(Vtd.as<double>(), ld, sd->Tin.as<double>(), ld, sd->Vh.as<double>(), ld, r, ld, ld, n, st);
+  gemm64(Btd.as<double>(), ld, sd->Tin.as<double>(), ld, Bh.as<double>(), ld, s, ld, ld, n, st);
+  // -Bs/2 for the factored right-hand side -Bs Bs^T = Bs (-Bs/2)^T + (-Bs/2) Bs^T
+  {
+    std::vector<double> tmp((size_t)s * ld);
+    LYAP_HIP(hipMemcpyAsync(tmp.data(), Bh.p, tmp.size() * 8, hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipStreamSynchronize(st));
+    for (auto& v : tmp) v *= -0.5;
+    LYAP_HIP(hipMemcpyAsync(Bhm.p, tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice, st));
+  }
+  // Xs0: T Xs0 + Xs0 T^T = -Bs Bs^T
+  DevBuf X0s(mat);
+  LYAP_HIP(hipMemsetAsync(X0s.p, 0, mat, st));
+  trilyap_launch(sd->T.as<double>(), sd->Tt.as<double>(), X0s.as<double>(), 0, nullptr, 0,
+                 Bh.as<double>(), Bhm.as<double>(), 0, (int)s, N, (int)ld, 1, nullptr, nullptr, st);
+  zeros(sd->c0, r);
+  project_launch(sd->Vh.as<double>(), X0s.as<double>(), 0, sd->c0.as<double>(), 0, (int)r, N,
+                 (int)ld, 1, nullptr, nullptr, st);
+  // Es = Z^T E_sym Z
+  std::vector<double> Eh((size_t)ld * ld, 0.0);
+  for (int i = 0; i < N; ++i) {
+    if (E_diag) Eh[(size_t)i * ld + i] = E[i];
+    else
+      for (int j = 0; j < N; ++j)
+        Eh[(size_t)i * ld + j] = 0.5 * (E[(size_t)i * n + j] + E[(size_t)j * n + i]);
+  }
+  DevBuf Ed(mat), EZ(mat), Es(mat);
+  LYAP_HIP(hipMemcpyAsync(Ed.p, Eh.data(), mat, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemsetAsync(EZ.p, 0, mat, st));
+  LYAP_HIP(hipMemsetAsync(Es.p, 0, mat, st));
+  gemm64(Ed.as<double>(), ld, sd->Tin.as<double>(), ld, EZ.as<double>(), ld, n, ld, ld, n, st);
+  gemm64(sd->Tout.as<double>(), ld, EZ.as<double>(), ld, Es.as<double>(), ld, n, ld, ld, n, st);
+  // t0 = trace(Es Xs0) (both symmetric)
+  double t0 = 0.0;
+  {
+    DevBuf tdev(sizeof(double));
+    batched_dot(tdev.as<double>(), X0s.as<double>(), ld, Es.as<double>(), ld, N, 1, N, 0.0, 1.0, st);
+    LYAP_HIP(hipMemcpyAsync(&t0, tdev.p, sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  // adjoint: T^T Gs + Gs T = Es, solved as the flipped upper problem
+  // T' = J T^T J, C' = J Es J, Gs = J G' J.
+  std::vector<double> Esh((size_t)ld * ld);
+  LYAP_HIP(hipMemcpyAsync(Esh.data(), Es.p, mat, hipMemcpyDeviceToHost, st));
+  LYAP_HIP(hipStreamSynchronize(st));
+  std::vector<double> Tf((size_t)ld * ld, 0.0), Tft((size_t)ld * ld, 0.0), Cf((size_t)ld * ld, 0.0);
+  for (int i = 0; i < N; ++i)
+    for (int k2 = 0; k2 < N; ++k2) {
+      const double v = Th[(size_t)(N - 1 - k2) * n + (N - 1 - i)];  // (J T^T J)[i][k]
+      Tf[(size_t)i * ld + k2] = v;
+      Tft[(size_t)k2 * ld + i] = v;
+      Cf[(size_t)i * ld + k2] = Esh[(size_t)(N - 1 - i) * ld + (N - 1 - k2)];
+    }
+  DevBuf Tfd(mat), Tftd(mat), Cfd(mat), Gf(mat);
+  LYAP_HIP(hipMemcpyAsync(Tfd.p, Tf.data(), mat, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(Tftd.p, Tft.data(), mat, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(Cfd.p, Cf.data(), mat, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemsetAsync(Gf.p, 0, mat, st));
+  trilyap_launch(Tfd.as<double>(), Tftd.as<double>(), Gf.as<double>(), 0, Cfd.as<double>(), 0, nullptr,
+                 nullptr, 0, 0, N, (int)ld, 1, nullptr, nullptr, st);
+  std::vector<double> Gfh((size_t)ld * ld), Gsh((size_t)ld * ld, 0.0);
+  LYAP_HIP(hipMemcpyAsync(Gfh.data(), Gf.p, mat, hipMemcpyDeviceToHost, st));
+  LYAP_HIP(hipStreamSynchronize(st));
+  // Gf stored by columns: column j = Gf[j*ld + i] = G'[i][j]; Gs[i][j] = G'[n-1-i][n-1-j]
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) Gsh[(size_t)i * ld + j] = Gfh[(size_t)(N - 1 - j) * ld + (N - 1 - i)];
+  DevBuf Gsd(mat);
+  LYAP_HIP(hipMemcpyAsync(Gsd.p, Gsh.data(), mat, hipMemcpyHostToDevice, st));
+  // Gamma_s^T = Us^T Gs (Gs symmetric); trace weights 2 Gamma_s^T; physical Gamma^T = Gamma_s^T Z^T
+  DevBuf Gms;
+  zeros(Gms, r);
+  gemm64(sd->Uh.as<double>(), ld, Gsd.as<double>(), ld, Gms.as<double>(), ld, r, ld, ld, n, st);
+  zeros(sd->Gam, r);
+  gemm64(Gms.as<double>(), ld, sd->Tout.as<double>(), ld, sd->Gam.as<double>(), ld, r, ld, ld, n, st);
+  {
+    std::vector<double> g((size_t)r * ld);
+    LYAP_HIP(hipMemcpyAsync(g.data(), Gms.p, g.size() * 8, hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipStreamSynchronize(st));
+    for (auto& v : g) v *= 2.0;
+    zeros(sd->gam, r);
+    LYAP_HIP(hipMemcpyAsync(sd->gam.p, g.data(), g.size() * 8, hipMemcpyHostToDevice, st));
+  }
+  LYAP_HIP(hipStreamSynchronize(st));
+  sd->t0 = t0;
+  sd->factor_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  guard.release();
+  return sd;
 }
 
 static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A0, const double* U,
@@ -290,7 +475,7 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
   check_finite(B, (size_t)n * s, "B");
   check_finite(E, E_diag ? (size_t)n : (size_t)n * n, "E");
   if (basis_req == LYAP_BASIS_SCHUR)
-    throw Error{LYAP_E_UNSUPPORTED, "the Schur-basis seed solve is not available in this build"};
+    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, 0.0, stream, t_start);
 
   const LapackFns& L = lapack();
   LYAP_REQUIRE(L.dgeev && L.dgetrf && L.dgetrs, LYAP_E_UNSUPPORTED,
@@ -311,7 +496,10 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
   std::vector<double> work(lwork);
   L.dgeev("N", "V", &N, Acm.data(), &N, wr.data(), wi.data(), nullptr, &one, VR.data(), &N,
           work.data(), &lwork, &info);
-  LYAP_REQUIRE(info == 0, LYAP_E_UNSTABLE, "dgeev failed to converge");
+  if (info != 0) {
+    LYAP_REQUIRE(basis_req == LYAP_BASIS_AUTO, LYAP_E_UNSTABLE, "dgeev failed to converge");
+    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, INFINITY, stream, t_start);
+  }
 
   // order: conjugate pairs first (Re, Im columns), then real eigenvalues
   std::vector<int> pairs, reals;
@@ -356,7 +544,11 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
   std::vector<double> LU(Scm), Sinv_cm((size_t)n * n, 0.0);
   std::vector<int> ipiv(n);
   L.dgetrf(&N, &N, LU.data(), &N, ipiv.data(), &info);
-  LYAP_REQUIRE(info == 0, LYAP_E_UNSTABLE, "eigenvector matrix is singular (defective seed)");
+  if (info != 0) {
+    LYAP_REQUIRE(basis_req == LYAP_BASIS_AUTO, LYAP_E_UNSTABLE,
+                 "eigenvector matrix is singular (defective seed)");
+    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, INFINITY, stream, t_start);
+  }
   for (int i = 0; i < N; ++i) Sinv_cm[(size_t)i * n + i] = 1.0;
   L.dgetrs("N", &N, &N, LU.data(), &N, ipiv.data(), Sinv_cm.data(), &N, &info);
   LYAP_REQUIRE(info == 0, LYAP_E_UNSTABLE, "dgetrs failed");
@@ -371,9 +563,7 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
   };
   const double cond = norm1(Scm) * norm1(Sinv_cm);
   if (basis_req == LYAP_BASIS_AUTO && !(cond <= max_cond))
-    throw Error{LYAP_E_UNSUPPORTED,
-                "eigenbasis condition " + std::to_string(cond) +
-                    " exceeds max_eig_cond and the Schur-basis path is not available"};
+    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, cond, stream, t_start);
 
   auto* sd = new lyap_seed_s();
   std::unique_ptr<lyap_seed_s> guard(sd);
@@ -656,6 +846,14 @@ const char* lyap_status_string(lyap_status s) {
     case LYAP_E_NONFINITE: return "non-finite value";
   }
   return "unknown status";
+}
+
+lyap_status lyap_real_schur(int64_t n, const double* A, double* T, double* Z) {
+  if (n < 1 || n > 16384 || !A || !T || !Z) return LYAP_E_INVAL;
+  LYAP_TRY({
+    if (!real_schur((int)n, A, T, Z, nullptr)) return LYAP_E_UNSTABLE;
+  });
+  return LYAP_OK;
 }
 
 const char* lyap_last_error(void) {

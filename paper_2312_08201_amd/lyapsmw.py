@@ -73,7 +73,7 @@ EXPORTS = ["seed_factor", "seed_info", "seed_release", "seed_device_bytes", "lya
            "smw_workspace_bytes", "smw_solve_batch", "trace_EX", "engine_create",
            "engine_device_bytes", "engine_destroy", "engine_submit", "engine_run",
            "engine_harvest", "lyap_status_string", "lyap_last_error", "lyap_profile_enable",
-           "lyap_profile_read", "lyap_calib_copy"]
+           "lyap_profile_read", "lyap_calib_copy", "lyap_real_schur"]
 
 
 def load(path: str = LIB_PATH):
@@ -112,6 +112,8 @@ def load(path: str = LIB_PATH):
     lib.lyap_profile_enable.restype = None
     lib.lyap_profile_read.argtypes = [C.POINTER(Profile)]
     lib.lyap_calib_copy.argtypes = [vp, vp, C.c_size_t, vp]
+    lib.lyap_real_schur.argtypes = [i64, vp, vp, vp]
+    lib.lyap_real_schur.restype = C.c_int
     lib.lyap_last_error.argtypes = []
     lib.lyap_last_error.restype = C.c_char_p
     for name in ("seed_factor", "seed_info", "seed_release", "lyap_seed_apply", "smw_solve_batch",
@@ -337,3 +339,13 @@ def calib_copy(src, dst, stream=None):
         raise ValueError("size mismatch")
     _check(load().lyap_calib_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes,
                                   _stream(stream)), "lyap_calib_copy")
+
+
+def real_schur(A):
+    """Host real Schur form of the library (A = Z T Z^T); no GPU needed."""
+    A = _host(A)
+    n = A.shape[0]
+    T = np.zeros((n, n))
+    Z = np.zeros((n, n))
+    _check(load().lyap_real_schur(n, A.ctypes.data, T.ctypes.data, Z.ctypes.data), "lyap_real_schur")
+    return T, Z

@@ -211,3 +211,51 @@ def test_engine_alone_vs_mixed():
         assert abs(got[i] - t) <= 1e-12 * abs(t)
     ref = oracle_traces(pr, [0, 5, 17])
     assert np.max(rel([got[0], got[5], got[17]], ref)) <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Schur-basis fallback
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("maker", [
+    lambda: W.small_chain(30, (5, 17), 3, 5),
+    lambda: W.random_stable(40, 2, 3, 4, 8),
+    lambda: W.small_multiagent(25, 2, 3, 4),
+])
+def test_schur_basis_forced(maker):
+    L, torch = lib()
+    pr = maker()
+    seed = L.Seed.from_problem(pr, basis="schur")
+    assert seed.info()["basis"] == 2
+    d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
+    Y, res = seed.solve(d, L.solve_opts(max_iter=2000))
+    tr = seed.trace(Y).cpu().numpy()
+    assert np.all(res["status"] == 0), res
+    ref = oracle_traces(pr)
+    assert np.max(rel(tr, ref)) <= 1e-10
+    assert np.max(rel(res["trace"], ref)) <= 1e-10
+    Yc = Y.cpu().numpy()
+    for i in range(pr.P):
+        X = oracle_X(pr, i)
+        Yref = pr.d[i][:, None] * (pr.V.T @ X)
+        assert np.linalg.norm(Yc[i] - Yref) <= 1e-9 * np.linalg.norm(Yref)
+    # the stand-alone seed solve in the Schur basis
+    Yb = np.random.default_rng(2).standard_normal((2, pr.r, pr.n))
+    G = seed.apply(torch.tensor(Yb, device="cuda")).cpu().numpy()
+    for q in range(2):
+        X, _ = O.lyapunov_bs(pr.A0, pr.U @ Yb[q] + Yb[q].T @ pr.U.T)
+        Gref = pr.V.T @ X.real
+        assert np.linalg.norm(G[q] - Gref) <= 1e-11 * np.linalg.norm(Gref)
+
+
+def test_schur_basis_auto_for_near_defective_seed():
+    """An ill-conditioned eigenbasis switches the seed to the Schur basis by itself."""
+    L, torch = lib()
+    pr = W.near_defective(40, 2, 3, 5, 1)
+    seed = L.Seed.from_problem(pr)
+    info = seed.info()
+    assert info["basis"] == 2 and info["cond_est"] > 1e6
+    d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
+    Y, res = seed.solve(d, L.solve_opts(max_iter=2000))
+    tr = seed.trace(Y).cpu().numpy()
+    assert np.all(res["status"] == 0)
+    assert np.max(rel(tr, oracle_traces(pr))) <= 1e-10

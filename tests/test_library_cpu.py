@@ -46,3 +46,26 @@ def test_binding_refuses_without_gpu():
     pr = W.small_chain(10, (3,), 2, 2)
     with pytest.raises(RuntimeError):
         L.Seed.from_problem(pr)
+
+
+@pytest.mark.parametrize("n,seed", [(7, 0), (40, 1), (150, 2)])
+def test_host_real_schur_matches_definition(n, seed):
+    """The library's Francis QR: A = Z T Z^T, Z orthogonal, standard quasi-triangular T,
+    eigenvalues equal to LAPACK's."""
+    import numpy as np
+    import paper_2312_08201_amd as L
+    from gen import workloads as W
+    A = W.random_stable(n, 1, 1, 1, seed).A0
+    T, Z = L.real_schur(A)
+    assert np.linalg.norm(Z @ T @ Z.T - A) <= 1e-13 * np.linalg.norm(A)
+    assert np.linalg.norm(Z.T @ Z - np.eye(n)) <= 1e-13 * n
+    assert np.all(np.tril(T, -2) == 0)
+    for i in range(n - 1):
+        if T[i + 1, i] != 0:  # 2x2 block: complex pair, not followed by another subdiagonal
+            assert i + 2 >= n or T[i + 2, i + 1] == 0
+            a, b, c, d = T[i, i], T[i, i + 1], T[i + 1, i], T[i + 1, i + 1]
+            assert (0.5 * (a - d)) ** 2 + b * c < 0
+    ev = np.linalg.eigvals(T)
+    ref = np.linalg.eigvals(A)
+    key = lambda z: (round(z.real, 8), round(z.imag, 8))
+    assert np.allclose(sorted(ev, key=key), sorted(ref, key=key), atol=1e-10)

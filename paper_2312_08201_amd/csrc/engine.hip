@@ -57,6 +57,7 @@ struct EngineArgs {
   const double* gam;
   double t0;
   int n, h, ld, r;
+  int NV;  // per-slot vector stride: r * ld padded to a multiple of 512
   // engine
   int S, m, max_iter, max_refine, use_precond, mixed;
   double tol, inner_tol;
@@ -237,7 +238,7 @@ __device__ inline void block_inverse(const EngineArgs& A, const double* dsh, int
 // Admission of queue entry qp into slot s (whole workgroup): preconditioner
 // blocks (I - D K1_j)^-1, right-hand side b = D c0, v0 = b / ||b||.
 __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
-  const int r = A.r, ld = A.ld, N = r * ld, nu = A.n - A.h;
+  const int r = A.r, ld = A.ld, N = r * ld, NV = A.NV, nu = A.n - A.h;
   int* si = A.si + (long)s * SI_N;
   double* sdv = A.sdv + (long)s * SD_N;
   const int qi = qp % A.Q;
@@ -253,9 +254,9 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
     if (!isfinite(v)) atomicOr(&bad, 1);
   }
   __syncthreads();
-  double* xs = A.x + (long)s * N;
-  double* V0 = A.V + (long)s * (A.m + 1) * N;
-  for (int e = threadIdx.x; e < N; e += blockDim.x) xs[e] = 0.0;
+  double* xs = A.x + (long)s * NV;
+  double* V0 = A.V + (long)s * (A.m + 1) * NV;
+  for (int e = threadIdx.x; e < NV; e += blockDim.x) xs[e] = 0.0;
   if (bad) {
     if (threadIdx.x == 0) {
       DevResult& o = A.res[qi];
@@ -343,7 +344,7 @@ __device__ inline int claim(const EngineArgs& A) {
 __device__ void finish(const EngineArgs& A, int s, int status, double relres, double* lds) {
   const int r = A.r, ld = A.ld, N = r * ld;
   int* si = A.si + (long)s * SI_N;
-  const double* xs = A.x + (long)s * N;
+  const double* xs = A.x + (long)s * A.NV;
   double acc = 0;
   for (int e = threadIdx.x; e < N; e += blockDim.x) acc += A.gam[e] * xs[e];
   const double tr = A.t0 + block_sum1(acc, lds);
@@ -422,13 +423,13 @@ __global__ void __launch_bounds__(KT) k_prep(EngineArgs A) {
   else return;
   const int N = A.r * A.ld;
   const int ph = A.si[(long)s * SI_N + SI_PHASE];
-  double* zs = A.z + (long)s * N;
+  double* zs = A.z + (long)s * A.NV;
   if (ph == PH_RESTART) {
-    const double* xs = A.x + (long)s * N;
+    const double* xs = A.x + (long)s * A.NV;
     for (int e = threadIdx.x; e < N; e += blockDim.x) zs[e] = xs[e];
   } else {
     const int j = A.si[(long)s * SI_N + SI_J];
-    const double* vj = A.V + ((long)s * (A.m + 1) + j) * N;
+    const double* vj = A.V + ((long)s * (A.m + 1) + j) * A.NV;
     if (A.use_precond) apply_pinv(A, s, vj, zs, false);
     else
       for (int e = threadIdx.x; e < N; e += blockDim.x) zs[e] = vj[e];
@@ -456,7 +457,7 @@ __global__ void __launch_bounds__(KT) k_formX(EngineArgs A, T* X, long plane, in
   const int a = (row / r) % r, b = row % r;
   const int s = A.lists[which * S + li];
   const double* va = A.Vh + (long)a * ld;
-  const double* zb = A.z + ((long)s * r + b) * ld;
+  const double* zb = A.z + (long)s * A.NV + (long)b * ld;
   const long base = (long)row * ld;
   const int nu = A.n - h;
   for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x) {
@@ -487,8 +488,8 @@ k_epilogue(EngineArgs A, const HT* H, const HT* Hp, int which, int ggrid, int gn
   const int KS = splitk_of(mta, ld / kGemmBN, ggrid, gnk);
   const long kstride = (long)mta * kGemmBM * ld;
   const HT* Hsrc = KS > 1 ? Hp : H;
-  const double* zs = A.z + (long)s * r * ld;
-  double* ws = A.w + ((long)s * r + a) * ld;
+  const double* zs = A.z + (long)s * A.NV;
+  double* ws = A.w + (long)s * A.NV + (long)a * ld;
   const double da = A.d[(long)s * r + a];
   const int nu = A.n - h;
   for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x) {
@@ -529,45 +530,62 @@ __global__ void __launch_bounds__(KT) k_epilogue_schur(EngineArgs A, const doubl
   const int a = row % r;
   const int s = A.lists[li];
   const double da = A.d[(long)s * r + a];
-  const double* zs = A.z + ((long)s * r + a) * ld;
+  const double* zs = A.z + (long)s * A.NV + (long)a * ld;
   const double* os = out + ((long)s * r + a) * ld;
-  double* ws = A.w + ((long)s * r + a) * ld;
+  double* ws = A.w + (long)s * A.NV + (long)a * ld;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < A.n; q += gridDim.x * blockDim.x)
     ws[q] = zs[q] - da * os[q];
 }
 
 // One workgroup per slot: orthogonalisation, Givens update, restart and
-// convergence of that slot's Krylov iteration.
+// convergence of that slot's Krylov iteration.  The slot's new vector w lives
+// in registers as NE2 double2 per thread (element pair e2 = tid + KT * i of
+// the padded slot vector, NV = 2 * KT * NE2), so each sweep over the basis
+// streams every basis vector once with independent 16-byte loads; all dot
+// products of a pass are reduced with a single barrier.
+template <int NE2>
 __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
+  __shared__ double part[4][kMaxRestart + 2];
   __shared__ double lds[4 * 9];
   __shared__ double ycoef[kMaxRestart + 1];
   __shared__ double hcol[kMaxRestart + 2];
   __shared__ int next_phase;
   const int s = blockIdx.x;
-  const int r = A.r, ld = A.ld, N = r * ld, m = A.m;
+  const int r = A.r, ld = A.ld, N = r * ld, NV = A.NV, m = A.m;
   int* si = A.si + (long)s * SI_N;
   double* sdv = A.sdv + (long)s * SD_N;
   const int ph = si[SI_PHASE];
   if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
 
-  double* Vs = A.V + (long)s * (m + 1) * N;
-  double* ws = A.w + (long)s * N;
-  double* xs = A.x + (long)s * N;
+  double* Vs = A.V + (long)s * (m + 1) * NV;
+  double* ws = A.w + (long)s * NV;
+  double* xs = A.x + (long)s * NV;
   double* gs = A.g + (long)s * (m + 1);
   double* Rs = A.R + (long)s * m * (m + 1);
   double* css = A.cs + (long)s * m;
   double* sns = A.sn + (long)s * m;
   const double bn = sdv[SD_BNORM];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  double2 w2[NE2];
+  {
+    const double2* src = reinterpret_cast<const double2*>(ws);
+#pragma unroll
+    for (int i = 0; i < NE2; ++i) w2[i] = src[tid + KT * i];
+  }
 
   if (ph == PH_RESTART) {
     // w = A y ; residual r = D c0 - w into V0
     const double* d = A.d + (long)s * r;
     double acc = 0;
-    for (int e = tid; e < N; e += blockDim.x) {
-      const double v = d[e / ld] * A.c0[e] - ws[e];
-      Vs[e] = v;
-      acc += v * v;
+#pragma unroll
+    for (int i = 0; i < NE2; ++i) {
+      const int e = 2 * (tid + KT * i);
+      const double r0 = e < N ? d[e / ld] * A.c0[e] - w2[i].x : 0.0;
+      const double r1 = e + 1 < N ? d[(e + 1) / ld] * A.c0[e + 1] - w2[i].y : 0.0;
+      w2[i].x = r0;
+      w2[i].y = r1;
+      acc += r0 * r0 + r1 * r1;
     }
     const double rn = sqrt(block_sum1(acc, lds));
     const double rel = rn / bn;
@@ -584,7 +602,9 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
       finish(A, s, LYAP_E_NOCONV, rel, lds);
     } else {
       const double inv = 1.0 / rn;
-      for (int e = tid; e < N; e += blockDim.x) Vs[e] *= inv;
+      double2* dst = reinterpret_cast<double2*>(Vs);
+#pragma unroll
+      for (int i = 0; i < NE2; ++i) dst[tid + KT * i] = make_double2(w2[i].x * inv, w2[i].y * inv);
       if (tid == 0) {
         gs[0] = rn;
         sdv[SD_BETA] = rn;
@@ -601,50 +621,91 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
   // ---- Arnoldi step j: w = A P^-1 v_j ----
   // Classical Gram-Schmidt with the Daniel-Gragg-Kaufman-Stewart criterion:
   // a second pass only when the first one cancelled more than 1/sqrt(2) of
-  // ||w||.  Each pass = one sweep for the dots (and ||w||^2), one sweep for the
-  // update (and the new ||w||^2).
+  // ||w||.  Each pass = one sweep for the dots, one for the update (+ norm).
   const int j = si[SI_J];
   if (tid < kMaxRestart + 2) hcol[tid] = 0.0;
-  __syncthreads();
   double wn2 = 0.0, hn = 0.0;
   for (int pass = 0; pass < 2; ++pass) {
-    for (int k0 = 0; k0 <= j; k0 += 8) {
-      double acc[9];
+    // dots h_k = <v_k, w>, k <= j, and ||w||^2 (first pass)
+    double ww = 0.0;
+    if (pass == 0) {
 #pragma unroll
-      for (int t = 0; t < 9; ++t) acc[t] = 0.0;
-      const int kc = min(8, j + 1 - k0);
-      for (int e = tid; e < N; e += blockDim.x) {
-        const double we = ws[e];
+      for (int i = 0; i < NE2; ++i) ww += w2[i].x * w2[i].x + w2[i].y * w2[i].y;
+    }
+    int k = 0;
+    for (; k + 4 <= j + 1; k += 4) {
+      double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+      const double2* v0 = reinterpret_cast<const double2*>(Vs + (long)k * NV);
+      const double2* v1 = reinterpret_cast<const double2*>(Vs + (long)(k + 1) * NV);
+      const double2* v2 = reinterpret_cast<const double2*>(Vs + (long)(k + 2) * NV);
+      const double2* v3 = reinterpret_cast<const double2*>(Vs + (long)(k + 3) * NV);
 #pragma unroll
-        for (int t = 0; t < 8; ++t)
-          if (t < kc) acc[t] += Vs[(long)(k0 + t) * N + e] * we;
-        if (k0 == 0 && pass == 0) acc[8] += we * we;
+      for (int i = 0; i < NE2; ++i) {
+        const int e = tid + KT * i;
+        const double2 x0 = v0[e], x1 = v1[e], x2 = v2[e], x3 = v3[e];
+        a0 += x0.x * w2[i].x + x0.y * w2[i].y;
+        a1 += x1.x * w2[i].x + x1.y * w2[i].y;
+        a2 += x2.x * w2[i].x + x2.y * w2[i].y;
+        a3 += x3.x * w2[i].x + x3.y * w2[i].y;
       }
-      block_sum<9>(acc, lds);
-      if (k0 == 0 && pass == 0) wn2 = acc[8];
-      if (tid == 0)
-        for (int t = 0; t < kc; ++t) {
-          hcol[k0 + t] += acc[t];
-          ycoef[k0 + t] = acc[t];
-        }
-      __syncthreads();
+      a0 = wave_sum(a0);
+      a1 = wave_sum(a1);
+      a2 = wave_sum(a2);
+      a3 = wave_sum(a3);
+      if (lane == 0) {
+        part[wave][k] = a0;
+        part[wave][k + 1] = a1;
+        part[wave][k + 2] = a2;
+        part[wave][k + 3] = a3;
+      }
+    }
+    for (; k <= j; ++k) {
+      double a0 = 0;
+      const double2* v0 = reinterpret_cast<const double2*>(Vs + (long)k * NV);
+#pragma unroll
+      for (int i = 0; i < NE2; ++i) {
+        const double2 x0 = v0[tid + KT * i];
+        a0 += x0.x * w2[i].x + x0.y * w2[i].y;
+      }
+      a0 = wave_sum(a0);
+      if (lane == 0) part[wave][k] = a0;
+    }
+    ww = wave_sum(ww);
+    if (lane == 0) part[wave][kMaxRestart + 1] = ww;
+    __syncthreads();
+    if (tid <= j) {
+      const double h = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
+      ycoef[tid] = h;
+      hcol[tid] += h;
+    }
+    if (pass == 0)
+      wn2 = part[0][kMaxRestart + 1] + part[1][kMaxRestart + 1] + part[2][kMaxRestart + 1] +
+            part[3][kMaxRestart + 1];
+    __syncthreads();
+    // update w -= sum_k h_k v_k and the new ||w||^2
+    for (int kk = 0; kk <= j; ++kk) {
+      const double c = ycoef[kk];
+      const double2* v0 = reinterpret_cast<const double2*>(Vs + (long)kk * NV);
+#pragma unroll
+      for (int i = 0; i < NE2; ++i) {
+        const double2 x0 = v0[tid + KT * i];
+        w2[i].x -= c * x0.x;
+        w2[i].y -= c * x0.y;
+      }
     }
     double nn = 0.0;
-    for (int e = tid; e < N; e += blockDim.x) {
-      double we = ws[e];
-      for (int k = 0; k <= j; ++k) we -= ycoef[k] * Vs[(long)k * N + e];
-      ws[e] = we;
-      nn += we * we;
-    }
+#pragma unroll
+    for (int i = 0; i < NE2; ++i) nn += w2[i].x * w2[i].x + w2[i].y * w2[i].y;
     nn = block_sum1(nn, lds);
     hn = sqrt(nn);
     if (!(nn < 0.5 * wn2)) break;  // no severe cancellation: one pass is enough
     wn2 = nn;
   }
-  double* vnext = Vs + (long)(j + 1) * N;
   if (hn > 0) {
     const double inv = 1.0 / hn;
-    for (int e = tid; e < N; e += blockDim.x) vnext[e] = ws[e] * inv;
+    double2* dst = reinterpret_cast<double2*>(Vs + (long)(j + 1) * NV);
+#pragma unroll
+    for (int i = 0; i < NE2; ++i) dst[tid + KT * i] = make_double2(w2[i].x * inv, w2[i].y * inv);
   }
   if (tid == 0) {
     hcol[j + 1] = hn;
@@ -695,23 +756,57 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
   if (next_phase == PH_RESTART) {
     const int jn = j + 1;
     // u = V y (into w), x += P^-1 u
-    for (int e = tid; e < N; e += blockDim.x) {
-      double u = 0;
-      for (int k = 0; k < jn; ++k) u += ycoef[k] * Vs[(long)k * N + e];
-      ws[e] = u;
+#pragma unroll
+    for (int i = 0; i < NE2; ++i) w2[i] = make_double2(0.0, 0.0);
+    for (int kk = 0; kk < jn; ++kk) {
+      const double c = ycoef[kk];
+      const double2* v0 = reinterpret_cast<const double2*>(Vs + (long)kk * NV);
+#pragma unroll
+      for (int i = 0; i < NE2; ++i) {
+        const double2 x0 = v0[tid + KT * i];
+        w2[i].x += c * x0.x;
+        w2[i].y += c * x0.y;
+      }
     }
+    double2* wd = reinterpret_cast<double2*>(ws);
+#pragma unroll
+    for (int i = 0; i < NE2; ++i) wd[tid + KT * i] = w2[i];
     __syncthreads();
     if (A.use_precond) apply_pinv(A, s, ws, xs, true);
     else
-      for (int e = tid; e < N; e += blockDim.x) xs[e] += ws[e];
+      for (int e = tid; e < NV; e += blockDim.x) xs[e] += ws[e];
     __syncthreads();
     if (tid == 0) si[SI_PHASE] = PH_RESTART;
   }
 }
 
-static void launch_krylov(const EngineArgs& A, int S, long long N, hipStream_t st) {
-  (void)N;
-  hipLaunchKernelGGL(k_krylov, dim3(S), dim3(KT), 0, st, A);
+// Per-slot vector stride: r * ld rounded up to 512 * NE2 with NE2 one of the
+// Krylov kernel's instantiations.
+static const int kNE2[] = {1, 2, 3, 4, 5, 6, 7, 8, 12, 16, 24, 32};
+static long long slot_stride(long long r, long long ld) {
+  const long long need = (r * ld + 511) / 512;
+  for (int v : kNE2)
+    if (need <= v) return 512LL * v;
+  throw Error{LYAP_E_INVAL, "r * n too large for the Krylov kernel (r * ld <= 16384)"};
+}
+
+// elements-per-thread bound of the Krylov kernel: NV = 512 * NE2
+static void launch_krylov(const EngineArgs& A, int S, long long NV, hipStream_t st) {
+  switch (NV / 512) {
+    case 1: hipLaunchKernelGGL(k_krylov<1>, dim3(S), dim3(KT), 0, st, A); break;
+    case 2: hipLaunchKernelGGL(k_krylov<2>, dim3(S), dim3(KT), 0, st, A); break;
+    case 3: hipLaunchKernelGGL(k_krylov<3>, dim3(S), dim3(KT), 0, st, A); break;
+    case 4: hipLaunchKernelGGL(k_krylov<4>, dim3(S), dim3(KT), 0, st, A); break;
+    case 5: hipLaunchKernelGGL(k_krylov<5>, dim3(S), dim3(KT), 0, st, A); break;
+    case 6: hipLaunchKernelGGL(k_krylov<6>, dim3(S), dim3(KT), 0, st, A); break;
+    case 7: hipLaunchKernelGGL(k_krylov<7>, dim3(S), dim3(KT), 0, st, A); break;
+    case 8: hipLaunchKernelGGL(k_krylov<8>, dim3(S), dim3(KT), 0, st, A); break;
+    case 12: hipLaunchKernelGGL(k_krylov<12>, dim3(S), dim3(KT), 0, st, A); break;
+    case 16: hipLaunchKernelGGL(k_krylov<16>, dim3(S), dim3(KT), 0, st, A); break;
+    case 24: hipLaunchKernelGGL(k_krylov<24>, dim3(S), dim3(KT), 0, st, A); break;
+    case 32: hipLaunchKernelGGL(k_krylov<32>, dim3(S), dim3(KT), 0, st, A); break;
+    default: throw Error{LYAP_E_INVAL, "unsupported r * n for the Krylov kernel"};
+  }
 }
 
 // Admission: every free slot takes the next queued parameter (device-side
@@ -795,7 +890,7 @@ struct EngineSizes {
 static EngineSizes engine_sizes(const lyap_seed_s* sd, long long S, const lyap_solve_opts& o,
                                 long long Q) {
   EngineSizes z;
-  const long long r = sd->r, ld = sd->ld, N = r * ld, m = o.restart;
+  const long long r = sd->r, ld = sd->ld, N = slot_stride(r, ld), m = o.restart;
   z.rows_pad = pad_to(S * r * r, 128);
   auto add = [&](size_t b) { z.total += (b + 255) / 256 * 256; };
   add(S * SI_N * 4);
@@ -840,7 +935,7 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     const int* cnt = E->lists.as<int>() + 2 * S;
     if (ev) LYAP_HIP(hipEventRecord(ev->g64[0], st));
     trilyap_launch(sd->T.as<double>(), sd->Tt.as<double>(), E->XS.as<double>(), (long)ld * ld,
-                   nullptr, 0, sd->Uh.as<double>(), E->z.as<double>(), (long)r * ld, r, n, ld, S,
+                   nullptr, 0, sd->Uh.as<double>(), E->z.as<double>(), (long)E->args.NV, r, n, ld, S,
                    E->lists.as<int>(), cnt, st);
     if (ev) LYAP_HIP(hipEventRecord(ev->g64[1], st));
     project_launch(sd->Vh.as<double>(), E->XS.as<double>(), (long)ld * ld, E->H.as<double>(),
@@ -904,7 +999,7 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
   }
   }  // eigen basis
   if (ev) LYAP_HIP(hipEventRecord(ev->kry[0], st));
-  launch_krylov(A, S, (long long)r * ld, st);
+  launch_krylov(A, S, (long long)A.NV, st);
   if (ev) LYAP_HIP(hipEventRecord(ev->kry[1], st));
   hipLaunchKernelGGL(k_admit, dim3(S), dim3(KT), 0, st, A);
   LYAP_HIP(hipGetLastError());
@@ -1009,7 +1104,7 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
                "the Schur-basis seed solve runs in FP64 only");
   E->low = o.prec == LYAP_PREC_BF16_IR ? GemmType::BF16X3 : GemmType::F32;
   E->Q = (int)Q;
-  const long long r = sd->r, ld = sd->ld, N = r * ld, m = o.restart;
+  const long long r = sd->r, ld = sd->ld, N = slot_stride(r, ld), m = o.restart;
   EngineSizes z = engine_sizes(sd, S, o, Q);
   E->rows_pad = z.rows_pad;
   auto zalloc = [&](DevBuf& b, size_t bytes) {
@@ -1058,6 +1153,7 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   A.h = (int)sd->h;
   A.ld = (int)ld;
   A.r = (int)r;
+  A.NV = (int)N;
   A.S = (int)S;
   A.m = (int)m;
   A.max_iter = o.max_iter;

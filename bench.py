@@ -37,6 +37,32 @@ WORKLOAD = {
 }
 
 
+def stored_traffic(config, prec):
+    """HBM bytes per launch of the dominant kernel from stored rocprofv3 --pmc runs.
+
+    Returns None unless the figures were taken on this workload and precision
+    with the current GEMM source (its hash is stored beside the counters).
+    """
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "cauchy_gemm_c%d_%s_traffic.txt" % (config, prec))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#") and "=" in line:
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, kv.get("source", ""))
+    if not os.path.exists(src):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if sha != kv.get("source_sha256_16"):
+        return None
+    return (float(kv["fetch_kib_avg"]) * float(kv["fetch_scale"]) +
+            float(kv["write_kib_avg"]) * float(kv["write_scale"])) * 1024.0
+
+
 def cpu_baseline(pr, idx):
     """The oracle as it stands, on this host's cores, for one parameter of the workload."""
     from oracle import lyap_bs as O
@@ -170,7 +196,8 @@ def main():
                 PEAK[args.prec]
         achieved = fl / (ms * 1e-3) / 1e12
         out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                           "frac": achieved / peak, "traffic": None,
+                           "frac": achieved / peak,
+                           "traffic": stored_traffic(args.config, args.prec),
                            "kernel": "Cauchy contraction GEMM (%s)" % args.prec,
                            "avg_launch_us": 1e3 * ms / nl, "launches": nl,
                            "algorithmic_flops_per_launch": fl / nl}

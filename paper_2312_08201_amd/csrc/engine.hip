@@ -331,6 +331,9 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
 
 // claim the next queue position, or -1
 __device__ inline int claim(const EngineArgs& A) {
+  // cheap check first: an empty queue costs no atomic traffic
+  if (__atomic_load_n(&A.qctl[0], __ATOMIC_RELAXED) >= __atomic_load_n(&A.qctl[1], __ATOMIC_RELAXED))
+    return -1;
   int old = atomicAdd(&A.qctl[0], 0);
   while (true) {
     const int tail = atomicAdd(&A.qctl[1], 0);
@@ -388,21 +391,27 @@ __global__ void __launch_bounds__(1024) k_lists(EngineArgs A) {
     if (ph == PH_RESTART || (ph == PH_ARNOLDI && !A.mixed)) ++n64;
     else if (ph == PH_ARNOLDI) ++nlo;
   }
+  // inclusive Hillis-Steele scan of the per-thread counts
   c64[threadIdx.x] = n64;
   clo[threadIdx.x] = nlo;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int a = 0, b = 0;
-    for (int t = 0; t < (int)blockDim.x; ++t) {
-      const int x = c64[t], y = clo[t];
-      c64[t] = a;
-      clo[t] = b;
-      a += x;
-      b += y;
-    }
-    A.lists[2 * S] = a;
-    A.lists[2 * S + 1] = b;
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const int a = threadIdx.x >= (unsigned)off ? c64[threadIdx.x - off] : 0;
+    const int b = threadIdx.x >= (unsigned)off ? clo[threadIdx.x - off] : 0;
+    __syncthreads();
+    c64[threadIdx.x] += a;
+    clo[threadIdx.x] += b;
+    __syncthreads();
   }
+  if (threadIdx.x == blockDim.x - 1) {
+    A.lists[2 * S] = c64[threadIdx.x];
+    A.lists[2 * S + 1] = clo[threadIdx.x];
+  }
+  // exclusive offsets
+  const int ex64 = c64[threadIdx.x] - n64, exlo = clo[threadIdx.x] - nlo;
+  __syncthreads();
+  c64[threadIdx.x] = ex64;
+  clo[threadIdx.x] = exlo;
   __syncthreads();
   int o64 = c64[threadIdx.x], olo = clo[threadIdx.x];
   for (int s = s0; s < min(S, s0 + per); ++s) {
@@ -412,27 +421,25 @@ __global__ void __launch_bounds__(1024) k_lists(EngineArgs A) {
   }
 }
 
-// z for every listed slot (both lists): one workgroup per list entry
+// z for every listed slot (both lists): workgroups stride over the entries
 __global__ void __launch_bounds__(KT) k_prep(EngineArgs A) {
   const int S = A.S;
-  const int li = blockIdx.x;
   const int c64 = A.lists[2 * S], clo = A.lists[2 * S + 1];
-  int s;
-  if (li < c64) s = A.lists[li];
-  else if (li < S && li - c64 < clo) s = A.lists[S + (li - c64)];
-  else return;
   const int N = A.r * A.ld;
-  const int ph = A.si[(long)s * SI_N + SI_PHASE];
-  double* zs = A.z + (long)s * A.NV;
-  if (ph == PH_RESTART) {
-    const double* xs = A.x + (long)s * A.NV;
-    for (int e = threadIdx.x; e < N; e += blockDim.x) zs[e] = xs[e];
-  } else {
-    const int j = A.si[(long)s * SI_N + SI_J];
-    const double* vj = A.V + ((long)s * (A.m + 1) + j) * A.NV;
-    if (A.use_precond) apply_pinv(A, s, vj, zs, false);
-    else
-      for (int e = threadIdx.x; e < N; e += blockDim.x) zs[e] = vj[e];
+  for (int li = blockIdx.x; li < c64 + clo; li += gridDim.x) {
+    const int s = li < c64 ? A.lists[li] : A.lists[S + (li - c64)];
+    const int ph = A.si[(long)s * SI_N + SI_PHASE];
+    double* zs = A.z + (long)s * A.NV;
+    if (ph == PH_RESTART) {
+      const double* xs = A.x + (long)s * A.NV;
+      for (int e = threadIdx.x; e < N; e += blockDim.x) zs[e] = xs[e];
+    } else {
+      const int j = A.si[(long)s * SI_N + SI_J];
+      const double* vj = A.V + ((long)s * (A.m + 1) + j) * A.NV;
+      if (A.use_precond) apply_pinv(A, s, vj, zs, false);
+      else
+        for (int e = threadIdx.x; e < N; e += blockDim.x) zs[e] = vj[e];
+    }
   }
 }
 
@@ -451,16 +458,18 @@ template <class T>
 __global__ void __launch_bounds__(KT) k_formX(EngineArgs A, T* X, long plane, int which) {
   const int S = A.S, r = A.r, ld = A.ld, h = A.h;
   const int cnt = A.lists[2 * S + which];
-  const int row = blockIdx.y;  // li * r * r + a * r + b
-  const int li = row / (r * r);
-  if (li >= cnt) return;
-  const int a = (row / r) % r, b = row % r;
-  const int s = A.lists[which * S + li];
-  const double* va = A.Vh + (long)a * ld;
-  const double* zb = A.z + (long)s * A.NV + (long)b * ld;
-  const long base = (long)row * ld;
   const int nu = A.n - h;
-  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x) {
+  const long total = (long)cnt * r * r * nu;
+  for (long g = (long)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (long)gridDim.x * blockDim.x) {
+    const int row = (int)(g / nu);  // li * r * r + a * r + b
+    const int u = (int)(g - (long)row * nu);
+    const int li = row / (r * r);
+    const int a = (row / r) % r, b = row % r;
+    const int s = A.lists[which * S + li];
+    const double* va = A.Vh + (long)a * ld;
+    const double* zb = A.z + (long)s * A.NV + (long)b * ld;
+    const long base = (long)row * ld;
     bool pr;
     const int q = uslot(u, h, pr);
     if (pr) {
@@ -479,20 +488,21 @@ __global__ void __launch_bounds__(KT)
 k_epilogue(EngineArgs A, const HT* H, const HT* Hp, int which, int ggrid, int gnk) {
   const int S = A.S, r = A.r, ld = A.ld, h = A.h;
   const int cnt = A.lists[2 * S + which];
-  const int row = blockIdx.y;  // li * r + a
-  const int li = row / r;
-  if (li >= cnt) return;
-  const int a = row % r;
-  const int s = A.lists[which * S + li];
+  const int nu = A.n - h;
   const int mta = (cnt * r * r + kGemmBM - 1) / kGemmBM;
   const int KS = splitk_of(mta, ld / kGemmBN, ggrid, gnk);
   const long kstride = (long)mta * kGemmBM * ld;
   const HT* Hsrc = KS > 1 ? Hp : H;
-  const double* zs = A.z + (long)s * A.NV;
-  double* ws = A.w + (long)s * A.NV + (long)a * ld;
-  const double da = A.d[(long)s * r + a];
-  const int nu = A.n - h;
-  for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < nu; u += gridDim.x * blockDim.x) {
+  const long total = (long)cnt * r * nu;
+  for (long g = (long)blockIdx.x * blockDim.x + threadIdx.x; g < total;
+       g += (long)gridDim.x * blockDim.x) {
+    const int row = (int)(g / nu);  // li * r + a
+    const int u = (int)(g - (long)row * nu);
+    const int li = row / r, a = row % r;
+    const int s = A.lists[which * S + li];
+    const double* zs = A.z + (long)s * A.NV;
+    double* ws = A.w + (long)s * A.NV + (long)a * ld;
+    const double da = A.d[(long)s * r + a];
     bool pr;
     const int q = uslot(u, h, pr);
     double sr = 0, si = 0;
@@ -809,6 +819,12 @@ static void launch_krylov(const EngineArgs& A, int S, long long NV, hipStream_t 
   }
 }
 
+// profiling: copy this step's list counts to a device slot (graph-capturable)
+__global__ void k_record_counts(const int* lists, int S, int* dst) {
+  dst[0] = lists[2 * S];
+  dst[1] = lists[2 * S + 1];
+}
+
 // Admission: every free slot takes the next queued parameter (device-side
 // queue), so a slot freed in this step starts its next parameter in the next.
 __global__ void __launch_bounds__(KT) k_admit(EngineArgs A) {
@@ -846,6 +862,12 @@ struct lyap_engine_s {
   bool owns_graph = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // profiling graph: kProfSteps steps with event pairs and recorded counts
+  hipGraph_t pgraph = nullptr;
+  hipGraphExec_t pgexec = nullptr;
+  std::vector<hipEvent_t> pev;
+  DevBuf pcounts;
+  bool prof_graph_ok = true;
   EngineArgs args{};
   std::vector<DevResult> res_host;
   std::vector<long long> done_pos;  // host-side list of positions already harvested
@@ -927,8 +949,10 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
   lyap_seed_s* sd = E->sd;
   const int S = E->S, r = (int)sd->r, ld = (int)sd->ld, nu = (int)(sd->n - sd->h);
   hipLaunchKernelGGL(k_lists, dim3(1), dim3(1024), 0, st, A);
-  hipLaunchKernelGGL(k_prep, dim3(S), dim3(KT), 0, st, A);
+  const int pgrid = std::min(S, 1024);
+  hipLaunchKernelGGL(k_prep, dim3(pgrid), dim3(KT), 0, st, A);
   const int ublocks = std::max(1, std::min((nu + KT - 1) / KT, 64));
+  const int egrid = 2048;  // grid-stride kernels: work proportional to the active count
   if (sd->basis == LYAP_BASIS_SCHUR) {
     // seed solve in the real Schur basis for every listed slot
     const int n = (int)sd->n;
@@ -945,8 +969,8 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
   } else {
   // FP64 list (which = 0)
   {
-    hipLaunchKernelGGL((k_formX<double>), dim3(ublocks, S * r * r), dim3(KT), 0, st, A,
-                       E->X.as<double>(), 0L, 0);
+    hipLaunchKernelGGL((k_formX<double>), dim3(egrid), dim3(KT), 0, st, A, E->X.as<double>(), 0L,
+                       0);
     GemmArgs g{};
     g.type = GemmType::F64;
     g.A = E->X.p;
@@ -964,8 +988,8 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     gemm_launch(g, st);
     if (ev) LYAP_HIP(hipEventRecord(ev->g64[1], st));
     const int ggrid = (int)(E->rows_pad / kGemmBM) * (ld / kGemmBN);
-    hipLaunchKernelGGL((k_epilogue<double>), dim3(ublocks, S * r), dim3(KT), 0, st, A,
-                       E->H.as<double>(), E->Hp.as<double>(), 0, ggrid, ld / gemm_bk(GemmType::F64));
+    hipLaunchKernelGGL((k_epilogue<double>), dim3(egrid), dim3(KT), 0, st, A, E->H.as<double>(),
+                       E->Hp.as<double>(), 0, ggrid, ld / gemm_bk(GemmType::F64));
   }
   if (E->mixed) {
     GemmArgs g{};
@@ -982,20 +1006,20 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     g.m_scale = r * r;
     g.Cpart = E->Hplo.p;
     if (E->low == GemmType::F32) {
-      hipLaunchKernelGGL((k_formX<float>), dim3(ublocks, S * r * r), dim3(KT), 0, st, A,
-                         E->Xlo.as<float>(), 0L, 1);
+      hipLaunchKernelGGL((k_formX<float>), dim3(egrid), dim3(KT), 0, st, A, E->Xlo.as<float>(),
+                         0L, 1);
     } else {
       g.a_plane = E->rows_pad * ld;
       g.b_plane = (long long)ld * ld;
-      hipLaunchKernelGGL((k_formX<__bf16>), dim3(ublocks, S * r * r), dim3(KT), 0, st, A,
+      hipLaunchKernelGGL((k_formX<__bf16>), dim3(egrid), dim3(KT), 0, st, A,
                          E->Xlo.as<__bf16>(), (long)(E->rows_pad * ld), 1);
     }
     if (ev) LYAP_HIP(hipEventRecord(ev->glo[0], st));
     gemm_launch(g, st);
     if (ev) LYAP_HIP(hipEventRecord(ev->glo[1], st));
     const int ggrid = (int)(E->rows_pad / kGemmBM) * (ld / kGemmBN);
-    hipLaunchKernelGGL((k_epilogue<float>), dim3(ublocks, S * r), dim3(KT), 0, st, A,
-                       E->Hlo.as<float>(), E->Hplo.as<float>(), 1, ggrid, ld / gemm_bk(E->low));
+    hipLaunchKernelGGL((k_epilogue<float>), dim3(egrid), dim3(KT), 0, st, A, E->Hlo.as<float>(),
+                       E->Hplo.as<float>(), 1, ggrid, ld / gemm_bk(E->low));
   }
   }  // eigen basis
   if (ev) LYAP_HIP(hipEventRecord(ev->kry[0], st));
@@ -1017,23 +1041,10 @@ static bool profiling() {
   return g_prof_on;
 }
 
-// Run k steps with event pairs and per-step active counts; accumulate the profile.
-static void profiled_steps(lyap_engine_s* E, long long k) {
-  hipStream_t st = E->stream;
-  const int S = E->S;
-  std::vector<StepEvents> evs(k);
-  for (auto& e : evs)
-    for (hipEvent_t* p : {&e.g64[0], &e.g64[1], &e.glo[0], &e.glo[1], &e.kry[0], &e.kry[1]})
-      LYAP_HIP(hipEventCreate(p));
-  int* counts = nullptr;
-  LYAP_HIP(hipHostMalloc((void**)&counts, sizeof(int) * 2 * k, hipHostMallocDefault));
-  for (long long i = 0; i < k; ++i) {
-    launch_step(E, st, &evs[i]);
-    // the lists (and counts) stay valid until the next step's k_lists
-    LYAP_HIP(hipMemcpyAsync(counts + 2 * i, E->lists.as<int>() + 2 * S, 2 * sizeof(int),
-                            hipMemcpyDeviceToHost, st));
-  }
-  LYAP_HIP(hipStreamSynchronize(st));
+constexpr int kProfSteps = 8;
+
+static void prof_accumulate(lyap_engine_s* E, const std::vector<StepEvents>& evs, const int* counts,
+                            long long k) {
   const double r = (double)E->sd->r, n = (double)E->sd->n;
   lyap_profile add{};
   for (long long i = 0; i < k; ++i) {
@@ -1058,10 +1069,6 @@ static void profiled_steps(lyap_engine_s* E, long long k) {
     add.slot_steps += counts[2 * i] + counts[2 * i + 1];
   }
   add.steps = k;
-  (void)hipHostFree(counts);
-  for (auto& e : evs)
-    for (hipEvent_t p : {e.g64[0], e.g64[1], e.glo[0], e.glo[1], e.kry[0], e.kry[1]})
-      (void)hipEventDestroy(p);
   std::lock_guard<std::mutex> g(g_prof_mu);
   g_prof.gemm64_ms += add.gemm64_ms;
   g_prof.gemm64_launches += add.gemm64_launches;
@@ -1073,6 +1080,80 @@ static void profiled_steps(lyap_engine_s* E, long long k) {
   g_prof.krylov_launches += add.krylov_launches;
   g_prof.slot_steps += add.slot_steps;
   g_prof.steps += add.steps;
+}
+
+static std::vector<StepEvents> prof_events(lyap_engine_s* E) {
+  std::vector<StepEvents> evs(kProfSteps);
+  for (int i = 0; i < kProfSteps; ++i) {
+    hipEvent_t* p = &evs[i].g64[0];
+    for (int q = 0; q < 6; ++q) p[q] = E->pev[6 * i + q];
+  }
+  return evs;
+}
+
+// Capture kProfSteps steps with event-record nodes (timing events) once.
+static void prof_graph_build(lyap_engine_s* E) {
+  hipStream_t st = E->stream;
+  E->pev.resize(6 * kProfSteps);
+  for (auto& e : E->pev) LYAP_HIP(hipEventCreate(&e));
+  E->pcounts.alloc(sizeof(int) * 2 * kProfSteps);
+  std::vector<StepEvents> evs = prof_events(E);
+  LYAP_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  try {
+    for (int i = 0; i < kProfSteps; ++i) {
+      launch_step(E, st, &evs[i]);
+      hipLaunchKernelGGL(k_record_counts, dim3(1), dim3(1), 0, st, E->lists.as<int>(), E->S,
+                         E->pcounts.as<int>() + 2 * i);
+    }
+  } catch (...) {
+    hipGraph_t tmp;
+    (void)hipStreamEndCapture(st, &tmp);
+    throw;
+  }
+  LYAP_HIP(hipStreamEndCapture(st, &E->pgraph));
+  LYAP_HIP(hipGraphInstantiate(&E->pgexec, E->pgraph, nullptr, nullptr, 0));
+}
+
+// Run k steps with event pairs and per-step active counts; accumulate the profile.
+// Preferred: the captured profiling graph (same launch path as production);
+// fallback: direct launches.
+static void profiled_steps(lyap_engine_s* E, long long k) {
+  hipStream_t st = E->stream;
+  const int S = E->S;
+  if (E->prof_graph_ok) {
+    try {
+      if (!E->pgexec) prof_graph_build(E);
+      std::vector<StepEvents> evs = prof_events(E);
+      int counts[2 * kProfSteps];
+      for (long long done = 0; done < k; done += kProfSteps) {
+        LYAP_HIP(hipGraphLaunch(E->pgexec, st));
+        LYAP_HIP(hipMemcpyAsync(counts, E->pcounts.p, sizeof(counts), hipMemcpyDeviceToHost, st));
+        LYAP_HIP(hipStreamSynchronize(st));
+        prof_accumulate(E, evs, counts, kProfSteps);
+      }
+      return;
+    } catch (const Error&) {
+      E->prof_graph_ok = false;  // e.g. event timing inside graphs unsupported
+      (void)hipGetLastError();
+    }
+  }
+  std::vector<StepEvents> evs(k);
+  for (auto& e : evs)
+    for (hipEvent_t* p : {&e.g64[0], &e.g64[1], &e.glo[0], &e.glo[1], &e.kry[0], &e.kry[1]})
+      LYAP_HIP(hipEventCreate(p));
+  int* counts = nullptr;
+  LYAP_HIP(hipHostMalloc((void**)&counts, sizeof(int) * 2 * k, hipHostMallocDefault));
+  for (long long i = 0; i < k; ++i) {
+    launch_step(E, st, &evs[i]);
+    LYAP_HIP(hipMemcpyAsync(counts + 2 * i, E->lists.as<int>() + 2 * S, 2 * sizeof(int),
+                            hipMemcpyDeviceToHost, st));
+  }
+  LYAP_HIP(hipStreamSynchronize(st));
+  prof_accumulate(E, evs, counts, k);
+  (void)hipHostFree(counts);
+  for (auto& e : evs)
+    for (hipEvent_t p : {e.g64[0], e.g64[1], e.glo[0], e.glo[1], e.kry[0], e.kry[1]})
+      (void)hipEventDestroy(p);
 }
 
 static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lyap_solve_opts* in,
@@ -1206,6 +1287,9 @@ static void engine_destroy_impl(lyap_engine_s* E) {
   (void)hipStreamSynchronize(E->stream);
   if (E->gexec) (void)hipGraphExecDestroy(E->gexec);
   if (E->graph) (void)hipGraphDestroy(E->graph);
+  if (E->pgexec) (void)hipGraphExecDestroy(E->pgexec);
+  if (E->pgraph) (void)hipGraphDestroy(E->pgraph);
+  for (auto& e : E->pev) (void)hipEventDestroy(e);
   if (E->stream) (void)hipStreamDestroy(E->stream);
   delete E;
 }

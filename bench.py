@@ -34,7 +34,56 @@ WORKLOAD = {
     1: "c1: damped chain n=2000 r=2, 32x32 log-spaced viscosity grid (P=1024), B n x 8, E=diag(I,0)",
     2: "c2: damped chain n=4000 r=3, 256 log-uniform viscosity triples, B n x 16, E=diag(I,0)",
     3: "c3: multi-agent N=500 (n=1000) r=8 (4 edge weights), 512 samples, B n x 4, E=I",
+    4: "c4: serving mix, Poisson arrivals of sweep requests (chain / multi-agent seeds, "
+       "r 1..4, P 8..512, 30% seed reuse), HBM-budget admission, continuous batching",
 }
+
+
+def serve_bench(args):
+    """Workload c4: replay a Poisson request stream through the serving loop."""
+    import torch
+    import paper_2312_08201_amd as L
+    from paper_2312_08201_amd import serve
+    from gen import workloads as W
+    from oracle import lyap_bs as O
+
+    sizes = tuple(int(x) for x in args.serve_sizes.split(","))
+    reqs = W.serving_requests(args.serve_requests, rate=args.serve_rate, seed=4, sizes=sizes)
+    probs = {q.rid: W.request_problem(q) for q in reqs}
+    sreqs = []
+    for q in reqs:
+        pr = probs[q.rid]
+        sreqs.append(serve.SweepRequest(q.rid, q.seed_id,
+                                        (lambda pr=pr: (pr.A0, pr.U, pr.V, pr.B, pr.E)), pr.d,
+                                        q.arrival))
+    budget = int(args.serve_budget_gib * (1 << 30))
+    srv = serve.Server(budget, slots=args.serve_slots, opts=L.solve_opts())
+    t = time.perf_counter()
+    done = srv.run(sreqs, realtime=True)
+    wall = time.perf_counter() - t
+    stats = serve.latency_stats(done)
+    ok = all(np.all(st.status == 0) for st in done)
+    # accuracy: one parameter of every request with n <= 1000 against the oracle
+    errs = []
+    for st in done:
+        pr = probs[st.req.rid]
+        if pr.n <= 1000:
+            i = 0
+            res = O.solve_one(pr.A0, pr.U, pr.V, pr.B, pr.E, pr.d[i], diagnostics=False)
+            errs.append(abs(st.traces[i] - res.trace) / abs(res.trace))
+    srv.close()
+    out = {
+        "metric": METRIC, "value": stats["evals"] / wall, "unit": "evals/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": 1e3 * wall, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOAD[4], "requests": len(reqs), "rate_per_s": args.serve_rate,
+                   "sizes": list(sizes), "hbm_budget_gib": args.serve_budget_gib,
+                   "slots_per_engine": args.serve_slots},
+        "p50_ms": 1e3 * stats["p50_s"], "p99_ms": 1e3 * stats["p99_s"],
+        "all_converged": ok, "max_rel_err_sampled": max(errs) if errs else None,
+        "seed_factor_s_total": srv.seed_factor_seconds, "evals": stats["evals"],
+    }
+    print(json.dumps(out), flush=True)
 
 
 def stored_traffic(config, prec):
@@ -89,6 +138,11 @@ def main():
     ap.add_argument("--restart", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="graph replay, no event timing")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-rate", type=float, default=4.0, help="request arrivals per second")
+    ap.add_argument("--serve-sizes", default="400,1000,2000")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-slots", type=int, default=256)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain copy of this many MiB (byte-counter calibration)")
     args = ap.parse_args()
@@ -115,6 +169,10 @@ def main():
             L.calib_copy(a, b)
         torch.cuda.synchronize()
         print(json.dumps({"calib_copy_bytes": nb, "ok": bool(torch.equal(a, b))}), flush=True)
+        return
+
+    if args.config == 4:
+        serve_bench(args)
         return
 
     pr = W.config(args.config)

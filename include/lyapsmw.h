@@ -195,6 +195,14 @@ lyap_status engine_submit(lyap_engine eng, int64_t count, const double* d_host,
  * number of parameters still queued or in flight. */
 lyap_status engine_run(lyap_engine eng, int64_t max_steps, int32_t poll_every, int64_t* busy);
 
+/* Non-blocking variant for overlapping several engines: enqueue `steps`
+ * Krylov steps on the engine's stream and return at once. */
+lyap_status engine_launch(lyap_engine eng, int64_t steps);
+
+/* Parameters submitted so far and finished so far (synchronises the engine's
+ * stream to read the device counter). */
+lyap_status engine_status(lyap_engine eng, int64_t* submitted, int64_t* done);
+
 /* Move up to `max_out` finished results to the caller (tags, results). */
 lyap_status engine_harvest(lyap_engine eng, int64_t max_out, int64_t* tags_out,
                            lyap_result* res_out, int64_t* n_out);

@@ -1447,6 +1447,27 @@ lyap_status engine_run(lyap_engine E, int64_t max_steps, int32_t poll_every, int
   return LYAP_OK;
 }
 
+lyap_status engine_launch(lyap_engine E, int64_t steps) {
+  if (!E || steps < 0) return LYAP_E_INVAL;
+  LYAP_TRY({
+    for (int64_t i = 0; i < steps; ++i) {
+      if (E->gexec) LYAP_HIP(hipGraphLaunch(E->gexec, E->stream));
+      else launch_step(E, E->stream);
+    }
+  });
+  return LYAP_OK;
+}
+
+lyap_status engine_status(lyap_engine E, int64_t* submitted, int64_t* done) {
+  if (!E) return LYAP_E_INVAL;
+  LYAP_TRY({
+    const long long d = engine_done_count(E);
+    if (submitted) *submitted = E->submitted;
+    if (done) *done = d;
+  });
+  return LYAP_OK;
+}
+
 lyap_status engine_harvest(lyap_engine E, int64_t max_out, int64_t* tags_out, lyap_result* res_out,
                            int64_t* n_out) {
   if (!E) return LYAP_E_INVAL;

@@ -72,7 +72,7 @@ _lib = None
 EXPORTS = ["seed_factor", "seed_info", "seed_release", "seed_device_bytes", "lyap_seed_apply",
            "smw_workspace_bytes", "smw_solve_batch", "trace_EX", "engine_create",
            "engine_device_bytes", "engine_destroy", "engine_submit", "engine_run",
-           "engine_harvest", "lyap_status_string", "lyap_last_error", "lyap_profile_enable",
+           "engine_harvest", "engine_launch", "engine_status", "lyap_status_string", "lyap_last_error", "lyap_profile_enable",
            "lyap_profile_read", "lyap_calib_copy", "lyap_real_schur"]
 
 
@@ -106,6 +106,8 @@ def load(path: str = LIB_PATH):
     lib.engine_submit.argtypes = [vp, i64, vp, vp]
     lib.engine_run.argtypes = [vp, i64, i32, C.POINTER(i64)]
     lib.engine_harvest.argtypes = [vp, i64, vp, C.POINTER(Result), C.POINTER(i64)]
+    lib.engine_launch.argtypes = [vp, i64]
+    lib.engine_status.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
     lib.lyap_status_string.argtypes = [i32]
     lib.lyap_status_string.restype = C.c_char_p
     lib.lyap_profile_enable.argtypes = [i32]
@@ -118,7 +120,8 @@ def load(path: str = LIB_PATH):
     lib.lyap_last_error.restype = C.c_char_p
     for name in ("seed_factor", "seed_info", "seed_release", "lyap_seed_apply", "smw_solve_batch",
                  "trace_EX", "engine_create", "engine_destroy", "engine_submit", "engine_run",
-                 "engine_harvest", "lyap_profile_read", "lyap_calib_copy"):
+                 "engine_harvest", "engine_launch", "engine_status", "lyap_profile_read",
+                 "lyap_calib_copy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -213,6 +216,9 @@ class Seed:
     def from_problem(cls, pr, **kw):
         return cls(pr.A0, pr.U, pr.V, pr.B, pr.E, **kw)
 
+    def device_bytes(self) -> int:
+        return int(load().seed_device_bytes(self.h))
+
     def info(self) -> dict:
         inf = SeedInfo()
         _check(load().seed_info(self.h, C.byref(inf)), "seed_info")
@@ -298,6 +304,20 @@ class Engine:
         _check(load().engine_run(self.h, int(max_steps), int(poll_every), C.byref(busy)),
                "engine_run")
         return busy.value
+
+    def launch(self, steps: int):
+        """Enqueue steps without waiting (engines on different streams overlap)."""
+        _check(load().engine_launch(self.h, int(steps)), "engine_launch")
+
+    def status(self):
+        sub, done = C.c_int64(), C.c_int64()
+        _check(load().engine_status(self.h, C.byref(sub), C.byref(done)), "engine_status")
+        return sub.value, done.value
+
+    @staticmethod
+    def device_bytes(seed: "Seed", slots: int, opts: Optional[SolveOpts] = None) -> int:
+        opts = opts or solve_opts()
+        return int(load().engine_device_bytes(seed.h, int(slots), C.byref(opts)))
 
     def harvest(self, max_out=1 << 20):
         cap = int(max_out)

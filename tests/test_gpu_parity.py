@@ -259,3 +259,32 @@ def test_schur_basis_auto_for_near_defective_seed():
     tr = seed.trace(Y).cpu().numpy()
     assert np.all(res["status"] == 0)
     assert np.max(rel(tr, oracle_traces(pr))) <= 1e-10
+
+
+def test_serving_loop_alone_vs_mix():
+    """Requests served concurrently (several seeds, overlapping engines, continuous
+    batching, seed reuse) give the traces they give alone, and match the oracle."""
+    L, torch = lib()
+    from paper_2312_08201_amd import serve
+    probs = [W.small_chain(25, (4, 11), 3, 12, seed=31), W.small_multiagent(20, 2, 3, 9, seed=32),
+             W.small_chain(25, (4, 11), 3, 7, seed=31), W.random_stable(30, 2, 2, 10, 33)]
+    keys = ["a", "b", "a", "c"]   # request 2 reuses the seed of request 0
+    reqs = [serve.SweepRequest(i, keys[i], (lambda pr=pr: (pr.A0, pr.U, pr.V, pr.B, pr.E)), pr.d,
+                               0.01 * i) for i, pr in enumerate(probs)]
+    srv = serve.Server(8 << 30, slots=6)
+    done = {st.req.rid: st for st in srv.run(reqs, realtime=False)}
+    assert len(srv.cache) == 3   # the seed of request 0 was reused
+    srv.close()
+    for i, pr in enumerate(probs):
+        st = done[i]
+        assert np.all(st.status == 0)
+        seed = L.Seed.from_problem(pr)
+        eng = L.Engine(seed, 1)
+        eng.submit(pr.d, np.arange(pr.P))
+        assert eng.run() == 0
+        tags, res = eng.harvest()
+        alone = np.empty(pr.P)
+        alone[tags] = res["trace"]
+        eng.close()
+        assert np.max(np.abs(st.traces - alone) / np.abs(alone)) <= 1e-12
+        assert np.max(rel(st.traces, oracle_traces(pr))) <= 1e-10

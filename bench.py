@@ -136,6 +136,8 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_ir", "bf16_ir", "fp32"])
     ap.add_argument("--restart", type=int, default=40)
+    ap.add_argument("--recycle-k", type=int, default=0,
+                    help="GCRO-DR recycle space dimension (0: restarted GMRES)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="graph replay, no event timing")
     ap.add_argument("--serve-requests", type=int, default=24)
@@ -181,7 +183,7 @@ def main():
     factor_s = time.perf_counter() - t
     info = seed.info()
     d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
-    opts = L.solve_opts(prec=args.prec, restart=args.restart)
+    opts = L.solve_opts(prec=args.prec, restart=args.restart, recycle_k=args.recycle_k)
 
     def step():
         Y, res = seed.solve(d, opts)
@@ -236,7 +238,8 @@ def main():
         "dtype": {"fp64": "f64", "fp32_ir": "f32+f64", "bf16_ir": "bf16+f64", "fp32": "f32"}[args.prec],
         "data": "synthetic",
         "config": {"workload": WORKLOAD[args.config], "P": P, "n": pr.n, "r": pr.r,
-                   "precision": args.prec, "restart": args.restart},
+                   "precision": args.prec, "restart": args.restart,
+                   "recycle_k": args.recycle_k},
         "p50_ms": 1e3 * float(np.percentile(lat, 50)),
         "p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "all_converged": ok,

@@ -83,7 +83,11 @@ typedef struct {
   int32_t max_iter;       /* total matrix-vector products per parameter (default 600) */
   int32_t restart;        /* Krylov dimension per cycle m (default 40, at most 64) */
   int32_t use_precond;    /* 1: right preconditioner = exact diagonal blocks of eq:prec (default 1) */
-  int32_t recycle_k;      /* reserved (0) */
+  int32_t recycle_k;      /* GCRO-DR recycle space dimension s (Section 2.1, Parks et al.):
+                             0 = restarted GMRES (default); at most 16, restart + recycle_k
+                             <= 64.  Each cycle end replaces the space by the harmonic Ritz
+                             vectors of smallest magnitude; a slot that takes a new parameter
+                             rebuilds C = A P^-1 U with recycle_k extra products */
   int32_t max_refine;     /* FP64 refinement steps for the *_IR modes (default 30) */
   double tol;             /* FP64 relative residual target ||b - A y|| / ||b|| (default 1e-12) */
   double inner_tol;       /* relative reduction per inner cycle in *_IR modes (default 1e-4) */

@@ -32,12 +32,17 @@
 
 namespace lyap {
 
-constexpr int kPrecRank = 8;  // block preconditioner up to r = 8
+constexpr int kPrecRank = 8;     // block preconditioner up to r = 8
+constexpr int kMaxRecycle = 16;  // recycle space dimension bound
+constexpr int kMaxBasis = kMaxRestart + kMaxRecycle;
 
-enum Phase : int { PH_FREE = 0, PH_ARNOLDI = 1, PH_RESTART = 2 };
+enum Phase : int { PH_FREE = 0, PH_ARNOLDI = 1, PH_RESTART = 2, PH_RECYC = 3, PH_NEWSPACE = 4 };
 
-// per-slot integer state
-enum SI : int { SI_PHASE = 0, SI_J, SI_ITERS, SI_CYCLES, SI_REFINE, SI_QPOS, SI_N };
+// per-slot integer state (KCUR: valid recycle vectors, RJ: next one to
+// rebuild for a new parameter, BANK: which of the two U/C banks is current)
+enum SI : int {
+  SI_PHASE = 0, SI_J, SI_ITERS, SI_CYCLES, SI_REFINE, SI_QPOS, SI_KCUR, SI_RJ, SI_BANK, SI_N
+};
 // per-slot double state
 enum SD : int { SD_BNORM = 0, SD_BETA, SD_N };
 
@@ -82,7 +87,21 @@ struct EngineArgs {
   int Q;
   double* sol;             // optional: solutions by tag, stride N (rho form)
   long long sol_cap;
+  // recycling (GCRO-DR); kmax = 0 disables it
+  int kmax;
+  double* Ur;   // S x 2 banks x kmax x NV: U with A P^-1 U = C
+  double* Cr;   // S x 2 banks x kmax x NV: C, orthonormal columns
+  double* Bk;   // S x kmax x m: C^T A P^-1 v_j of the current cycle
+  double* Hr;   // S x m x (m+1): unrotated Hessenberg columns
+  double* Fs;   // S x kRecScratch: recycle-update work matrix
 };
+
+__device__ inline double* rec_u(const EngineArgs& A, int s, int bank, int l) {
+  return A.Ur + (((long)s * 2 + bank) * A.kmax + l) * (long)A.NV;
+}
+__device__ inline double* rec_c(const EngineArgs& A, int s, int bank, int l) {
+  return A.Cr + (((long)s * 2 + bank) * A.kmax + l) * (long)A.NV;
+}
 
 // ---------------------------------------------------------------------------
 // reductions (64-wide wavefronts, 256-thread workgroups)
@@ -316,10 +335,14 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
   const double inv = 1.0 / bn;
   for (int e = threadIdx.x; e < N; e += blockDim.x) V0[e] *= inv;
   if (threadIdx.x == 0) {
-    si[SI_PHASE] = PH_ARNOLDI;
+    // a slot that kept a recycle space from its previous parameter first
+    // rebuilds C = A(p) P(p)^-1 U for the new parameter
+    const bool rec = A.kmax > 0 && si[SI_KCUR] > 0;
+    si[SI_PHASE] = rec ? PH_RECYC : PH_ARNOLDI;
+    si[SI_RJ] = 0;
     si[SI_J] = 0;
     si[SI_ITERS] = 0;
-    si[SI_CYCLES] = 1;
+    si[SI_CYCLES] = rec ? 0 : 1;
     si[SI_REFINE] = 0;
     si[SI_QPOS] = qp;
     sdv[SD_BNORM] = bn;
@@ -329,19 +352,19 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
   __syncthreads();
 }
 
-// claim the next queue position, or -1
+// claim the next queue position, or -1.  The tail only moves between
+// launches (host submissions are ordered on the engine stream), so one
+// fetch-add hands out each position below the tail exactly once; a claim at
+// or past the tail is given back, which keeps the head from ever falling
+// below the tail once it has reached it.  No compare-and-swap retry loop:
+// a step in which every slot claims costs one atomic per slot.
 __device__ inline int claim(const EngineArgs& A) {
-  // cheap check first: an empty queue costs no atomic traffic
-  if (__atomic_load_n(&A.qctl[0], __ATOMIC_RELAXED) >= __atomic_load_n(&A.qctl[1], __ATOMIC_RELAXED))
-    return -1;
-  int old = atomicAdd(&A.qctl[0], 0);
-  while (true) {
-    const int tail = atomicAdd(&A.qctl[1], 0);
-    if (old >= tail) return -1;
-    const int got = atomicCAS(&A.qctl[0], old, old + 1);
-    if (got == old) return old;
-    old = got;
-  }
+  const int tail = __atomic_load_n(&A.qctl[1], __ATOMIC_RELAXED);
+  if (__atomic_load_n(&A.qctl[0], __ATOMIC_RELAXED) >= tail) return -1;
+  const int pos = atomicAdd(&A.qctl[0], 1);
+  if (pos < tail) return pos;
+  atomicSub(&A.qctl[0], 1);
+  return -1;
 }
 
 __device__ void finish(const EngineArgs& A, int s, int status, double relres, double* lds) {
@@ -388,8 +411,9 @@ __global__ void __launch_bounds__(1024) k_lists(EngineArgs A) {
   int n64 = 0, nlo = 0;
   for (int s = s0; s < min(S, s0 + per); ++s) {
     const int ph = A.si[(long)s * SI_N + SI_PHASE];
-    if (ph == PH_RESTART || (ph == PH_ARNOLDI && !A.mixed)) ++n64;
-    else if (ph == PH_ARNOLDI) ++nlo;
+    const bool arn = ph == PH_ARNOLDI || ph == PH_RECYC;
+    if (ph == PH_RESTART || (arn && !A.mixed)) ++n64;
+    else if (arn) ++nlo;
   }
   // inclusive Hillis-Steele scan of the per-thread counts
   c64[threadIdx.x] = n64;
@@ -416,8 +440,9 @@ __global__ void __launch_bounds__(1024) k_lists(EngineArgs A) {
   int o64 = c64[threadIdx.x], olo = clo[threadIdx.x];
   for (int s = s0; s < min(S, s0 + per); ++s) {
     const int ph = A.si[(long)s * SI_N + SI_PHASE];
-    if (ph == PH_RESTART || (ph == PH_ARNOLDI && !A.mixed)) A.lists[o64++] = s;
-    else if (ph == PH_ARNOLDI) A.lists[S + olo++] = s;
+    const bool arn = ph == PH_ARNOLDI || ph == PH_RECYC;
+    if (ph == PH_RESTART || (arn && !A.mixed)) A.lists[o64++] = s;
+    else if (arn) A.lists[S + olo++] = s;
   }
 }
 
@@ -434,8 +459,9 @@ __global__ void __launch_bounds__(KT) k_prep(EngineArgs A) {
       const double* xs = A.x + (long)s * A.NV;
       for (int e = threadIdx.x; e < N; e += blockDim.x) zs[e] = xs[e];
     } else {
-      const int j = A.si[(long)s * SI_N + SI_J];
-      const double* vj = A.V + ((long)s * (A.m + 1) + j) * A.NV;
+      const int* sis = A.si + (long)s * SI_N;
+      const double* vj = ph == PH_RECYC ? rec_u(A, s, sis[SI_BANK], sis[SI_RJ])
+                                        : A.V + ((long)s * (A.m + 1) + sis[SI_J]) * A.NV;
       if (A.use_precond) apply_pinv(A, s, vj, zs, false);
       else
         for (int e = threadIdx.x; e < N; e += blockDim.x) zs[e] = vj[e];
@@ -547,108 +573,39 @@ __global__ void __launch_bounds__(KT) k_epilogue_schur(EngineArgs A, const doubl
     ws[q] = zs[q] - da * os[q];
 }
 
-// One workgroup per slot: orthogonalisation, Givens update, restart and
-// convergence of that slot's Krylov iteration.  The slot's new vector w lives
-// in registers as NE2 double2 per thread (element pair e2 = tid + KT * i of
-// the padded slot vector, NV = 2 * KT * NE2), so each sweep over the basis
-// streams every basis vector once with independent 16-byte loads; all dot
+// ---------------------------------------------------------------------------
+// Krylov kernels.  One workgroup per slot; the slot's new vector w lives in
+// registers as NE2 double2 per thread (element pair e2 = tid + KT * i of the
+// padded slot vector, NV = 2 * KT * NE2), so each sweep over a basis streams
+// every basis vector once with independent 16-byte loads, and all dot
 // products of a pass are reduced with a single barrier.
-template <int NE2>
-__global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
-  __shared__ double part[4][kMaxRestart + 2];
-  __shared__ double lds[4 * 9];
-  __shared__ double ycoef[kMaxRestart + 1];
-  __shared__ double hcol[kMaxRestart + 2];
-  __shared__ int next_phase;
-  const int s = blockIdx.x;
-  const int r = A.r, ld = A.ld, N = r * ld, NV = A.NV, m = A.m;
-  int* si = A.si + (long)s * SI_N;
-  double* sdv = A.sdv + (long)s * SD_N;
-  const int ph = si[SI_PHASE];
-  if (ph != PH_ARNOLDI && ph != PH_RESTART) return;
+// ---------------------------------------------------------------------------
+constexpr int kPart = kMaxBasis + 2;
 
-  double* Vs = A.V + (long)s * (m + 1) * NV;
-  double* ws = A.w + (long)s * NV;
-  double* xs = A.x + (long)s * NV;
-  double* gs = A.g + (long)s * (m + 1);
-  double* Rs = A.R + (long)s * m * (m + 1);
-  double* css = A.cs + (long)s * m;
-  double* sns = A.sn + (long)s * m;
-  const double bn = sdv[SD_BNORM];
+// Orthogonalise w against the unit vectors vec(0..nvec-1): classical
+// Gram-Schmidt, with a second pass only when the first one cancelled more
+// than 1/sqrt(2) of ||w|| (Daniel-Gragg-Kaufman-Stewart criterion).
+// coef[t] receives the summed projections; returns ||w|| afterwards and the
+// norm before in wn0.
+template <int NE2, class VecF>
+__device__ double cgs2(double2 (&w2)[NE2], int nvec, VecF vec, double* coef,
+                       double (*part)[kPart], double* ytmp, double* lds, double& wn0) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-  double2 w2[NE2];
-  {
-    const double2* src = reinterpret_cast<const double2*>(ws);
-#pragma unroll
-    for (int i = 0; i < NE2; ++i) w2[i] = src[tid + KT * i];
-  }
-
-  if (ph == PH_RESTART) {
-    // w = A y ; residual r = D c0 - w into V0
-    const double* d = A.d + (long)s * r;
-    double acc = 0;
-#pragma unroll
-    for (int i = 0; i < NE2; ++i) {
-      const int e = 2 * (tid + KT * i);
-      const double r0 = e < N ? d[e / ld] * A.c0[e] - w2[i].x : 0.0;
-      const double r1 = e + 1 < N ? d[(e + 1) / ld] * A.c0[e + 1] - w2[i].y : 0.0;
-      w2[i].x = r0;
-      w2[i].y = r1;
-      acc += r0 * r0 + r1 * r1;
-    }
-    const double rn = sqrt(block_sum1(acc, lds));
-    const double rel = rn / bn;
-    const int iters = si[SI_ITERS] + 1;
-    const int refines = si[SI_REFINE];
-    __syncthreads();
-    if (tid == 0) si[SI_ITERS] = iters;
-    __syncthreads();
-    if (!isfinite(rel)) {
-      finish(A, s, LYAP_E_NONFINITE, rel, lds);
-    } else if (rel <= A.tol) {
-      finish(A, s, LYAP_OK, rel, lds);
-    } else if (iters >= A.max_iter || (A.mixed && refines >= A.max_refine)) {
-      finish(A, s, LYAP_E_NOCONV, rel, lds);
-    } else {
-      const double inv = 1.0 / rn;
-      double2* dst = reinterpret_cast<double2*>(Vs);
-#pragma unroll
-      for (int i = 0; i < NE2; ++i) dst[tid + KT * i] = make_double2(w2[i].x * inv, w2[i].y * inv);
-      if (tid == 0) {
-        gs[0] = rn;
-        sdv[SD_BETA] = rn;
-        si[SI_J] = 0;
-        si[SI_CYCLES] += 1;
-        si[SI_REFINE] = refines + 1;
-        si[SI_PHASE] = PH_ARNOLDI;
-      }
-      __syncthreads();
-    }
-    return;
-  }
-
-  // ---- Arnoldi step j: w = A P^-1 v_j ----
-  // Classical Gram-Schmidt with the Daniel-Gragg-Kaufman-Stewart criterion:
-  // a second pass only when the first one cancelled more than 1/sqrt(2) of
-  // ||w||.  Each pass = one sweep for the dots, one for the update (+ norm).
-  const int j = si[SI_J];
-  if (tid < kMaxRestart + 2) hcol[tid] = 0.0;
+  if (tid < nvec) coef[tid] = 0.0;
   double wn2 = 0.0, hn = 0.0;
   for (int pass = 0; pass < 2; ++pass) {
-    // dots h_k = <v_k, w>, k <= j, and ||w||^2 (first pass)
     double ww = 0.0;
     if (pass == 0) {
 #pragma unroll
       for (int i = 0; i < NE2; ++i) ww += w2[i].x * w2[i].x + w2[i].y * w2[i].y;
     }
     int k = 0;
-    for (; k + 4 <= j + 1; k += 4) {
+    for (; k + 4 <= nvec; k += 4) {
       double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-      const double2* v0 = reinterpret_cast<const double2*>(Vs + (long)k * NV);
-      const double2* v1 = reinterpret_cast<const double2*>(Vs + (long)(k + 1) * NV);
-      const double2* v2 = reinterpret_cast<const double2*>(Vs + (long)(k + 2) * NV);
-      const double2* v3 = reinterpret_cast<const double2*>(Vs + (long)(k + 3) * NV);
+      const double2* v0 = reinterpret_cast<const double2*>(vec(k));
+      const double2* v1 = reinterpret_cast<const double2*>(vec(k + 1));
+      const double2* v2 = reinterpret_cast<const double2*>(vec(k + 2));
+      const double2* v3 = reinterpret_cast<const double2*>(vec(k + 3));
 #pragma unroll
       for (int i = 0; i < NE2; ++i) {
         const int e = tid + KT * i;
@@ -669,9 +626,9 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
         part[wave][k + 3] = a3;
       }
     }
-    for (; k <= j; ++k) {
+    for (; k < nvec; ++k) {
       double a0 = 0;
-      const double2* v0 = reinterpret_cast<const double2*>(Vs + (long)k * NV);
+      const double2* v0 = reinterpret_cast<const double2*>(vec(k));
 #pragma unroll
       for (int i = 0; i < NE2; ++i) {
         const double2 x0 = v0[tid + KT * i];
@@ -681,21 +638,37 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
       if (lane == 0) part[wave][k] = a0;
     }
     ww = wave_sum(ww);
-    if (lane == 0) part[wave][kMaxRestart + 1] = ww;
+    if (lane == 0) part[wave][kPart - 1] = ww;
     __syncthreads();
-    if (tid <= j) {
+    if (tid < nvec) {
       const double h = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
-      ycoef[tid] = h;
-      hcol[tid] += h;
+      ytmp[tid] = h;
+      coef[tid] += h;
     }
-    if (pass == 0)
-      wn2 = part[0][kMaxRestart + 1] + part[1][kMaxRestart + 1] + part[2][kMaxRestart + 1] +
-            part[3][kMaxRestart + 1];
+    if (pass == 0) {
+      wn2 = part[0][kPart - 1] + part[1][kPart - 1] + part[2][kPart - 1] + part[3][kPart - 1];
+      wn0 = sqrt(wn2);
+    }
     __syncthreads();
-    // update w -= sum_k h_k v_k and the new ||w||^2
-    for (int kk = 0; kk <= j; ++kk) {
-      const double c = ycoef[kk];
-      const double2* v0 = reinterpret_cast<const double2*>(Vs + (long)kk * NV);
+    // w -= sum_k h_k v_k, four vectors per sweep step
+    int kk = 0;
+    for (; kk + 4 <= nvec; kk += 4) {
+      const double c0 = ytmp[kk], c1 = ytmp[kk + 1], c2 = ytmp[kk + 2], c3 = ytmp[kk + 3];
+      const double2* v0 = reinterpret_cast<const double2*>(vec(kk));
+      const double2* v1 = reinterpret_cast<const double2*>(vec(kk + 1));
+      const double2* v2 = reinterpret_cast<const double2*>(vec(kk + 2));
+      const double2* v3 = reinterpret_cast<const double2*>(vec(kk + 3));
+#pragma unroll
+      for (int i = 0; i < NE2; ++i) {
+        const int e = tid + KT * i;
+        const double2 x0 = v0[e], x1 = v1[e], x2 = v2[e], x3 = v3[e];
+        w2[i].x -= c0 * x0.x + c1 * x1.x + c2 * x2.x + c3 * x3.x;
+        w2[i].y -= c0 * x0.y + c1 * x1.y + c2 * x2.y + c3 * x3.y;
+      }
+    }
+    for (; kk < nvec; ++kk) {
+      const double c = ytmp[kk];
+      const double2* v0 = reinterpret_cast<const double2*>(vec(kk));
 #pragma unroll
       for (int i = 0; i < NE2; ++i) {
         const double2 x0 = v0[tid + KT * i];
@@ -711,14 +684,213 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
     if (!(nn < 0.5 * wn2)) break;  // no severe cancellation: one pass is enough
     wn2 = nn;
   }
-  if (hn > 0) {
-    const double inv = 1.0 / hn;
-    double2* dst = reinterpret_cast<double2*>(Vs + (long)(j + 1) * NV);
+  return hn;
+}
+
+// acc = sum_t coef[t] * vec(t) (registers)
+template <int NE2, class VecF>
+__device__ inline void combine(double2 (&acc)[NE2], int nvec, VecF vec, const double* coef) {
+  for (int t = 0; t < nvec; ++t) {
+    const double c = coef[t];
+    const double2* v0 = reinterpret_cast<const double2*>(vec(t));
 #pragma unroll
-    for (int i = 0; i < NE2; ++i) dst[tid + KT * i] = make_double2(w2[i].x * inv, w2[i].y * inv);
+    for (int i = 0; i < NE2; ++i) {
+      const double2 x0 = v0[threadIdx.x + KT * i];
+      acc[i].x += c * x0.x;
+      acc[i].y += c * x0.y;
+    }
   }
+}
+
+template <int NE2>
+__device__ inline void store2(double* dst, const double2 (&v)[NE2], double scale) {
+  double2* d2 = reinterpret_cast<double2*>(dst);
+#pragma unroll
+  for (int i = 0; i < NE2; ++i)
+    d2[threadIdx.x + KT * i] = make_double2(v[i].x * scale, v[i].y * scale);
+}
+
+template <int NE2>
+__device__ inline void load2(double2 (&v)[NE2], const double* src) {
+  const double2* s2 = reinterpret_cast<const double2*>(src);
+#pragma unroll
+  for (int i = 0; i < NE2; ++i) v[i] = s2[threadIdx.x + KT * i];
+}
+
+// u = U coef (current bank) written to the slot's w buffer, then x += P^-1 u.
+template <int NE2>
+__device__ void x_add_recycled(const EngineArgs& A, int s, int bank, int nvec, const double* coef,
+                               double2 (&tmp)[NE2]) {
+#pragma unroll
+  for (int i = 0; i < NE2; ++i) tmp[i] = make_double2(0.0, 0.0);
+  combine<NE2>(tmp, nvec, [&](int t) { return rec_u(A, s, bank, t); }, coef);
+  double* ws = A.w + (long)s * A.NV;
+  double* xs = A.x + (long)s * A.NV;
+  store2<NE2>(ws, tmp, 1.0);
+  __syncthreads();
+  if (A.use_precond) apply_pinv(A, s, ws, xs, true);
+  else
+    for (int e = threadIdx.x; e < A.NV; e += blockDim.x) xs[e] += ws[e];
+  __syncthreads();
+}
+
+// Per slot and step, according to the slot's phase:
+//   RESTART  w = A x: true residual r = D c0 - w, convergence test, finish or
+//            start a new cycle (r projected off the recycle space C first)
+//   ARNOLDI  w = A P^-1 v_j: orthogonalise against [C, V], Givens update;
+//            at the cycle end x += P^-1 (V y - U B y)
+//   RECYC    w = A P^-1 u_rj for a recycled u (new parameter): C = A P^-1 U
+//            rebuilt one column per step (incremental QR); then x0 from the
+//            recycle space.
+// With REC false the recycle space is empty and this is restarted GMRES.
+template <int NE2, bool REC>
+__global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
+  __shared__ double part[4][kPart];
+  __shared__ double lds[4 * 9];
+  __shared__ double coef[kMaxBasis + 1];
+  __shared__ double ytmp[kMaxBasis + 1];
+  __shared__ double ycoef[kMaxRestart + 1];
+  __shared__ double hcol[kMaxRestart + 2];
+  __shared__ double tco[kMaxRecycle];
+  __shared__ int next_phase;
+  const int s = blockIdx.x;
+  const int r = A.r, ld = A.ld, N = r * ld, NV = A.NV, m = A.m;
+  int* si = A.si + (long)s * SI_N;
+  double* sdv = A.sdv + (long)s * SD_N;
+  const int ph = si[SI_PHASE];
+  if (ph != PH_ARNOLDI && ph != PH_RESTART && !(REC && ph == PH_RECYC)) return;
+
+  double* Vs = A.V + (long)s * (m + 1) * NV;
+  double* ws = A.w + (long)s * NV;
+  double* gs = A.g + (long)s * (m + 1);
+  double* Rs = A.R + (long)s * m * (m + 1);
+  double* css = A.cs + (long)s * m;
+  double* sns = A.sn + (long)s * m;
+  const double bn = sdv[SD_BNORM];
+  const int tid = threadIdx.x;
+  const int kc = REC ? si[SI_KCUR] : 0;
+  const int bank = REC ? si[SI_BANK] : 0;
+  auto cvec = [&](int l) { return rec_c(A, s, bank, l); };
+  const double* d = A.d + (long)s * r;
+
+  double2 w2[NE2];
+  load2<NE2>(w2, ws);
+  double wn0 = 0.0;
+
+  if (REC && ph == PH_RECYC) {
+    // w = A P^-1 u_rj = sum_{l<rj} c_l rho_l + rho c_rj
+    const int rj = si[SI_RJ];
+    const double hn = cgs2<NE2>(w2, rj, cvec, coef, part, ytmp, lds, wn0);
+    const bool ok = isfinite(hn) && hn > 1e-10 * wn0;
+    if (ok) {
+      store2<NE2>(rec_c(A, s, bank, rj), w2, 1.0 / hn);
+      // u_rj = (u_rj - sum_l u_l rho_l) / rho keeps A P^-1 U = C
+      double* urj = rec_u(A, s, bank, rj);
+      load2<NE2>(w2, urj);
+      double2 acc[NE2];
+#pragma unroll
+      for (int i = 0; i < NE2; ++i) acc[i] = make_double2(0.0, 0.0);
+      combine<NE2>(acc, rj, [&](int t) { return rec_u(A, s, bank, t); }, coef);
+#pragma unroll
+      for (int i = 0; i < NE2; ++i) {
+        w2[i].x -= acc[i].x;
+        w2[i].y -= acc[i].y;
+      }
+      store2<NE2>(urj, w2, 1.0 / hn);
+    }
+    const int kn = ok ? rj + 1 : rj;
+    __syncthreads();
+    if (!ok || kn == kc) {
+      // C complete (or cut at a dependent column): x0 = P^-1 U C^T b, b = D c0
+      if (kn > 0) {
+#pragma unroll
+        for (int i = 0; i < NE2; ++i) {
+          const int e = 2 * (tid + KT * i);
+          w2[i].x = e < N ? d[e / ld] * A.c0[e] : 0.0;
+          w2[i].y = e + 1 < N ? d[(e + 1) / ld] * A.c0[e + 1] : 0.0;
+        }
+        double dummy;
+        cgs2<NE2>(w2, kn, cvec, coef, part, ytmp, lds, dummy);
+        x_add_recycled<NE2>(A, s, bank, kn, coef, w2);
+      }
+      if (tid == 0) {
+        si[SI_KCUR] = kn;
+        si[SI_PHASE] = PH_RESTART;
+      }
+    } else if (tid == 0) {
+      si[SI_RJ] = rj + 1;
+    }
+    if (tid == 0) si[SI_ITERS] += 1;
+    return;
+  }
+
+  if (ph == PH_RESTART) {
+    // w = A y ; residual r = D c0 - w into V0
+    double acc = 0;
+#pragma unroll
+    for (int i = 0; i < NE2; ++i) {
+      const int e = 2 * (tid + KT * i);
+      const double r0 = e < N ? d[e / ld] * A.c0[e] - w2[i].x : 0.0;
+      const double r1 = e + 1 < N ? d[(e + 1) / ld] * A.c0[e + 1] - w2[i].y : 0.0;
+      w2[i].x = r0;
+      w2[i].y = r1;
+      acc += r0 * r0 + r1 * r1;
+    }
+    double rn = sqrt(block_sum1(acc, lds));
+    const double rel = rn / bn;
+    const int iters = si[SI_ITERS] + 1;
+    const int refines = si[SI_REFINE];
+    __syncthreads();
+    if (tid == 0) si[SI_ITERS] = iters;
+    __syncthreads();
+    if (!isfinite(rel)) {
+      finish(A, s, LYAP_E_NONFINITE, rel, lds);
+    } else if (rel <= A.tol) {
+      finish(A, s, LYAP_OK, rel, lds);
+    } else if (iters >= A.max_iter || (A.mixed && refines >= A.max_refine)) {
+      finish(A, s, LYAP_E_NOCONV, rel, lds);
+    } else {
+      if (REC && kc > 0) {
+        // project r off C and add the matching correction P^-1 U C^T r to x
+        rn = cgs2<NE2>(w2, kc, cvec, coef, part, ytmp, lds, wn0);
+        if (rn > 0) store2<NE2>(Vs, w2, 1.0 / rn);
+        x_add_recycled<NE2>(A, s, bank, kc, coef, w2);
+        if (!(rn > 0)) {  // r lay in span(C): x is updated, test it again
+          if (tid == 0) si[SI_PHASE] = PH_RESTART;
+          return;
+        }
+      } else {
+        store2<NE2>(Vs, w2, 1.0 / rn);
+      }
+      if (tid == 0) {
+        gs[0] = rn;
+        sdv[SD_BETA] = rn;
+        si[SI_J] = 0;
+        si[SI_CYCLES] += 1;
+        si[SI_REFINE] = refines + 1;
+        si[SI_PHASE] = PH_ARNOLDI;
+      }
+      __syncthreads();
+    }
+    return;
+  }
+
+  // ---- Arnoldi step j: w = A P^-1 v_j, orthogonalised against [C, V_0..j] ----
+  const int j = si[SI_J];
+  const double hn = cgs2<NE2>(
+      w2, kc + j + 1,
+      [&](int t) { return t < kc ? cvec(t) : Vs + (long)(t - kc) * NV; }, coef, part, ytmp, lds,
+      wn0);
+  if (REC && tid < kc) A.Bk[((long)s * A.kmax + tid) * m + j] = coef[tid];
+  if (tid <= j) hcol[tid] = coef[kc + tid];
+  if (hn > 0) store2<NE2>(Vs + (long)(j + 1) * NV, w2, 1.0 / hn);
+  __syncthreads();
   if (tid == 0) {
     hcol[j + 1] = hn;
+    if (REC) {
+      double* hr = A.Hr + ((long)s * m + j) * (m + 1);
+      for (int k = 0; k <= j + 1; ++k) hr[k] = hcol[k];
+    }
     // apply previous rotations
     for (int k = 0; k < j; ++k) {
       const double a = hcol[k], b = hcol[k + 1];
@@ -752,7 +924,12 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
     if (A.mixed) target = fmax(target, A.inner_tol * sdv[SD_BETA]);
     const bool end = est <= target || jn >= m || !(hn > 1e-300 * bn) || iters >= A.max_iter ||
                      !isfinite(est);
-    next_phase = end ? PH_RESTART : PH_ARNOLDI;
+    // a new recycle space only where it can serve: the system restarts
+    // unconverged, or queued parameters may still come to this slot
+    const bool more = !(est <= 0.5 * A.tol * bn) ||
+                      __atomic_load_n(&A.qctl[0], __ATOMIC_RELAXED) <
+                          __atomic_load_n(&A.qctl[1], __ATOMIC_RELAXED);
+    next_phase = !end ? PH_ARNOLDI : ((REC && A.kmax > 0 && more) ? PH_NEWSPACE : PH_RESTART);
     if (end) {
       // back substitution R y = g
       for (int k = jn - 1; k >= 0; --k) {
@@ -760,33 +937,334 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
         for (int l = k + 1; l < jn; ++l) v -= Rs[(long)l * (m + 1) + k] * ycoef[l];
         ycoef[k] = v / Rs[(long)k * (m + 1) + k];
       }
+      // recycle coefficients t = -B y (the C component of the minimiser)
+      for (int l = 0; l < kc; ++l) {
+        const double* bl = A.Bk + ((long)s * A.kmax + l) * m;
+        double v = 0;
+        for (int k = 0; k < jn; ++k) v += bl[k] * ycoef[k];
+        tco[l] = -v;
+      }
     }
   }
   __syncthreads();
-  if (next_phase == PH_RESTART) {
+  if (next_phase != PH_ARNOLDI) {
     const int jn = j + 1;
-    // u = V y (into w), x += P^-1 u
+    // u = V y - U B y (into w), x += P^-1 u
 #pragma unroll
     for (int i = 0; i < NE2; ++i) w2[i] = make_double2(0.0, 0.0);
-    for (int kk = 0; kk < jn; ++kk) {
-      const double c = ycoef[kk];
-      const double2* v0 = reinterpret_cast<const double2*>(Vs + (long)kk * NV);
-#pragma unroll
-      for (int i = 0; i < NE2; ++i) {
-        const double2 x0 = v0[tid + KT * i];
-        w2[i].x += c * x0.x;
-        w2[i].y += c * x0.y;
-      }
-    }
-    double2* wd = reinterpret_cast<double2*>(ws);
-#pragma unroll
-    for (int i = 0; i < NE2; ++i) wd[tid + KT * i] = w2[i];
+    combine<NE2>(w2, jn, [&](int t) { return Vs + (long)t * NV; }, ycoef);
+    if (REC && kc > 0) combine<NE2>(w2, kc, [&](int t) { return rec_u(A, s, bank, t); }, tco);
+    store2<NE2>(ws, w2, 1.0);
     __syncthreads();
+    double* xs = A.x + (long)s * NV;
     if (A.use_precond) apply_pinv(A, s, ws, xs, true);
     else
       for (int e = tid; e < NV; e += blockDim.x) xs[e] += ws[e];
     __syncthreads();
-    if (tid == 0) si[SI_PHASE] = PH_RESTART;
+    if (tid == 0) si[SI_PHASE] = next_phase;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Recycle-space update at the end of a cycle (GCRO-DR, deflated restart).
+// The cycle gave  A P^-1 Vh = Wh G  with  Vh = [U Dk, V_0..mm-1],
+// Wh = [C, V_0..mm]  (orthonormal),  G = [[Dk, B], [0, Hbar]]  (upper
+// Hessenberg), Dk = diag(1/||u_l||).  Its Givens QR is G = Q R with
+// Q = diag(I, Q_H), R = [[Dk, B], [0, R_H]].  Harmonic Ritz values theta of
+// A P^-1 on span(Vh) are 1/mu for the eigenvalues mu of
+// F = Q^T (Wh^T Vh) R^-1; the kt of smallest |theta| span the dominant
+// invariant subspace Z of F (orthogonal iteration).  New space:
+// U = Vh R^-1 Z,  C = Wh G R^-1 Z, orthonormalised together, so that
+// A P^-1 U = C holds to the accuracy of the Arnoldi relation.
+// ---------------------------------------------------------------------------
+constexpr int kRecIters = 24;
+constexpr int kRecScratch = (kMaxRestart + 1) * kMaxRestart;  // F, row-major, ld kMaxRestart
+
+// in-place Cholesky of the kt x kt Gram matrix (thread 0); returns the number
+// of leading columns that are numerically independent
+__device__ inline int chol_small(double* Gm, int kt, int ldg) {
+  double dmax = 0;
+  for (int q = 0; q < kt; ++q) dmax = fmax(dmax, Gm[q * ldg + q]);
+  for (int q = 0; q < kt; ++q) {
+    double v = Gm[q * ldg + q];
+    for (int p = 0; p < q; ++p) v -= Gm[q * ldg + p] * Gm[q * ldg + p];
+    if (!(v > 1e-24 * dmax)) return q;
+    const double lq = sqrt(v);
+    Gm[q * ldg + q] = lq;
+    for (int i = q + 1; i < kt; ++i) {
+      double u = Gm[i * ldg + q];
+      for (int p = 0; p < q; ++p) u -= Gm[i * ldg + p] * Gm[q * ldg + p];
+      Gm[i * ldg + q] = u / lq;
+    }
+  }
+  return kt;
+}
+
+template <int NE2>
+__global__ void __launch_bounds__(KT) k_recycle(EngineArgs A) {
+  constexpr int G = NE2 <= 8 ? 4 : (NE2 <= 16 ? 2 : 1);  // vectors held in registers
+  constexpr int LDZ = kMaxRecycle;
+  __shared__ double Z[kMaxRestart + 1][LDZ];
+  __shared__ double FZ[kMaxRestart + 1][LDZ];
+  __shared__ double CU[kMaxRecycle][kMaxRecycle];
+  __shared__ double VU[kMaxRestart + 1][kMaxRecycle];
+  __shared__ double part[4][(kMaxBasis + 1) * 4];
+  __shared__ double Gm[kMaxRecycle * kMaxRecycle];
+  __shared__ double dk[kMaxRecycle];
+  __shared__ int kt_sh;
+  const int s = blockIdx.x;
+  int* si = A.si + (long)s * SI_N;
+  if (si[SI_PHASE] != PH_NEWSPACE) return;
+  const int m = A.m, NV = A.NV;
+  const int kk = si[SI_KCUR], mm = si[SI_J], bank = si[SI_BANK];
+  const int nh = kk + mm;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double* Vs = A.V + (long)s * (m + 1) * NV;
+  const double* Rs = A.R + (long)s * m * (m + 1);
+  const double* Hr = A.Hr + (long)s * m * (m + 1);
+  const double* Bk = A.Bk + (long)s * A.kmax * m;
+  const double* css = A.cs + (long)s * m;
+  const double* sns = A.sn + (long)s * m;
+  double* F = A.Fs + (long)s * kRecScratch;
+  auto wvec = [&](int t) { return t < kk ? rec_c(A, s, bank, t) : Vs + (long)(t - kk) * NV; };
+  auto vvec = [&](int t) { return t < kk ? rec_u(A, s, bank, t) : Vs + (long)(t - kk) * NV; };
+
+  // ---- A: dots  C^T U,  V_0..mm^T U  and ||u_l|| (G recycled vectors at a time) ----
+  for (int l0 = 0; l0 < kk; l0 += G) {
+    const int gn = min(G, kk - l0);
+    double2 u[G][NE2];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      if (g < gn) load2<NE2>(u[g], rec_u(A, s, bank, l0 + g));
+      else
+#pragma unroll
+        for (int i = 0; i < NE2; ++i) u[g][i] = make_double2(0.0, 0.0);
+    }
+    const int nt = kk + mm + 1;  // Wh columns
+    for (int t = 0; t <= nt; ++t) {
+      // t < nt: <Wh_t, u_g>;  t == nt: ||u_g||^2
+      double a[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) a[g] = 0.0;
+      if (t < nt) {
+        const double2* x = reinterpret_cast<const double2*>(wvec(t));
+#pragma unroll
+        for (int i = 0; i < NE2; ++i) {
+          const double2 xv = x[tid + KT * i];
+#pragma unroll
+          for (int g = 0; g < G; ++g) a[g] += xv.x * u[g][i].x + xv.y * u[g][i].y;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < NE2; ++i)
+#pragma unroll
+          for (int g = 0; g < G; ++g) a[g] += u[g][i].x * u[g][i].x + u[g][i].y * u[g][i].y;
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        a[g] = wave_sum(a[g]);
+        if (lane == 0) part[wave][t * G + g] = a[g];
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < (nt + 1) * gn; e += KT) {
+      const int t = e / gn, g = e % gn;
+      const double v = part[0][t * G + g] + part[1][t * G + g] + part[2][t * G + g] +
+                       part[3][t * G + g];
+      const int l = l0 + g;
+      if (t < kk) CU[t][l] = v;
+      else if (t < nt) VU[t - kk][l] = v;
+      else dk[l] = 1.0 / sqrt(v);
+    }
+    __syncthreads();
+  }
+
+  // R (nh x nh upper triangular) entry
+  auto Rget = [&](int l, int c) -> double {
+    if (l > c) return 0.0;
+    if (c < kk) return l == c ? dk[c] : 0.0;
+    const int cc = c - kk;
+    return l < kk ? Bk[(long)l * m + cc] : Rs[(long)cc * (m + 1) + (l - kk)];
+  };
+  // G ((nh+1) x nh upper Hessenberg) entry
+  auto Gget = [&](int i, int c) -> double {
+    if (c < kk) return i == c ? dk[c] : 0.0;
+    const int cc = c - kk;
+    return i < kk ? Bk[(long)i * m + cc] : Hr[(long)cc * (m + 1) + (i - kk)];
+  };
+
+  // ---- B1: Y = Q^T (Wh^T Vh), one column per thread, into F ----
+  if (tid < nh) {
+    const int c = tid;
+    // top rows (C^T): C^T U Dk for c < kk, 0 for the V columns
+    for (int i = 0; i < kk; ++i) F[i * kMaxRestart + c] = c < kk ? CU[i][c] * dk[c] : 0.0;
+    // bottom: Q_H^T applied to V^T U Dk or to e_(c-kk); rows kk..kk+mm of
+    // column c serve as the work vector (row kk+mm is the spare row of F)
+    double* col = F + (long)kk * kMaxRestart + c;
+    for (int i = 0; i <= mm; ++i)
+      col[i * kMaxRestart] = c < kk ? VU[i][c] * dk[c] : (i == c - kk ? 1.0 : 0.0);
+    for (int i = 0; i < mm; ++i) {  // the cycle's rotations, in order
+      const double a = col[i * kMaxRestart], b = col[(i + 1) * kMaxRestart];
+      col[i * kMaxRestart] = css[i] * a + sns[i] * b;
+      col[(i + 1) * kMaxRestart] = -sns[i] * a + css[i] * b;
+    }
+  }
+  __syncthreads();
+  // ---- B2: F = Y R^-1, one row per thread (forward substitution x R = y) ----
+  if (tid < nh) {
+    double* fr = F + tid * kMaxRestart;
+    for (int c = 0; c < nh; ++c) {
+      double v = fr[c];
+      for (int l = 0; l < c; ++l) v -= fr[l] * Rget(l, c);
+      fr[c] = v / Rget(c, c);
+    }
+  }
+  if (tid == 0) kt_sh = min(A.kmax, nh);
+  // deterministic start block
+  for (int e = tid; e < nh * LDZ; e += KT) {
+    const int i = e / LDZ, q = e % LDZ;
+    unsigned h = (unsigned)(i * 2654435761u) ^ (unsigned)((q + 1) * 2246822519u);
+    h ^= h >> 15;
+    h *= 2654435761u;
+    h ^= h >> 13;
+    Z[i][q] = ((double)(h & 0xffffff) / 8388608.0) - 1.0;
+  }
+  __syncthreads();
+
+  // ---- B3: orthogonal iteration on F, block orthonormalised by Cholesky QR ----
+  for (int it = 0; it <= kRecIters; ++it) {
+    const int kt = kt_sh;
+    if (kt == 0) break;
+    if (it > 0) {
+      for (int e = tid; e < nh * kt; e += KT) {
+        const int i = e / kt, q = e % kt;
+        const double* fr = F + i * kMaxRestart;
+        double v = 0;
+        for (int l = 0; l < nh; ++l) v += fr[l] * Z[l][q];
+        FZ[i][q] = v;
+      }
+    } else {
+      for (int e = tid; e < nh * kt; e += KT) FZ[e / kt][e % kt] = Z[e / kt][e % kt];
+    }
+    __syncthreads();
+    for (int e = tid; e < kt * kt; e += KT) {
+      const int p = e / kt, q = e % kt;
+      double v = 0;
+      for (int i = 0; i < nh; ++i) v += FZ[i][p] * FZ[i][q];
+      Gm[p * kMaxRecycle + q] = v;
+    }
+    __syncthreads();
+    if (tid == 0) kt_sh = chol_small(Gm, kt, kMaxRecycle);
+    __syncthreads();
+    const int kn = kt_sh;
+    // Z = FZ L^-T (row-wise), first kn columns
+    if (tid < nh) {
+      for (int q = 0; q < kn; ++q) {
+        double v = FZ[tid][q];
+        for (int p = 0; p < q; ++p) v -= Z[tid][p] * Gm[q * kMaxRecycle + p];
+        Z[tid][q] = v / Gm[q * kMaxRecycle + q];
+      }
+    }
+    __syncthreads();
+  }
+  const int kt = kt_sh;
+
+  // ---- B4: P = R^-1 Z (in place, back substitution per column) ----
+  if (tid < kt) {
+    const int q = tid;
+    for (int i = nh - 1; i >= 0; --i) {
+      double v = Z[i][q];
+      for (int l = i + 1; l < nh; ++l) v -= Rget(i, l) * Z[l][q];
+      Z[i][q] = v / Rget(i, i);
+    }
+  }
+  __syncthreads();
+  // ---- B5: c = G P, then (c, P) L^-T twice so that Wh c is orthonormal ----
+  int kf = kt;
+  for (int rep = 0; rep < 3 && kf > 0; ++rep) {
+    if (rep == 0) {
+      for (int e = tid; e < (nh + 1) * kf; e += KT) {
+        const int i = e / kf, q = e % kf;
+        double v = 0;
+        const int c0 = i < kk ? 0 : max(kk, kk + (i - kk) - 1);  // Hessenberg: G[i][c] = 0 for c < i-1
+        for (int c = c0; c < nh; ++c) v += Gget(i, c) * Z[c][q];
+        FZ[i][q] = v;
+      }
+      __syncthreads();
+      continue;
+    }
+    for (int e = tid; e < kf * kf; e += KT) {
+      const int p = e / kf, q = e % kf;
+      double v = 0;
+      for (int i = 0; i <= nh; ++i) v += FZ[i][p] * FZ[i][q];
+      Gm[p * kMaxRecycle + q] = v;
+    }
+    __syncthreads();
+    if (tid == 0) kt_sh = chol_small(Gm, kf, kMaxRecycle);
+    __syncthreads();
+    const int kn = kt_sh;
+    if (tid <= nh) {
+      for (int q = 0; q < kn; ++q) {
+        double vc = FZ[tid][q], vp = tid < nh ? Z[tid][q] : 0.0;
+        for (int p = 0; p < q; ++p) {
+          vc -= FZ[tid][p] * Gm[q * kMaxRecycle + p];
+          if (tid < nh) vp -= Z[tid][p] * Gm[q * kMaxRecycle + p];
+        }
+        FZ[tid][q] = vc / Gm[q * kMaxRecycle + q];
+        if (tid < nh) Z[tid][q] = vp / Gm[q * kMaxRecycle + q];
+      }
+    }
+    __syncthreads();
+    kf = kn;
+  }
+  // fold Dk into the U rows of P; a non-finite coefficient drops the space
+  for (int e = tid; e < kk * kf; e += KT) Z[e / kf][e % kf] *= dk[e / kf];
+  if (tid == 0) kt_sh = 0;
+  __syncthreads();
+  for (int e = tid; e < (nh + 1) * kf; e += KT) {
+    const int i = e / kf, q = e % kf;
+    if (!isfinite(FZ[i][q]) || (i < nh && !isfinite(Z[i][q]))) kt_sh = 1;
+  }
+  __syncthreads();
+  if (kt_sh) kf = 0;
+
+  // ---- C: new U = Vh P, C = Wh c into the other bank ----
+  const int nb = bank ^ 1;
+  for (int q0 = 0; q0 < kf; q0 += G) {
+    const int gn = min(G, kf - q0);
+    for (int which = 0; which < 2; ++which) {
+      double2 acc[G][NE2];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int i = 0; i < NE2; ++i) acc[g][i] = make_double2(0.0, 0.0);
+      const int nt = which == 0 ? nh : nh + 1;
+      for (int t = 0; t < nt; ++t) {
+        const double2* x = reinterpret_cast<const double2*>(which == 0 ? vvec(t) : wvec(t));
+        double cf[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) cf[g] = g < gn ? (which == 0 ? Z[t][q0 + g] : FZ[t][q0 + g]) : 0.0;
+#pragma unroll
+        for (int i = 0; i < NE2; ++i) {
+          const double2 xv = x[tid + KT * i];
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            acc[g][i].x += cf[g] * xv.x;
+            acc[g][i].y += cf[g] * xv.y;
+          }
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        if (g < gn)
+          store2<NE2>(which == 0 ? rec_u(A, s, nb, q0 + g) : rec_c(A, s, nb, q0 + g), acc[g], 1.0);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    si[SI_KCUR] = kf;
+    si[SI_BANK] = nb;
+    si[SI_PHASE] = PH_RESTART;
   }
 }
 
@@ -800,21 +1278,34 @@ static long long slot_stride(long long r, long long ld) {
   throw Error{LYAP_E_INVAL, "r * n too large for the Krylov kernel (r * ld <= 16384)"};
 }
 
-// elements-per-thread bound of the Krylov kernel: NV = 512 * NE2
-static void launch_krylov(const EngineArgs& A, int S, long long NV, hipStream_t st) {
+template <int NE2>
+static void launch_krylov_ne(const EngineArgs& A, int S, hipStream_t st, bool update) {
+  if (update) {
+    hipLaunchKernelGGL((k_recycle<NE2>), dim3(S), dim3(KT), 0, st, A);
+  } else if (A.kmax > 0) {
+    hipLaunchKernelGGL((k_krylov<NE2, true>), dim3(S), dim3(KT), 0, st, A);
+  } else {
+    hipLaunchKernelGGL((k_krylov<NE2, false>), dim3(S), dim3(KT), 0, st, A);
+  }
+}
+
+// elements-per-thread bound of the Krylov kernels: NV = 512 * NE2.  update
+// selects the recycle-space update kernel instead of the Krylov step.
+static void launch_krylov(const EngineArgs& A, int S, long long NV, hipStream_t st,
+                          bool update = false) {
   switch (NV / 512) {
-    case 1: hipLaunchKernelGGL(k_krylov<1>, dim3(S), dim3(KT), 0, st, A); break;
-    case 2: hipLaunchKernelGGL(k_krylov<2>, dim3(S), dim3(KT), 0, st, A); break;
-    case 3: hipLaunchKernelGGL(k_krylov<3>, dim3(S), dim3(KT), 0, st, A); break;
-    case 4: hipLaunchKernelGGL(k_krylov<4>, dim3(S), dim3(KT), 0, st, A); break;
-    case 5: hipLaunchKernelGGL(k_krylov<5>, dim3(S), dim3(KT), 0, st, A); break;
-    case 6: hipLaunchKernelGGL(k_krylov<6>, dim3(S), dim3(KT), 0, st, A); break;
-    case 7: hipLaunchKernelGGL(k_krylov<7>, dim3(S), dim3(KT), 0, st, A); break;
-    case 8: hipLaunchKernelGGL(k_krylov<8>, dim3(S), dim3(KT), 0, st, A); break;
-    case 12: hipLaunchKernelGGL(k_krylov<12>, dim3(S), dim3(KT), 0, st, A); break;
-    case 16: hipLaunchKernelGGL(k_krylov<16>, dim3(S), dim3(KT), 0, st, A); break;
-    case 24: hipLaunchKernelGGL(k_krylov<24>, dim3(S), dim3(KT), 0, st, A); break;
-    case 32: hipLaunchKernelGGL(k_krylov<32>, dim3(S), dim3(KT), 0, st, A); break;
+    case 1: launch_krylov_ne<1>(A, S, st, update); break;
+    case 2: launch_krylov_ne<2>(A, S, st, update); break;
+    case 3: launch_krylov_ne<3>(A, S, st, update); break;
+    case 4: launch_krylov_ne<4>(A, S, st, update); break;
+    case 5: launch_krylov_ne<5>(A, S, st, update); break;
+    case 6: launch_krylov_ne<6>(A, S, st, update); break;
+    case 7: launch_krylov_ne<7>(A, S, st, update); break;
+    case 8: launch_krylov_ne<8>(A, S, st, update); break;
+    case 12: launch_krylov_ne<12>(A, S, st, update); break;
+    case 16: launch_krylov_ne<16>(A, S, st, update); break;
+    case 24: launch_krylov_ne<24>(A, S, st, update); break;
+    case 32: launch_krylov_ne<32>(A, S, st, update); break;
     default: throw Error{LYAP_E_INVAL, "unsupported r * n for the Krylov kernel"};
   }
 }
@@ -856,6 +1347,7 @@ struct lyap_engine_s {
   long long harvested = 0;   // queue positions whose result was returned
   long long next_tag = 0;
   DevBuf si, sdv, d, R, g, cs, sn, V, x, z, w, Pinv, lists, X, H, Hp, Xlo, Hlo, Hplo, XS;
+  DevBuf Ur, Cr, Bk, Hr, Fs;  // recycle space (GCRO-DR)
   DevBuf qd, qtag, qctl, res;
   double* sol = nullptr;
   long long sol_cap = 0;
@@ -902,6 +1394,10 @@ static void validate_opts(const lyap_solve_opts& o) {
   LYAP_REQUIRE(o.restart >= 1 && o.restart <= kMaxRestart, LYAP_E_INVAL, "restart out of [1, 64]");
   LYAP_REQUIRE(o.tol > 0 && o.tol < 1, LYAP_E_INVAL, "tol out of (0, 1)");
   LYAP_REQUIRE(o.max_iter >= 1, LYAP_E_INVAL, "max_iter < 1");
+  LYAP_REQUIRE(o.recycle_k >= 0 && o.recycle_k <= kMaxRecycle, LYAP_E_INVAL,
+               "recycle_k out of [0, 16]");
+  LYAP_REQUIRE(o.restart + o.recycle_k <= kMaxRestart, LYAP_E_INVAL,
+               "restart + recycle_k > 64");
 }
 
 struct EngineSizes {
@@ -926,6 +1422,13 @@ static EngineSizes engine_sizes(const lyap_seed_s* sd, long long S, const lyap_s
   add(S * r * r * ld * 8);
   add((2 * S + 2) * 4);
   add(z.rows_pad * ld * 8 * 3);  // X, H, split-K partials fp64
+  if (o.recycle_k > 0) {
+    const long long k = o.recycle_k;
+    add(S * 2 * k * N * 8 * 2);        // U, C (two banks each)
+    add(S * k * m * 8);                // B
+    add(S * m * (m + 1) * 8);          // unrotated Hessenberg
+    add(S * (long long)kRecScratch * 8);
+  }
   if (sd->basis == LYAP_BASIS_SCHUR) add(S * ld * ld * 8);  // per-slot Schur-basis solutions
   const bool mixed = o.prec != LYAP_PREC_FP64;
   if (mixed) {
@@ -1025,6 +1528,7 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
   if (ev) LYAP_HIP(hipEventRecord(ev->kry[0], st));
   launch_krylov(A, S, (long long)A.NV, st);
   if (ev) LYAP_HIP(hipEventRecord(ev->kry[1], st));
+  if (A.kmax > 0) launch_krylov(A, S, (long long)A.NV, st, true);
   hipLaunchKernelGGL(k_admit, dim3(S), dim3(KT), 0, st, A);
   LYAP_HIP(hipGetLastError());
 }
@@ -1205,6 +1709,14 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   zalloc(E->w, S * N * 8);
   zalloc(E->Pinv, S * r * r * ld * 8);
   zalloc(E->lists, (2 * S + 2) * 4);
+  if (o.recycle_k > 0) {
+    const long long k = o.recycle_k;
+    zalloc(E->Ur, S * 2 * k * N * 8);
+    zalloc(E->Cr, S * 2 * k * N * 8);
+    zalloc(E->Bk, S * k * m * 8);
+    zalloc(E->Hr, S * m * (m + 1) * 8);
+    zalloc(E->Fs, S * (long long)kRecScratch * 8);
+  }
   if (sd->basis == LYAP_BASIS_SCHUR) zalloc(E->XS, S * ld * ld * 8);
   zalloc(E->X, z.rows_pad * ld * 8);
   zalloc(E->H, z.rows_pad * ld * 8);
@@ -1263,6 +1775,12 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   A.Q = (int)Q;
   A.sol = sol;
   A.sol_cap = sol_cap;
+  A.kmax = o.recycle_k;
+  A.Ur = E->Ur.as<double>();
+  A.Cr = E->Cr.as<double>();
+  A.Bk = E->Bk.as<double>();
+  A.Hr = E->Hr.as<double>();
+  A.Fs = E->Fs.as<double>();
   LYAP_HIP(hipStreamSynchronize(st));
 
   if (use_graph) {

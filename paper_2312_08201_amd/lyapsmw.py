@@ -178,10 +178,10 @@ def _dev_ptr(t, dtype_name="float64", shape=None):
 
 
 def solve_opts(prec="fp64", tol=1e-12, max_iter=600, restart=40, use_precond=True,
-               max_refine=30, inner_tol=1e-4) -> SolveOpts:
+               max_refine=30, inner_tol=1e-4, recycle_k=0) -> SolveOpts:
     return SolveOpts(PREC[prec] if isinstance(prec, str) else int(prec), int(max_iter),
-                     int(restart), 1 if use_precond else 0, 0, int(max_refine), float(tol),
-                     float(inner_tol))
+                     int(restart), 1 if use_precond else 0, int(recycle_k), int(max_refine),
+                     float(tol), float(inner_tol))
 
 
 class Seed:

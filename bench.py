@@ -136,6 +136,8 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_ir", "bf16_ir", "fp32"])
     ap.add_argument("--restart", type=int, default=40)
+    ap.add_argument("--tsvd-rank", type=int, default=0,
+                    help="rank of the coupling TSVD in the preconditioner (0: block-diagonal part)")
     ap.add_argument("--recycle-k", type=int, default=0,
                     help="GCRO-DR recycle space dimension (0: restarted GMRES)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -179,7 +181,7 @@ def main():
 
     pr = W.config(args.config)
     t = time.perf_counter()
-    seed = L.Seed.from_problem(pr)
+    seed = L.Seed.from_problem(pr, tsvd_rank=args.tsvd_rank)
     factor_s = time.perf_counter() - t
     info = seed.info()
     d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
@@ -239,7 +241,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD[args.config], "P": P, "n": pr.n, "r": pr.r,
                    "precision": args.prec, "restart": args.restart,
-                   "recycle_k": args.recycle_k},
+                   "recycle_k": args.recycle_k, "tsvd_rank": args.tsvd_rank},
         "p50_ms": 1e3 * float(np.percentile(lat, 50)),
         "p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "all_converged": ok,

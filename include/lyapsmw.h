@@ -76,13 +76,21 @@ typedef struct {
   int32_t basis;          /* lyap_basis */
   int32_t E_is_diag;      /* 1: E is an n-vector (diagonal); 0: E is dense n x n (symmetrised) */
   double max_eig_cond;    /* AUTO switches to the Schur basis above this (default 1e6 if <= 0) */
+  int32_t tsvd_rank;      /* rank pbar of the truncated SVD of the dense coupling block that
+                             completes the preconditioner of eq:prec (Section 2.1); 0 (default)
+                             keeps only its exact block-diagonal part; at most 64; eigenbasis
+                             seeds only (ignored in the Schur basis) */
+  int32_t reserved;       /* 0 */
 } lyap_seed_opts;
 
 typedef struct {
   int32_t prec;           /* lyap_prec */
   int32_t max_iter;       /* total matrix-vector products per parameter (default 600) */
   int32_t restart;        /* Krylov dimension per cycle m (default 40, at most 64) */
-  int32_t use_precond;    /* 1: right preconditioner = exact diagonal blocks of eq:prec (default 1) */
+  int32_t use_precond;    /* right preconditioner of eq:prec: 1 (default) = its exact
+                             block-diagonal part plus the seed's coupling TSVD if it holds one
+                             (lyap_seed_opts.tsvd_rank), 2 = block-diagonal part only,
+                             0 = none; the eigenbasis path with r <= 8 only */
   int32_t recycle_k;      /* GCRO-DR recycle space dimension s (Section 2.1, Parks et al.):
                              0 = restarted GMRES (default); at most 16, restart + recycle_k
                              <= 64.  Each cycle end replaces the space by the harmonic Ritz
@@ -107,7 +115,7 @@ typedef struct {
   int64_t npairs;         /* complex-conjugate eigenvalue pairs (h); real eigenvalues = n - 2h */
   int64_t ld;             /* padded leading dimension of every n-vector on the device */
   int32_t basis;          /* basis actually used */
-  int32_t reserved;
+  int32_t tsvd_rank;      /* rank of the coupling TSVD held by the seed (0: none) */
   double cond_est;        /* ||S||_1 ||S^-1||_1 of the real eigenbasis (unit-norm eigenvectors) */
   double min_lam_sum;     /* min |lambda_i + lambda_j| / max |lambda_i + lambda_j| */
   double max_re_lambda;   /* largest real part of the seed spectrum */

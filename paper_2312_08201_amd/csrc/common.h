@@ -118,6 +118,9 @@ struct GemmArgs {
   const int* M_dev;   // optional device row count (scaled by m_scale)
   int m_scale;
   void* Cpart;        // optional split-K partial buffer (same size as C), dynamic M only
+  int64_t grid_min;   // optional: launch at least this many workgroups (more split-K
+                      // slices for skinny shapes; Cpart must then hold grid_min / 2
+                      // row tiles)
 };
 
 constexpr int kGemmBM = 128;

@@ -5,7 +5,8 @@
 // a HIP graph):
 //   k_lists     compact the slots that need an FP64 or a low-precision
 //               matrix-vector product into two lists (device counts)
-//   k_prep      z = P^-1 v_j (Arnoldi step) or z = y (residual step)
+//   k_prep      z = P^-1 v_j (Arnoldi step) or z = P^-1 u (residual step);
+//               the iterate u is kept before preconditioning, y = P^-1 u
 //   k_formX     rows (p, a, b) of the Cauchy GEMM: Vh_a o z_b
 //   GEMM        H = X * Mc  (MFMA, FP64 or FP32 / split-BF16)
 //   k_epilogue  w = z - D (sum_b z_b o K1_ab + sum_b Uh_b o H_pab)
@@ -41,8 +42,10 @@ enum Phase : int { PH_FREE = 0, PH_ARNOLDI = 1, PH_RESTART = 2, PH_RECYC = 3, PH
 // per-slot integer state (KCUR: valid recycle vectors, RJ: next one to
 // rebuild for a new parameter, BANK: which of the two U/C banks is current)
 enum SI : int {
-  SI_PHASE = 0, SI_J, SI_ITERS, SI_CYCLES, SI_REFINE, SI_QPOS, SI_KCUR, SI_RJ, SI_BANK, SI_N
+  SI_PHASE = 0, SI_J, SI_ITERS, SI_CYCLES, SI_REFINE, SI_QPOS, SI_KCUR, SI_RJ, SI_BANK, SI_CAPSET,
+  SI_N
 };
+constexpr int kPbarMax = 64;  // TSVD rank bound of the preconditioner
 // per-slot double state
 enum SD : int { SD_BNORM = 0, SD_BETA, SD_N };
 
@@ -94,6 +97,16 @@ struct EngineArgs {
   double* Bk;   // S x kmax x m: C^T A P^-1 v_j of the current cycle
   double* Hr;   // S x m x (m+1): unrotated Hessenberg columns
   double* Fs;   // S x kRecScratch: recycle-update work matrix
+  // low-rank coupling of the preconditioner (TSVD rank pbar; 0 disables it)
+  int pbar, Ks;         // Ks = r * ld
+  const double* TsM;    // Ks x 128: Mt
+  const double* TsN;    // Ks x 128: Nt
+  double* Cpinv;        // S x 64 x 64: (I - Mt^T B^-1 D Nt)^-1 per slot
+  double* Yc;           // list-compacted y = B^-1 v rows (Ks)
+  double* Tbuf;         // list rows x 128: Mt^T y
+  double* Tpart;        // split-K partials of Tbuf
+  double* Sc;           // list rows x 128: Cp^-1 Mt^T y
+  double* Qc;           // list rows x Ks: Nt Cp^-1 Mt^T y
 };
 
 __device__ inline double* rec_u(const EngineArgs& A, int s, int bank, int l) {
@@ -144,7 +157,7 @@ __device__ inline int uslot(int u, int h, bool& pr) {
 
 // z_a[u] = sum_b P[a][b][u] o v_b[u] for one slot (all units, all a)
 __device__ inline void apply_pinv(const EngineArgs& A, int s, const double* v, double* zout,
-                                  bool accumulate) {
+                                  bool accumulate, const double* vscale = nullptr) {
   const int r = A.r, ld = A.ld, nu = A.n - A.h;
   const double* P = A.Pinv + (long)s * r * r * ld;
   for (int u = threadIdx.x; u < nu; u += blockDim.x) {
@@ -156,11 +169,12 @@ __device__ inline void apply_pinv(const EngineArgs& A, int s, const double* v, d
         const double* pb = P + (long)(a * r + b) * ld;
         const double* vb = v + (long)b * ld;
         if (pr) {
-          const double pr_ = pb[q], pi_ = pb[q + 1], vr = vb[q], vi = vb[q + 1];
+          const double f = vscale ? vscale[b] : 1.0;
+          const double pr_ = pb[q], pi_ = pb[q + 1], vr = f * vb[q], vi = f * vb[q + 1];
           sr += pr_ * vr - pi_ * vi;
           si += pr_ * vi + pi_ * vr;
         } else {
-          sr += pb[q] * vb[q];
+          sr += pb[q] * (vscale ? vscale[b] : 1.0) * vb[q];
         }
       }
       double* za = zout + (long)a * ld;
@@ -340,6 +354,7 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
     const bool rec = A.kmax > 0 && si[SI_KCUR] > 0;
     si[SI_PHASE] = rec ? PH_RECYC : PH_ARNOLDI;
     si[SI_RJ] = 0;
+    si[SI_CAPSET] = A.pbar > 0 ? 1 : 0;
     si[SI_J] = 0;
     si[SI_ITERS] = 0;
     si[SI_CYCLES] = rec ? 0 : 1;
@@ -370,7 +385,8 @@ __device__ inline int claim(const EngineArgs& A) {
 __device__ void finish(const EngineArgs& A, int s, int status, double relres, double* lds) {
   const int r = A.r, ld = A.ld, N = r * ld;
   int* si = A.si + (long)s * SI_N;
-  const double* xs = A.x + (long)s * A.NV;
+  // the solution y = P^-1 u, formed by this step's prep for the residual
+  const double* xs = A.z + (long)s * A.NV;
   double acc = 0;
   for (int e = threadIdx.x; e < N; e += blockDim.x) acc += A.gam[e] * xs[e];
   const double tr = A.t0 + block_sum1(acc, lds);
@@ -430,6 +446,7 @@ __global__ void __launch_bounds__(1024) k_lists(EngineArgs A) {
   if (threadIdx.x == blockDim.x - 1) {
     A.lists[2 * S] = c64[threadIdx.x];
     A.lists[2 * S + 1] = clo[threadIdx.x];
+    A.lists[2 * S + 2] = c64[threadIdx.x] + clo[threadIdx.x];
   }
   // exclusive offsets
   const int ex64 = c64[threadIdx.x] - n64, exlo = clo[threadIdx.x] - nlo;
@@ -455,18 +472,207 @@ __global__ void __launch_bounds__(KT) k_prep(EngineArgs A) {
     const int s = li < c64 ? A.lists[li] : A.lists[S + (li - c64)];
     const int ph = A.si[(long)s * SI_N + SI_PHASE];
     double* zs = A.z + (long)s * A.NV;
-    if (ph == PH_RESTART) {
-      const double* xs = A.x + (long)s * A.NV;
-      for (int e = threadIdx.x; e < N; e += blockDim.x) zs[e] = xs[e];
-    } else {
-      const int* sis = A.si + (long)s * SI_N;
-      const double* vj = ph == PH_RECYC ? rec_u(A, s, sis[SI_BANK], sis[SI_RJ])
-                                        : A.V + ((long)s * (A.m + 1) + sis[SI_J]) * A.NV;
-      if (A.use_precond) apply_pinv(A, s, vj, zs, false);
-      else
-        for (int e = threadIdx.x; e < N; e += blockDim.x) zs[e] = vj[e];
+    // source: the iterate u (residual step), v_j (Arnoldi) or a recycled u_rj
+    const int* sis = A.si + (long)s * SI_N;
+    const double* src = ph == PH_RESTART ? A.x + (long)s * A.NV
+                        : ph == PH_RECYC ? rec_u(A, s, sis[SI_BANK], sis[SI_RJ])
+                                         : A.V + ((long)s * (A.m + 1) + sis[SI_J]) * A.NV;
+    if (A.use_precond) apply_pinv(A, s, src, zs, false);
+    else
+      for (int e = threadIdx.x; e < N; e += blockDim.x) zs[e] = src[e];
+    if (A.pbar > 0) {
+      __syncthreads();
+      double* yc = A.Yc + (long)li * A.Ks;
+      for (int e = threadIdx.x; e < N; e += blockDim.x) yc[e] = zs[e];
+      __syncthreads();
     }
   }
+}
+
+// ---- low-rank part of the preconditioner (TSVD of the coupling) ----
+// P = B - D Nt Mt^T with B the block-diagonal part; by SMW
+//   P^-1 v = y + B^-1 D Nt Cp^-1 Mt^T y,  y = B^-1 v,  Cp = I - Mt^T B^-1 D Nt.
+// Per step: k_prep (y), GEMM Tbuf = Yc Mt, k_cap (Sc = Cp^-1 Tbuf),
+// GEMM Qc = Sc Nt^T, k_prep2 (z = y + B^-1 D Qc).
+__global__ void __launch_bounds__(KT) k_cap(EngineArgs A, int ggrid) {
+  __shared__ double t[kPbarMax];
+  const int S = A.S, p = A.pbar;
+  const int c64 = A.lists[2 * S], cnt = A.lists[2 * S + 2];
+  const int mta = (cnt + kGemmBM - 1) / kGemmBM;
+  const int KS = splitk_of(mta, 1, ggrid, A.Ks / 16);  // FP64 K-tile 16
+  const long kstride = (long)mta * kGemmBM * 128;
+  const double* src = KS > 1 ? A.Tpart : A.Tbuf;
+  const int tid = threadIdx.x;
+  for (int li = blockIdx.x; li < cnt; li += gridDim.x) {
+    const int s = li < c64 ? A.lists[li] : A.lists[S + (li - c64)];
+    __syncthreads();
+    if (tid < p) {
+      double v = 0;
+      for (int k = 0; k < KS; ++k) v += src[k * kstride + (long)li * 128 + tid];
+      t[tid] = v;
+    }
+    __syncthreads();
+    if (tid < 128) {
+      double v = 0;
+      if (tid < p) {
+        const double* ci = A.Cpinv + ((long)s * kPbarMax + tid) * kPbarMax;
+        for (int i = 0; i < p; ++i) v += ci[i] * t[i];
+      }
+      A.Sc[(long)li * 128 + tid] = v;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(KT) k_prep2(EngineArgs A) {
+  const int S = A.S;
+  const int c64 = A.lists[2 * S], cnt = A.lists[2 * S + 2];
+  for (int li = blockIdx.x; li < cnt; li += gridDim.x) {
+    const int s = li < c64 ? A.lists[li] : A.lists[S + (li - c64)];
+    apply_pinv(A, s, A.Qc + (long)li * A.Ks, A.z + (long)s * A.NV, true, A.d + (long)s * A.r);
+  }
+}
+
+// Admission part of the TSVD preconditioner: Cp = I - Mt^T B^-1 D Nt for the
+// slot's new parameter (pbar x pbar, accumulated unit by unit through LDS,
+// 4 x 4 register blocks per thread) and its inverse by Gauss-Jordan with
+// partial pivoting.  A singular Cp leaves Cp^-1 = 0 (block-diagonal part only).
+__global__ void __launch_bounds__(KT) k_capsetup(EngineArgs A) {
+  constexpr int LW = 8;  // rho rows (unit x row a) per chunk
+  __shared__ double Ml[LW * 2][kPbarMax];
+  __shared__ double Wl[LW * 2][kPbarMax];
+  __shared__ double Cm[kPbarMax][kPbarMax + 1];
+  __shared__ double fcol[kPbarMax];
+  __shared__ double dsh[kMaxRank];
+  __shared__ int piv_sh, bad;
+  const int s = blockIdx.x;
+  int* si = A.si + (long)s * SI_N;
+  if (si[SI_CAPSET] == 0) return;
+  const int r = A.r, ld = A.ld, h = A.h, nu = A.n - h, p = A.pbar;
+  const int tid = threadIdx.x;
+  const int CH = max(1, LW / r);
+  const int nb = (p + 3) / 4;
+  const int jb = tid / nb, ib = tid % nb;
+  const bool owner = tid < nb * nb;
+  if (tid < r) dsh[tid] = A.d[(long)s * r + tid];
+  if (tid == 0) bad = 0;
+  const double* P = A.Pinv + (long)s * r * r * ld;
+  double acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+  for (int u0 = 0; u0 < nu; u0 += CH) {
+    const int cu = min(CH, nu - u0);
+    __syncthreads();
+    for (int e = tid; e < cu * r * kPbarMax; e += KT) {
+      const int c = e % kPbarMax, ua = e / kPbarMax;
+      const int a = ua % r, uu = ua / r;
+      if (c >= p) {
+        Ml[2 * ua][c] = Ml[2 * ua + 1][c] = Wl[2 * ua][c] = Wl[2 * ua + 1][c] = 0.0;
+        continue;
+      }
+      bool pr;
+      const int q = uslot(u0 + uu, h, pr);
+      const long ea = (long)a * ld + q;
+      Ml[2 * ua][c] = A.TsM[ea * 128 + c];
+      Ml[2 * ua + 1][c] = pr ? A.TsM[(ea + 1) * 128 + c] : 0.0;
+      double wr = 0, wi = 0;  // (B^-1 D Nt_c)[a] at this unit
+      for (int b = 0; b < r; ++b) {
+        const double* pb = P + (long)(a * r + b) * ld;
+        const long eb = (long)b * ld + q;
+        const double nr = dsh[b] * A.TsN[eb * 128 + c];
+        if (pr) {
+          const double ni = dsh[b] * A.TsN[(eb + 1) * 128 + c];
+          wr += pb[q] * nr - pb[q + 1] * ni;
+          wi += pb[q] * ni + pb[q + 1] * nr;
+        } else {
+          wr += pb[q] * nr;
+        }
+      }
+      Wl[2 * ua][c] = wr;
+      Wl[2 * ua + 1][c] = wi;
+    }
+    __syncthreads();
+    if (owner) {
+      for (int row = 0; row < 2 * cu * r; ++row) {
+        double mv[4], wv[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          mv[x] = Ml[row][min(4 * jb + x, kPbarMax - 1)];
+          wv[x] = Wl[row][min(4 * ib + x, kPbarMax - 1)];
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] += mv[x] * wv[y];
+      }
+    }
+  }
+  __syncthreads();
+  if (owner) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        const int j = 4 * jb + x, i = 4 * ib + y;
+        if (j < p && i < p) Cm[j][i] = (i == j ? 1.0 : 0.0) - acc[x][y];
+      }
+  }
+  // inverse into the slot's Cp^-1 (global), Gauss-Jordan on [Cm | Inv]
+  double* Inv = A.Cpinv + (long)s * kPbarMax * kPbarMax;
+  for (int e = tid; e < p * kPbarMax; e += KT) Inv[e] = (e / kPbarMax == e % kPbarMax) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int c = 0; c < p; ++c) {
+    if (tid == 0) {
+      int pv = c;
+      double best = fabs(Cm[c][c]);
+      for (int i = c + 1; i < p; ++i)
+        if (fabs(Cm[i][c]) > best) {
+          best = fabs(Cm[i][c]);
+          pv = i;
+        }
+      piv_sh = pv;
+      if (!(best > 1e-13)) bad = 1;
+    }
+    __syncthreads();
+    if (bad) break;
+    const int pv = piv_sh;
+    if (pv != c) {
+      for (int k = tid; k < 2 * p; k += KT) {
+        if (k < p) {
+          const double t = Cm[c][k];
+          Cm[c][k] = Cm[pv][k];
+          Cm[pv][k] = t;
+        } else {
+          const int kk = k - p;
+          const double t = Inv[c * kPbarMax + kk];
+          Inv[c * kPbarMax + kk] = Inv[pv * kPbarMax + kk];
+          Inv[pv * kPbarMax + kk] = t;
+        }
+      }
+    }
+    __syncthreads();
+    const double inv = 1.0 / Cm[c][c];
+    __syncthreads();
+    for (int k = tid; k < 2 * p; k += KT) {
+      if (k < p) Cm[c][k] *= inv;
+      else Inv[c * kPbarMax + (k - p)] *= inv;
+    }
+    __syncthreads();
+    if (tid < p) fcol[tid] = Cm[tid][c];
+    __syncthreads();
+    for (int e = tid; e < p * 2 * p; e += KT) {
+      const int i = e / (2 * p), k = e % (2 * p);
+      if (i == c) continue;
+      const double f = fcol[i];
+      if (k < p) Cm[i][k] -= f * Cm[c][k];
+      else Inv[i * kPbarMax + (k - p)] -= f * Inv[c * kPbarMax + (k - p)];
+    }
+    __syncthreads();
+  }
+  if (bad)
+    for (int e = tid; e < p * kPbarMax; e += KT) Inv[e] = 0.0;
+  if (tid == 0) si[SI_CAPSET] = 0;
 }
 
 // X rows (li, a, b) = Vh_a o z_{slot(li), b} in precision T
@@ -717,28 +923,21 @@ __device__ inline void load2(double2 (&v)[NE2], const double* src) {
   for (int i = 0; i < NE2; ++i) v[i] = s2[threadIdx.x + KT * i];
 }
 
-// u = U coef (current bank) written to the slot's w buffer, then x += P^-1 u.
+// u += U coef (current bank)
 template <int NE2>
 __device__ void x_add_recycled(const EngineArgs& A, int s, int bank, int nvec, const double* coef,
                                double2 (&tmp)[NE2]) {
-#pragma unroll
-  for (int i = 0; i < NE2; ++i) tmp[i] = make_double2(0.0, 0.0);
-  combine<NE2>(tmp, nvec, [&](int t) { return rec_u(A, s, bank, t); }, coef);
-  double* ws = A.w + (long)s * A.NV;
   double* xs = A.x + (long)s * A.NV;
-  store2<NE2>(ws, tmp, 1.0);
-  __syncthreads();
-  if (A.use_precond) apply_pinv(A, s, ws, xs, true);
-  else
-    for (int e = threadIdx.x; e < A.NV; e += blockDim.x) xs[e] += ws[e];
-  __syncthreads();
+  load2<NE2>(tmp, xs);
+  combine<NE2>(tmp, nvec, [&](int t) { return rec_u(A, s, bank, t); }, coef);
+  store2<NE2>(xs, tmp, 1.0);
 }
 
 // Per slot and step, according to the slot's phase:
-//   RESTART  w = A x: true residual r = D c0 - w, convergence test, finish or
+//   RESTART  w = A P^-1 u: true residual r = D c0 - w, convergence test, finish or
 //            start a new cycle (r projected off the recycle space C first)
 //   ARNOLDI  w = A P^-1 v_j: orthogonalise against [C, V], Givens update;
-//            at the cycle end x += P^-1 (V y - U B y)
+//            at the cycle end u += V y - U B y
 //   RECYC    w = A P^-1 u_rj for a recycled u (new parameter): C = A P^-1 U
 //            rebuilt one column per step (incremental QR); then x0 from the
 //            recycle space.
@@ -801,7 +1000,7 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
     const int kn = ok ? rj + 1 : rj;
     __syncthreads();
     if (!ok || kn == kc) {
-      // C complete (or cut at a dependent column): x0 = P^-1 U C^T b, b = D c0
+      // C complete (or cut at a dependent column): u0 = U C^T b, b = D c0
       if (kn > 0) {
 #pragma unroll
         for (int i = 0; i < NE2; ++i) {
@@ -851,7 +1050,7 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
       finish(A, s, LYAP_E_NOCONV, rel, lds);
     } else {
       if (REC && kc > 0) {
-        // project r off C and add the matching correction P^-1 U C^T r to x
+        // project r off C and add the matching correction U C^T r to u
         rn = cgs2<NE2>(w2, kc, cvec, coef, part, ytmp, lds, wn0);
         if (rn > 0) store2<NE2>(Vs, w2, 1.0 / rn);
         x_add_recycled<NE2>(A, s, bank, kc, coef, w2);
@@ -949,18 +1148,12 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
   __syncthreads();
   if (next_phase != PH_ARNOLDI) {
     const int jn = j + 1;
-    // u = V y - U B y (into w), x += P^-1 u
-#pragma unroll
-    for (int i = 0; i < NE2; ++i) w2[i] = make_double2(0.0, 0.0);
+    // u += V y - U B y  (the iterate is kept before preconditioning)
+    double* xs = A.x + (long)s * NV;
+    load2<NE2>(w2, xs);
     combine<NE2>(w2, jn, [&](int t) { return Vs + (long)t * NV; }, ycoef);
     if (REC && kc > 0) combine<NE2>(w2, kc, [&](int t) { return rec_u(A, s, bank, t); }, tco);
-    store2<NE2>(ws, w2, 1.0);
-    __syncthreads();
-    double* xs = A.x + (long)s * NV;
-    if (A.use_precond) apply_pinv(A, s, ws, xs, true);
-    else
-      for (int e = tid; e < NV; e += blockDim.x) xs[e] += ws[e];
-    __syncthreads();
+    store2<NE2>(xs, w2, 1.0);
     if (tid == 0) si[SI_PHASE] = next_phase;
   }
 }
@@ -1348,6 +1541,7 @@ struct lyap_engine_s {
   long long next_tag = 0;
   DevBuf si, sdv, d, R, g, cs, sn, V, x, z, w, Pinv, lists, X, H, Hp, Xlo, Hlo, Hplo, XS;
   DevBuf Ur, Cr, Bk, Hr, Fs;  // recycle space (GCRO-DR)
+  DevBuf Cpinv, Tbuf, Tpart, Sc;  // low-rank preconditioner part
   DevBuf qd, qtag, qctl, res;
   double* sol = nullptr;
   long long sol_cap = 0;
@@ -1394,6 +1588,7 @@ static void validate_opts(const lyap_solve_opts& o) {
   LYAP_REQUIRE(o.restart >= 1 && o.restart <= kMaxRestart, LYAP_E_INVAL, "restart out of [1, 64]");
   LYAP_REQUIRE(o.tol > 0 && o.tol < 1, LYAP_E_INVAL, "tol out of (0, 1)");
   LYAP_REQUIRE(o.max_iter >= 1, LYAP_E_INVAL, "max_iter < 1");
+  LYAP_REQUIRE(o.use_precond >= 0 && o.use_precond <= 2, LYAP_E_INVAL, "use_precond out of [0, 2]");
   LYAP_REQUIRE(o.recycle_k >= 0 && o.recycle_k <= kMaxRecycle, LYAP_E_INVAL,
                "recycle_k out of [0, 16]");
   LYAP_REQUIRE(o.restart + o.recycle_k <= kMaxRestart, LYAP_E_INVAL,
@@ -1420,7 +1615,14 @@ static EngineSizes engine_sizes(const lyap_seed_s* sd, long long S, const lyap_s
   add(S * (m + 1) * N * 8);
   add(S * N * 8 * 3);
   add(S * r * r * ld * 8);
-  add((2 * S + 2) * 4);
+  add((2 * S + 3) * 4);
+  const bool tsvd = sd->pbar > 0 && o.use_precond == 1 && sd->r <= kPrecRank;
+  if (tsvd) {
+    const long long Sp = pad_to(S, 128);
+    add(S * kPbarMax * kPbarMax * 8);  // Cp^-1
+    add(Sp * 128 * 8 * 2);             // Tbuf, Sc
+    add(128LL * 128 * 128 * 8);        // split-K partials (grid 256)
+  }
   add(z.rows_pad * ld * 8 * 3);  // X, H, split-K partials fp64
   if (o.recycle_k > 0) {
     const long long k = o.recycle_k;
@@ -1454,6 +1656,41 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
   hipLaunchKernelGGL(k_lists, dim3(1), dim3(1024), 0, st, A);
   const int pgrid = std::min(S, 1024);
   hipLaunchKernelGGL(k_prep, dim3(pgrid), dim3(KT), 0, st, A);
+  if (A.pbar > 0) {
+    // low-rank preconditioner part: two skinny GEMMs over the listed slots
+    constexpr int kTsvdGrid = 256;
+    GemmArgs g{};
+    g.type = GemmType::F64;
+    g.A = A.Yc;
+    g.B = A.TsM;
+    g.C = A.Tbuf;
+    g.M = S;
+    g.N = 128;
+    g.K = A.Ks;
+    g.lda = A.Ks;
+    g.ldb = g.ldc = g.Nstore = 128;
+    g.M_dev = E->lists.as<int>() + 2 * S + 2;
+    g.m_scale = 1;
+    g.Cpart = A.Tpart;
+    g.grid_min = kTsvdGrid;
+    gemm_launch(g, st);
+    const int ggrid = std::max((S + kGemmBM - 1) / kGemmBM, kTsvdGrid);
+    hipLaunchKernelGGL(k_cap, dim3(pgrid), dim3(KT), 0, st, A, ggrid);
+    GemmArgs q{};
+    q.type = GemmType::F64;
+    q.A = A.Sc;
+    q.B = sd->TsNt.p;
+    q.C = A.Qc;
+    q.M = S;
+    q.N = A.Ks;
+    q.K = 128;
+    q.lda = 128;
+    q.ldb = q.ldc = q.Nstore = A.Ks;
+    q.M_dev = E->lists.as<int>() + 2 * S + 2;
+    q.m_scale = 1;
+    gemm_launch(q, st);
+    hipLaunchKernelGGL(k_prep2, dim3(pgrid), dim3(KT), 0, st, A);
+  }
   const int ublocks = std::max(1, std::min((nu + KT - 1) / KT, 64));
   const int egrid = 2048;  // grid-stride kernels: work proportional to the active count
   if (sd->basis == LYAP_BASIS_SCHUR) {
@@ -1530,6 +1767,7 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
   if (ev) LYAP_HIP(hipEventRecord(ev->kry[1], st));
   if (A.kmax > 0) launch_krylov(A, S, (long long)A.NV, st, true);
   hipLaunchKernelGGL(k_admit, dim3(S), dim3(KT), 0, st, A);
+  if (A.pbar > 0) hipLaunchKernelGGL(k_capsetup, dim3(S), dim3(KT), 0, st, A);
   LYAP_HIP(hipGetLastError());
 }
 
@@ -1708,7 +1946,15 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   zalloc(E->z, S * N * 8);
   zalloc(E->w, S * N * 8);
   zalloc(E->Pinv, S * r * r * ld * 8);
-  zalloc(E->lists, (2 * S + 2) * 4);
+  zalloc(E->lists, (2 * S + 3) * 4);
+  const bool tsvd = sd->pbar > 0 && o.use_precond == 1 && r <= kPrecRank;
+  if (tsvd) {
+    const long long Sp = pad_to(S, 128);
+    zalloc(E->Cpinv, S * kPbarMax * kPbarMax * 8);
+    zalloc(E->Tbuf, Sp * 128 * 8);
+    zalloc(E->Sc, Sp * 128 * 8);
+    zalloc(E->Tpart, 128LL * 128 * 128 * 8);
+  }
   if (o.recycle_k > 0) {
     const long long k = o.recycle_k;
     zalloc(E->Ur, S * 2 * k * N * 8);
@@ -1752,6 +1998,17 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   A.max_iter = o.max_iter;
   A.max_refine = o.max_refine;
   A.use_precond = (o.use_precond && r <= kPrecRank && sd->basis != LYAP_BASIS_SCHUR) ? 1 : 0;
+  // use_precond 1: all of eq:prec the seed holds; 2: its block-diagonal part only
+  A.pbar = tsvd ? (int)sd->pbar : 0;
+  A.Ks = (int)(r * ld);
+  A.TsM = sd->TsM.as<double>();
+  A.TsN = sd->TsN.as<double>();
+  A.Cpinv = E->Cpinv.as<double>();
+  A.Yc = E->X.as<double>();
+  A.Qc = E->H.as<double>();
+  A.Tbuf = E->Tbuf.as<double>();
+  A.Tpart = E->Tpart.as<double>();
+  A.Sc = E->Sc.as<double>();
   A.mixed = E->mixed ? 1 : 0;
   A.tol = o.tol;
   A.inner_tol = o.inner_tol;

@@ -13,6 +13,8 @@
 // multiplied.  Workgroups are mapped to tiles so that consecutive tiles of one
 // B column panel land on the same XCD (blocks are dispatched round-robin over
 // the 8 XCDs), which keeps the shared B panel in that XCD's L2.
+#include <algorithm>
+
 #include "common.h"
 
 namespace lyap {
@@ -94,6 +96,7 @@ gemm_kernel(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
   } else {
     tile_of(blockIdx.x, mtiles, ntiles, mt, nt);
   }
+  if (KS == 1 && (int)blockIdx.x >= mtiles * ntiles) return;  // grid padded for split-K
   const int row0 = mt * BM;
   const int col0 = nt * BN;
   if (row0 >= Meff) return;
@@ -230,6 +233,7 @@ gemm_bf16x3_kernel(const __bf16* __restrict__ A, long a_plane, const __bf16* __r
   } else {
     tile_of(blockIdx.x, mtiles, ntiles, mt, nt);
   }
+  if (KS == 1 && (int)blockIdx.x >= mtiles * ntiles) return;  // grid padded for split-K
   const int row0 = mt * BM;
   const int col0 = nt * BN;
   if (row0 >= Meff) return;
@@ -339,7 +343,7 @@ void gemm_launch(const GemmArgs& g, hipStream_t s) {
   LYAP_REQUIRE(g.Cpart == nullptr || g.M_dev != nullptr, LYAP_E_INVAL, "gemm: split-K needs M_dev");
   const int mtiles = (int)((g.M + BM - 1) / BM);
   const int ntiles = (int)(g.N / BN);
-  dim3 grid(mtiles * ntiles), block(NTHREADS);
+  dim3 grid((unsigned)std::max<int64_t>(mtiles * ntiles, g.grid_min)), block(NTHREADS);
   switch (g.type) {
     case GemmType::F64:
       LYAP_REQUIRE(g.K % 16 == 0, LYAP_E_INVAL, "gemm: K not padded");

@@ -40,13 +40,18 @@ struct lyap_seed_s {
   lyap::DevBuf gam;     // r x ld: trace(E X) = t0 + sum_b <gam_b, rho(Yhat_b)>
   lyap::DevBuf Gam;     // r x ld: physical Gamma^T (trace = t0 + 2 <Gamma^T, Y>)
   lyap::DevBuf T, Tt;   // Schur basis only: quasi-triangular T and T^T (ld x ld)
+  // rank-pbar TSVD of the dense coupling (preconditioner of eq:prec), r*ld x 128
+  int pbar = 0;
+  double tsvd_sigma_ratio = 0;  // sigma_(pbar+1) / sigma_1 of the coupling
+  lyap::DevBuf TsM, TsN;  // Mt, Nt (row-major r*ld x 128, columns >= pbar zero)
+  lyap::DevBuf TsNt;      // Nt^T (128 x r*ld)
   lyap::DevBuf scratch; // grown on demand by lyap_seed_apply / trace_EX
   size_t scratch_bytes = 0;
 
   size_t device_bytes() const {
     return lam.bytes + Mc.bytes + Mc32.bytes + Mcb.bytes + Tin.bytes + Tout.bytes + Uh.bytes +
            Vh.bytes + K1.bytes + c0.bytes + gam.bytes + Gam.bytes + T.bytes + Tt.bytes +
-           scratch.bytes;
+           TsM.bytes + TsN.bytes + TsNt.bytes + scratch.bytes;
   }
 };
 

@@ -264,6 +264,178 @@ static inline void gemm64(const double* A, long lda, const double* B, long ldb, 
 }
 
 // ---------------------------------------------------------------------------
+// Low-rank part of the preconditioner of eq:prec (Section 2.1): truncated
+// SVD of the parameter-independent dense coupling of the capacitance
+// operator.  In the folded n*r system the operator is
+//   K(Y)_a = sum_b Y_b o K1_ab  +  sum_b Uh_b o ((Vh_a o Y_b) L),
+// the first term being the exact block-diagonal part; the second (dense)
+// term T plays the role of the off-diagonal blocks N1^T L0^-1 M2 and
+// N2^T L0^-1 M1, and T ~ Nt Mt^T (rank pbar) is what the paper truncates.
+// ---------------------------------------------------------------------------
+
+// Dense T on the padded rho layout (index (a, i) = a * ld + i):
+//   T[(a, i)][(b, j)] = (C_{Uh_b} Mc^T C_{Vh_a})[i][j],
+// C_x being the real 2 x 2-block matrix of the rho-complex product with x.
+__global__ void k_build_coupling(double* T, const double* Mc, const double* Uh, const double* Vh,
+                                 int n, int h, int ld, int r) {
+  const long Ks = (long)r * ld;
+  const long col = (long)blockIdx.x * blockDim.x + threadIdx.x;  // (b, j)
+  const long row = blockIdx.y;                                  // (a, i)
+  if (col >= Ks) return;
+  const int a = (int)(row / ld), i = (int)(row % ld), b = (int)(col / ld), j = (int)(col % ld);
+  double v = 0.0;
+  if (i < n && j < n) {
+    const double* U = Uh + (long)b * ld;
+    const double* Vv = Vh + (long)a * ld;
+    int ip[2] = {i, i}, jp[2] = {j, j};
+    double cu[2] = {0.0, 0.0}, cv[2] = {0.0, 0.0};
+    int ni = 1, nj = 1;
+    if (i < 2 * h) {  // row i of C_U on the pair (k, k + 1)
+      const int k = i & ~1;
+      const double ur = U[k], ui = U[k + 1];
+      ip[0] = k;
+      ip[1] = k + 1;
+      cu[0] = (i & 1) ? ui : ur;
+      cu[1] = (i & 1) ? ur : -ui;
+      ni = 2;
+    } else {
+      cu[0] = U[i];
+    }
+    if (j < 2 * h) {  // column j of C_V on the pair (m, m + 1)
+      const int m = j & ~1;
+      const double vr = Vv[m], vi = Vv[m + 1];
+      jp[0] = m;
+      jp[1] = m + 1;
+      cv[0] = (j & 1) ? -vi : vr;
+      cv[1] = (j & 1) ? vr : vi;
+      nj = 2;
+    } else {
+      cv[0] = Vv[j];
+    }
+    for (int x = 0; x < ni; ++x)
+      for (int y = 0; y < nj; ++y) v += cu[x] * Mc[(long)jp[y] * ld + ip[x]] * cv[y];
+  }
+  T[row * Ks + col] = v;
+}
+
+// Randomised range finder with one power iteration (Halko, Martinsson and
+// Tropp, SIAM Rev. 2011, Algorithms 4.3 and 5.1) on kS = 128 Gaussian
+// samples: the products with T are device GEMMs, the thin QR and the SVD of
+// the kS x Ks sketch run in host LAPACK.  Results: Mt, Nt (Ks x 128, columns
+// >= pbar zero) with T ~ Nt Mt^T, and NtT = Nt^T (128 x Ks).
+static void coupling_tsvd(lyap_seed_s* sd, int pbar, hipStream_t st) {
+  constexpr int kS = 128;
+  const long ld = sd->ld, r = sd->r, Ks = r * ld;
+  const int Ksi = (int)Ks, kSi = kS;
+  const LapackFns& L = lapack();
+  LYAP_REQUIRE(L.dgeqrf && L.dorgqr && L.dgesdd, LYAP_E_UNSUPPORTED,
+               "host LAPACK (dgeqrf, dorgqr, dgesdd) not found");
+  DevBuf T((size_t)Ks * Ks * sizeof(double));
+  {
+    dim3 grid((unsigned)((Ks + 255) / 256), (unsigned)Ks);
+    hipLaunchKernelGGL(k_build_coupling, grid, dim3(256), 0, st, T.as<double>(),
+                       sd->Mc.as<double>(), sd->Uh.as<double>(), sd->Vh.as<double>(), (int)sd->n,
+                       (int)sd->h, (int)ld, (int)r);
+    LYAP_HIP(hipGetLastError());
+  }
+  // Gaussian samples: splitmix64 stream, Box-Muller
+  std::vector<double> W((size_t)Ks * kS);
+  uint64_t state = 0x2312082013ull;
+  auto next = [&]() {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  for (size_t q = 0; q < W.size(); q += 2) {
+    const double u1 = ((double)(next() >> 11) + 1.0) * 0x1.0p-53;
+    const double u2 = (double)(next() >> 11) * 0x1.0p-53;
+    const double rad = std::sqrt(-2.0 * std::log(u1));
+    W[q] = rad * std::cos(2.0 * M_PI * u2);
+    if (q + 1 < W.size()) W[q + 1] = rad * std::sin(2.0 * M_PI * u2);
+  }
+  const size_t thin = (size_t)Ks * kS * sizeof(double);
+  DevBuf Wd(thin), Yd(thin), Qtd(thin), Bd(thin);
+  std::vector<double> A((size_t)Ks * kS), tau(kS);
+  int info = 0;
+  // Y (device, Ks x kS row-major) -> Q^T (device, kS x Ks row-major) and on the host in A
+  auto orth = [&]() {
+    std::vector<double> Yh((size_t)Ks * kS);
+    LYAP_HIP(hipMemcpyAsync(Yh.data(), Yd.p, thin, hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipStreamSynchronize(st));
+    for (long i = 0; i < Ks; ++i)
+      for (int c = 0; c < kS; ++c) A[(size_t)c * Ks + i] = Yh[(size_t)i * kS + c];
+    double wq = 0;
+    int lwork = -1;
+    L.dgeqrf(&Ksi, &kSi, A.data(), &Ksi, tau.data(), &wq, &lwork, &info);
+    lwork = (int)wq + 1;
+    std::vector<double> work(lwork);
+    L.dgeqrf(&Ksi, &kSi, A.data(), &Ksi, tau.data(), work.data(), &lwork, &info);
+    LYAP_REQUIRE(info == 0, LYAP_E_DEVICE, "dgeqrf failed in the coupling TSVD");
+    lwork = -1;
+    L.dorgqr(&Ksi, &kSi, &kSi, A.data(), &Ksi, tau.data(), &wq, &lwork, &info);
+    lwork = (int)wq + 1;
+    work.assign(lwork, 0.0);
+    L.dorgqr(&Ksi, &kSi, &kSi, A.data(), &Ksi, tau.data(), work.data(), &lwork, &info);
+    LYAP_REQUIRE(info == 0, LYAP_E_DEVICE, "dorgqr failed in the coupling TSVD");
+    // column-major Q (Ks x kS) is Q^T row-major (kS x Ks)
+    LYAP_HIP(hipMemcpyAsync(Qtd.p, A.data(), thin, hipMemcpyHostToDevice, st));
+  };
+  std::vector<double> Bh((size_t)kS * Ks);
+  LYAP_HIP(hipMemcpyAsync(Wd.p, W.data(), thin, hipMemcpyHostToDevice, st));
+  for (int it = 0; it < 2; ++it) {
+    gemm64_rm(T.as<double>(), Ks, Wd.as<double>(), kS, Yd.as<double>(), kS, Ks, kS, Ks, kS, st);
+    orth();
+    gemm64_rm(Qtd.as<double>(), Ks, T.as<double>(), Ks, Bd.as<double>(), Ks, kS, Ks, Ks, Ks, st);
+    LYAP_HIP(hipMemcpyAsync(Bh.data(), Bd.p, thin, hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipStreamSynchronize(st));
+    if (it == 0) {  // power iteration: next samples T^T Q = B^T
+      for (int c = 0; c < kS; ++c)
+        for (long e = 0; e < Ks; ++e) W[(size_t)e * kS + c] = Bh[(size_t)c * Ks + e];
+      LYAP_HIP(hipMemcpyAsync(Wd.p, W.data(), thin, hipMemcpyHostToDevice, st));
+    }
+  }
+  // SVD of the sketch B = Q^T T (kS x Ks): B = Ub diag(sv) VT
+  std::vector<double> Bcm((size_t)kS * Ks), sv(kS), Ub((size_t)kS * kS), VT((size_t)kS * Ks);
+  for (int c = 0; c < kS; ++c)
+    for (long e = 0; e < Ks; ++e) Bcm[(size_t)e * kS + c] = Bh[(size_t)c * Ks + e];
+  std::vector<int> iwork(8 * kS);
+  {
+    double wq = 0;
+    int lwork = -1;
+    L.dgesdd("S", &kSi, &Ksi, Bcm.data(), &kSi, sv.data(), Ub.data(), &kSi, VT.data(), &kSi, &wq,
+             &lwork, iwork.data(), &info);
+    lwork = (int)wq + 1;
+    std::vector<double> work(lwork);
+    L.dgesdd("S", &kSi, &Ksi, Bcm.data(), &kSi, sv.data(), Ub.data(), &kSi, VT.data(), &kSi,
+             work.data(), &lwork, iwork.data(), &info);
+    LYAP_REQUIRE(info == 0, LYAP_E_DEVICE, "dgesdd failed in the coupling TSVD");
+  }
+  // Nt = Q Ub[:, :p] diag(sv[:p]),  Mt = VT[:p, :]^T
+  const int p = pbar;
+  std::vector<double> Mt((size_t)Ks * kS, 0.0), Nt((size_t)Ks * kS, 0.0), NtT((size_t)kS * Ks, 0.0);
+  for (long e = 0; e < Ks; ++e)
+    for (int c = 0; c < p; ++c) {
+      double v = 0;
+      for (int t = 0; t < kS; ++t) v += A[(size_t)t * Ks + e] * Ub[(size_t)c * kS + t];
+      v *= sv[c];
+      Nt[(size_t)e * kS + c] = v;
+      NtT[(size_t)c * Ks + e] = v;
+      Mt[(size_t)e * kS + c] = VT[(size_t)e * kS + c];
+    }
+  sd->TsM.alloc(thin);
+  sd->TsN.alloc(thin);
+  sd->TsNt.alloc(thin);
+  LYAP_HIP(hipMemcpyAsync(sd->TsM.p, Mt.data(), thin, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(sd->TsN.p, Nt.data(), thin, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(sd->TsNt.p, NtT.data(), thin, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipStreamSynchronize(st));
+  sd->pbar = p;
+  sd->tsvd_sigma_ratio = sv[0] > 0 ? sv[std::min(p, kS - 1)] / sv[0] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
 // seed_factor
 // ---------------------------------------------------------------------------
 static void check_finite(const double* p, size_t count, const char* what) {
@@ -468,6 +640,8 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
   const int E_diag = opts ? opts->E_is_diag : 1;
   const int basis_req = opts ? opts->basis : LYAP_BASIS_AUTO;
   double max_cond = opts && opts->max_eig_cond > 0 ? opts->max_eig_cond : 1e6;
+  const int tsvd_rank = opts ? opts->tsvd_rank : 0;
+  LYAP_REQUIRE(tsvd_rank >= 0 && tsvd_rank <= 64, LYAP_E_INVAL, "tsvd_rank out of [0, 64]");
   LYAP_REQUIRE(basis_req >= 0 && basis_req <= 2, LYAP_E_INVAL, "basis out of range");
   check_finite(A0, (size_t)n * n, "A0");
   check_finite(U, (size_t)n * r, "U");
@@ -668,6 +842,8 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
            st);
     LYAP_HIP(hipStreamSynchronize(st));
   }
+  // ---- optional low-rank coupling of eq:prec (TSVD, rank pbar) ----
+  if (tsvd_rank > 0) coupling_tsvd(sd, tsvd_rank, st);
 
   // chunked "rows x Cauchy, contract" helper: out[g] += scale * sum_t w_t o (a_g o b_t) L
   // rows ordered (g, t); a has ngroups rows, b and w have G rows.
@@ -812,7 +988,7 @@ lyap_status seed_info(lyap_seed sd, lyap_seed_info* o) {
   o->npairs = sd->h;
   o->ld = sd->ld;
   o->basis = sd->basis;
-  o->reserved = 0;
+  o->tsvd_rank = sd->pbar;
   o->cond_est = sd->cond_est;
   o->min_lam_sum = sd->min_lam_sum;
   o->max_re_lambda = sd->max_re;

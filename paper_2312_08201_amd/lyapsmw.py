@@ -32,7 +32,8 @@ class LyapError(RuntimeError):
 
 
 class SeedOpts(C.Structure):
-    _fields_ = [("basis", C.c_int32), ("E_is_diag", C.c_int32), ("max_eig_cond", C.c_double)]
+    _fields_ = [("basis", C.c_int32), ("E_is_diag", C.c_int32), ("max_eig_cond", C.c_double),
+                ("tsvd_rank", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -48,7 +49,7 @@ class Result(C.Structure):
 
 class SeedInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("r", C.c_int64), ("s", C.c_int64), ("npairs", C.c_int64),
-                ("ld", C.c_int64), ("basis", C.c_int32), ("reserved", C.c_int32),
+                ("ld", C.c_int64), ("basis", C.c_int32), ("tsvd_rank", C.c_int32),
                 ("cond_est", C.c_double), ("min_lam_sum", C.c_double),
                 ("max_re_lambda", C.c_double), ("t0", C.c_double),
                 ("factor_seconds", C.c_double), ("device_bytes", C.c_size_t)]
@@ -177,17 +178,25 @@ def _dev_ptr(t, dtype_name="float64", shape=None):
     return C.c_void_p(t.data_ptr())
 
 
+def _precond_mode(v) -> int:
+    """True/1: all of eq:prec the seed holds; 2: block-diagonal part only; False/0: none."""
+    if isinstance(v, bool):
+        return 1 if v else 0
+    return int(v)
+
+
 def solve_opts(prec="fp64", tol=1e-12, max_iter=600, restart=40, use_precond=True,
                max_refine=30, inner_tol=1e-4, recycle_k=0) -> SolveOpts:
     return SolveOpts(PREC[prec] if isinstance(prec, str) else int(prec), int(max_iter),
-                     int(restart), 1 if use_precond else 0, int(recycle_k), int(max_refine),
+                     int(restart), _precond_mode(use_precond), int(recycle_k), int(max_refine),
                      float(tol), float(inner_tol))
 
 
 class Seed:
     """seed_factor: offline stage for one (A0, U, V, B, E)."""
 
-    def __init__(self, A0, U, V, B, E, basis="auto", max_eig_cond=0.0, stream=None):
+    def __init__(self, A0, U, V, B, E, basis="auto", max_eig_cond=0.0, stream=None,
+                 tsvd_rank=0):
         lib = load()
         _torch()
         A0 = _host(A0)
@@ -204,7 +213,7 @@ class Seed:
         if (diag and E.shape != (n,)) or (not diag and E.shape != (n, n)):
             raise ValueError("E must be (n,) or (n, n)")
         self._keep = (A0, U, V, B, E)
-        opts = SeedOpts(BASIS[basis], diag, float(max_eig_cond))
+        opts = SeedOpts(BASIS[basis], diag, float(max_eig_cond), int(tsvd_rank), 0)
         h = C.c_void_p()
         st = lib.seed_factor(n, r, s, A0.ctypes.data, U.ctypes.data, V.ctypes.data, B.ctypes.data,
                              E.ctypes.data, C.byref(opts), _stream(stream), C.byref(h))

@@ -43,7 +43,7 @@ enum Phase : int { PH_FREE = 0, PH_ARNOLDI = 1, PH_RESTART = 2, PH_RECYC = 3, PH
 // rebuild for a new parameter, BANK: which of the two U/C banks is current)
 enum SI : int {
   SI_PHASE = 0, SI_J, SI_ITERS, SI_CYCLES, SI_REFINE, SI_QPOS, SI_KCUR, SI_RJ, SI_BANK, SI_CAPSET,
-  SI_N
+  SI_PINV, SI_N
 };
 constexpr int kPbarMax = 64;  // TSVD rank bound of the preconditioner
 // per-slot double state
@@ -119,7 +119,8 @@ __device__ inline double* rec_c(const EngineArgs& A, int s, int bank, int l) {
 // ---------------------------------------------------------------------------
 // reductions (64-wide wavefronts, 256-thread workgroups)
 // ---------------------------------------------------------------------------
-constexpr int KT = 256;
+constexpr int KT = 256;   // threads of the per-slot and grid-stride kernels
+constexpr int KK = 1024;  // threads of the Krylov kernel (16 wavefronts per slot)
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -127,10 +128,11 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// sum over the workgroup of NV values per thread, result visible to all threads
+// sum over the workgroup of NV values per thread, result visible to all
+// threads (lds: NV * waves doubles; waves summed in fixed order)
 template <int NV>
 __device__ inline void block_sum(double (&v)[NV], double* lds) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
   if (lane == 0) {
@@ -139,7 +141,11 @@ __device__ inline void block_sum(double (&v)[NV], double* lds) {
   }
   __syncthreads();
 #pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = lds[i] + lds[NV + i] + lds[2 * NV + i] + lds[3 * NV + i];
+  for (int i = 0; i < NV; ++i) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += lds[w * NV + i];
+    v[i] = t;
+  }
   __syncthreads();
 }
 
@@ -268,6 +274,108 @@ __device__ inline void block_inverse(const EngineArgs& A, const double* dsh, int
     }
 }
 
+// (I - D K1_q)^-1 for 4 < r <= 8 by one wavefront: lane 8 i + j holds
+// entry (i, j) of the matrix and of its inverse (complex on a conjugate
+// pair); Gauss-Jordan with partial pivoting through lane shuffles.
+__device__ inline void wave_inverse(const EngineArgs& A, const double* d, int q, bool pr,
+                                    double* P, int lane) {
+  const int r = A.r, ld = A.ld;
+  const int i = lane >> 3, j = lane & 7;
+  const bool in = i < r && j < r;
+  double mr = 0, mi = 0, ir = 0, ii = 0;
+  if (in) {
+    const double* k = A.K1 + (long)(i * r + j) * ld;
+    mr = (i == j ? 1.0 : 0.0) - d[i] * k[q];
+    mi = pr ? -d[i] * k[q + 1] : 0.0;
+    ir = i == j ? 1.0 : 0.0;
+  }
+  for (int c = 0; c < r; ++c) {
+    // pivot row: largest |entry| in column c at or below row c
+    double mag = (in && j == c && i >= c) ? fabs(mr) + fabs(mi) : -1.0;
+    int row = i;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double om = __shfl_xor(mag, o, 64);
+      const int orow = __shfl_xor(row, o, 64);
+      if (om > mag || (om == mag && orow < row)) {
+        mag = om;
+        row = orow;
+      }
+    }
+    const int pv = row;
+    // swap rows c and pv
+    const int src = i == c ? pv * 8 + j : (i == pv ? c * 8 + j : lane);
+    mr = __shfl(mr, src, 64);
+    mi = __shfl(mi, src, 64);
+    ir = __shfl(ir, src, 64);
+    ii = __shfl(ii, src, 64);
+    // scale row c by 1 / pivot
+    const double pr_ = __shfl(mr, c * 8 + c, 64), pi_ = __shfl(mi, c * 8 + c, 64);
+    const double den = pr_ * pr_ + pi_ * pi_;
+    const double vr = pr_ / den, vi = -pi_ / den;
+    if (i == c) {
+      double t = mr * vr - mi * vi;
+      mi = mr * vi + mi * vr;
+      mr = t;
+      t = ir * vr - ii * vi;
+      ii = ir * vi + ii * vr;
+      ir = t;
+    }
+    // eliminate column c from the other rows
+    const double fr = __shfl(mr, i * 8 + c, 64), fi = __shfl(mi, i * 8 + c, 64);
+    const double cr = __shfl(mr, c * 8 + j, 64), ci = __shfl(mi, c * 8 + j, 64);
+    const double jr = __shfl(ir, c * 8 + j, 64), ji = __shfl(ii, c * 8 + j, 64);
+    if (i != c) {
+      mr -= fr * cr - fi * ci;
+      mi -= fr * ci + fi * cr;
+      ir -= fr * jr - fi * ji;
+      ii -= fr * ji + fi * jr;
+    }
+  }
+  if (in) {
+    double* pb = P + (long)(i * r + j) * ld;
+    pb[q] = ir;
+    if (pr) pb[q + 1] = ii;
+  }
+}
+
+// Preconditioner blocks for the slots admitted in this step.  Grid (S,
+// chunks): one slot's units are spread over many workgroups, so an admission
+// adds one short kernel to the step instead of one long workgroup.
+constexpr int kPinvUnitsWave = 32;  // r > 4: units per workgroup (8 per wavefront)
+__global__ void __launch_bounds__(KT) k_pinv(EngineArgs A) {
+  const int s = blockIdx.x;
+  if (A.si[(long)s * SI_N + SI_PINV] == 0) return;
+  const int r = A.r, h = A.h, nu = A.n - h;
+  const double* d = A.d + (long)s * r;
+  double* P = A.Pinv + (long)s * r * r * A.ld;
+  if (r <= 4) {
+    const int u = blockIdx.y * KT + threadIdx.x;
+    if (u >= nu) return;
+    bool pr;
+    const int q = uslot(u, h, pr);
+    switch (r) {
+      case 1: block_inverse<1>(A, d, q, pr, P); break;
+      case 2: block_inverse<2>(A, d, q, pr, P); break;
+      case 3: block_inverse<3>(A, d, q, pr, P); break;
+      default: block_inverse<4>(A, d, q, pr, P); break;
+    }
+  } else {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int uu = wave; uu < kPinvUnitsWave; uu += KT / 64) {
+      const int u = blockIdx.y * kPinvUnitsWave + uu;
+      if (u >= nu) break;
+      bool pr;
+      const int q = uslot(u, h, pr);
+      wave_inverse(A, d, q, pr, P, lane);
+    }
+  }
+}
+
+static int pinv_chunks(int r, int nu) {
+  return r <= 4 ? (nu + KT - 1) / KT : (nu + kPinvUnitsWave - 1) / kPinvUnitsWave;
+}
+
 // Admission of queue entry qp into slot s (whole workgroup): preconditioner
 // blocks (I - D K1_j)^-1, right-hand side b = D c0, v0 = b / ||b||.
 __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
@@ -306,22 +414,7 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
     __syncthreads();
     return;
   }
-  // preconditioner blocks
-  if (A.use_precond) {
-    double* P = A.Pinv + (long)s * r * r * ld;
-    for (int u = threadIdx.x; u < nu; u += blockDim.x) {
-      bool pr;
-      const int q = uslot(u, A.h, pr);
-      switch (r) {
-        case 1: block_inverse<1>(A, dsh, q, pr, P); break;
-        case 2: block_inverse<2>(A, dsh, q, pr, P); break;
-        case 3: block_inverse<3>(A, dsh, q, pr, P); break;
-        case 4: block_inverse<4>(A, dsh, q, pr, P); break;
-        default: block_inverse<kPrecRank>(A, dsh, q, pr, P, r); break;
-      }
-    }
-  }
-  // b = D c0 ; ||b||
+  // b = D c0 ; ||b||  (the preconditioner blocks follow in k_pinv)
   double acc = 0;
   for (int e = threadIdx.x; e < N; e += blockDim.x) {
     const double v = dsh[e / ld] * A.c0[e];
@@ -355,6 +448,7 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
     si[SI_PHASE] = rec ? PH_RECYC : PH_ARNOLDI;
     si[SI_RJ] = 0;
     si[SI_CAPSET] = A.pbar > 0 ? 1 : 0;
+    si[SI_PINV] = A.use_precond ? 1 : 0;
     si[SI_J] = 0;
     si[SI_ITERS] = 0;
     si[SI_CYCLES] = rec ? 0 : 1;
@@ -472,6 +566,7 @@ __global__ void __launch_bounds__(KT) k_prep(EngineArgs A) {
     const int s = li < c64 ? A.lists[li] : A.lists[S + (li - c64)];
     const int ph = A.si[(long)s * SI_N + SI_PHASE];
     double* zs = A.z + (long)s * A.NV;
+    if (threadIdx.x == 0) A.si[(long)s * SI_N + SI_PINV] = 0;  // blocks were built last step
     // source: the iterate u (residual step), v_j (Arnoldi) or a recycled u_rj
     const int* sis = A.si + (long)s * SI_N;
     const double* src = ph == PH_RESTART ? A.x + (long)s * A.NV
@@ -793,7 +888,7 @@ constexpr int kPart = kMaxBasis + 2;
 // than 1/sqrt(2) of ||w|| (Daniel-Gragg-Kaufman-Stewart criterion).
 // coef[t] receives the summed projections; returns ||w|| afterwards and the
 // norm before in wn0.
-template <int NE2, class VecF>
+template <int NE2, int BT, class VecF>
 __device__ double cgs2(double2 (&w2)[NE2], int nvec, VecF vec, double* coef,
                        double (*part)[kPart], double* ytmp, double* lds, double& wn0) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -814,7 +909,7 @@ __device__ double cgs2(double2 (&w2)[NE2], int nvec, VecF vec, double* coef,
       const double2* v3 = reinterpret_cast<const double2*>(vec(k + 3));
 #pragma unroll
       for (int i = 0; i < NE2; ++i) {
-        const int e = tid + KT * i;
+        const int e = tid + BT * i;
         const double2 x0 = v0[e], x1 = v1[e], x2 = v2[e], x3 = v3[e];
         a0 += x0.x * w2[i].x + x0.y * w2[i].y;
         a1 += x1.x * w2[i].x + x1.y * w2[i].y;
@@ -837,7 +932,7 @@ __device__ double cgs2(double2 (&w2)[NE2], int nvec, VecF vec, double* coef,
       const double2* v0 = reinterpret_cast<const double2*>(vec(k));
 #pragma unroll
       for (int i = 0; i < NE2; ++i) {
-        const double2 x0 = v0[tid + KT * i];
+        const double2 x0 = v0[tid + BT * i];
         a0 += x0.x * w2[i].x + x0.y * w2[i].y;
       }
       a0 = wave_sum(a0);
@@ -847,12 +942,14 @@ __device__ double cgs2(double2 (&w2)[NE2], int nvec, VecF vec, double* coef,
     if (lane == 0) part[wave][kPart - 1] = ww;
     __syncthreads();
     if (tid < nvec) {
-      const double h = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
+      double h = 0.0;
+      for (int w = 0; w < BT / 64; ++w) h += part[w][tid];
       ytmp[tid] = h;
       coef[tid] += h;
     }
     if (pass == 0) {
-      wn2 = part[0][kPart - 1] + part[1][kPart - 1] + part[2][kPart - 1] + part[3][kPart - 1];
+      wn2 = 0.0;
+      for (int w = 0; w < BT / 64; ++w) wn2 += part[w][kPart - 1];
       wn0 = sqrt(wn2);
     }
     __syncthreads();
@@ -866,7 +963,7 @@ __device__ double cgs2(double2 (&w2)[NE2], int nvec, VecF vec, double* coef,
       const double2* v3 = reinterpret_cast<const double2*>(vec(kk + 3));
 #pragma unroll
       for (int i = 0; i < NE2; ++i) {
-        const int e = tid + KT * i;
+        const int e = tid + BT * i;
         const double2 x0 = v0[e], x1 = v1[e], x2 = v2[e], x3 = v3[e];
         w2[i].x -= c0 * x0.x + c1 * x1.x + c2 * x2.x + c3 * x3.x;
         w2[i].y -= c0 * x0.y + c1 * x1.y + c2 * x2.y + c3 * x3.y;
@@ -877,7 +974,7 @@ __device__ double cgs2(double2 (&w2)[NE2], int nvec, VecF vec, double* coef,
       const double2* v0 = reinterpret_cast<const double2*>(vec(kk));
 #pragma unroll
       for (int i = 0; i < NE2; ++i) {
-        const double2 x0 = v0[tid + KT * i];
+        const double2 x0 = v0[tid + BT * i];
         w2[i].x -= c * x0.x;
         w2[i].y -= c * x0.y;
       }
@@ -894,43 +991,43 @@ __device__ double cgs2(double2 (&w2)[NE2], int nvec, VecF vec, double* coef,
 }
 
 // acc = sum_t coef[t] * vec(t) (registers)
-template <int NE2, class VecF>
+template <int NE2, int BT, class VecF>
 __device__ inline void combine(double2 (&acc)[NE2], int nvec, VecF vec, const double* coef) {
   for (int t = 0; t < nvec; ++t) {
     const double c = coef[t];
     const double2* v0 = reinterpret_cast<const double2*>(vec(t));
 #pragma unroll
     for (int i = 0; i < NE2; ++i) {
-      const double2 x0 = v0[threadIdx.x + KT * i];
+      const double2 x0 = v0[threadIdx.x + BT * i];
       acc[i].x += c * x0.x;
       acc[i].y += c * x0.y;
     }
   }
 }
 
-template <int NE2>
+template <int NE2, int BT = KT>
 __device__ inline void store2(double* dst, const double2 (&v)[NE2], double scale) {
   double2* d2 = reinterpret_cast<double2*>(dst);
 #pragma unroll
   for (int i = 0; i < NE2; ++i)
-    d2[threadIdx.x + KT * i] = make_double2(v[i].x * scale, v[i].y * scale);
+    d2[threadIdx.x + BT * i] = make_double2(v[i].x * scale, v[i].y * scale);
 }
 
-template <int NE2>
+template <int NE2, int BT = KT>
 __device__ inline void load2(double2 (&v)[NE2], const double* src) {
   const double2* s2 = reinterpret_cast<const double2*>(src);
 #pragma unroll
-  for (int i = 0; i < NE2; ++i) v[i] = s2[threadIdx.x + KT * i];
+  for (int i = 0; i < NE2; ++i) v[i] = s2[threadIdx.x + BT * i];
 }
 
 // u += U coef (current bank)
-template <int NE2>
+template <int NE2, int BT>
 __device__ void x_add_recycled(const EngineArgs& A, int s, int bank, int nvec, const double* coef,
                                double2 (&tmp)[NE2]) {
   double* xs = A.x + (long)s * A.NV;
-  load2<NE2>(tmp, xs);
-  combine<NE2>(tmp, nvec, [&](int t) { return rec_u(A, s, bank, t); }, coef);
-  store2<NE2>(xs, tmp, 1.0);
+  load2<NE2, BT>(tmp, xs);
+  combine<NE2, BT>(tmp, nvec, [&](int t) { return rec_u(A, s, bank, t); }, coef);
+  store2<NE2, BT>(xs, tmp, 1.0);
 }
 
 // Per slot and step, according to the slot's phase:
@@ -942,10 +1039,10 @@ __device__ void x_add_recycled(const EngineArgs& A, int s, int bank, int nvec, c
 //            rebuilt one column per step (incremental QR); then x0 from the
 //            recycle space.
 // With REC false the recycle space is empty and this is restarted GMRES.
-template <int NE2, bool REC>
-__global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
-  __shared__ double part[4][kPart];
-  __shared__ double lds[4 * 9];
+template <int NE2, bool REC, int BT>
+__global__ void __launch_bounds__(BT) k_krylov(EngineArgs A) {
+  __shared__ double part[BT / 64][kPart];
+  __shared__ double lds[(BT / 64) * 9];
   __shared__ double coef[kMaxBasis + 1];
   __shared__ double ytmp[kMaxBasis + 1];
   __shared__ double ycoef[kMaxRestart + 1];
@@ -973,29 +1070,29 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
   const double* d = A.d + (long)s * r;
 
   double2 w2[NE2];
-  load2<NE2>(w2, ws);
+  load2<NE2, BT>(w2, ws);
   double wn0 = 0.0;
 
   if (REC && ph == PH_RECYC) {
     // w = A P^-1 u_rj = sum_{l<rj} c_l rho_l + rho c_rj
     const int rj = si[SI_RJ];
-    const double hn = cgs2<NE2>(w2, rj, cvec, coef, part, ytmp, lds, wn0);
+    const double hn = cgs2<NE2, BT>(w2, rj, cvec, coef, part, ytmp, lds, wn0);
     const bool ok = isfinite(hn) && hn > 1e-10 * wn0;
     if (ok) {
-      store2<NE2>(rec_c(A, s, bank, rj), w2, 1.0 / hn);
+      store2<NE2, BT>(rec_c(A, s, bank, rj), w2, 1.0 / hn);
       // u_rj = (u_rj - sum_l u_l rho_l) / rho keeps A P^-1 U = C
       double* urj = rec_u(A, s, bank, rj);
-      load2<NE2>(w2, urj);
+      load2<NE2, BT>(w2, urj);
       double2 acc[NE2];
 #pragma unroll
       for (int i = 0; i < NE2; ++i) acc[i] = make_double2(0.0, 0.0);
-      combine<NE2>(acc, rj, [&](int t) { return rec_u(A, s, bank, t); }, coef);
+      combine<NE2, BT>(acc, rj, [&](int t) { return rec_u(A, s, bank, t); }, coef);
 #pragma unroll
       for (int i = 0; i < NE2; ++i) {
         w2[i].x -= acc[i].x;
         w2[i].y -= acc[i].y;
       }
-      store2<NE2>(urj, w2, 1.0 / hn);
+      store2<NE2, BT>(urj, w2, 1.0 / hn);
     }
     const int kn = ok ? rj + 1 : rj;
     __syncthreads();
@@ -1004,13 +1101,13 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
       if (kn > 0) {
 #pragma unroll
         for (int i = 0; i < NE2; ++i) {
-          const int e = 2 * (tid + KT * i);
+          const int e = 2 * (tid + BT * i);
           w2[i].x = e < N ? d[e / ld] * A.c0[e] : 0.0;
           w2[i].y = e + 1 < N ? d[(e + 1) / ld] * A.c0[e + 1] : 0.0;
         }
         double dummy;
-        cgs2<NE2>(w2, kn, cvec, coef, part, ytmp, lds, dummy);
-        x_add_recycled<NE2>(A, s, bank, kn, coef, w2);
+        cgs2<NE2, BT>(w2, kn, cvec, coef, part, ytmp, lds, dummy);
+        x_add_recycled<NE2, BT>(A, s, bank, kn, coef, w2);
       }
       if (tid == 0) {
         si[SI_KCUR] = kn;
@@ -1028,7 +1125,7 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
     double acc = 0;
 #pragma unroll
     for (int i = 0; i < NE2; ++i) {
-      const int e = 2 * (tid + KT * i);
+      const int e = 2 * (tid + BT * i);
       const double r0 = e < N ? d[e / ld] * A.c0[e] - w2[i].x : 0.0;
       const double r1 = e + 1 < N ? d[(e + 1) / ld] * A.c0[e + 1] - w2[i].y : 0.0;
       w2[i].x = r0;
@@ -1051,15 +1148,15 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
     } else {
       if (REC && kc > 0) {
         // project r off C and add the matching correction U C^T r to u
-        rn = cgs2<NE2>(w2, kc, cvec, coef, part, ytmp, lds, wn0);
-        if (rn > 0) store2<NE2>(Vs, w2, 1.0 / rn);
-        x_add_recycled<NE2>(A, s, bank, kc, coef, w2);
+        rn = cgs2<NE2, BT>(w2, kc, cvec, coef, part, ytmp, lds, wn0);
+        if (rn > 0) store2<NE2, BT>(Vs, w2, 1.0 / rn);
+        x_add_recycled<NE2, BT>(A, s, bank, kc, coef, w2);
         if (!(rn > 0)) {  // r lay in span(C): x is updated, test it again
           if (tid == 0) si[SI_PHASE] = PH_RESTART;
           return;
         }
       } else {
-        store2<NE2>(Vs, w2, 1.0 / rn);
+        store2<NE2, BT>(Vs, w2, 1.0 / rn);
       }
       if (tid == 0) {
         gs[0] = rn;
@@ -1076,13 +1173,13 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
 
   // ---- Arnoldi step j: w = A P^-1 v_j, orthogonalised against [C, V_0..j] ----
   const int j = si[SI_J];
-  const double hn = cgs2<NE2>(
+  const double hn = cgs2<NE2, BT>(
       w2, kc + j + 1,
       [&](int t) { return t < kc ? cvec(t) : Vs + (long)(t - kc) * NV; }, coef, part, ytmp, lds,
       wn0);
   if (REC && tid < kc) A.Bk[((long)s * A.kmax + tid) * m + j] = coef[tid];
   if (tid <= j) hcol[tid] = coef[kc + tid];
-  if (hn > 0) store2<NE2>(Vs + (long)(j + 1) * NV, w2, 1.0 / hn);
+  if (hn > 0) store2<NE2, BT>(Vs + (long)(j + 1) * NV, w2, 1.0 / hn);
   __syncthreads();
   if (tid == 0) {
     hcol[j + 1] = hn;
@@ -1150,10 +1247,10 @@ __global__ void __launch_bounds__(KT) k_krylov(EngineArgs A) {
     const int jn = j + 1;
     // u += V y - U B y  (the iterate is kept before preconditioning)
     double* xs = A.x + (long)s * NV;
-    load2<NE2>(w2, xs);
-    combine<NE2>(w2, jn, [&](int t) { return Vs + (long)t * NV; }, ycoef);
-    if (REC && kc > 0) combine<NE2>(w2, kc, [&](int t) { return rec_u(A, s, bank, t); }, tco);
-    store2<NE2>(xs, w2, 1.0);
+    load2<NE2, BT>(w2, xs);
+    combine<NE2, BT>(w2, jn, [&](int t) { return Vs + (long)t * NV; }, ycoef);
+    if (REC && kc > 0) combine<NE2, BT>(w2, kc, [&](int t) { return rec_u(A, s, bank, t); }, tco);
+    store2<NE2, BT>(xs, w2, 1.0);
     if (tid == 0) si[SI_PHASE] = next_phase;
   }
 }
@@ -1461,46 +1558,52 @@ __global__ void __launch_bounds__(KT) k_recycle(EngineArgs A) {
   }
 }
 
-// Per-slot vector stride: r * ld rounded up to 512 * NE2 with NE2 one of the
-// Krylov kernel's instantiations.
-static const int kNE2[] = {1, 2, 3, 4, 5, 6, 7, 8, 12, 16, 24, 32};
+// Per-slot vector stride.  Short vectors (r * ld <= 2048) use 256-thread
+// Krylov workgroups and a stride of 512 * NE2 (NE2 = 1..4); longer ones use
+// 1024 threads (16 wavefronts per slot) and a stride of 2048 * NE2 (NE2 =
+// 2..8).  The recycle-update kernel runs 256 threads with stride / 512
+// double2 per thread.
 static long long slot_stride(long long r, long long ld) {
-  const long long need = (r * ld + 511) / 512;
-  for (int v : kNE2)
-    if (need <= v) return 512LL * v;
-  throw Error{LYAP_E_INVAL, "r * n too large for the Krylov kernel (r * ld <= 16384)"};
+  const long long n = r * ld;
+  if (n <= 2048) return 512LL * ((n + 511) / 512);
+  const long long need = (n + 2 * KK - 1) / (2 * KK);
+  LYAP_REQUIRE(need <= 8, LYAP_E_INVAL, "r * n too large for the Krylov kernel (r * ld <= 16384)");
+  return 2LL * KK * need;
 }
 
-template <int NE2>
+template <int NE2, int BT>
 static void launch_krylov_ne(const EngineArgs& A, int S, hipStream_t st, bool update) {
   if (update) {
-    hipLaunchKernelGGL((k_recycle<NE2>), dim3(S), dim3(KT), 0, st, A);
+    hipLaunchKernelGGL((k_recycle<NE2 * BT / KT>), dim3(S), dim3(KT), 0, st, A);
   } else if (A.kmax > 0) {
-    hipLaunchKernelGGL((k_krylov<NE2, true>), dim3(S), dim3(KT), 0, st, A);
+    hipLaunchKernelGGL((k_krylov<NE2, true, BT>), dim3(S), dim3(BT), 0, st, A);
   } else {
-    hipLaunchKernelGGL((k_krylov<NE2, false>), dim3(S), dim3(KT), 0, st, A);
+    hipLaunchKernelGGL((k_krylov<NE2, false, BT>), dim3(S), dim3(BT), 0, st, A);
   }
 }
 
-// elements-per-thread bound of the Krylov kernels: NV = 512 * NE2.  update
-// selects the recycle-space update kernel instead of the Krylov step.
+// update selects the recycle-space update kernel instead of the Krylov step.
 static void launch_krylov(const EngineArgs& A, int S, long long NV, hipStream_t st,
                           bool update = false) {
-  switch (NV / 512) {
-    case 1: launch_krylov_ne<1>(A, S, st, update); break;
-    case 2: launch_krylov_ne<2>(A, S, st, update); break;
-    case 3: launch_krylov_ne<3>(A, S, st, update); break;
-    case 4: launch_krylov_ne<4>(A, S, st, update); break;
-    case 5: launch_krylov_ne<5>(A, S, st, update); break;
-    case 6: launch_krylov_ne<6>(A, S, st, update); break;
-    case 7: launch_krylov_ne<7>(A, S, st, update); break;
-    case 8: launch_krylov_ne<8>(A, S, st, update); break;
-    case 12: launch_krylov_ne<12>(A, S, st, update); break;
-    case 16: launch_krylov_ne<16>(A, S, st, update); break;
-    case 24: launch_krylov_ne<24>(A, S, st, update); break;
-    case 32: launch_krylov_ne<32>(A, S, st, update); break;
-    default: throw Error{LYAP_E_INVAL, "unsupported r * n for the Krylov kernel"};
+  if (NV <= 2048) {
+    switch (NV / (2 * KT)) {
+      case 1: launch_krylov_ne<1, KT>(A, S, st, update); return;
+      case 2: launch_krylov_ne<2, KT>(A, S, st, update); return;
+      case 3: launch_krylov_ne<3, KT>(A, S, st, update); return;
+      case 4: launch_krylov_ne<4, KT>(A, S, st, update); return;
+    }
+  } else {
+    switch (NV / (2 * KK)) {
+      case 2: launch_krylov_ne<2, KK>(A, S, st, update); return;
+      case 3: launch_krylov_ne<3, KK>(A, S, st, update); return;
+      case 4: launch_krylov_ne<4, KK>(A, S, st, update); return;
+      case 5: launch_krylov_ne<5, KK>(A, S, st, update); return;
+      case 6: launch_krylov_ne<6, KK>(A, S, st, update); return;
+      case 7: launch_krylov_ne<7, KK>(A, S, st, update); return;
+      case 8: launch_krylov_ne<8, KK>(A, S, st, update); return;
+    }
   }
+  throw Error{LYAP_E_INVAL, "unsupported r * n for the Krylov kernel"};
 }
 
 // profiling: copy this step's list counts to a device slot (graph-capturable)
@@ -1767,6 +1870,8 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
   if (ev) LYAP_HIP(hipEventRecord(ev->kry[1], st));
   if (A.kmax > 0) launch_krylov(A, S, (long long)A.NV, st, true);
   hipLaunchKernelGGL(k_admit, dim3(S), dim3(KT), 0, st, A);
+  if (A.use_precond)
+    hipLaunchKernelGGL(k_pinv, dim3(S, pinv_chunks(r, nu)), dim3(KT), 0, st, A);
   if (A.pbar > 0) hipLaunchKernelGGL(k_capsetup, dim3(S), dim3(KT), 0, st, A);
   LYAP_HIP(hipGetLastError());
 }

@@ -77,6 +77,8 @@ def test_seed_apply_matches_cpu_lyapunov():
     lambda: W.small_chain(45, (7, 30, 41), 4, 6),
     lambda: W.small_multiagent(30, 2, 3, 6),
     lambda: W.random_stable(40, 2, 3, 5, 3),
+    lambda: W.random_stable(50, 6, 3, 5, 13),    # r = 6: wavefront block inverse
+    lambda: W.random_stable(60, 12, 2, 4, 14),   # r = 12: no preconditioner (r > 8)
 ])
 def test_small_problems_fp64_elementwise(maker):
     pr = maker()

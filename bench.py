@@ -113,7 +113,7 @@ def stored_traffic(config, prec):
 
 
 def cpu_baseline(pr, idx):
-    """The oracle as it stands, on this host's cores, for one parameter of the workload."""
+    """The oracle as it stands, on this host's cores, for a few parameters of the workload."""
     from oracle import lyap_bs as O
     try:
         from threadpoolctl import threadpool_info
@@ -121,11 +121,44 @@ def cpu_baseline(pr, idx):
     except Exception:
         threads = os.cpu_count()
     t = time.perf_counter()
-    res = O.solve_one(pr.A0, pr.U, pr.V, pr.B, pr.E, pr.d[idx], diagnostics=False)
+    traces = [O.solve_one(pr.A0, pr.U, pr.V, pr.B, pr.E, pr.d[i], diagnostics=False).trace
+              for i in idx]
     dt = time.perf_counter() - t
-    return {"value": 1.0 / dt, "unit": "evals/s", "cores": int(threads), "kind": "oracle",
-            "sample": "1 parameter (index %d) of the same workload, complex-Schur Bartels-Stewart, "
-                      "%.1f s wall, multithreaded host BLAS" % (idx, dt)}, res.trace
+    return {"value": len(idx) / dt, "unit": "evals/s", "cores": int(threads), "kind": "oracle",
+            "sample": "%d parameters (indices %s) of the same workload, one after another, "
+                      "complex-Schur Bartels-Stewart, %.1f s wall, multithreaded host BLAS"
+                      % (len(idx), idx, dt)}, traces
+
+
+# The paper's own timings for this path (MATLAB, unstated laptop, FP64): context only,
+# different workloads and hardware, so vs_baseline stays null.
+PAPER_CONTEXT = {
+    "evals_s_derived": {"Ex.2 (196 agents, n=392)": 10.5, "Ex.3 k=41 (200 agents, n=400)": 5.9},
+    "hardware": "MATLAB on an unstated laptop", "precision": "FP64 (implied)",
+    "source": "Section 4, Examples 2 and 3 (tables of average times); per-evaluation rates "
+              "derived by dividing by the number of stable parameter vectors",
+}
+
+
+def per_parameter_baseline(L, torch, pr, traces, count=2):
+    """Plain FP64 per-parameter solve through the same library: each A(p) is factored as
+    its own seed (host eigendecomposition, device Cauchy solve); trace(E X(p)) is that
+    seed's t0.  No SMW correction, no Krylov iteration."""
+    P = pr.P
+    idx = [(P * (k + 1)) // (count + 1) for k in range(count)]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    got = []
+    for i in idx:
+        sd = L.Seed(pr.A_of(i), pr.U, pr.V, pr.B, pr.E)
+        got.append(sd.info()["t0"])
+        sd.release()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    return {"value": len(idx) / dt, "unit": "evals/s",
+            "kind": "per-parameter seed_factor of A(p) (no SMW, no Krylov)",
+            "sample": "%d parameters (indices %s), %.2f s" % (len(idx), idx, dt),
+            "rel_diff_vs_smw": float(max(abs(g - traces[i]) / abs(g) for g, i in zip(got, idx)))}
 
 
 def main():
@@ -142,6 +175,8 @@ def main():
                     help="GCRO-DR recycle space dimension (0: restarted GMRES)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="graph replay, no event timing")
+    ap.add_argument("--profile-krylov", action="store_true",
+                    help="also time the Krylov kernel (adds event nodes to every step)")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-rate", type=float, default=4.0, help="request arrivals per second")
     ap.add_argument("--serve-sizes", default="400,1000,2000")
@@ -197,7 +232,7 @@ def main():
     torch.cuda.synchronize()
 
     if not args.no_profile:
-        L.profile_enable(True)
+        L.profile_enable(2 if args.profile_krylov else 1)
     lat = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -264,12 +299,23 @@ def main():
                            "kernel": "Cauchy contraction GEMM (%s)" % args.prec,
                            "avg_launch_us": 1e3 * ms / nl, "launches": nl,
                            "algorithmic_flops_per_launch": fl / nl}
-        out["kernel_time_share"] = {
-            "cauchy_gemm": (prof["gemm64_ms"] + prof["gemmlo_ms"]) / (1e3 * wall),
-            "krylov": prof["krylov_ms"] / (1e3 * wall)}
+        out["roofline"]["timed_in_graph"] = prof["graph_steps"] == prof["steps"]
+        if prof["graph_steps"] != prof["steps"]:
+            out["roofline"]["note"] = L.last_error()
+        out["roofline"]["timed_steps"] = prof["steps"]
+        if args.profile_krylov:
+            out["kernel_time_share"] = {
+                "cauchy_gemm": (prof["gemm64_ms"] + prof["gemmlo_ms"]) / (1e3 * wall),
+                "krylov": prof["krylov_ms"] / (1e3 * wall)}
+    # the plain per-parameter solve on the same GPU path (no SMW, no Krylov)
+    out["gpu_per_parameter_baseline"] = per_parameter_baseline(L, torch, pr, traces)
+    out["paper_context"] = PAPER_CONTEXT
     if not args.no_cpu_baseline:
-        cb, ctrace = cpu_baseline(pr, P // 2 + 5)
-        cb["rel_diff_vs_gpu"] = abs(ctrace - traces[P // 2 + 5]) / abs(ctrace)
+        # about 15 s of oracle work: its time per solve grows like n^3 (about 5 s at n = 2000)
+        count = int(min(P, max(1, round(15.0 / (5.0 * (pr.n / 2000.0) ** 3)))))
+        idx = sorted({(P // 2 + 5 + k * (P // count)) % P for k in range(count)})
+        cb, ctraces = cpu_baseline(pr, idx)
+        cb["rel_diff_vs_gpu"] = float(max(abs(c - traces[i]) / abs(c) for c, i in zip(ctraces, idx)))
         out["cpu_baseline"] = cb
     print(json.dumps(out), flush=True)
 

@@ -224,20 +224,24 @@ lyap_status engine_harvest(lyap_engine eng, int64_t max_out, int64_t* tags_out,
 /* ------------------------------------------------------------------------ */
 
 /* Per-kernel timings of engine steps, accumulated process-wide while
- * profiling is enabled.  When enabled, engines launch their steps directly
- * (not as a graph) with HIP event pairs around the FP64 Cauchy GEMM, the
- * low-precision Cauchy GEMM and the Krylov kernel, on the stream those kernels
- * run on.  *_flops are algorithmic: 2 r^2 n^2 per active parameter per
- * product (the real-compressed Cauchy contraction), not the padded tile work. */
+ * profiling is enabled.  Level 1: one batch of 8 steps in 4 is timed (the
+ * others replay the production graph); a timed step replays captured segments
+ * before, between and after the Cauchy products and launches each product
+ * between two HIP events on the engine stream, per-step active counts being
+ * recorded by a small kernel.  Level 2: every step launched directly with
+ * events also around the Krylov kernel.  *_flops are algorithmic: 2 r^2 n^2
+ * per active parameter per product (the real-compressed Cauchy contraction),
+ * not the padded tile work.  krylov_* stay zero at level 1. */
 typedef struct {
   double gemm64_ms, gemm64_flops;
   double gemmlo_ms, gemmlo_flops;
   double krylov_ms;
   int64_t gemm64_launches, gemmlo_launches, krylov_launches;
   int64_t steps, slot_steps;
+  int64_t graph_steps;    /* steps timed inside the captured profiling graph (the rest: direct launches) */
 } lyap_profile;
 
-void lyap_profile_enable(int32_t on); /* also resets the counters */
+void lyap_profile_enable(int32_t level); /* 0 off, 1 GEMMs, 2 GEMMs + Krylov; resets counters */
 lyap_status lyap_profile_read(lyap_profile* out);
 
 /* Host-only real Schur decomposition used by the Schur-basis seed solve:

@@ -5,4 +5,4 @@ thin ctypes binding.  Importing the package does not touch the GPU.
 """
 from .lyapsmw import (Seed, Engine, LyapError, solve_opts, load, EXPORTS,  # noqa: F401
                       RESULT_DTYPE, PREC, BASIS, profile_enable, profile_read, calib_copy,
-                      real_schur)
+                      real_schur, last_error)

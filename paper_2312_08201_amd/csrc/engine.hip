@@ -1606,10 +1606,13 @@ static void launch_krylov(const EngineArgs& A, int S, long long NV, hipStream_t 
   throw Error{LYAP_E_INVAL, "unsupported r * n for the Krylov kernel"};
 }
 
-// profiling: copy this step's list counts to a device slot (graph-capturable)
-__global__ void k_record_counts(const int* lists, int S, int* dst) {
-  dst[0] = lists[2 * S];
-  dst[1] = lists[2 * S + 1];
+// profiling: append this step's list counts at dst[2 * (*counter)]
+// (graph-capturable: the position comes from a device counter)
+__global__ void k_record_counts(const int* lists, int S, int* dst, int* counter) {
+  const int i = counter[0];
+  counter[0] = i + 1;
+  dst[2 * i] = lists[2 * S];
+  dst[2 * i + 1] = lists[2 * S + 1];
 }
 
 // Admission: every free slot takes the next queued parameter (device-side
@@ -1651,12 +1654,14 @@ struct lyap_engine_s {
   bool owns_graph = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  // profiling graph: kProfSteps steps with event pairs and recorded counts
-  hipGraph_t pgraph = nullptr;
-  hipGraphExec_t pgexec = nullptr;
+  // profiling: captured step segments around the Cauchy products
+  hipGraph_t pseg[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t psegx[3] = {nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> pev;
   DevBuf pcounts;
   bool prof_graph_ok = true;
+  int prof_level = 0;        // level the profiling segments were captured with
+  long long prof_batches = 0;  // poll batches run while profiling (sampling)
   EngineArgs args{};
   std::vector<DevResult> res_host;
   std::vector<long long> done_pos;  // host-side list of positions already harvested
@@ -1752,14 +1757,24 @@ struct StepEvents {
   hipEvent_t g64[2], glo[2], kry[2];
 };
 
-static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullptr) {
+// Parts of one step: everything (PART_ALL), or the segments around the
+// Cauchy products, so that a profiled step can replay the segments as graphs
+// and launch the timed products between HIP events on the same stream.
+enum StepPart { PART_ALL = -1, PART_PRE = 0, PART_G64 = 1, PART_MID = 2, PART_GLO = 3, PART_POST = 4 };
+
+static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullptr,
+                        int part = PART_ALL) {
   const EngineArgs& A = E->args;
   lyap_seed_s* sd = E->sd;
   const int S = E->S, r = (int)sd->r, ld = (int)sd->ld, nu = (int)(sd->n - sd->h);
-  hipLaunchKernelGGL(k_lists, dim3(1), dim3(1024), 0, st, A);
+  auto on = [&](int p) { return part == PART_ALL || part == p; };
+  if (part != PART_ALL) ev = nullptr;
   const int pgrid = std::min(S, 1024);
+  if (on(PART_PRE)) {
+  hipLaunchKernelGGL(k_lists, dim3(1), dim3(1024), 0, st, A);
   hipLaunchKernelGGL(k_prep, dim3(pgrid), dim3(KT), 0, st, A);
-  if (A.pbar > 0) {
+  }
+  if (on(PART_PRE) && A.pbar > 0) {
     // low-rank preconditioner part: two skinny GEMMs over the listed slots
     constexpr int kTsvdGrid = 256;
     GemmArgs g{};
@@ -1800,18 +1815,23 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     // seed solve in the real Schur basis for every listed slot
     const int n = (int)sd->n;
     const int* cnt = E->lists.as<int>() + 2 * S;
+    if (on(PART_G64)) {
     if (ev) LYAP_HIP(hipEventRecord(ev->g64[0], st));
     trilyap_launch(sd->T.as<double>(), sd->Tt.as<double>(), E->XS.as<double>(), (long)ld * ld,
                    nullptr, 0, sd->Uh.as<double>(), E->z.as<double>(), (long)E->args.NV, r, n, ld, S,
                    E->lists.as<int>(), cnt, st);
     if (ev) LYAP_HIP(hipEventRecord(ev->g64[1], st));
+    }
+    if (on(PART_MID)) {
     project_launch(sd->Vh.as<double>(), E->XS.as<double>(), (long)ld * ld, E->H.as<double>(),
                    (long)r * ld, r, n, ld, S, E->lists.as<int>(), cnt, st);
     hipLaunchKernelGGL(k_epilogue_schur, dim3(ublocks, S * r), dim3(KT), 0, st, A,
                        E->H.as<double>());
+    }
   } else {
   // FP64 list (which = 0)
   {
+    if (on(PART_PRE))
     hipLaunchKernelGGL((k_formX<double>), dim3(egrid), dim3(KT), 0, st, A, E->X.as<double>(), 0L,
                        0);
     GemmArgs g{};
@@ -1827,10 +1847,13 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     g.M_dev = E->lists.as<int>() + 2 * S;
     g.m_scale = r * r;
     g.Cpart = E->Hp.p;
+    if (on(PART_G64)) {
     if (ev) LYAP_HIP(hipEventRecord(ev->g64[0], st));
     gemm_launch(g, st);
     if (ev) LYAP_HIP(hipEventRecord(ev->g64[1], st));
+    }
     const int ggrid = (int)(E->rows_pad / kGemmBM) * (ld / kGemmBN);
+    if (on(PART_MID))
     hipLaunchKernelGGL((k_epilogue<double>), dim3(egrid), dim3(KT), 0, st, A, E->H.as<double>(),
                        E->Hp.as<double>(), 0, ggrid, ld / gemm_bk(GemmType::F64));
   }
@@ -1848,26 +1871,36 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     g.M_dev = E->lists.as<int>() + 2 * S + 1;
     g.m_scale = r * r;
     g.Cpart = E->Hplo.p;
-    if (E->low == GemmType::F32) {
-      hipLaunchKernelGGL((k_formX<float>), dim3(egrid), dim3(KT), 0, st, A, E->Xlo.as<float>(),
-                         0L, 1);
-    } else {
+    if (E->low != GemmType::F32) {
       g.a_plane = E->rows_pad * ld;
       g.b_plane = (long long)ld * ld;
-      hipLaunchKernelGGL((k_formX<__bf16>), dim3(egrid), dim3(KT), 0, st, A,
-                         E->Xlo.as<__bf16>(), (long)(E->rows_pad * ld), 1);
     }
+    if (on(PART_MID)) {
+      if (E->low == GemmType::F32)
+        hipLaunchKernelGGL((k_formX<float>), dim3(egrid), dim3(KT), 0, st, A, E->Xlo.as<float>(),
+                           0L, 1);
+      else
+        hipLaunchKernelGGL((k_formX<__bf16>), dim3(egrid), dim3(KT), 0, st, A,
+                           E->Xlo.as<__bf16>(), (long)(E->rows_pad * ld), 1);
+    }
+    if (on(PART_GLO)) {
     if (ev) LYAP_HIP(hipEventRecord(ev->glo[0], st));
     gemm_launch(g, st);
     if (ev) LYAP_HIP(hipEventRecord(ev->glo[1], st));
+    }
     const int ggrid = (int)(E->rows_pad / kGemmBM) * (ld / kGemmBN);
+    if (on(PART_POST))
     hipLaunchKernelGGL((k_epilogue<float>), dim3(egrid), dim3(KT), 0, st, A, E->Hlo.as<float>(),
                        E->Hplo.as<float>(), 1, ggrid, ld / gemm_bk(E->low));
   }
   }  // eigen basis
-  if (ev) LYAP_HIP(hipEventRecord(ev->kry[0], st));
+  if (!on(PART_POST)) {
+    LYAP_HIP(hipGetLastError());
+    return;
+  }
+  if (ev && ev->kry[0]) LYAP_HIP(hipEventRecord(ev->kry[0], st));
   launch_krylov(A, S, (long long)A.NV, st);
-  if (ev) LYAP_HIP(hipEventRecord(ev->kry[1], st));
+  if (ev && ev->kry[0]) LYAP_HIP(hipEventRecord(ev->kry[1], st));
   if (A.kmax > 0) launch_krylov(A, S, (long long)A.NV, st, true);
   hipLaunchKernelGGL(k_admit, dim3(S), dim3(KT), 0, st, A);
   if (A.use_precond)
@@ -1879,19 +1912,20 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
 // ---- process-wide profile (lyap_profile_*) ----
 namespace {
 std::mutex g_prof_mu;
-bool g_prof_on = false;
+int g_prof_level = 0;  // 0 off, 1 Cauchy GEMM events, 2 also the Krylov kernel
 lyap_profile g_prof{};
 }  // namespace
 
-static bool profiling() {
+static int profiling() {
   std::lock_guard<std::mutex> g(g_prof_mu);
-  return g_prof_on;
+  return g_prof_level;
 }
 
 constexpr int kProfSteps = 8;
+constexpr int kProfEvery = 4;
 
 static void prof_accumulate(lyap_engine_s* E, const std::vector<StepEvents>& evs, const int* counts,
-                            long long k) {
+                            long long k, bool graph) {
   const double r = (double)E->sd->r, n = (double)E->sd->n;
   lyap_profile add{};
   for (long long i = 0; i < k; ++i) {
@@ -1910,13 +1944,17 @@ static void prof_accumulate(lyap_engine_s* E, const std::vector<StepEvents>& evs
         add.gemmlo_flops += 2.0 * counts[2 * i + 1] * r * r * n * n;
       }
     }
-    LYAP_HIP(hipEventElapsedTime(&t, evs[i].kry[0], evs[i].kry[1]));
-    add.krylov_ms += t;
-    add.krylov_launches += 1;
+    if (evs[i].kry[0]) {
+      LYAP_HIP(hipEventElapsedTime(&t, evs[i].kry[0], evs[i].kry[1]));
+      add.krylov_ms += t;
+      add.krylov_launches += 1;
+    }
     add.slot_steps += counts[2 * i] + counts[2 * i + 1];
   }
   add.steps = k;
+  add.graph_steps = graph ? k : 0;
   std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof.graph_steps += add.graph_steps;
   g_prof.gemm64_ms += add.gemm64_ms;
   g_prof.gemm64_launches += add.gemm64_launches;
   g_prof.gemm64_flops += add.gemm64_flops;
@@ -1934,54 +1972,80 @@ static std::vector<StepEvents> prof_events(lyap_engine_s* E) {
   for (int i = 0; i < kProfSteps; ++i) {
     hipEvent_t* p = &evs[i].g64[0];
     for (int q = 0; q < 6; ++q) p[q] = E->pev[6 * i + q];
+    if (E->prof_level < 2) evs[i].kry[0] = evs[i].kry[1] = nullptr;  // GEMM events only
   }
   return evs;
 }
 
-// Capture kProfSteps steps with event-record nodes (timing events) once.
-static void prof_graph_build(lyap_engine_s* E) {
+// Profiled steps.  Event-record nodes inside a graph cannot be read back
+// with hipEventElapsedTime on this runtime, so a profiled step replays three
+// captured segments (before, between and after the Cauchy products) and
+// launches the products themselves directly, each between two HIP events on
+// the engine stream; per-step active counts are appended by a small kernel
+// in the last segment.  Level 2 (also timing the Krylov kernel) and any
+// failure fall back to direct launches of whole steps.
+static void prof_segments_build(lyap_engine_s* E) {
   hipStream_t st = E->stream;
-  E->pev.resize(6 * kProfSteps);
-  for (auto& e : E->pev) LYAP_HIP(hipEventCreate(&e));
-  E->pcounts.alloc(sizeof(int) * 2 * kProfSteps);
-  std::vector<StepEvents> evs = prof_events(E);
-  LYAP_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-  try {
-    for (int i = 0; i < kProfSteps; ++i) {
-      launch_step(E, st, &evs[i]);
-      hipLaunchKernelGGL(k_record_counts, dim3(1), dim3(1), 0, st, E->lists.as<int>(), E->S,
-                         E->pcounts.as<int>() + 2 * i);
-    }
-  } catch (...) {
-    hipGraph_t tmp;
-    (void)hipStreamEndCapture(st, &tmp);
-    throw;
+  if (E->pev.empty()) {
+    E->pev.resize(6 * kProfSteps);
+    for (auto& e : E->pev) LYAP_HIP(hipEventCreate(&e));
+    E->pcounts.alloc(sizeof(int) * (2 * kProfSteps + 1));
   }
-  LYAP_HIP(hipStreamEndCapture(st, &E->pgraph));
-  LYAP_HIP(hipGraphInstantiate(&E->pgexec, E->pgraph, nullptr, nullptr, 0));
+  const int parts[3] = {PART_PRE, PART_MID, PART_POST};
+  for (int q = 0; q < 3; ++q) {
+    LYAP_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+      launch_step(E, st, nullptr, parts[q]);
+      if (parts[q] == PART_POST)
+        hipLaunchKernelGGL(k_record_counts, dim3(1), dim3(1), 0, st, E->lists.as<int>(), E->S,
+                           E->pcounts.as<int>() + 1, E->pcounts.as<int>());
+    } catch (...) {
+      hipGraph_t tmp;
+      (void)hipStreamEndCapture(st, &tmp);
+      throw;
+    }
+    LYAP_HIP(hipStreamEndCapture(st, &E->pseg[q]));
+    LYAP_HIP(hipGraphInstantiate(&E->psegx[q], E->pseg[q], nullptr, nullptr, 0));
+  }
 }
 
-// Run k steps with event pairs and per-step active counts; accumulate the profile.
-// Preferred: the captured profiling graph (same launch path as production);
-// fallback: direct launches.
-static void profiled_steps(lyap_engine_s* E, long long k) {
+// Run k steps with event pairs around the Cauchy products and per-step active
+// counts; accumulate the profile.
+static void profiled_steps(lyap_engine_s* E, long long k, int level) {
   hipStream_t st = E->stream;
   const int S = E->S;
-  if (E->prof_graph_ok) {
+  if (level == 1 && E->prof_graph_ok) {
     try {
-      if (!E->pgexec) prof_graph_build(E);
+      if (!E->psegx[0]) prof_segments_build(E);
+      E->prof_level = level;
       std::vector<StepEvents> evs = prof_events(E);
       int counts[2 * kProfSteps];
       for (long long done = 0; done < k; done += kProfSteps) {
-        LYAP_HIP(hipGraphLaunch(E->pgexec, st));
-        LYAP_HIP(hipMemcpyAsync(counts, E->pcounts.p, sizeof(counts), hipMemcpyDeviceToHost, st));
+        const int kk = (int)std::min<long long>(kProfSteps, k - done);
+        LYAP_HIP(hipMemsetAsync(E->pcounts.p, 0, sizeof(int), st));
+        for (int i = 0; i < kk; ++i) {
+          LYAP_HIP(hipGraphLaunch(E->psegx[0], st));
+          LYAP_HIP(hipEventRecord(evs[i].g64[0], st));
+          launch_step(E, st, nullptr, PART_G64);
+          LYAP_HIP(hipEventRecord(evs[i].g64[1], st));
+          LYAP_HIP(hipGraphLaunch(E->psegx[1], st));
+          if (E->mixed) {
+            LYAP_HIP(hipEventRecord(evs[i].glo[0], st));
+            launch_step(E, st, nullptr, PART_GLO);
+            LYAP_HIP(hipEventRecord(evs[i].glo[1], st));
+          }
+          LYAP_HIP(hipGraphLaunch(E->psegx[2], st));
+        }
+        LYAP_HIP(hipMemcpyAsync(counts, E->pcounts.as<int>() + 1, sizeof(int) * 2 * kk,
+                                hipMemcpyDeviceToHost, st));
         LYAP_HIP(hipStreamSynchronize(st));
-        prof_accumulate(E, evs, counts, kProfSteps);
+        prof_accumulate(E, evs, counts, kk, true);
       }
       return;
-    } catch (const Error&) {
-      E->prof_graph_ok = false;  // e.g. event timing inside graphs unsupported
+    } catch (const Error& e) {
+      E->prof_graph_ok = false;
       (void)hipGetLastError();
+      set_last_error("profiling segments unavailable, direct launches: " + e.msg);
     }
   }
   std::vector<StepEvents> evs(k);
@@ -1996,7 +2060,7 @@ static void profiled_steps(lyap_engine_s* E, long long k) {
                             hipMemcpyDeviceToHost, st));
   }
   LYAP_HIP(hipStreamSynchronize(st));
-  prof_accumulate(E, evs, counts, k);
+  prof_accumulate(E, evs, counts, k, false);
   (void)hipHostFree(counts);
   for (auto& e : evs)
     for (hipEvent_t p : {e.g64[0], e.g64[1], e.glo[0], e.glo[1], e.kry[0], e.kry[1]})
@@ -2167,11 +2231,30 @@ static void engine_destroy_impl(lyap_engine_s* E) {
   (void)hipStreamSynchronize(E->stream);
   if (E->gexec) (void)hipGraphExecDestroy(E->gexec);
   if (E->graph) (void)hipGraphDestroy(E->graph);
-  if (E->pgexec) (void)hipGraphExecDestroy(E->pgexec);
-  if (E->pgraph) (void)hipGraphDestroy(E->pgraph);
+  for (int q = 0; q < 3; ++q) {
+    if (E->psegx[q]) (void)hipGraphExecDestroy(E->psegx[q]);
+    if (E->pseg[q]) (void)hipGraphDestroy(E->pseg[q]);
+  }
   for (auto& e : E->pev) (void)hipEventDestroy(e);
   if (E->stream) (void)hipStreamDestroy(E->stream);
   delete E;
+}
+
+// Back to the state of a new engine (free slots, empty queue, no recycle
+// space), ordered after the caller's stream; buffers and graphs are kept.
+static void engine_reset(lyap_engine_s* E, hipStream_t user) {
+  hipStream_t st = E->stream;
+  hipEvent_t ev;
+  LYAP_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  LYAP_HIP(hipEventRecord(ev, user));
+  LYAP_HIP(hipStreamWaitEvent(st, ev, 0));
+  LYAP_HIP(hipEventDestroy(ev));
+  LYAP_HIP(hipMemsetAsync(E->si.p, 0, E->si.bytes, st));
+  LYAP_HIP(hipMemsetAsync(E->qctl.p, 0, E->qctl.bytes, st));
+  LYAP_HIP(hipMemsetAsync(E->res.p, 0, E->res.bytes, st));
+  E->submitted = E->harvested = E->next_tag = 0;
+  E->got.assign(E->Q, 0);
+  E->done_pos.clear();
 }
 
 // host -> device queue append (positions submitted .. submitted+count)
@@ -2220,8 +2303,11 @@ static long long engine_run_impl(lyap_engine_s* E, long long max_steps, int poll
     const long long busy = E->submitted - engine_done_count(E);
     if (busy <= 0) return 0;
     const long long k = std::min<long long>(poll_every, max_steps - steps);
-    if (profiling()) {
-      profiled_steps(E, k);
+    const int level = profiling();
+    // level 1 times one batch of steps in kProfEvery (an unbiased sample of
+    // every launch size; the other batches replay the production graph)
+    if (level && (level > 1 || E->prof_batches++ % kProfEvery == 0)) {
+      profiled_steps(E, k, level);
     } else {
       for (long long i = 0; i < k; ++i) {
         if (E->gexec) LYAP_HIP(hipGraphLaunch(E->gexec, E->stream));
@@ -2361,7 +2447,7 @@ lyap_status engine_harvest(lyap_engine E, int64_t max_out, int64_t* tags_out, ly
 
 void lyap_profile_enable(int32_t on) {
   std::lock_guard<std::mutex> g(g_prof_mu);
-  g_prof_on = on != 0;
+  g_prof_level = on < 0 ? 0 : (on > 2 ? 2 : on);
   g_prof = lyap_profile{};
 }
 
@@ -2394,18 +2480,52 @@ lyap_status smw_solve_batch(lyap_seed sd, int64_t P, const double* d_dev,
     LYAP_REQUIRE(workspace_dev == nullptr || workspace_bytes >= need, LYAP_E_INVAL,
                  "workspace too small");
     const long long r = sd->r, ld = sd->ld, n = sd->n;
-    // the solution store comes from the workspace (or a private allocation)
+    const long long S = default_slots(sd, P);
+    // The seed keeps this call's engine (buffers, captured step graphs) for the
+    // next call with the same slots, length, options and solution store; a call
+    // that finds the cache in use by another thread builds a private engine.
+    std::unique_lock<std::mutex> lk(sd->cache_mu, std::try_to_lock);
     DevBuf own;
     double* sol;
     if (workspace_dev) {
       sol = reinterpret_cast<double*>(workspace_dev);
+    } else if (lk.owns_lock()) {
+      const size_t b = (size_t)P * r * ld * sizeof(double);
+      if (sd->sol_buf.bytes < b) {
+        if (sd->eng_cache) {  // the cached engine refers to the old store
+          engine_destroy_impl(reinterpret_cast<lyap_engine_s*>(sd->eng_cache));
+          sd->eng_cache = nullptr;
+        }
+        sd->sol_buf.alloc(b);
+      }
+      sol = sd->sol_buf.as<double>();
     } else {
       own.alloc((size_t)P * r * ld * sizeof(double));
       sol = own.as<double>();
     }
-    const long long S = default_slots(sd, P);
-    lyap_engine_s* E = engine_create_impl(sd, S, &o, st, P, sol, P, true);
-    std::unique_ptr<lyap_engine_s, void (*)(lyap_engine_s*)> eg(E, engine_destroy_impl);
+    std::unique_ptr<lyap_engine_s, void (*)(lyap_engine_s*)> eg(nullptr, engine_destroy_impl);
+    lyap_engine_s* E = nullptr;
+    if (lk.owns_lock()) {
+      auto* C = reinterpret_cast<lyap_engine_s*>(sd->eng_cache);
+      if (C && C->S == S && C->Q == P && C->sol == sol && C->sol_cap == P &&
+          std::memcmp(&C->opts, &o, sizeof(o)) == 0) {
+        E = C;
+        engine_reset(E, st);
+      } else {
+        if (C) engine_destroy_impl(C);
+        sd->eng_cache = nullptr;
+        E = engine_create_impl(sd, S, &o, st, P, sol, P, true);
+        sd->eng_cache = E;
+        sd->eng_cache_free = [](void* q) { engine_destroy_impl(reinterpret_cast<lyap_engine_s*>(q)); };
+        sd->eng_cache_bytes = [](const void* q) {
+          const auto* e = reinterpret_cast<const lyap_engine_s*>(q);
+          return engine_sizes(e->sd, e->S, e->opts, e->Q).total;
+        };
+      }
+    } else {
+      E = engine_create_impl(sd, S, &o, st, P, sol, P, true);
+      eg.reset(E);
+    }
     const hipStream_t user = st;
     st = E->stream;
     // queue: d from device, tags 0..P-1

@@ -17,6 +17,8 @@
 //   rho(V^T Q0) = V^T S.
 #pragma once
 
+#include <mutex>
+
 #include "common.h"
 
 struct lyap_seed_s {
@@ -47,11 +49,24 @@ struct lyap_seed_s {
   lyap::DevBuf TsNt;      // Nt^T (128 x r*ld)
   lyap::DevBuf scratch; // grown on demand by lyap_seed_apply / trace_EX
   size_t scratch_bytes = 0;
+  // smw_solve_batch keeps its engine (buffers and captured step graphs) for the
+  // next call with the same slots, queue length, options and solution store;
+  // sol_buf is the solution store when the caller passes no workspace.
+  std::mutex cache_mu;
+  void* eng_cache = nullptr;
+  void (*eng_cache_free)(void*) = nullptr;
+  size_t (*eng_cache_bytes)(const void*) = nullptr;
+  lyap::DevBuf sol_buf;
+
+  ~lyap_seed_s() {
+    if (eng_cache && eng_cache_free) eng_cache_free(eng_cache);
+  }
 
   size_t device_bytes() const {
     return lam.bytes + Mc.bytes + Mc32.bytes + Mcb.bytes + Tin.bytes + Tout.bytes + Uh.bytes +
            Vh.bytes + K1.bytes + c0.bytes + gam.bytes + Gam.bytes + T.bytes + Tt.bytes +
-           TsM.bytes + TsN.bytes + TsNt.bytes + scratch.bytes;
+           TsM.bytes + TsN.bytes + TsNt.bytes + scratch.bytes + sol_buf.bytes +
+           (eng_cache && eng_cache_bytes ? eng_cache_bytes(eng_cache) : 0);
   }
 };
 

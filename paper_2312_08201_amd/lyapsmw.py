@@ -60,7 +60,7 @@ class Profile(C.Structure):
                 ("gemmlo_ms", C.c_double), ("gemmlo_flops", C.c_double),
                 ("krylov_ms", C.c_double), ("gemm64_launches", C.c_int64),
                 ("gemmlo_launches", C.c_int64), ("krylov_launches", C.c_int64),
-                ("steps", C.c_int64), ("slot_steps", C.c_int64)]
+                ("steps", C.c_int64), ("slot_steps", C.c_int64), ("graph_steps", C.c_int64)]
 
 
 RESULT_DTYPE = np.dtype([("status", np.int32), ("iters", np.int32), ("cycles", np.int32),
@@ -351,8 +351,15 @@ class Engine:
             pass
 
 
-def profile_enable(on: bool = True):
-    load().lyap_profile_enable(1 if on else 0)
+def last_error() -> str:
+    """The library's most recent error or diagnostic message."""
+    return load().lyap_last_error().decode()
+
+
+def profile_enable(on=True):
+    """False/0: off; True/1: events around the Cauchy GEMMs; 2: also the Krylov kernel."""
+    level = (1 if on else 0) if isinstance(on, bool) else int(on)
+    load().lyap_profile_enable(level)
 
 
 def profile_read() -> dict:

@@ -290,3 +290,24 @@ def test_serving_loop_alone_vs_mix():
         eng.close()
         assert np.max(np.abs(st.traces - alone) / np.abs(alone)) <= 1e-12
         assert np.max(rel(st.traces, oracle_traces(pr))) <= 1e-10
+
+
+def test_repeated_solves_reuse_engine_identically():
+    """smw_solve_batch keeps its engine on the seed: repeated calls (same or
+    other options, other lengths) give the results of a fresh seed, bit for bit."""
+    L, torch = lib()
+    pr = W.small_chain(45, (7, 30, 41), 4, 9)
+    d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
+    seed = L.Seed.from_problem(pr)
+    runs = []
+    for kw in ({}, {}, {"restart": 12}, {}, {"recycle_k": 4, "restart": 10}, {}):
+        Y, res = seed.solve(d, L.solve_opts(**kw))
+        runs.append((kw, Y.cpu().numpy(), res))
+    Y3, res3 = seed.solve(d[:3], L.solve_opts())
+    fresh = L.Seed.from_problem(pr)
+    for kw, Y, res in runs:
+        Yf, rf = fresh.solve(d, L.solve_opts(**kw))
+        assert np.array_equal(Y, Yf.cpu().numpy()), kw
+        assert np.array_equal(res["trace"], rf["trace"]), kw
+    assert np.array_equal(Y3.cpu().numpy(), runs[0][1][:3])
+    assert np.max(rel(runs[0][2]["trace"], oracle_traces(pr))) <= 1e-10

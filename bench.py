@@ -303,6 +303,8 @@ def main():
         if prof["graph_steps"] != prof["steps"]:
             out["roofline"]["note"] = L.last_error()
         out["roofline"]["timed_steps"] = prof["steps"]
+        out["gemm_launch_tuned"] = {"bk": prof["tuned_bk"], "grid_min": prof["tuned_grid_min"],
+                                    "xcd_mapping": not prof["tuned_xcd_off"]}
         if args.profile_krylov:
             out["kernel_time_share"] = {
                 "cauchy_gemm": (prof["gemm64_ms"] + prof["gemmlo_ms"]) / (1e3 * wall),

@@ -239,6 +239,8 @@ typedef struct {
   int64_t gemm64_launches, gemmlo_launches, krylov_launches;
   int64_t steps, slot_steps;
   int64_t graph_steps;    /* steps timed inside the captured profiling graph (the rest: direct launches) */
+  int64_t tuned_bk, tuned_grid_min, tuned_xcd_off;  /* FP64 Cauchy GEMM launch chosen by the
+                                                       autotuner for the last engine created */
 } lyap_profile;
 
 void lyap_profile_enable(int32_t level); /* 0 off, 1 GEMMs, 2 GEMMs + Krylov; resets counters */

@@ -117,15 +117,19 @@ struct GemmArgs {
   int64_t a_plane, b_plane;  // element offsets of the lo planes (BF16X3)
   const int* M_dev;   // optional device row count (scaled by m_scale)
   int m_scale;
-  void* Cpart;        // optional split-K partial buffer (same size as C), dynamic M only
+  void* Cpart;        // optional split-K partial buffer, dynamic M only (size: see grid_min)
   int64_t grid_min;   // optional: launch at least this many workgroups (more split-K
-                      // slices for skinny shapes; Cpart must then hold grid_min / 2
-                      // row tiles)
+                      // slices for skinny shapes); Cpart must hold
+                      // max(row tiles, grid / column tiles) row tiles of ldc
+  int64_t Cpart_rows; // rows (of ldc elements) that Cpart holds; checked before launch
+  int bk;             // K-tile depth (0: the type's default; F64 8 or 16, F32 16 or 32)
+  int xcd_off;        // 1: plain tile order instead of the XCD-aware mapping
 };
 
 constexpr int kGemmBM = 128;
 constexpr int kGemmBN = 128;
 inline int gemm_bk(GemmType t) { return t == GemmType::F64 ? 16 : 32; }
+inline int gemm_bk_of(const GemmArgs& g) { return g.bk > 0 ? g.bk : gemm_bk(g.type); }
 
 void gemm_launch(const GemmArgs& g, hipStream_t s);
 

@@ -24,9 +24,13 @@
 // restart evaluates the residual with the FP64 GEMM (iterative refinement).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <memory>
+#include <tuple>
 #include <mutex>
 
 #include "internal.h"
@@ -46,6 +50,14 @@ enum SI : int {
   SI_PINV, SI_N
 };
 constexpr int kPbarMax = 64;  // TSVD rank bound of the preconditioner
+constexpr int kTsvdGrid = 256;  // workgroup budget of the skinny TSVD GEMM (split-K)
+// Split-K partials: a launch of G workgroups over ntiles column tiles writes
+// at most G / ntiles row tiles of partials (the doubling rule of splitk_of
+// keeps slices x active row tiles <= G / ntiles).  The Cauchy GEMM's budget is
+// at most twice its tile count (autotuner candidates), so its partial buffer
+// holds twice the padded rows; the TSVD GEMM (one column tile) holds
+// kTsvdGrid row tiles.
+constexpr int kPartRowsFactor = 2;
 // per-slot double state
 enum SD : int { SD_BNORM = 0, SD_BETA, SD_N };
 
@@ -1634,8 +1646,16 @@ __global__ void __launch_bounds__(KT) k_admit(EngineArgs A) {
 // ---------------------------------------------------------------------------
 using namespace lyap;
 
+// Launch configuration of the Cauchy GEMM chosen by the autotuner.
+struct GemmTune {
+  int bk = 0;               // K-tile depth (0: default)
+  long long grid_min = 0;   // workgroup budget for split-K (0: one per output tile)
+  int xcd_off = 0;          // plain tile order instead of the XCD-aware mapping
+};
+
 struct lyap_engine_s {
   lyap_seed sd = nullptr;
+  GemmTune t64, tlo;  // Cauchy GEMM launch configurations (FP64, low precision)
   int S = 0, m = 40;
   lyap_solve_opts opts{};
   hipStream_t stream = nullptr;  // private non-blocking stream (graph capture needs one)
@@ -1729,9 +1749,9 @@ static EngineSizes engine_sizes(const lyap_seed_s* sd, long long S, const lyap_s
     const long long Sp = pad_to(S, 128);
     add(S * kPbarMax * kPbarMax * 8);  // Cp^-1
     add(Sp * 128 * 8 * 2);             // Tbuf, Sc
-    add(128LL * 128 * 128 * 8);        // split-K partials (grid 256)
+    add((long long)kTsvdGrid * 128 * 128 * 8);  // split-K partials
   }
-  add(z.rows_pad * ld * 8 * 3);  // X, H, split-K partials fp64
+  add(z.rows_pad * ld * 8 * (2 + kPartRowsFactor));  // X, H, split-K partials fp64
   if (o.recycle_k > 0) {
     const long long k = o.recycle_k;
     add(S * 2 * k * N * 8 * 2);        // U, C (two banks each)
@@ -1743,7 +1763,7 @@ static EngineSizes engine_sizes(const lyap_seed_s* sd, long long S, const lyap_s
   const bool mixed = o.prec != LYAP_PREC_FP64;
   if (mixed) {
     add(z.rows_pad * ld * 4);      // Xlo (float, or two bf16 planes)
-    add(z.rows_pad * ld * 4 * 2);  // Hlo, split-K partials (float)
+    add(z.rows_pad * ld * 4 * (1 + kPartRowsFactor));  // Hlo, split-K partials (float)
   }
   add(Q * r * 8);
   add(Q * 8);
@@ -1776,7 +1796,6 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
   }
   if (on(PART_PRE) && A.pbar > 0) {
     // low-rank preconditioner part: two skinny GEMMs over the listed slots
-    constexpr int kTsvdGrid = 256;
     GemmArgs g{};
     g.type = GemmType::F64;
     g.A = A.Yc;
@@ -1790,6 +1809,7 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     g.M_dev = E->lists.as<int>() + 2 * S + 2;
     g.m_scale = 1;
     g.Cpart = A.Tpart;
+    g.Cpart_rows = (long long)kTsvdGrid * 128;
     g.grid_min = kTsvdGrid;
     gemm_launch(g, st);
     const int ggrid = std::max((S + kGemmBM - 1) / kGemmBM, kTsvdGrid);
@@ -1847,15 +1867,19 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     g.M_dev = E->lists.as<int>() + 2 * S;
     g.m_scale = r * r;
     g.Cpart = E->Hp.p;
+    g.Cpart_rows = kPartRowsFactor * E->rows_pad;
+    g.bk = E->t64.bk;
+    g.grid_min = E->t64.grid_min;
+    g.xcd_off = E->t64.xcd_off;
     if (on(PART_G64)) {
     if (ev) LYAP_HIP(hipEventRecord(ev->g64[0], st));
     gemm_launch(g, st);
     if (ev) LYAP_HIP(hipEventRecord(ev->g64[1], st));
     }
-    const int ggrid = (int)(E->rows_pad / kGemmBM) * (ld / kGemmBN);
+    const int ggrid = (int)std::max<long long>((E->rows_pad / kGemmBM) * (ld / kGemmBN), g.grid_min);
     if (on(PART_MID))
     hipLaunchKernelGGL((k_epilogue<double>), dim3(egrid), dim3(KT), 0, st, A, E->H.as<double>(),
-                       E->Hp.as<double>(), 0, ggrid, ld / gemm_bk(GemmType::F64));
+                       E->Hp.as<double>(), 0, ggrid, ld / gemm_bk_of(g));
   }
   if (E->mixed) {
     GemmArgs g{};
@@ -1871,6 +1895,10 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     g.M_dev = E->lists.as<int>() + 2 * S + 1;
     g.m_scale = r * r;
     g.Cpart = E->Hplo.p;
+    g.Cpart_rows = kPartRowsFactor * E->rows_pad;
+    g.bk = E->tlo.bk;
+    g.grid_min = E->tlo.grid_min;
+    g.xcd_off = E->tlo.xcd_off;
     if (E->low != GemmType::F32) {
       g.a_plane = E->rows_pad * ld;
       g.b_plane = (long long)ld * ld;
@@ -1888,10 +1916,10 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     gemm_launch(g, st);
     if (ev) LYAP_HIP(hipEventRecord(ev->glo[1], st));
     }
-    const int ggrid = (int)(E->rows_pad / kGemmBM) * (ld / kGemmBN);
+    const int ggrid = (int)std::max<long long>((E->rows_pad / kGemmBM) * (ld / kGemmBN), g.grid_min);
     if (on(PART_POST))
     hipLaunchKernelGGL((k_epilogue<float>), dim3(egrid), dim3(KT), 0, st, A, E->Hlo.as<float>(),
-                       E->Hplo.as<float>(), 1, ggrid, ld / gemm_bk(E->low));
+                       E->Hplo.as<float>(), 1, ggrid, ld / gemm_bk_of(g));
   }
   }  // eigen basis
   if (!on(PART_POST)) {
@@ -2067,6 +2095,108 @@ static void profiled_steps(lyap_engine_s* E, long long k, int level) {
       (void)hipEventDestroy(p);
 }
 
+// ---- launch autotuner of the Cauchy GEMM ----
+// For the engine's GEMM shape (rows_pad x ld x ld) every candidate launch
+// configuration (K-tile depth x split-K workgroup budget x tile order) is
+// timed with HIP events at three active-row counts that stand for a sweep:
+// the full batch, an eighth of it and one row tile (the tail), weighted by
+// the share of steps spent in each (0.15, 0.15, 0.7).  The fastest is kept
+// for the process, per (precision, rows, ld).  The engine's own GEMM buffers
+// serve as operands before its first step.
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, long long, long long>, GemmTune> g_tune;
+GemmTune g_last_tune;
+}  // namespace
+
+static GemmTune tune_cauchy(lyap_engine_s* E, GemmType type) {
+  if (type == GemmType::BF16X3) return GemmTune{};
+  const long long ld = E->sd->ld, rows = E->rows_pad;
+  const long long sgrid0 = (rows / kGemmBM) * (ld / kGemmBN);
+  // LYAP_GEMM_CONFIG="bk,grid_mult,xcd_off" fixes the configuration (tests,
+  // diagnostics); bk must be one of the candidates of the precision
+  if (const char* env = std::getenv("LYAP_GEMM_CONFIG")) {
+    int bk = 0, mult = 0, xoff = 0;
+    LYAP_REQUIRE(std::sscanf(env, "%d,%d,%d", &bk, &mult, &xoff) == 3, LYAP_E_INVAL,
+                 "LYAP_GEMM_CONFIG must be bk,grid_mult,xcd_off");
+    const bool ok_bk = type == GemmType::F64 ? (bk == 8 || bk == 16) : (bk == 16 || bk == 32);
+    LYAP_REQUIRE(ok_bk && (mult == 0 || mult == kPartRowsFactor) && (xoff == 0 || xoff == 1),
+                 LYAP_E_INVAL,
+                 "LYAP_GEMM_CONFIG out of the candidate set");
+    return GemmTune{bk, mult * sgrid0, xoff};
+  }
+  const auto key = std::make_tuple((int)type, rows, ld);
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+  }
+  hipStream_t st = E->stream;
+  const long long sgrid = (rows / kGemmBM) * (ld / kGemmBN);
+  const int bks[2] = {type == GemmType::F64 ? 8 : 16, type == GemmType::F64 ? 16 : 32};
+  std::vector<GemmTune> cand;
+  for (int bk : bks)
+    for (long long gm : {0LL, (long long)kPartRowsFactor * sgrid})
+      for (int x : {0, 1}) cand.push_back(GemmTune{bk, gm, x});
+  const long long full = rows;
+  const long long regimes[3] = {full, std::max<long long>(kGemmBM, (full / 8) / kGemmBM * kGemmBM),
+                                std::min<long long>(full, kGemmBM)};
+  const double weight[3] = {0.15, 0.15, 0.7};
+  DevBuf mdev(sizeof(int));
+  hipEvent_t e0, e1;
+  LYAP_HIP(hipEventCreate(&e0));
+  LYAP_HIP(hipEventCreate(&e1));
+  GemmTune best{};
+  double best_t = 1e300;
+  try {
+    for (const GemmTune& c : cand) {
+      GemmArgs g{};
+      g.type = type;
+      g.A = type == GemmType::F64 ? E->X.p : E->Xlo.p;
+      g.B = type == GemmType::F64 ? E->sd->Mc.p : E->sd->Mc32.p;
+      g.C = type == GemmType::F64 ? E->H.p : E->Hlo.p;
+      g.M = rows;
+      g.N = ld;
+      g.K = ld;
+      g.lda = g.ldb = g.ldc = ld;
+      g.Nstore = ld;
+      g.M_dev = mdev.as<int>();
+      g.m_scale = 1;
+      g.Cpart = type == GemmType::F64 ? E->Hp.p : E->Hplo.p;
+      g.Cpart_rows = kPartRowsFactor * rows;
+      g.bk = c.bk;
+      g.grid_min = c.grid_min;
+      g.xcd_off = c.xcd_off;
+      double tot = 0;
+      for (int q = 0; q < 3; ++q) {
+        const int m = (int)regimes[q];
+        LYAP_HIP(hipMemcpy(mdev.p, &m, sizeof(int), hipMemcpyHostToDevice));
+        gemm_launch(g, st);
+        LYAP_HIP(hipEventRecord(e0, st));
+        for (int rep = 0; rep < 3; ++rep) gemm_launch(g, st);
+        LYAP_HIP(hipEventRecord(e1, st));
+        LYAP_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        LYAP_HIP(hipEventElapsedTime(&ms, e0, e1));
+        tot += weight[q] * ms / 3;
+      }
+      if (tot < best_t) {
+        best_t = tot;
+        best = c;
+      }
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune[key] = best;
+  return best;
+}
+
 static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lyap_solve_opts* in,
                                          hipStream_t st, long long Q, double* sol,
                                          long long sol_cap, bool use_graph) {
@@ -2122,7 +2252,7 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
     zalloc(E->Cpinv, S * kPbarMax * kPbarMax * 8);
     zalloc(E->Tbuf, Sp * 128 * 8);
     zalloc(E->Sc, Sp * 128 * 8);
-    zalloc(E->Tpart, 128LL * 128 * 128 * 8);
+    zalloc(E->Tpart, (long long)kTsvdGrid * 128 * 128 * 8);
   }
   if (o.recycle_k > 0) {
     const long long k = o.recycle_k;
@@ -2135,11 +2265,11 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   if (sd->basis == LYAP_BASIS_SCHUR) zalloc(E->XS, S * ld * ld * 8);
   zalloc(E->X, z.rows_pad * ld * 8);
   zalloc(E->H, z.rows_pad * ld * 8);
-  zalloc(E->Hp, z.rows_pad * ld * 8);
+  zalloc(E->Hp, kPartRowsFactor * z.rows_pad * ld * 8);
   if (E->mixed) {
     zalloc(E->Xlo, z.rows_pad * ld * 4);
     zalloc(E->Hlo, z.rows_pad * ld * 4);
-    zalloc(E->Hplo, z.rows_pad * ld * 4);
+    zalloc(E->Hplo, kPartRowsFactor * z.rows_pad * ld * 4);
   }
   zalloc(E->qd, Q * r * 8);
   zalloc(E->qtag, Q * 8);
@@ -2208,6 +2338,12 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   A.Hr = E->Hr.as<double>();
   A.Fs = E->Fs.as<double>();
   LYAP_HIP(hipStreamSynchronize(st));
+  if (sd->basis != LYAP_BASIS_SCHUR) {
+    E->t64 = tune_cauchy(E, GemmType::F64);
+    if (E->mixed) E->tlo = tune_cauchy(E, E->low);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_last_tune = E->t64;
+  }
 
   if (use_graph) {
     LYAP_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -2453,7 +2589,15 @@ void lyap_profile_enable(int32_t on) {
 
 lyap_status lyap_profile_read(lyap_profile* out) {
   if (!out) return LYAP_E_INVAL;
+  GemmTune t;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    t = g_last_tune;
+  }
   std::lock_guard<std::mutex> g(g_prof_mu);
+  g_prof.tuned_bk = t.bk;
+  g_prof.tuned_grid_min = t.grid_min;
+  g_prof.tuned_xcd_off = t.xcd_off;
   *out = g_prof;
   return LYAP_OK;
 }

@@ -40,12 +40,12 @@ template <class T> struct Acc;
 template <> struct Acc<double> { typedef double4_ type; };
 template <> struct Acc<float> { typedef float4_ type; };
 
-// Tile index -> (m-tile, n-tile) with XCD-aware grouping.
-__device__ inline void tile_of(int bid, int mtiles, int ntiles, int& mt, int& nt) {
+// Tile index -> (m-tile, n-tile), with XCD-aware grouping unless xcd == 0.
+__device__ inline void tile_of(int bid, int mtiles, int ntiles, int& mt, int& nt, int xcd = 1) {
   const int T = mtiles * ntiles;
   int t = bid;
   const int full = (T / 8) * 8;
-  if (bid < full) {
+  if (xcd && bid < full) {
     const int per = full / 8;
     t = (bid % 8) * per + bid / 8;
   }
@@ -64,7 +64,7 @@ template <class T, int BK>
 __global__ void __launch_bounds__(NTHREADS)
 gemm_kernel(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
             int M, int N, int K, long lda, long ldb, long ldc, int Nstore,
-            const int* __restrict__ M_dev, int m_scale, T* __restrict__ Cpart) {
+            const int* __restrict__ M_dev, int m_scale, T* __restrict__ Cpart, int xcd) {
   typedef typename Acc<T>::type acc_t;
   constexpr int PADA = 4;
   constexpr int PADB = 4;
@@ -91,10 +91,10 @@ gemm_kernel(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
       nt = t / mta;
       mt = t % mta;
     } else {
-      tile_of(blockIdx.x, mtiles, ntiles, mt, nt);
+      tile_of(blockIdx.x, mtiles, ntiles, mt, nt, xcd);
     }
   } else {
-    tile_of(blockIdx.x, mtiles, ntiles, mt, nt);
+    tile_of(blockIdx.x, mtiles, ntiles, mt, nt, xcd);
   }
   if (KS == 1 && (int)blockIdx.x >= mtiles * ntiles) return;  // grid padded for split-K
   const int row0 = mt * BM;
@@ -343,22 +343,33 @@ void gemm_launch(const GemmArgs& g, hipStream_t s) {
   LYAP_REQUIRE(g.Cpart == nullptr || g.M_dev != nullptr, LYAP_E_INVAL, "gemm: split-K needs M_dev");
   const int mtiles = (int)((g.M + BM - 1) / BM);
   const int ntiles = (int)(g.N / BN);
-  dim3 grid((unsigned)std::max<int64_t>(mtiles * ntiles, g.grid_min)), block(NTHREADS);
+  const int64_t nblocks = std::max<int64_t>((int64_t)mtiles * ntiles, g.grid_min);
+  // split-K writes at most max(mtiles, nblocks / ntiles) row tiles of partials
+  LYAP_REQUIRE(g.Cpart == nullptr ||
+                   g.Cpart_rows >= std::max<int64_t>(mtiles, nblocks / ntiles) * BM,
+               LYAP_E_INVAL, "gemm: split-K partial buffer too small for the launch");
+  dim3 grid((unsigned)nblocks), block(NTHREADS);
   switch (g.type) {
-    case GemmType::F64:
-      LYAP_REQUIRE(g.K % 16 == 0, LYAP_E_INVAL, "gemm: K not padded");
-      hipLaunchKernelGGL((gemm_kernel<double, 16>), grid, block, 0, s,
-                         (const double*)g.A, (const double*)g.B, (double*)g.C, (int)g.M,
-                         (int)g.N, (int)g.K, (long)g.lda, (long)g.ldb, (long)g.ldc,
-                         (int)g.Nstore, g.M_dev, g.m_scale, (double*)g.Cpart);
+    case GemmType::F64: {
+      const int bk = gemm_bk_of(g);
+      LYAP_REQUIRE(g.K % bk == 0, LYAP_E_INVAL, "gemm: K not padded");
+      auto kern = bk == 8 ? gemm_kernel<double, 8> : gemm_kernel<double, 16>;
+      hipLaunchKernelGGL(kern, grid, block, 0, s, (const double*)g.A, (const double*)g.B,
+                         (double*)g.C, (int)g.M, (int)g.N, (int)g.K, (long)g.lda, (long)g.ldb,
+                         (long)g.ldc, (int)g.Nstore, g.M_dev, g.m_scale, (double*)g.Cpart,
+                         g.xcd_off ? 0 : 1);
       break;
-    case GemmType::F32:
-      LYAP_REQUIRE(g.K % 32 == 0, LYAP_E_INVAL, "gemm: K not padded");
-      hipLaunchKernelGGL((gemm_kernel<float, 32>), grid, block, 0, s, (const float*)g.A,
-                         (const float*)g.B, (float*)g.C, (int)g.M, (int)g.N, (int)g.K,
-                         (long)g.lda, (long)g.ldb, (long)g.ldc, (int)g.Nstore, g.M_dev,
-                         g.m_scale, (float*)g.Cpart);
+    }
+    case GemmType::F32: {
+      const int bk = gemm_bk_of(g);
+      LYAP_REQUIRE(g.K % bk == 0, LYAP_E_INVAL, "gemm: K not padded");
+      auto kern = bk == 16 ? gemm_kernel<float, 16> : gemm_kernel<float, 32>;
+      hipLaunchKernelGGL(kern, grid, block, 0, s, (const float*)g.A, (const float*)g.B,
+                         (float*)g.C, (int)g.M, (int)g.N, (int)g.K, (long)g.lda, (long)g.ldb,
+                         (long)g.ldc, (int)g.Nstore, g.M_dev, g.m_scale, (float*)g.Cpart,
+                         g.xcd_off ? 0 : 1);
       break;
+    }
     case GemmType::BF16X3:
       LYAP_REQUIRE(g.K % BK16 == 0, LYAP_E_INVAL, "gemm: K not padded");
       hipLaunchKernelGGL(gemm_bf16x3_kernel, grid, block, 0, s, (const __bf16*)g.A,

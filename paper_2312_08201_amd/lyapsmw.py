@@ -60,7 +60,8 @@ class Profile(C.Structure):
                 ("gemmlo_ms", C.c_double), ("gemmlo_flops", C.c_double),
                 ("krylov_ms", C.c_double), ("gemm64_launches", C.c_int64),
                 ("gemmlo_launches", C.c_int64), ("krylov_launches", C.c_int64),
-                ("steps", C.c_int64), ("slot_steps", C.c_int64), ("graph_steps", C.c_int64)]
+                ("steps", C.c_int64), ("slot_steps", C.c_int64), ("graph_steps", C.c_int64),
+                ("tuned_bk", C.c_int64), ("tuned_grid_min", C.c_int64), ("tuned_xcd_off", C.c_int64)]
 
 
 RESULT_DTYPE = np.dtype([("status", np.int32), ("iters", np.int32), ("cycles", np.int32),

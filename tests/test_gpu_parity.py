@@ -311,3 +311,20 @@ def test_repeated_solves_reuse_engine_identically():
         assert np.array_equal(res["trace"], rf["trace"]), kw
     assert np.array_equal(Y3.cpu().numpy(), runs[0][1][:3])
     assert np.max(rel(runs[0][2]["trace"], oracle_traces(pr))) <= 1e-10
+
+
+@pytest.mark.parametrize("cfg", ["8,0,0", "8,0,1", "8,2,0", "8,2,1", "16,0,0", "16,0,1", "16,2,0",
+                                 "16,2,1"])
+def test_every_gemm_launch_configuration(cfg, monkeypatch):
+    """Each configuration the GEMM autotuner can choose (K-tile depth, split-K
+    workgroup budget, tile order), forced, gives oracle-exact traces: a full
+    batch and a ragged tail (one slow parameter) so split-K slices occur."""
+    L, torch = lib()
+    monkeypatch.setenv("LYAP_GEMM_CONFIG", cfg)
+    pr = W.small_chain(150, (20, 75, 130), 4, 24, seed=8)   # n = 300, ld = 384
+    seed = L.Seed.from_problem(pr)
+    d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
+    Y, res = seed.solve(d, L.solve_opts())
+    assert np.all(res["status"] == 0)
+    assert np.max(rel(res["trace"], oracle_traces(pr))) <= 1e-10
+    seed.release()

@@ -224,8 +224,8 @@ lyap_status engine_harvest(lyap_engine eng, int64_t max_out, int64_t* tags_out,
 /* ------------------------------------------------------------------------ */
 
 /* Per-kernel timings of engine steps, accumulated process-wide while
- * profiling is enabled.  Level 1: one batch of 8 steps in 4 is timed (the
- * others replay the production graph); a timed step replays captured segments
+ * profiling is enabled.  Level 1: one step in 4 is timed (the others replay
+ * the production graph); a timed step replays captured segments
  * before, between and after the Cauchy products and launches each product
  * between two HIP events on the engine stream, per-step active counts being
  * recorded by a small kernel.  Level 2: every step launched directly with

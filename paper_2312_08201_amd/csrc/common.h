@@ -124,6 +124,7 @@ struct GemmArgs {
   int64_t Cpart_rows; // rows (of ldc elements) that Cpart holds; checked before launch
   int bk;             // K-tile depth (0: the type's default; F64 8 or 16, F32 16 or 32)
   int xcd_off;        // 1: plain tile order instead of the XCD-aware mapping
+  int tuning;         // 1: autotuner timing launch (separate kernel symbol)
 };
 
 constexpr int kGemmBM = 128;

@@ -256,7 +256,7 @@ gemm_bf16x3_kernel(const __bf16* __restrict__ A, long a_plane, const __bf16* __r
   const __bf16* a_src = A + (long)a_grow * lda + g_k + (long)kt0 * BK16;
   const __bf16* b_src = Bt + (long)(col0 + g_row) * ldb + g_k + (long)kt0 * BK16;
 
-  typedef uint4 vec_t;  // 8 bf16
+  typedef unsigned int vec_t __attribute__((ext_vector_type(4)));  // 8 bf16 (native vector: stays in registers)
   vec_t ra[2][2], rb[2][2];  // [plane][half]
 
   auto gload = [&](int kt) {

@@ -298,6 +298,8 @@ class Engine:
                                  C.byref(h)), "engine_create")
         self.h = h
         self.slots = slots
+        self._queued = 0    # parameters submitted
+        self._returned = 0  # results handed out by harvest
 
     def submit(self, d, tags=None):
         d = _host(d)
@@ -308,6 +310,7 @@ class Engine:
             tg = np.ascontiguousarray(tags, dtype=np.int64)
         _check(load().engine_submit(self.h, d.shape[0], d.ctypes.data,
                                     tg.ctypes.data if tg is not None else None), "engine_submit")
+        self._queued += d.shape[0]
 
     def run(self, max_steps=1 << 30, poll_every=8) -> int:
         busy = C.c_int64()
@@ -329,14 +332,16 @@ class Engine:
         opts = opts or solve_opts()
         return int(load().engine_device_bytes(seed.h, int(slots), C.byref(opts)))
 
-    def harvest(self, max_out=1 << 20):
-        cap = int(max_out)
+    def harvest(self, max_out=None):
+        """Results of parameters finished since the last harvest (tags, records)."""
+        cap = int(max_out) if max_out is not None else max(1, self._queued - self._returned)
         tags = np.zeros(cap, dtype=np.int64)
         res = (Result * cap)()
         n = C.c_int64()
         _check(load().engine_harvest(self.h, cap, tags.ctypes.data, res, C.byref(n)),
                "engine_harvest")
         k = n.value
+        self._returned += k
         out = np.frombuffer(bytes(res), dtype=RESULT_DTYPE)[:k].copy()
         return tags[:k].copy(), out
 

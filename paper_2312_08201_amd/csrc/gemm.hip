@@ -206,9 +206,11 @@ gemm_bf16x3_kernel(const __bf16* __restrict__ A, long a_plane, const __bf16* __r
                    long b_plane, float* __restrict__ C, int M, int N, int K, long lda, long ldb,
                    long ldc, int Nstore, const int* __restrict__ M_dev, int m_scale,
                    float* __restrict__ Cpart) {
+  // One LDS buffer (40 KB: two workgroups fit a CU); the next K-tile waits in
+  // registers while the current one is multiplied, two barriers per K-tile.
   constexpr int PAD = 8;  // bf16 elements
-  __shared__ __attribute__((aligned(16))) __bf16 Ash[2][2][BM][BK16 + PAD];  // [buf][plane]
-  __shared__ __attribute__((aligned(16))) __bf16 Bsh[2][2][BN][BK16 + PAD];
+  __shared__ __attribute__((aligned(16))) __bf16 Ash[1][2][BM][BK16 + PAD];  // [buf][plane]
+  __shared__ __attribute__((aligned(16))) __bf16 Bsh[1][2][BN][BK16 + PAD];
 
   const int mtiles = (M + BM - 1) / BM;
   const int ntiles = N / BN;
@@ -296,7 +298,7 @@ gemm_bf16x3_kernel(const __bf16* __restrict__ A, long a_plane, const __bf16* __r
   const int lr = lane & 15;
   const int lk = (lane >> 4) * 8;
   for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
+    const int cur = 0;
     if (kt + 1 < nk) gload(kt + 1);
     bf16x8_ ah[4], al[4], bh[4], bl[4];
 #pragma unroll
@@ -317,7 +319,8 @@ gemm_bf16x3_kernel(const __bf16* __restrict__ A, long a_plane, const __bf16* __r
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
       }
-    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();  // every wave is done reading this tile
+    if (kt + 1 < nk) sstore(0);
     __syncthreads();
   }
 

@@ -224,6 +224,9 @@ def main():
     ap.add_argument("--recycle-k", type=int, default=0,
                     help="GCRO-DR recycle space dimension (0: restarted GMRES)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--optimize", action="store_true",
+                    help="instead: the viscosity optimisation loop on the workload's seed "
+                         "(Nelder-Mead from 100, tol 1e-4), without and with recycling")
     ap.add_argument("--stream-sweeps", type=int, default=5,
                     help="also measure this many sweeps streamed through one engine (0: skip)")
     ap.add_argument("--no-profile", action="store_true", help="graph replay, no event timing")
@@ -269,6 +272,18 @@ def main():
     pr = W.config(args.config)
     t = time.perf_counter()
     seed = L.Seed.from_problem(pr, tsvd_rank=args.tsvd_rank)
+    if args.optimize:
+        from paper_2312_08201_amd import optimize as OPT
+        runs = {}
+        for k in (0, 10):
+            o = OPT.optimize_viscosities(seed, np.full(pr.r, 100.0), recycle_k=k)
+            runs["recycle_k=%d" % k] = {
+                "v_opt": o.v.tolist(), "energy": o.energy, "evals": o.evals,
+                "krylov_products": o.products, "products_per_eval": o.products / o.evals,
+                "seconds": o.seconds, "ms_per_eval": 1e3 * o.seconds / o.evals,
+                "converged": o.converged}
+        print(json.dumps({"optimize": WORKLOAD[args.config], "runs": runs}), flush=True)
+        return
     factor_s = time.perf_counter() - t
     info = seed.info()
     d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")

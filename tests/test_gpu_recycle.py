@@ -132,3 +132,35 @@ def test_recycling_invalid_options():
         with pytest.raises(L.LyapError) as e:
             seed.solve(d, L.solve_opts(**kw))
         assert e.value.status == 1
+
+
+def test_viscosity_optimisation_sequence():
+    """The paper's outer loop: Nelder-Mead over two viscosities, tolerance 1e-4,
+    every evaluation one parameter of a one-slot engine, with and without
+    carrying the recycle space from one iterate to the next.  (This small
+    chain needs ~800 products at v = 100, so the search starts at v = 10.)"""
+    L, torch = lib()
+    from paper_2312_08201_amd import optimize as OPT
+    pr = W.small_chain(40, (9, 28), 3, 1, seed=11)
+    seed = L.Seed.from_problem(pr)
+    v0 = np.full(pr.r, 10.0)
+    plain = OPT.optimize_viscosities(seed, v0, recycle_k=0)
+    rec = OPT.optimize_viscosities(seed, v0, recycle_k=10)
+    assert plain.converged and rec.converged
+    print("evals %d / %d, products %d / %d (plain / recycled), v* = %s" % (
+        plain.evals, rec.evals, plain.products, rec.products, plain.v))
+    # a different Krylov solver changes iterations, not energies: same optimum
+    assert abs(rec.energy - plain.energy) <= 1e-6 * abs(plain.energy)
+    # the energy at the optimum is the oracle's
+    ref = O.solve_one(pr.A0, pr.U, pr.V, pr.B, pr.E, plain.v, diagnostics=False).trace
+    assert abs(plain.energy - ref) <= 1e-10 * abs(ref)
+    # no nearby point (+-2% per viscosity) is lower beyond the stopping tolerance
+    steps = np.array([[i, j] for i in (-1, 0, 1) for j in (-1, 0, 1)], dtype=float)
+    grid = plain.v[None, :] * (1.0 + 0.02 * steps)
+    eng = L.Engine(seed, 9)
+    eng.submit(grid, np.arange(9))
+    assert eng.run() == 0
+    _, res = eng.harvest()
+    eng.close()
+    assert np.all(res["status"] == 0)
+    assert res["trace"].min() >= plain.energy * (1 - 2e-4)

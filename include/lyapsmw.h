@@ -45,6 +45,7 @@ extern "C" {
 
 typedef struct lyap_seed_s* lyap_seed;
 typedef struct lyap_engine_s* lyap_engine;
+typedef struct lyap_ek_s* lyap_ek;
 
 typedef enum {
   LYAP_OK = 0,
@@ -218,6 +219,88 @@ lyap_status engine_status(lyap_engine eng, int64_t* submitted, int64_t* done);
 /* Move up to `max_out` finished results to the caller (tags, results). */
 lyap_status engine_harvest(lyap_engine eng, int64_t max_out, int64_t* tags_out,
                            lyap_result* res_out, int64_t* n_out);
+
+/* ------------------------------------------------------------------------ */
+/* Projection framework (Section 2.2, eq:EK_def, eq:param_projected,          */
+/* Proposition on the backward error, Algorithm EKSM_opt).                    */
+/*                                                                            */
+/* One extended Krylov space EK_m(A0, P), P = [X0 V, U], serves every         */
+/* parameter.  The projected equation of a parameter is the SMW capacitance   */
+/* system of a small projected seed (T_m = Q_m^T A0 Q_m, U_m, V_m, E_m), solved */
+/* by the same batched Krylov engine; the backward error of each projected    */
+/* solution is computed on the device from the p-independent tables of the    */
+/* Proposition.  The basis is built on the host with LU solves of A0 (host    */
+/* LAPACK dgetrf/dgetrs) and kept in host memory; each level's projected seed */
+/* lives on the device.                                                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t status;         /* LYAP_OK: accepted (delta <= eps, or the space became invariant);
+                             LYAP_E_NOCONV: not accepted up to m_max; else the failure
+                             status of the projected solve at the last level tried (a
+                             parameter whose projected solve fails is retried at the
+                             next level) */
+  int32_t level;          /* level m of the last projected solve (blocks in the basis) */
+  int32_t dim;            /* projected dimension at that level */
+  int32_t iters;          /* Krylov products over all levels tried */
+  double delta;           /* backward error at that level */
+  double trace;           /* trace(E X(p)) = t0 + trace(E_m Y_m(p)) at that level */
+} lyap_ek_result;
+
+typedef struct {
+  int64_t n, r;
+  int64_t level, dim;     /* current level and its projected dimension */
+  int64_t blocks;         /* blocks built (the current level uses the first `level`) */
+  int64_t basis_cols;     /* columns of the basis built so far */
+  int32_t exhausted;      /* 1: the last block deflated to nothing (invariant space) */
+  int32_t proj_basis;     /* basis of the projected seed (LYAP_BASIS_*), -1 before a level */
+  double proj_cond;       /* eigenbasis condition estimate of the projected seed */
+  double basis_seconds;   /* host time spent building basis blocks */
+  double level_seconds;   /* host time spent forming projected seeds */
+} lyap_ek_info;
+
+/* V^T X0 of a factored seed, returned as X0 V (host n x r row-major): the
+ * first half of P for ek_create when the seed solution comes from seed_factor. */
+lyap_status seed_x0v(lyap_seed seed, double* X0V_host);
+
+/* Build the first basis block span[P, A0^-1 P] (eq:EK_def).
+ *   A0 : host n x n row-major (must be nonsingular; LU-factored here).
+ *   U, V : host n x r (A(p) = A0 - U diag(d) V^T; the paper's B_l = U, B_r = V).
+ *   X0V  : host n x r, X0 V with X0 the seed solution (A0 X0 + X0 A0^T = -B B^T).
+ *   t0   : trace(E X0).      E : host n (E_is_diag) or n x n.
+ * 2 <= n, 1 <= r <= 16, 4 r <= n.  The handle keeps host copies of its
+ * inputs; ek_release frees everything. */
+lyap_status ek_create(int64_t n, int64_t r, const double* A0, const double* U, const double* V,
+                      const double* X0V, double t0, const double* E, int32_t E_is_diag,
+                      void* hip_stream, lyap_ek* out);
+
+/* Make level m current: extend the basis to m + 1 blocks (block m + 1 gives the
+ * backward error of level m), project, factor the projected seed (proj_opts:
+ * basis, max_eig_cond, tsvd_rank; E_is_diag is ignored) and upload the
+ * backward-error data.  If the space becomes invariant first, the level stops
+ * at the last nonempty block (ek_info reports the level actually used). */
+lyap_status ek_set_level(lyap_ek ek, int32_t m, const lyap_seed_opts* proj_opts);
+
+/* Solve the projected equations of P parameters at the current level.
+ *   d_dev     : device P x r.      W_dev : device P x r x dim output (the
+ *               capacitance solution of the projected seed, physical coordinates).
+ *   delta_dev : device P output, backward error of each projected solution.
+ *   norms_dev : device 2P output (||Y_m||_F, ||L Y_m||_F per parameter) or NULL.
+ *   res_host  : host P results of the projected solves (trace = EK trace).
+ * Synchronises the handle's stream before returning. */
+lyap_status ek_solve(lyap_ek ek, int64_t P, const double* d_dev, const lyap_solve_opts* opts,
+                     double* W_dev, double* delta_dev, double* norms_dev, lyap_result* res_host);
+
+/* Algorithm EKSM_opt for P parameters (host d, P x r): levels 1, 1 + check_every,
+ * ... up to m_max; at each level every parameter not yet accepted is solved and
+ * accepted if its backward error is <= eps (a batched reading of the
+ * algorithm's sequential loop).  out: host P results. */
+lyap_status ek_sweep(lyap_ek ek, int64_t P, const double* d_host, const lyap_solve_opts* opts,
+                     const lyap_seed_opts* proj_opts, double eps, int32_t m_max,
+                     int32_t check_every, lyap_ek_result* out);
+
+lyap_status ek_info(lyap_ek ek, lyap_ek_info* out);
+lyap_status ek_release(lyap_ek ek);
 
 /* ------------------------------------------------------------------------ */
 /* Measurement helpers (not part of the method).                             */

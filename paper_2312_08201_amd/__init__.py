@@ -5,4 +5,4 @@ thin ctypes binding.  Importing the package does not touch the GPU.
 """
 from .lyapsmw import (Seed, Engine, LyapError, solve_opts, load, EXPORTS,  # noqa: F401
                       RESULT_DTYPE, PREC, BASIS, profile_enable, profile_read, calib_copy,
-                      real_schur, last_error)
+                      real_schur, last_error, EKSpace, seed_x0v, EK_RESULT_DTYPE)

@@ -84,6 +84,19 @@ void batched_dot(double* out, const double* X, long ldx, const double* Y, long l
                  int count, int n, double base, double scale, hipStream_t s);
 void convert_f64_f32(float* out, const double* in, long count, hipStream_t s);
 
+// ---- projected seeds (seed.hip) ----
+// A seed whose right-hand side is known only through V^T X0 (c0t, host r x n
+// row-major) and t0 = trace(E X0): the Galerkin-projected equations of the
+// extended Krylov framework, where X0 is the full seed solution seen through
+// the basis.  No stability requirement on A0 (only lambda_i + lambda_j != 0).
+struct ProjRhs {
+  const double* c0t;
+  double t0;
+};
+lyap_seed_s* factor_projected(int64_t n, int64_t r, const double* A0, const double* U,
+                              const double* V, const double* E, const ProjRhs& proj,
+                              const lyap_seed_opts* opts, hipStream_t stream);
+
 // ---- Schur basis (schur.hip) ----
 // T Xs + Xs T^T = C per problem; C dense (Cd, row-major) or F G^T + G F^T
 // (F: k shared rows, G: k rows per problem).  X stored column by column.

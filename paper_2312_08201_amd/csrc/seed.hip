@@ -451,10 +451,29 @@ static void upload_rows(double* dst, long dst_ld, const double* src_host_rowmajo
 }
 
 // Schur-basis seed: A0 = Z T Z^T (host Francis QR), precompute on the device.
+// Right-hand side given through V^T X0 and t0 instead of B (projected seeds):
+// c0 = rho(V^T X0 Q0^-T) = (V^T X0) Tin in either basis.
+static void apply_projected_rhs(lyap_seed_s* sd, const ProjRhs* proj, hipStream_t st) {
+  const long r = sd->r, n = sd->n, ld = sd->ld;
+  check_finite(proj->c0t, (size_t)r * n, "V^T X0");
+  LYAP_REQUIRE(std::isfinite(proj->t0), LYAP_E_INVAL, "t0 is not finite");
+  std::vector<double> c((size_t)r * ld, 0.0);
+  for (long a = 0; a < r; ++a)
+    for (long i = 0; i < n; ++i) c[(size_t)a * ld + i] = proj->c0t[(size_t)a * n + i];
+  DevBuf cd(c.size() * sizeof(double));
+  LYAP_HIP(hipMemcpyAsync(cd.p, c.data(), cd.bytes, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemsetAsync(sd->c0.p, 0, sd->c0.bytes, st));
+  gemm64_rm(cd.as<double>(), ld, sd->Tin.as<double>(), ld, sd->c0.as<double>(), ld, r, ld, ld, n,
+            st);
+  LYAP_HIP(hipStreamSynchronize(st));
+  sd->t0 = proj->t0;
+}
+
 static lyap_seed_s* factor_schur(int64_t n, int64_t r, int64_t s, const double* A0, const double* U,
                                  const double* V, const double* B, const double* E, int E_diag,
                                  double cond, hipStream_t st,
-                                 std::chrono::steady_clock::time_point t_start) {
+                                 std::chrono::steady_clock::time_point t_start,
+                                 const ProjRhs* proj) {
   LYAP_REQUIRE(n <= 4096, LYAP_E_UNSUPPORTED, "Schur-basis path limited to n <= 4096");
   const int N = (int)n;
   std::vector<double> Th((size_t)n * n), Zh((size_t)n * n);
@@ -485,7 +504,7 @@ static lyap_seed_s* factor_schur(int64_t n, int64_t r, int64_t s, const double* 
       min_sum = std::min(min_sum, a);
       max_sum = std::max(max_sum, a);
     }
-  LYAP_REQUIRE(max_re < 0, LYAP_E_UNSTABLE, "seed A0 is not stable (max Re lambda >= 0)");
+  LYAP_REQUIRE(proj || max_re < 0, LYAP_E_UNSTABLE, "seed A0 is not stable (max Re lambda >= 0)");
   LYAP_REQUIRE(min_sum > 1e-13 * max_sum, LYAP_E_UNSTABLE, "lambda_i + lambda_j ~ 0 for the seed");
 
   auto* sd = new lyap_seed_s();
@@ -624,6 +643,7 @@ static lyap_seed_s* factor_schur(int64_t n, int64_t r, int64_t s, const double* 
   }
   LYAP_HIP(hipStreamSynchronize(st));
   sd->t0 = t0;
+  if (proj) apply_projected_rhs(sd, proj, st);
   sd->factor_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   guard.release();
@@ -632,7 +652,8 @@ static lyap_seed_s* factor_schur(int64_t n, int64_t r, int64_t s, const double* 
 
 static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A0, const double* U,
                                 const double* V, const double* B, const double* E,
-                                const lyap_seed_opts* opts, hipStream_t stream) {
+                                const lyap_seed_opts* opts, hipStream_t stream,
+                                const ProjRhs* proj = nullptr) {
   auto t_start = std::chrono::steady_clock::now();
   LYAP_REQUIRE(n >= 1 && n <= 16384, LYAP_E_INVAL, "n out of range [1, 16384]");
   LYAP_REQUIRE(r >= 1 && r <= n && r <= kMaxRank, LYAP_E_INVAL, "r out of range [1, min(n, 16)]");
@@ -649,7 +670,7 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
   check_finite(B, (size_t)n * s, "B");
   check_finite(E, E_diag ? (size_t)n : (size_t)n * n, "E");
   if (basis_req == LYAP_BASIS_SCHUR)
-    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, 0.0, stream, t_start);
+    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, 0.0, stream, t_start, proj);
 
   const LapackFns& L = lapack();
   LYAP_REQUIRE(L.dgeev && L.dgetrf && L.dgetrs, LYAP_E_UNSUPPORTED,
@@ -672,7 +693,7 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
           work.data(), &lwork, &info);
   if (info != 0) {
     LYAP_REQUIRE(basis_req == LYAP_BASIS_AUTO, LYAP_E_UNSTABLE, "dgeev failed to converge");
-    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, INFINITY, stream, t_start);
+    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, INFINITY, stream, t_start, proj);
   }
 
   // order: conjugate pairs first (Re, Im columns), then real eigenvalues
@@ -711,7 +732,7 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
       min_sum = std::min(min_sum, a);
       max_sum = std::max(max_sum, a);
     }
-  LYAP_REQUIRE(max_re < 0, LYAP_E_UNSTABLE, "seed A0 is not stable (max Re lambda >= 0)");
+  LYAP_REQUIRE(proj || max_re < 0, LYAP_E_UNSTABLE, "seed A0 is not stable (max Re lambda >= 0)");
   LYAP_REQUIRE(min_sum > 1e-13 * max_sum, LYAP_E_UNSTABLE, "lambda_i + lambda_j ~ 0 for the seed");
 
   // S^-1 by LU; condition estimate ||S||_1 ||S^-1||_1
@@ -721,7 +742,7 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
   if (info != 0) {
     LYAP_REQUIRE(basis_req == LYAP_BASIS_AUTO, LYAP_E_UNSTABLE,
                  "eigenvector matrix is singular (defective seed)");
-    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, INFINITY, stream, t_start);
+    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, INFINITY, stream, t_start, proj);
   }
   for (int i = 0; i < N; ++i) Sinv_cm[(size_t)i * n + i] = 1.0;
   L.dgetrs("N", &N, &N, LU.data(), &N, ipiv.data(), Sinv_cm.data(), &N, &info);
@@ -737,7 +758,7 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
   };
   const double cond = norm1(Scm) * norm1(Sinv_cm);
   if (basis_req == LYAP_BASIS_AUTO && !(cond <= max_cond))
-    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, cond, stream, t_start);
+    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, cond, stream, t_start, proj);
 
   auto* sd = new lyap_seed_s();
   std::unique_ptr<lyap_seed_s> guard(sd);
@@ -955,10 +976,18 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
     LYAP_HIP(hipGetLastError());
   }
   LYAP_HIP(hipStreamSynchronize(st));
+  if (proj) apply_projected_rhs(sd, proj, st);
   sd->factor_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   guard.release();
   return sd;
+}
+
+lyap_seed_s* factor_projected(int64_t n, int64_t r, const double* A0, const double* U,
+                              const double* V, const double* E, const ProjRhs& proj,
+                              const lyap_seed_opts* opts, hipStream_t stream) {
+  std::vector<double> B0((size_t)n, 0.0);
+  return factor_impl(n, r, 1, A0, U, V, B0.data(), E, opts, stream, &proj);
 }
 
 }  // namespace lyap

@@ -64,6 +64,21 @@ class Profile(C.Structure):
                 ("tuned_bk", C.c_int64), ("tuned_grid_min", C.c_int64), ("tuned_xcd_off", C.c_int64)]
 
 
+class EkResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("level", C.c_int32), ("dim", C.c_int32),
+                ("iters", C.c_int32), ("delta", C.c_double), ("trace", C.c_double)]
+
+
+class EkInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("r", C.c_int64), ("level", C.c_int64), ("dim", C.c_int64),
+                ("blocks", C.c_int64), ("basis_cols", C.c_int64), ("exhausted", C.c_int32),
+                ("proj_basis", C.c_int32), ("proj_cond", C.c_double),
+                ("basis_seconds", C.c_double), ("level_seconds", C.c_double)]
+
+
+EK_RESULT_DTYPE = np.dtype([("status", np.int32), ("level", np.int32), ("dim", np.int32),
+                            ("iters", np.int32), ("delta", np.float64), ("trace", np.float64)])
+
 RESULT_DTYPE = np.dtype([("status", np.int32), ("iters", np.int32), ("cycles", np.int32),
                          ("refinements", np.int32), ("rel_residual", np.float64),
                          ("trace", np.float64)])
@@ -75,7 +90,8 @@ EXPORTS = ["seed_factor", "seed_info", "seed_release", "seed_device_bytes", "lya
            "smw_workspace_bytes", "smw_solve_batch", "trace_EX", "engine_create",
            "engine_device_bytes", "engine_destroy", "engine_submit", "engine_run",
            "engine_harvest", "engine_launch", "engine_status", "lyap_status_string", "lyap_last_error", "lyap_profile_enable",
-           "lyap_profile_read", "lyap_calib_copy", "lyap_real_schur"]
+           "lyap_profile_read", "lyap_calib_copy", "lyap_real_schur", "seed_x0v", "ek_create",
+           "ek_set_level", "ek_solve", "ek_sweep", "ek_info", "ek_release"]
 
 
 def load(path: str = LIB_PATH):
@@ -118,12 +134,21 @@ def load(path: str = LIB_PATH):
     lib.lyap_calib_copy.argtypes = [vp, vp, C.c_size_t, vp]
     lib.lyap_real_schur.argtypes = [i64, vp, vp, vp]
     lib.lyap_real_schur.restype = C.c_int
+    lib.seed_x0v.argtypes = [vp, vp]
+    lib.ek_create.argtypes = [i64, i64, vp, vp, vp, vp, C.c_double, vp, i32, vp, C.POINTER(vp)]
+    lib.ek_set_level.argtypes = [vp, i32, C.POINTER(SeedOpts)]
+    lib.ek_solve.argtypes = [vp, i64, vp, C.POINTER(SolveOpts), vp, vp, vp, C.POINTER(Result)]
+    lib.ek_sweep.argtypes = [vp, i64, vp, C.POINTER(SolveOpts), C.POINTER(SeedOpts), C.c_double,
+                             i32, i32, C.POINTER(EkResult)]
+    lib.ek_info.argtypes = [vp, C.POINTER(EkInfo)]
+    lib.ek_release.argtypes = [vp]
     lib.lyap_last_error.argtypes = []
     lib.lyap_last_error.restype = C.c_char_p
     for name in ("seed_factor", "seed_info", "seed_release", "lyap_seed_apply", "smw_solve_batch",
                  "trace_EX", "engine_create", "engine_destroy", "engine_submit", "engine_run",
                  "engine_harvest", "engine_launch", "engine_status", "lyap_profile_read",
-                 "lyap_calib_copy"):
+                 "lyap_calib_copy", "seed_x0v", "ek_create", "ek_set_level", "ek_solve",
+                 "ek_sweep", "ek_info", "ek_release"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -284,6 +309,95 @@ class Seed:
         t = torch.empty(P, dtype=torch.float64, device=Y.device)
         _check(load().trace_EX(self.h, P, _dev_ptr(Y), _dev_ptr(t), _stream(stream)), "trace_EX")
         return t
+
+
+def seed_x0v(seed: "Seed") -> np.ndarray:
+    """X0 V (n x r) of a factored seed: the first half of P for the projection framework."""
+    out = np.zeros((seed.n, seed.r), dtype=np.float64)
+    _check(load().seed_x0v(seed.h, out.ctypes.data), "seed_x0v")
+    return out
+
+
+class EKSpace:
+    """Projection framework: one extended Krylov space EK_m(A0, [X0 V, U]) for all parameters."""
+
+    def __init__(self, A0, U, V, X0V, t0, E, stream=None):
+        lib = load()
+        _torch()
+        A0 = _host(A0)
+        n = A0.shape[0]
+        U, V, X0V, E = _host(U), _host(V), _host(X0V), _host(E)
+        if A0.shape != (n, n) or U.ndim != 2 or U.shape[0] != n or V.shape != U.shape \
+                or X0V.shape != U.shape:
+            raise ValueError("inconsistent shapes")
+        diag = 1 if E.ndim == 1 else 0
+        if (diag and E.shape != (n,)) or (not diag and E.shape != (n, n)):
+            raise ValueError("E must be (n,) or (n, n)")
+        self.n, self.r = n, U.shape[1]
+        self._stream = stream
+        h = C.c_void_p()
+        st = lib.ek_create(n, self.r, A0.ctypes.data, U.ctypes.data, V.ctypes.data, X0V.ctypes.data,
+                           float(t0), E.ctypes.data, diag, _stream(stream), C.byref(h))
+        _check(st, "ek_create")
+        self.h = h
+
+    @classmethod
+    def from_seed(cls, seed: "Seed", A0, U, V, E, stream=None):
+        """X0 V and t0 taken from a factored seed of the same (A0, U, V, B, E)."""
+        return cls(A0, U, V, seed_x0v(seed), seed.info()["t0"], E, stream=stream)
+
+    def set_level(self, m: int, basis="auto", max_eig_cond=0.0, tsvd_rank=0):
+        o = SeedOpts(BASIS[basis], 0, float(max_eig_cond), int(tsvd_rank), 0)
+        _check(load().ek_set_level(self.h, int(m), C.byref(o)), "ek_set_level")
+        return self.info()
+
+    def solve(self, d, opts: Optional[SolveOpts] = None):
+        """Projected solves at the current level for d (P x r, CUDA float64).
+        Returns (W, delta, norms, results)."""
+        torch = _torch()
+        opts = opts or solve_opts()
+        P = d.shape[0]
+        _dev_ptr(d, shape=(P, self.r))
+        dim = self.info()["dim"]
+        W = torch.empty((P, self.r, dim), dtype=torch.float64, device=d.device)
+        delta = torch.empty(P, dtype=torch.float64, device=d.device)
+        norms = torch.empty((P, 2), dtype=torch.float64, device=d.device)
+        res = (Result * P)()
+        st = load().ek_solve(self.h, P, _dev_ptr(d), C.byref(opts), _dev_ptr(W), _dev_ptr(delta),
+                             _dev_ptr(norms), res)
+        _check(st, "ek_solve")
+        return W, delta, norms, np.frombuffer(bytes(res), dtype=RESULT_DTYPE).copy()
+
+    def sweep(self, d, eps: float, m_max: int, check_every: int = 1,
+              opts: Optional[SolveOpts] = None, basis="auto", max_eig_cond=0.0, tsvd_rank=0):
+        """Algorithm EKSM_opt over host parameters d (P x r)."""
+        d = _host(d)
+        P = d.shape[0]
+        if d.shape != (P, self.r):
+            raise ValueError("d must be P x r")
+        opts = opts or solve_opts()
+        po = SeedOpts(BASIS[basis], 0, float(max_eig_cond), int(tsvd_rank), 0)
+        out = (EkResult * P)()
+        st = load().ek_sweep(self.h, P, d.ctypes.data, C.byref(opts), C.byref(po), float(eps),
+                             int(m_max), int(check_every), out)
+        _check(st, "ek_sweep")
+        return np.frombuffer(bytes(out), dtype=EK_RESULT_DTYPE).copy()
+
+    def info(self) -> dict:
+        inf = EkInfo()
+        _check(load().ek_info(self.h, C.byref(inf)), "ek_info")
+        return {k: getattr(inf, k) for k, _ in EkInfo._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().ek_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Engine:

@@ -211,6 +211,68 @@ def per_parameter_baseline(L, torch, pr, traces, count=2):
             "rel_diff_vs_smw": float(max(abs(g - traces[i]) / abs(g) for g, i in zip(got, idx)))}
 
 
+def ek_bench(args, L, torch, W, seed, pr, factor_s):
+    """Projection framework (Algorithm EKSM_opt) against the exact SMW path on
+    the same seed and parameters.  One line of JSON; not the headline metric."""
+    t = time.perf_counter()
+    ek = L.EKSpace.from_seed(seed, pr.A0, pr.U, pr.V, pr.E)
+    create_s = time.perf_counter() - t
+    walls, out = [], None
+    for it in range(args.warmup + args.steps):
+        t = time.perf_counter()
+        out = ek.sweep(pr.d, eps=args.ek_eps, m_max=args.ek_mmax, check_every=args.ek_check_every)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        print("ek sweep %d: %.3f s" % (it, dt), file=sys.stderr, flush=True)
+        if it >= args.warmup:
+            walls.append(dt)
+    info = ek.info()
+    sweeps = args.warmup + args.steps
+    # exact path on the same parameters
+    d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
+    opts = L.solve_opts()
+    seed.solve(d, opts)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.steps):
+        Y, res = seed.solve(d, opts)
+        tr = seed.trace(Y)
+    torch.cuda.synchronize()
+    smw_wall = (time.perf_counter() - t) / args.steps
+    exact = tr.cpu().numpy()
+    max_rel = None
+    gold_path = os.path.join(ROOT, "tests", "golden", "oracle_traces.json")
+    if os.path.exists(gold_path) and not args.agents:
+        gold = json.load(open(gold_path)).get("c%d" % args.config)
+        if gold:
+            idx = [g["index"] for g in gold["samples"]]
+            ref = np.array([g["trace"] for g in gold["samples"]])
+            max_rel = float(np.max(np.abs(out["trace"][idx] - ref) / np.abs(ref)))
+    wall = float(np.median(walls))
+    levels, counts = np.unique(out["level"], return_counts=True)
+    print(json.dumps({
+        "ek": WORKLOAD[args.config] if not args.agents else
+        "multi-agent N=%d (n=%d) r=8 (4 edge weights), 512 samples, B n x 4, E=I" % (args.agents, pr.n),
+        "P": pr.P, "n": pr.n, "r": pr.r,
+        "eps": args.ek_eps, "m_max": args.ek_mmax, "check_every": args.ek_check_every,
+        "evals_per_s": pr.P / wall, "sweep_s_median": wall, "create_s": create_s,
+        "all_accepted": bool(np.all(out["status"] == 0)),
+        "levels": {int(k): int(v) for k, v in zip(levels, counts)},
+        "dim_mean": float(out["dim"].mean()), "dim_max": int(out["dim"].max()),
+        "iters_mean_all_levels": float(out["iters"].mean()),
+        "basis_seconds_total": info["basis_seconds"],
+        "level_seconds_total": info["level_seconds"],
+        "solve_seconds_per_sweep": info["solve_seconds"] / sweeps,
+        "delta_seconds_per_sweep": info["delta_seconds"] / sweeps,
+        "batches_per_sweep": info["batches"] / sweeps,
+        "seed_factor_s": factor_s,
+        "max_rel_err_sampled_vs_oracle": max_rel,
+        "max_rel_diff_vs_exact_smw": float(np.max(np.abs(out["trace"] - exact) / np.abs(exact))),
+        "smw_exact_evals_per_s": pr.P / smw_wall,
+        "speedup_vs_smw": smw_wall / wall}), flush=True)
+    ek.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +289,13 @@ def main():
     ap.add_argument("--optimize", action="store_true",
                     help="instead: the viscosity optimisation loop on the workload's seed "
                          "(Nelder-Mead from 100, tol 1e-4), without and with recycling")
+    ap.add_argument("--ek", action="store_true",
+                    help="projection framework (Algorithm EKSM_opt) vs the exact path")
+    ap.add_argument("--ek-eps", type=float, default=1e-10)
+    ap.add_argument("--ek-mmax", type=int, default=40)
+    ap.add_argument("--ek-check-every", type=int, default=1)
+    ap.add_argument("--agents", type=int, default=0,
+                    help="with --ek: the multi-agent workload with this many agents (n = 2N)")
     ap.add_argument("--stream-sweeps", type=int, default=5,
                     help="also measure this many sweeps streamed through one engine (0: skip)")
     ap.add_argument("--no-profile", action="store_true", help="graph replay, no event timing")
@@ -270,8 +339,14 @@ def main():
         return
 
     pr = W.config(args.config)
+    if args.agents:
+        # the multi-agent construction of workload 3 at another size
+        pr = W.multiagent_problem(args.agents, 6.0, 4, 4, 512, 3, "agents%d" % args.agents)
     t = time.perf_counter()
     seed = L.Seed.from_problem(pr, tsvd_rank=args.tsvd_rank)
+    if args.ek:
+        ek_bench(args, L, torch, W, seed, pr, time.perf_counter() - t)
+        return
     if args.optimize:
         from paper_2312_08201_amd import optimize as OPT
         runs = {}

@@ -163,7 +163,10 @@ lyap_status lyap_seed_apply(lyap_seed seed, int64_t batch, const double* Y_dev, 
 /* Online stage (Table 1, right column).                                     */
 /* ------------------------------------------------------------------------ */
 
-/* Device workspace smw_solve_batch needs for P parameters. */
+/* Device workspace smw_solve_batch needs for P parameters; 0 if the seed or the
+ * options are not supported by the engine (lyap_last_error says why).  The
+ * Krylov kernel holds one capacitance vector per workgroup: r * ld <= 16384,
+ * ld = n rounded up to a multiple of 128. */
 size_t smw_workspace_bytes(lyap_seed seed, int64_t P, const lyap_solve_opts* opts);
 
 /* Solve the capacitance system for P parameters.
@@ -257,6 +260,9 @@ typedef struct {
   double proj_cond;       /* eigenbasis condition estimate of the projected seed */
   double basis_seconds;   /* host time spent building basis blocks */
   double level_seconds;   /* host time spent forming projected seeds */
+  double solve_seconds;   /* wall time of the batched projected solves */
+  double delta_seconds;   /* wall time of the backward-error computations */
+  int64_t batches;        /* batched projected solves run so far */
 } lyap_ek_info;
 
 /* V^T X0 of a factored seed, returned as X0 V (host n x r row-major): the
@@ -291,10 +297,13 @@ lyap_status ek_set_level(lyap_ek ek, int32_t m, const lyap_seed_opts* proj_opts)
 lyap_status ek_solve(lyap_ek ek, int64_t P, const double* d_dev, const lyap_solve_opts* opts,
                      double* W_dev, double* delta_dev, double* norms_dev, lyap_result* res_host);
 
-/* Algorithm EKSM_opt for P parameters (host d, P x r): levels 1, 1 + check_every,
- * ... up to m_max; at each level every parameter not yet accepted is solved and
- * accepted if its backward error is <= eps (a batched reading of the
- * algorithm's sequential loop).  out: host P results. */
+/* Algorithm EKSM_opt for P parameters (host d, P x r), levels 1, 1 + check_every,
+ * ... up to m_max.  Parameters are tested in order; the first whose backward
+ * error exceeds eps (or whose projected solve fails) moves it and all after it
+ * to the next level.  The queue head is solved in batches of 1, 4, 16, ...
+ * parameters, keeping the accepted prefix of each batch, which reproduces the
+ * sequential loop's decisions.  Levels (projected seeds, engines) are kept in
+ * the handle and reused by later sweeps.  out: host P results. */
 lyap_status ek_sweep(lyap_ek ek, int64_t P, const double* d_host, const lyap_solve_opts* opts,
                      const lyap_seed_opts* proj_opts, double eps, int32_t m_max,
                      int32_t check_every, lyap_ek_result* out);

@@ -35,13 +35,13 @@ Readings (listed with the others in the design notes):
   column whose norm falls below DEFLATE times its norm before
   orthogonalisation is dropped (the deflation the paper leaves to standard
   strategies).
-* Acceptance.  The paper tests the parameters one after another and, at the
-  first failure, enlarges the space for all that remain.  Here every
-  parameter not yet accepted is tested at every level and is accepted at the
-  smallest level whose backward error is at most eps (the batched reading).
-  Levels are 1, 1 + check_every, 1 + 2 check_every, ... up to m_max.  Once
-  the next block deflates to nothing the space is invariant, the projected
-  solution is exact, and every remaining parameter is accepted there.
+* Acceptance, as in Algorithm EKSM_opt: the parameters are tested one after
+  another in their given order; at the first one whose backward error
+  exceeds eps the space is enlarged and the test resumes with that parameter.
+  Levels are 1, 1 + check_every, 1 + 2 check_every, ... up to m_max (the
+  algorithm itself has check_every = 1).  Once the next block deflates to
+  nothing the space is invariant, the projected solution is exact, and every
+  remaining parameter is accepted there.
 * The seed solution X0 comes from the naive Bartels-Stewart solve of A0.
 """
 from __future__ import annotations
@@ -144,15 +144,16 @@ def backward_error_def(A, Vm, Y, P, J):
 
 @dataclass
 class EKResult:
-    trace: np.ndarray        # f(X(d)) per parameter (nan if not accepted)
-    level: np.ndarray        # accepted level m (0 if none)
+    trace: np.ndarray        # f(X(d)) at the last level the parameter was tested (nan if never)
+    level: np.ndarray        # that level (0 if never tested)
     dim: np.ndarray          # basis dimension at that level
     delta: np.ndarray        # backward error at that level
+    accepted: np.ndarray     # bool: backward error <= eps there (or the space was invariant)
     t0: float
 
 
 def eksm_trace(A0, U, V, B, E, d_all, eps, m_max, check_every=1) -> EKResult:
-    """Algorithm EKSM_opt with f = trace(E X), batched acceptance."""
+    """Algorithm EKSM_opt with f = trace(E X)."""
     d_all = np.atleast_2d(np.asarray(d_all, dtype=np.float64))
     Pn = d_all.shape[0]
     X0 = seed_solution(A0, B)
@@ -163,9 +164,9 @@ def eksm_trace(A0, U, V, B, E, d_all, eps, m_max, check_every=1) -> EKResult:
     level = np.zeros(Pn, dtype=np.int64)
     dim = np.zeros(Pn, dtype=np.int64)
     delta = np.full(Pn, np.nan)
-    todo = list(range(Pn))
-    m = 1
-    while todo and m <= m_max:
+    accepted = np.zeros(Pn, dtype=bool)
+    pos, m = 0, 1
+    while pos < Pn and m <= m_max:
         while len(sp.blocks) < m + 1:      # the Proposition needs block m+1
             if not sp.expand():
                 break
@@ -173,18 +174,17 @@ def eksm_trace(A0, U, V, B, E, d_all, eps, m_max, check_every=1) -> EKResult:
         Em = Vm.T @ Ed @ Vm
         # an invariant space (no next block) makes the projection exact
         invariant = len(sp.blocks) < m + 1 or sp.blocks[m].shape[1] == 0
-        rest = []
-        for p in todo:
-            d = d_all[p]
+        while pos < Pn:
+            d = d_all[pos]
             Y, A, P, J = projected_solution(A0, U, V, X0, Vm, d)
             be = backward_error_def(A, Vm, Y, P, J)
-            if be <= eps or invariant:
-                trace[p] = t0 + float(np.sum(Em * Y))
-                level[p], dim[p], delta[p] = m, Vm.shape[1], be
-            else:
-                rest.append(p)
-        todo = rest
+            trace[pos] = t0 + float(np.sum(Em * Y))
+            level[pos], dim[pos], delta[pos] = m, Vm.shape[1], be
+            if not (be <= eps or invariant):
+                break
+            accepted[pos] = True
+            pos += 1
         if invariant:
             break
         m += check_every
-    return EKResult(trace, level, dim, delta, t0)
+    return EKResult(trace, level, dim, delta, accepted, t0)

@@ -126,6 +126,22 @@ k_ek_delta(const double* __restrict__ Xs, long xstride, int n, int ld,
 
 using namespace lyap;
 
+// One level of the projection: the projected seed, the real Schur data of
+// T_m for the backward error, and an engine for the projected solves.  A
+// level depends on the basis only, so it is kept for later sweeps.
+struct EkLevel {
+  int m = 0, dim = 0, q = 0;
+  lyap_seed_opts opts{};
+  lyap_seed_s* proj = nullptr;
+  DevBuf Ts, Tst, Zd, Fl, Lz;
+  lyap_engine_s* eng = nullptr;
+  DevBuf sol;
+  ~EkLevel() {
+    if (eng) engine_batch_destroy(eng);
+    delete proj;
+  }
+};
+
 struct lyap_ek_s {
   int64_t n = 0, r = 0;
   int E_diag = 1;
@@ -136,41 +152,44 @@ struct lyap_ek_s {
   std::vector<double> X0V;      // row-major n x r
   std::vector<double> E;        // n (diagonal) or symmetrised n x n row-major
   double t0 = 0.0;
-  // basis columns, each contiguous (column-major n x dim), and A0 times them
-  std::vector<double> Q, AQ;
+  // basis columns, each contiguous (column-major n x D), A0 and E times them
+  std::vector<double> Q, AQ, EQ;
   std::vector<int> bstart{0};   // block b holds columns [bstart[b], bstart[b+1])
   std::vector<int> bplus;       // leading columns of block b from positive powers
   bool exhausted = false;
+  // projections onto all D columns built so far, row-major with stride D:
+  // TQ = Q^T A0 Q, EM = Q^T E Q (D x D); UQ = Q^T U, VQ = Q^T V, XQ = Q^T X0 V (D x r)
+  int D = 0;
+  std::vector<double> TQ, EM, UQ, VQ, XQ;
   // p-independent tables of the backward error
   std::vector<double> cst;      // [||A0||_F^2, (U^T U) o (V^T V), diag(U^T A0 V), Gram(P)]
-  // current level
-  int level = 0, dim = 0, q = 0;
-  lyap_seed_s* proj = nullptr;
-  DevBuf Ts, Tst, Zd, Fl, Lz, cstd;
+  DevBuf cstd;
+  std::vector<std::unique_ptr<EkLevel>> levels;  // index m (0 unused)
+  EkLevel* cur = nullptr;
   DevBuf Wbuf, Wp, Gs, Xs, ddev, dl;
   hipStream_t st = nullptr;
   double basis_seconds = 0.0, level_seconds = 0.0;
+  double solve_seconds = 0.0, delta_seconds = 0.0;  // projected solves / backward errors
+  int64_t batches = 0;
 
   int nblocks() const { return (int)bstart.size() - 1; }
   const double* col(int j) const { return Q.data() + (size_t)j * n; }
-
-  ~lyap_ek_s() { delete proj; }
 };
 
 namespace {
 
+double dotn(const double* a, const double* b, long n) {
+  double s = 0.0;
+  for (long i = 0; i < n; ++i) s += a[i] * b[i];
+  return s;
+}
+
 void ek_matvec_block(const lyap_ek_s* ek, const double* X, int c, double* Y) {
   // Y (n x c column-major) = A0 X
   const long n = ek->n;
-  for (int k = 0; k < c; ++k) std::memset(Y + (size_t)k * n, 0, sizeof(double) * n);
   for (long i = 0; i < n; ++i) {
     const double* Ai = ek->A0.data() + (size_t)i * n;
-    for (int k = 0; k < c; ++k) {
-      const double* x = X + (size_t)k * n;
-      double s = 0.0;
-      for (long j = 0; j < n; ++j) s += Ai[j] * x[j];
-      Y[(size_t)k * n + i] = s;
-    }
+    for (int k = 0; k < c; ++k) Y[(size_t)k * n + i] = dotn(Ai, X + (size_t)k * n, n);
   }
 }
 
@@ -182,6 +201,49 @@ void ek_solve_block(const lyap_ek_s* ek, double* X, int c) {
   LYAP_REQUIRE(info == 0, LYAP_E_UNSTABLE, "dgetrs with A0 failed");
 }
 
+// Extend the projections TQ, EM, UQ, VQ, XQ to the columns D .. D' - 1.
+void ek_project_new(lyap_ek_s* ek) {
+  const long n = ek->n, r = ek->r;
+  const int D0 = ek->D, D1 = (int)(ek->Q.size() / n);
+  if (D1 == D0) return;
+  std::vector<double> T1((size_t)D1 * D1), E1((size_t)D1 * D1);
+  for (int a = 0; a < D0; ++a)
+    for (int b = 0; b < D0; ++b) {
+      T1[(size_t)a * D1 + b] = ek->TQ[(size_t)a * D0 + b];
+      E1[(size_t)a * D1 + b] = ek->EM[(size_t)a * D0 + b];
+    }
+  for (int a = 0; a < D1; ++a)
+    for (int b = 0; b < D1; ++b) {
+      if (a < D0 && b < D0) continue;
+      T1[(size_t)a * D1 + b] = dotn(ek->col(a), ek->AQ.data() + (size_t)b * n, n);
+      if (b >= a) {
+        const double e = dotn(ek->col(a), ek->EQ.data() + (size_t)b * n, n);
+        E1[(size_t)a * D1 + b] = e;
+        E1[(size_t)b * D1 + a] = e;
+      }
+    }
+  ek->TQ.swap(T1);
+  ek->EM.swap(E1);
+  ek->UQ.resize((size_t)D1 * r);
+  ek->VQ.resize((size_t)D1 * r);
+  ek->XQ.resize((size_t)D1 * r);
+  for (int a = D0; a < D1; ++a) {
+    const double* qa = ek->col(a);
+    for (long c = 0; c < r; ++c) {
+      double su = 0, sv = 0, sx = 0;
+      for (long i = 0; i < n; ++i) {
+        su += qa[i] * ek->U[(size_t)i * r + c];
+        sv += qa[i] * ek->V[(size_t)i * r + c];
+        sx += qa[i] * ek->X0V[(size_t)i * r + c];
+      }
+      ek->UQ[(size_t)a * r + c] = su;
+      ek->VQ[(size_t)a * r + c] = sv;
+      ek->XQ[(size_t)a * r + c] = sx;
+    }
+  }
+  ek->D = D1;
+}
+
 // Orthogonalise the c candidate columns against the basis (twice) and among
 // themselves; append survivors.  Returns the indices that survived.
 std::vector<int> ek_append_block(lyap_ek_s* ek, std::vector<double>& W, int c) {
@@ -189,20 +251,14 @@ std::vector<int> ek_append_block(lyap_ek_s* ek, std::vector<double>& W, int c) {
   const int dim = (int)(ek->Q.size() / n);
   std::vector<double> nrm0(c);
   for (int k = 0; k < c; ++k) {
-    double s = 0.0;
-    for (long i = 0; i < n; ++i) s += W[(size_t)k * n + i] * W[(size_t)k * n + i];
-    nrm0[k] = std::sqrt(s);
+    const double* w = W.data() + (size_t)k * n;
+    nrm0[k] = std::sqrt(dotn(w, w, n));
   }
   std::vector<double> coef(dim);
   for (int pass = 0; pass < 2 && dim > 0; ++pass)
     for (int k = 0; k < c; ++k) {
       double* w = W.data() + (size_t)k * n;
-      for (int j = 0; j < dim; ++j) {
-        const double* qj = ek->col(j);
-        double s = 0.0;
-        for (long i = 0; i < n; ++i) s += qj[i] * w[i];
-        coef[j] = s;
-      }
+      for (int j = 0; j < dim; ++j) coef[j] = dotn(ek->col(j), w, n);
       for (int j = 0; j < dim; ++j) {
         const double* qj = ek->col(j);
         const double cj = coef[j];
@@ -210,7 +266,6 @@ std::vector<int> ek_append_block(lyap_ek_s* ek, std::vector<double>& W, int c) {
       }
     }
   std::vector<int> kept;
-  std::vector<const double*> fresh;
   std::vector<double> newcols;
   newcols.reserve((size_t)c * n);
   for (int k = 0; k < c; ++k) {
@@ -218,13 +273,10 @@ std::vector<int> ek_append_block(lyap_ek_s* ek, std::vector<double>& W, int c) {
     for (int pass = 0; pass < 2; ++pass)
       for (size_t t = 0; t < kept.size(); ++t) {
         const double* qt = newcols.data() + t * n;
-        double s = 0.0;
-        for (long i = 0; i < n; ++i) s += qt[i] * w[i];
+        const double s = dotn(qt, w.data(), n);
         for (long i = 0; i < n; ++i) w[i] -= s * qt[i];
       }
-    double s = 0.0;
-    for (long i = 0; i < n; ++i) s += w[i] * w[i];
-    s = std::sqrt(s);
+    const double s = std::sqrt(dotn(w.data(), w.data(), n));
     if (s > kDeflate * nrm0[k]) {
       for (long i = 0; i < n; ++i) newcols.push_back(w[i] / s);
       kept.push_back(k);
@@ -232,10 +284,21 @@ std::vector<int> ek_append_block(lyap_ek_s* ek, std::vector<double>& W, int c) {
   }
   const int add = (int)kept.size();
   ek->Q.insert(ek->Q.end(), newcols.begin(), newcols.end());
-  std::vector<double> AQn((size_t)add * n);
+  std::vector<double> AQn((size_t)add * n), EQn((size_t)add * n);
   if (add) ek_matvec_block(ek, newcols.data(), add, AQn.data());
+  for (int k = 0; k < add; ++k) {
+    const double* qk = newcols.data() + (size_t)k * n;
+    double* out = EQn.data() + (size_t)k * n;
+    if (ek->E_diag) {
+      for (long i = 0; i < n; ++i) out[i] = ek->E[i] * qk[i];
+    } else {
+      for (long i = 0; i < n; ++i) out[i] = dotn(ek->E.data() + (size_t)i * n, qk, n);
+    }
+  }
   ek->AQ.insert(ek->AQ.end(), AQn.begin(), AQn.end());
+  ek->EQ.insert(ek->EQ.end(), EQn.begin(), EQn.end());
   ek->bstart.push_back(dim + add);
+  ek_project_new(ek);
   return kept;
 }
 
@@ -273,12 +336,6 @@ bool ek_expand(lyap_ek_s* ek) {
   ek->bplus.push_back(plus);
   if (kept.empty()) ek->exhausted = true;
   return !kept.empty();
-}
-
-double dotn(const double* a, const double* b, long n) {
-  double s = 0.0;
-  for (long i = 0; i < n; ++i) s += a[i] * b[i];
-  return s;
 }
 
 lyap_ek_s* ek_create_impl(int64_t n, int64_t r, const double* A0, const double* U, const double* V,
@@ -352,6 +409,9 @@ lyap_ek_s* ek_create_impl(int64_t n, int64_t r, const double* A0, const double* 
     auto pcol = [&](long a) { return a < r ? &Xc[(size_t)a * n] : &Uc[(size_t)(a - r) * n]; };
     for (long a = 0; a < r2; ++a)
       for (long b = 0; b < r2; ++b) G[a * r2 + b] = dotn(pcol(a), pcol(b), n);
+    ek->cstd.alloc(c.size() * sizeof(double));
+    LYAP_HIP(hipMemcpyAsync(ek->cstd.p, c.data(), ek->cstd.bytes, hipMemcpyHostToDevice, st));
+    LYAP_HIP(hipStreamSynchronize(st));
   }
   ek_first_block(ek.get());
   LYAP_REQUIRE(!ek->exhausted, LYAP_E_INVAL, "P = [X0 V, U] is zero");
@@ -360,75 +420,42 @@ lyap_ek_s* ek_create_impl(int64_t n, int64_t r, const double* A0, const double* 
   return ek.release();
 }
 
-// Projected seed and backward-error data for level m (blocks 0..m-1).
-void ek_set_level_impl(lyap_ek_s* ek, int m, const lyap_seed_opts* popts) {
-  LYAP_REQUIRE(m >= 1 && m <= 100000, LYAP_E_INVAL, "level out of range");
-  auto t_start = std::chrono::steady_clock::now();
-  while (ek->nblocks() < m + 1 && !ek->exhausted) ek_expand(ek);
-  ek->basis_seconds +=
-      std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-  const int mm = std::min(m, ek->nblocks());
-  const long n = ek->n, r = ek->r;
+bool same_opts(const lyap_seed_opts& a, const lyap_seed_opts& b) {
+  return a.basis == b.basis && a.max_eig_cond == b.max_eig_cond && a.tsvd_rank == b.tsvd_rank;
+}
+
+// Level m (blocks 0..m-1): the projected seed and the backward-error data.
+EkLevel* ek_build_level(lyap_ek_s* ek, int mm, const lyap_seed_opts& o) {
+  const long r = ek->r;
   const int N = ek->bstart[mm];
   LYAP_REQUIRE(N >= r, LYAP_E_INVAL, "projected dimension below the rank");
   const int q = mm < ek->nblocks() ? ek->bstart[mm + 1] - ek->bstart[mm] : 0;
-  auto t1 = std::chrono::steady_clock::now();
-  // T_m, L, U_m, V_m, C, E_m (row-major)
-  std::vector<double> T((size_t)N * N), Lc((size_t)std::max(q, 1) * N), Um((size_t)N * r),
-      Vm((size_t)N * r), Ct((size_t)r * N), Em((size_t)N * N);
+  const int D = ek->D;
+  auto lv = std::make_unique<EkLevel>();
+  lv->m = mm;
+  lv->dim = N;
+  lv->q = q;
+  lv->opts = o;
+  std::vector<double> T((size_t)N * N), Em((size_t)N * N), Um((size_t)N * r), Vm((size_t)N * r),
+      Ct((size_t)r * N);
   for (int a = 0; a < N; ++a) {
-    const double* qa = ek->col(a);
-    for (int b = 0; b < N; ++b) T[(size_t)a * N + b] = dotn(qa, ek->AQ.data() + (size_t)b * n, n);
-    for (long c = 0; c < r; ++c) {
-      double su = 0, sv = 0, sx = 0;
-      for (long i = 0; i < n; ++i) {
-        su += qa[i] * ek->U[(size_t)i * r + c];
-        sv += qa[i] * ek->V[(size_t)i * r + c];
-        sx += qa[i] * ek->X0V[(size_t)i * r + c];
-      }
-      Um[(size_t)a * r + c] = su;
-      Vm[(size_t)a * r + c] = sv;
-      Ct[(size_t)c * N + a] = sx;
-    }
-  }
-  for (int a = 0; a < q; ++a) {
-    const double* qa = ek->col(N + a);
-    for (int b = 0; b < N; ++b) Lc[(size_t)a * N + b] = dotn(qa, ek->AQ.data() + (size_t)b * n, n);
-  }
-  {
-    std::vector<double> EQ((size_t)N * n);  // column b: E q_b
     for (int b = 0; b < N; ++b) {
-      const double* qb = ek->col(b);
-      double* out = EQ.data() + (size_t)b * n;
-      if (ek->E_diag) {
-        for (long i = 0; i < n; ++i) out[i] = ek->E[i] * qb[i];
-      } else {
-        for (long i = 0; i < n; ++i) out[i] = dotn(ek->E.data() + (size_t)i * n, qb, n);
-      }
+      T[(size_t)a * N + b] = ek->TQ[(size_t)a * D + b];
+      Em[(size_t)a * N + b] = ek->EM[(size_t)a * D + b];
     }
-    for (int a = 0; a < N; ++a)
-      for (int b = a; b < N; ++b) {
-        const double v = dotn(ek->col(a), EQ.data() + (size_t)b * n, n);
-        Em[(size_t)a * N + b] = v;
-        Em[(size_t)b * N + a] = v;
-      }
+    for (long c = 0; c < r; ++c) {
+      Um[(size_t)a * r + c] = ek->UQ[(size_t)a * r + c];
+      Vm[(size_t)a * r + c] = ek->VQ[(size_t)a * r + c];
+      Ct[(size_t)c * N + a] = ek->XQ[(size_t)a * r + c];
+    }
   }
-  // projected seed (replaces the previous level's)
-  lyap_seed_opts o{};
-  o.basis = popts ? popts->basis : LYAP_BASIS_AUTO;
-  o.E_is_diag = 0;
-  o.max_eig_cond = popts ? popts->max_eig_cond : 0.0;
-  o.tsvd_rank = popts ? popts->tsvd_rank : 0;
-  delete ek->proj;
-  ek->proj = nullptr;
-  ek->level = 0;
   ProjRhs pr{Ct.data(), ek->t0};
-  ek->proj = factor_projected(N, r, T.data(), Um.data(), Vm.data(), Em.data(), pr, &o, ek->st);
+  lv->proj = factor_projected(N, r, T.data(), Um.data(), Vm.data(), Em.data(), pr, &o, ek->st);
   // real Schur form of T_m for the backward error
   std::vector<double> Th((size_t)N * N), Zh((size_t)N * N);
   LYAP_REQUIRE(real_schur(N, T.data(), Th.data(), Zh.data(), nullptr), LYAP_E_UNSTABLE,
                "real Schur iteration on T_m did not converge");
-  const long ld = ek->proj->ld;
+  const long ld = lv->proj->ld;
   const size_t mat = (size_t)ld * ld * sizeof(double);
   std::vector<double> Tp((size_t)ld * ld, 0.0), Ttp((size_t)ld * ld, 0.0), Zp((size_t)ld * ld, 0.0);
   for (int i = 0; i < N; ++i)
@@ -437,7 +464,7 @@ void ek_set_level_impl(lyap_ek_s* ek, int m, const lyap_seed_opts* popts) {
       Ttp[(size_t)j * ld + i] = Th[(size_t)i * N + j];
       Zp[(size_t)i * ld + j] = Zh[(size_t)i * N + j];
     }
-  // Fl = U_m^T Z (r x ld), Lz = L Z (q x ld)
+  // Fl = U_m^T Z (r x ld); Lz = L Z (q x ld), L = rows N..N+q-1 of Q^T A0 Q, columns < N
   std::vector<double> Flh((size_t)r * ld, 0.0), Lzh((size_t)std::max(q, 1) * ld, 0.0);
   for (long a = 0; a < r; ++a)
     for (int j = 0; j < N; ++j) {
@@ -448,34 +475,53 @@ void ek_set_level_impl(lyap_ek_s* ek, int m, const lyap_seed_opts* popts) {
   for (int a = 0; a < q; ++a)
     for (int j = 0; j < N; ++j) {
       double s = 0.0;
-      for (int i = 0; i < N; ++i) s += Lc[(size_t)a * N + i] * Zh[(size_t)i * N + j];
+      for (int i = 0; i < N; ++i) s += ek->TQ[(size_t)(N + a) * D + i] * Zh[(size_t)i * N + j];
       Lzh[(size_t)a * ld + j] = s;
     }
   hipStream_t st = ek->st;
-  ek->Ts.alloc(mat);
-  ek->Tst.alloc(mat);
-  ek->Zd.alloc(mat);
-  ek->Fl.alloc(Flh.size() * sizeof(double));
-  ek->Lz.alloc(Lzh.size() * sizeof(double));
-  ek->cstd.alloc(ek->cst.size() * sizeof(double));
-  LYAP_HIP(hipMemcpyAsync(ek->Ts.p, Tp.data(), mat, hipMemcpyHostToDevice, st));
-  LYAP_HIP(hipMemcpyAsync(ek->Tst.p, Ttp.data(), mat, hipMemcpyHostToDevice, st));
-  LYAP_HIP(hipMemcpyAsync(ek->Zd.p, Zp.data(), mat, hipMemcpyHostToDevice, st));
-  LYAP_HIP(hipMemcpyAsync(ek->Fl.p, Flh.data(), ek->Fl.bytes, hipMemcpyHostToDevice, st));
-  LYAP_HIP(hipMemcpyAsync(ek->Lz.p, Lzh.data(), ek->Lz.bytes, hipMemcpyHostToDevice, st));
-  LYAP_HIP(hipMemcpyAsync(ek->cstd.p, ek->cst.data(), ek->cstd.bytes, hipMemcpyHostToDevice, st));
+  lv->Ts.alloc(mat);
+  lv->Tst.alloc(mat);
+  lv->Zd.alloc(mat);
+  lv->Fl.alloc(Flh.size() * sizeof(double));
+  lv->Lz.alloc(Lzh.size() * sizeof(double));
+  LYAP_HIP(hipMemcpyAsync(lv->Ts.p, Tp.data(), mat, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(lv->Tst.p, Ttp.data(), mat, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(lv->Zd.p, Zp.data(), mat, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(lv->Fl.p, Flh.data(), lv->Fl.bytes, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(lv->Lz.p, Lzh.data(), lv->Lz.bytes, hipMemcpyHostToDevice, st));
   LYAP_HIP(hipStreamSynchronize(st));
-  ek->level = mm;
-  ek->dim = N;
-  ek->q = q;
-  ek->level_seconds +=
-      std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
+  return lv.release();
 }
 
-// Backward errors of P parameters at the current level from W (P x r x dim).
-void ek_delta_impl(lyap_ek_s* ek, int64_t P, const double* d_dev, const double* W_dev,
+// Make level m current (built on first use, kept afterwards).
+EkLevel* ek_level(lyap_ek_s* ek, int m, const lyap_seed_opts* popts) {
+  LYAP_REQUIRE(m >= 1 && m <= 100000, LYAP_E_INVAL, "level out of range");
+  lyap_seed_opts o{};
+  o.basis = popts ? popts->basis : LYAP_BASIS_AUTO;
+  o.E_is_diag = 0;
+  o.max_eig_cond = popts ? popts->max_eig_cond : 0.0;
+  o.tsvd_rank = popts ? popts->tsvd_rank : 0;
+  auto t0 = std::chrono::steady_clock::now();
+  while (ek->nblocks() < m + 1 && !ek->exhausted) ek_expand(ek);
+  auto t1 = std::chrono::steady_clock::now();
+  ek->basis_seconds += std::chrono::duration<double>(t1 - t0).count();
+  const int mm = std::min(m, ek->nblocks());
+  if ((int)ek->levels.size() <= mm) ek->levels.resize(mm + 1);
+  auto& slot = ek->levels[mm];
+  if (!slot || !same_opts(slot->opts, o)) {
+    slot.reset();
+    slot.reset(ek_build_level(ek, mm, o));
+    ek->level_seconds +=
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
+  }
+  ek->cur = slot.get();
+  return ek->cur;
+}
+
+// Backward errors of P parameters at level lv from W (P x r x dim).
+void ek_delta_impl(lyap_ek_s* ek, EkLevel* lv, int64_t P, const double* d_dev, const double* W_dev,
                    double* delta_dev, double* nrm_dev) {
-  const long r = ek->r, N = ek->dim, ld = ek->proj->ld;
+  const long r = ek->r, N = lv->dim, ld = lv->proj->ld;
   hipStream_t st = ek->st;
   for (int64_t p0 = 0; p0 < P; p0 += kDeltaChunk) {
     const int cnt = (int)std::min<int64_t>(kDeltaChunk, P - p0);
@@ -490,27 +536,108 @@ void ek_delta_impl(lyap_ek_s* ek, int64_t P, const double* d_dev, const double* 
     hipLaunchKernelGGL(k_pad_rows_ek, dim3(ub, cnt * r), dim3(256), 0, st, ek->Wp.as<double>(), ld,
                        W_dev + (size_t)p0 * r * N, N, (int)N);
     LYAP_HIP(hipGetLastError());
-    // Gs = W Z: the per-parameter factor of Zs^T (U_m W + W^T U_m^T) Zs
-    gemm64_rm(ek->Wp.as<double>(), ld, ek->Zd.as<double>(), ld, ek->Gs.as<double>(), ld,
+    // Gs = W Z: the per-parameter factor of Z^T (U_m W + W^T U_m^T) Z
+    gemm64_rm(ek->Wp.as<double>(), ld, lv->Zd.as<double>(), ld, ek->Gs.as<double>(), ld,
               (long)cnt * r, ld, ld, ld, st);
-    trilyap_launch(ek->Ts.as<double>(), ek->Tst.as<double>(), ek->Xs.as<double>(), ld * ld, nullptr,
-                   0, ek->Fl.as<double>(), ek->Gs.as<double>(), r * ld, (int)r, (int)N, (int)ld,
+    trilyap_launch(lv->Ts.as<double>(), lv->Tst.as<double>(), ek->Xs.as<double>(), ld * ld, nullptr,
+                   0, lv->Fl.as<double>(), ek->Gs.as<double>(), r * ld, (int)r, (int)N, (int)ld,
                    cnt, nullptr, nullptr, st);
     hipLaunchKernelGGL(k_ek_delta, dim3(cnt), dim3(NT), 0, st, ek->Xs.as<double>(), ld * ld, (int)N,
-                       (int)ld, ek->Lz.as<double>(), ek->q, d_dev + (size_t)p0 * r, (int)r,
+                       (int)ld, lv->Lz.as<double>(), lv->q, d_dev + (size_t)p0 * r, (int)r,
                        ek->cstd.as<double>(), delta_dev + p0, nrm_dev ? nrm_dev + 2 * p0 : nullptr);
     LYAP_HIP(hipGetLastError());
   }
 }
 
-void ek_solve_impl(lyap_ek_s* ek, int64_t P, const double* d_dev, const lyap_solve_opts* opts,
-                   double* W_dev, double* delta_dev, double* nrm_dev, lyap_result* res) {
-  LYAP_REQUIRE(ek->proj, LYAP_E_INVAL, "ek_set_level was not called");
+// Projected solves of P parameters at level lv, then their backward errors.
+void ek_solve_level(lyap_ek_s* ek, EkLevel* lv, int64_t P, const double* d_dev,
+                    const lyap_solve_opts* opts, double* W_dev, double* delta_dev, double* nrm_dev,
+                    lyap_result* res) {
   LYAP_REQUIRE(P >= 1 && d_dev && W_dev && delta_dev && res, LYAP_E_INVAL, "bad argument");
-  const lyap_status s = smw_solve_batch(ek->proj, P, d_dev, opts, W_dev, res, nullptr, 0, ek->st);
-  if (s != LYAP_OK) throw Error{s, std::string("projected solve: ") + lyap_last_error()};
-  ek_delta_impl(ek, P, d_dev, W_dev, delta_dev, nrm_dev);
+  if (!lv->eng || !engine_batch_fits(lv->eng, P, opts)) {
+    if (lv->eng) engine_batch_destroy(lv->eng);
+    lv->eng = nullptr;
+    const long long cap = std::max<long long>(P, 64);
+    lv->sol.alloc((size_t)cap * ek->r * lv->proj->ld * sizeof(double));
+    lv->eng = engine_batch_create(lv->proj, cap, opts, ek->st, lv->sol.as<double>());
+  } else {
+    engine_batch_reset(lv->eng, ek->st);
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  engine_batch_run(lv->eng, P, d_dev, W_dev, res);
+  auto t1 = std::chrono::steady_clock::now();
+  ek_delta_impl(ek, lv, P, d_dev, W_dev, delta_dev, nrm_dev);
   LYAP_HIP(hipStreamSynchronize(ek->st));
+  ek->solve_seconds += std::chrono::duration<double>(t1 - t0).count();
+  ek->delta_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
+  ++ek->batches;
+}
+
+// Algorithm EKSM_opt: parameters in order; at each level the queue is tested
+// from its head and the longest accepted prefix leaves; the first failure
+// moves every remaining parameter to the next level.  The queue head is
+// solved in chunks that grow fourfold after every fully accepted chunk
+// (1, 4, 16, ...) and restart at one on a new level, so the accepted prefix is
+// the one the sequential loop finds while the solves stay batched.
+void ek_sweep_impl(lyap_ek_s* ek, int64_t P, const double* d_host, const lyap_solve_opts* opts,
+                   const lyap_seed_opts* popts, double eps, int m_max, int check_every,
+                   lyap_ek_result* out) {
+  const long r = ek->r;
+  for (int64_t i = 0; i < P * r; ++i)
+    LYAP_REQUIRE(std::isfinite(d_host[i]), LYAP_E_INVAL, "non-finite parameter");
+  for (int64_t i = 0; i < P; ++i) out[i] = lyap_ek_result{LYAP_E_NOCONV, 0, 0, 0, NAN, NAN};
+  if (ek->ddev.bytes < (size_t)P * r * sizeof(double)) ek->ddev.alloc((size_t)P * r * sizeof(double));
+  if (ek->dl.bytes < (size_t)P * sizeof(double)) ek->dl.alloc((size_t)P * sizeof(double));
+  LYAP_HIP(hipMemcpyAsync(ek->ddev.p, d_host, (size_t)P * r * sizeof(double), hipMemcpyHostToDevice,
+                          ek->st));
+  std::vector<double> delta;
+  std::vector<lyap_result> res;
+  int64_t pos = 0, chunk = 1;
+  int m = 1;
+  while (pos < P && m <= m_max) {
+    EkLevel* lv = ek_level(ek, m, popts);
+    const int64_t cnt = std::min<int64_t>(chunk, P - pos);
+    const size_t wb = (size_t)cnt * r * lv->dim * sizeof(double);
+    if (ek->Wbuf.bytes < wb) ek->Wbuf.alloc(wb);
+    res.resize(cnt);
+    ek_solve_level(ek, lv, cnt, ek->ddev.as<double>() + (size_t)pos * r, opts, ek->Wbuf.as<double>(),
+                   ek->dl.as<double>() + pos, nullptr, res.data());
+    delta.resize(cnt);
+    LYAP_HIP(hipMemcpyAsync(delta.data(), ek->dl.as<double>() + pos, (size_t)cnt * sizeof(double),
+                            hipMemcpyDeviceToHost, ek->st));
+    LYAP_HIP(hipStreamSynchronize(ek->st));
+    const bool invariant = lv->q == 0;  // the projection is exact
+    int64_t t = 0;
+    for (; t < cnt; ++t) {
+      lyap_ek_result& o = out[pos + t];
+      o.iters += res[t].iters;
+      o.level = lv->m;
+      o.dim = lv->dim;
+      o.delta = delta[t];
+      o.trace = res[t].trace;
+      if (res[t].status != LYAP_OK) {
+        o.status = res[t].status;
+        break;
+      }
+      if (!(delta[t] <= eps || invariant)) break;
+      o.status = LYAP_OK;
+    }
+    // chunk members after the first failure were solved but are not tested at
+    // this level (the sequential loop never reaches them): their work counts
+    for (int64_t u = t + 1; u < cnt; ++u) out[pos + u].iters += res[u].iters;
+    pos += t;
+    if (t < cnt) {
+      if (invariant) {
+        ++pos;  // the space cannot grow: the projected solve itself failed
+        chunk = 1;
+        continue;
+      }
+      m = lv->m + check_every;
+      chunk = 1;
+    } else {
+      chunk = std::min<int64_t>(4 * chunk, P);
+    }
+  }
 }
 
 }  // namespace
@@ -546,14 +673,17 @@ lyap_status ek_create(int64_t n, int64_t r, const double* A0, const double* U, c
 
 lyap_status ek_set_level(lyap_ek ek, int32_t m, const lyap_seed_opts* proj_opts) {
   if (!ek) return LYAP_E_INVAL;
-  LYAP_TRY(ek_set_level_impl(ek, m, proj_opts));
+  LYAP_TRY(ek_level(ek, m, proj_opts));
   return LYAP_OK;
 }
 
 lyap_status ek_solve(lyap_ek ek, int64_t P, const double* d_dev, const lyap_solve_opts* opts,
                      double* W_dev, double* delta_dev, double* norms_dev, lyap_result* res_host) {
   if (!ek) return LYAP_E_INVAL;
-  LYAP_TRY(ek_solve_impl(ek, P, d_dev, opts, W_dev, delta_dev, norms_dev, res_host));
+  LYAP_TRY({
+    LYAP_REQUIRE(ek->cur, LYAP_E_INVAL, "ek_set_level was not called");
+    ek_solve_level(ek, ek->cur, P, d_dev, opts, W_dev, delta_dev, norms_dev, res_host);
+  });
   return LYAP_OK;
 }
 
@@ -562,70 +692,7 @@ lyap_status ek_sweep(lyap_ek ek, int64_t P, const double* d_host, const lyap_sol
                      int32_t check_every, lyap_ek_result* out) {
   if (!ek || P < 1 || !d_host || !out || !(eps > 0) || m_max < 1 || check_every < 1)
     return LYAP_E_INVAL;
-  LYAP_TRY({
-    const long r = ek->r;
-    for (int64_t i = 0; i < P * r; ++i)
-      LYAP_REQUIRE(std::isfinite(d_host[i]), LYAP_E_INVAL, "non-finite parameter");
-    for (int64_t i = 0; i < P; ++i) {
-      out[i].status = LYAP_E_NOCONV;
-      out[i].level = 0;
-      out[i].dim = 0;
-      out[i].iters = 0;
-      out[i].delta = NAN;
-      out[i].trace = NAN;
-    }
-    std::vector<int64_t> todo(P);
-    for (int64_t i = 0; i < P; ++i) todo[i] = i;
-    std::vector<double> dl, delta;
-    std::vector<lyap_result> res;
-    int m = 1;
-    while (!todo.empty() && m <= m_max) {
-      ek_set_level_impl(ek, m, proj_opts);
-      const int64_t R = (int64_t)todo.size();
-      dl.resize((size_t)R * r);
-      for (int64_t t = 0; t < R; ++t)
-        std::memcpy(&dl[(size_t)t * r], d_host + (size_t)todo[t] * r, sizeof(double) * r);
-      if (ek->ddev.bytes < dl.size() * sizeof(double)) ek->ddev.alloc(dl.size() * sizeof(double));
-      const size_t wb = (size_t)R * r * ek->dim * sizeof(double);
-      if (ek->Wbuf.bytes < wb) ek->Wbuf.alloc(wb);
-      if (ek->dl.bytes < (size_t)R * sizeof(double)) ek->dl.alloc((size_t)R * sizeof(double));
-      LYAP_HIP(hipMemcpyAsync(ek->ddev.p, dl.data(), dl.size() * sizeof(double),
-                              hipMemcpyHostToDevice, ek->st));
-      res.resize(R);
-      ek_solve_impl(ek, R, ek->ddev.as<double>(), opts, ek->Wbuf.as<double>(), ek->dl.as<double>(),
-                    nullptr, res.data());
-      delta.resize(R);
-      LYAP_HIP(hipMemcpyAsync(delta.data(), ek->dl.p, (size_t)R * sizeof(double),
-                              hipMemcpyDeviceToHost, ek->st));
-      LYAP_HIP(hipStreamSynchronize(ek->st));
-      std::vector<int64_t> rest;
-      const bool last = ek->q == 0;  // the space is invariant: the projection is exact
-      for (int64_t t = 0; t < R; ++t) {
-        lyap_ek_result& o = out[todo[t]];
-        o.iters += res[t].iters;
-        o.level = ek->level;
-        o.dim = ek->dim;
-        o.delta = delta[t];
-        o.trace = res[t].trace;
-        if (res[t].status != LYAP_OK) {
-          // the projected solve failed at this level: kept for the next one,
-          // its status stands if no later level accepts it
-          o.status = res[t].status;
-          rest.push_back(todo[t]);
-          continue;
-        }
-        if (delta[t] <= eps || last) {
-          o.status = LYAP_OK;
-        } else {
-          o.status = LYAP_E_NOCONV;
-          rest.push_back(todo[t]);
-        }
-      }
-      todo.swap(rest);
-      if (last) break;
-      m = ek->level + check_every;
-    }
-  });
+  LYAP_TRY(ek_sweep_impl(ek, P, d_host, opts, proj_opts, eps, m_max, check_every, out));
   return LYAP_OK;
 }
 
@@ -633,15 +700,18 @@ lyap_status ek_info(lyap_ek ek, lyap_ek_info* o) {
   if (!ek || !o) return LYAP_E_INVAL;
   o->n = ek->n;
   o->r = ek->r;
-  o->level = ek->level;
-  o->dim = ek->dim;
+  o->level = ek->cur ? ek->cur->m : 0;
+  o->dim = ek->cur ? ek->cur->dim : 0;
   o->blocks = ek->nblocks();
-  o->basis_cols = (int64_t)(ek->Q.size() / ek->n);
+  o->basis_cols = ek->D;
   o->exhausted = ek->exhausted ? 1 : 0;
-  o->proj_basis = ek->proj ? ek->proj->basis : -1;
-  o->proj_cond = ek->proj ? ek->proj->cond_est : 0.0;
+  o->proj_basis = ek->cur ? ek->cur->proj->basis : -1;
+  o->proj_cond = ek->cur ? ek->cur->proj->cond_est : 0.0;
   o->basis_seconds = ek->basis_seconds;
   o->level_seconds = ek->level_seconds;
+  o->solve_seconds = ek->solve_seconds;
+  o->delta_seconds = ek->delta_seconds;
+  o->batches = ek->batches;
   return LYAP_OK;
 }
 

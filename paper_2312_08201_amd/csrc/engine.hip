@@ -2542,13 +2542,86 @@ static long long default_slots(const lyap_seed_s* sd, long long P) {
   return std::max<long long>(1, std::min(S, P));
 }
 
+namespace lyap {
+
+// Run P parameters (device d, tags 0..P-1) through an engine whose queue and
+// solution store hold at least P, then write the physical solutions
+// Y = rho(Yhat) Tout to Y_dev (P x r x n) and the results to res_host.
+// The engine must have been reset (or freshly created) on the caller's stream.
+void engine_batch_run(lyap_engine_s* E, long long P, const double* d_dev, double* Y_dev,
+                      lyap_result* res_host) {
+  lyap_seed_s* sd = E->sd;
+  LYAP_REQUIRE(P >= 1 && P <= E->Q && P <= E->sol_cap, LYAP_E_INVAL, "batch exceeds the engine");
+  const long long r = sd->r, ld = sd->ld, n = sd->n, S = E->S;
+  const lyap_solve_opts o = E->opts;
+  double* sol = E->sol;
+  hipStream_t st = E->stream;
+  // queue: d from device, tags 0..P-1
+  LYAP_HIP(hipMemcpyAsync(E->qd.p, d_dev, P * r * sizeof(double), hipMemcpyDeviceToDevice, st));
+  std::vector<long long> tags(P);
+  for (long long i = 0; i < P; ++i) tags[i] = i;
+  LYAP_HIP(hipMemcpyAsync(E->qtag.p, tags.data(), P * sizeof(long long), hipMemcpyHostToDevice, st));
+  const int tail = (int)P;
+  LYAP_HIP(hipMemcpyAsync(E->qctl.as<int>() + 1, &tail, sizeof(int), hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipStreamSynchronize(st));
+  E->submitted = P;
+  const long long max_steps = (long long)o.max_iter * ((P + S - 1) / S + 1) + 16;
+  engine_run_impl(E, max_steps, 8);
+  std::vector<long long> tg(P);
+  std::vector<lyap_result> rr(P);
+  const long long got = engine_harvest_impl(E, P, tg.data(), rr.data());
+  for (long long i = 0; i < P; ++i) res_host[i] = lyap_result{LYAP_E_NOCONV, 0, 0, 0, NAN, NAN};
+  for (long long i = 0; i < got; ++i)
+    if (tg[i] >= 0 && tg[i] < P) res_host[tg[i]] = rr[i];
+  // physical Y = rho(Yhat) Tout  (transform-out GEMM, n columns stored)
+  GemmArgs g{};
+  g.type = GemmType::F64;
+  g.A = sol;
+  g.B = sd->Tout.p;
+  g.C = Y_dev;
+  g.M = P * r;
+  g.N = ld;
+  g.K = ld;
+  g.lda = ld;
+  g.ldb = ld;
+  g.ldc = n;
+  g.Nstore = n;
+  g.M_dev = nullptr;
+  g.m_scale = 1;
+  gemm_launch(g, st);
+  LYAP_HIP(hipStreamSynchronize(st));
+}
+
+// Engines owned by other parts of the library (one batch size cap, one store).
+lyap_engine_s* engine_batch_create(lyap_seed_s* sd, long long P_cap, const lyap_solve_opts* opts,
+                                   hipStream_t st, double* sol) {
+  lyap_solve_opts o;
+  fill_defaults(o, opts);
+  validate_opts(o);
+  return engine_create_impl(sd, default_slots(sd, P_cap), &o, st, P_cap, sol, P_cap, true);
+}
+void engine_batch_reset(lyap_engine_s* E, hipStream_t st) { engine_reset(E, st); }
+void engine_batch_destroy(lyap_engine_s* E) { engine_destroy_impl(E); }
+bool engine_batch_fits(const lyap_engine_s* E, long long P, const lyap_solve_opts* opts) {
+  lyap_solve_opts o;
+  fill_defaults(o, opts);
+  return P <= E->Q && P <= E->sol_cap && std::memcmp(&o, &E->opts, sizeof(o)) == 0;
+}
+
+}  // namespace lyap
+
 extern "C" {
 
 size_t engine_device_bytes(lyap_seed sd, int64_t slots, const lyap_solve_opts* opts) {
   if (!sd || slots < 1) return 0;
-  lyap_solve_opts o;
-  fill_defaults(o, opts);
-  return engine_sizes(sd, slots, o, std::max<int64_t>(4 * slots, 1024)).total;
+  try {
+    lyap_solve_opts o;
+    fill_defaults(o, opts);
+    return engine_sizes(sd, slots, o, std::max<int64_t>(4 * slots, 1024)).total;
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return 0;
+  }
 }
 
 lyap_status engine_create(lyap_seed sd, int64_t slots, const lyap_solve_opts* opts,
@@ -2636,11 +2709,16 @@ lyap_status lyap_profile_read(lyap_profile* out) {
 
 size_t smw_workspace_bytes(lyap_seed sd, int64_t P, const lyap_solve_opts* opts) {
   if (!sd || P < 1) return 0;
-  lyap_solve_opts o;
-  fill_defaults(o, opts);
-  const long long S = default_slots(sd, P);
-  const size_t sol = (size_t)P * sd->r * sd->ld * sizeof(double);
-  return engine_sizes(sd, S, o, P).total + sol;
+  try {
+    lyap_solve_opts o;
+    fill_defaults(o, opts);
+    const long long S = default_slots(sd, P);
+    const size_t sol = (size_t)P * sd->r * sd->ld * sizeof(double);
+    return engine_sizes(sd, S, o, P).total + sol;
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return 0;
+  }
 }
 
 lyap_status smw_solve_batch(lyap_seed sd, int64_t P, const double* d_dev,
@@ -2702,45 +2780,7 @@ lyap_status smw_solve_batch(lyap_seed sd, int64_t P, const double* d_dev,
       E = engine_create_impl(sd, S, &o, st, P, sol, P, true);
       eg.reset(E);
     }
-    const hipStream_t user = st;
-    st = E->stream;
-    // queue: d from device, tags 0..P-1
-    LYAP_HIP(hipMemcpyAsync(E->qd.p, d_dev, P * r * sizeof(double), hipMemcpyDeviceToDevice, st));
-    std::vector<long long> tags(P);
-    for (long long i = 0; i < P; ++i) tags[i] = i;
-    LYAP_HIP(hipMemcpyAsync(E->qtag.p, tags.data(), P * sizeof(long long), hipMemcpyHostToDevice, st));
-    const int tail = (int)P;
-    LYAP_HIP(hipMemcpyAsync(E->qctl.as<int>() + 1, &tail, sizeof(int), hipMemcpyHostToDevice, st));
-    LYAP_HIP(hipStreamSynchronize(st));
-    E->submitted = P;
-    const long long max_steps = (long long)o.max_iter * ((P + S - 1) / S + 1) + 16;
-    engine_run_impl(E, max_steps, 8);
-    std::vector<long long> tg(P);
-    std::vector<lyap_result> rr(P);
-    const long long got = engine_harvest_impl(E, P, tg.data(), rr.data());
-    for (long long i = 0; i < P; ++i) {
-      res_host[i] = lyap_result{LYAP_E_NOCONV, 0, 0, 0, NAN, NAN};
-    }
-    for (long long i = 0; i < got; ++i)
-      if (tg[i] >= 0 && tg[i] < P) res_host[tg[i]] = rr[i];
-    // physical Y = rho(Yhat) Tout  (transform-out GEMM, n columns stored)
-    GemmArgs g{};
-    g.type = GemmType::F64;
-    g.A = sol;
-    g.B = sd->Tout.p;
-    g.C = Y_dev;
-    g.M = P * r;
-    g.N = ld;
-    g.K = ld;
-    g.lda = ld;
-    g.ldb = ld;
-    g.ldc = n;
-    g.Nstore = n;
-    g.M_dev = nullptr;
-    g.m_scale = 1;
-    gemm_launch(g, st);
-    LYAP_HIP(hipStreamSynchronize(st));
-    (void)user;
+    engine_batch_run(E, P, d_dev, Y_dev, res_host);
   });
   return LYAP_OK;
 }

@@ -97,6 +97,17 @@ lyap_seed_s* factor_projected(int64_t n, int64_t r, const double* A0, const doub
                               const double* V, const double* E, const ProjRhs& proj,
                               const lyap_seed_opts* opts, hipStream_t stream);
 
+// ---- engines owned inside the library (engine.hip) ----
+// An engine with queue and solution store for up to P_cap parameters; batches
+// of any size up to that run on it after a reset (see smw_solve_batch).
+lyap_engine_s* engine_batch_create(lyap_seed_s* sd, long long P_cap, const lyap_solve_opts* opts,
+                                   hipStream_t st, double* sol);
+void engine_batch_reset(lyap_engine_s* E, hipStream_t st);
+void engine_batch_destroy(lyap_engine_s* E);
+bool engine_batch_fits(const lyap_engine_s* E, long long P, const lyap_solve_opts* opts);
+void engine_batch_run(lyap_engine_s* E, long long P, const double* d_dev, double* Y_dev,
+                      lyap_result* res_host);
+
 // ---- Schur basis (schur.hip) ----
 // T Xs + Xs T^T = C per problem; C dense (Cd, row-major) or F G^T + G F^T
 // (F: k shared rows, G: k rows per problem).  X stored column by column.

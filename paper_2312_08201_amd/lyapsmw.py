@@ -73,7 +73,9 @@ class EkInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("r", C.c_int64), ("level", C.c_int64), ("dim", C.c_int64),
                 ("blocks", C.c_int64), ("basis_cols", C.c_int64), ("exhausted", C.c_int32),
                 ("proj_basis", C.c_int32), ("proj_cond", C.c_double),
-                ("basis_seconds", C.c_double), ("level_seconds", C.c_double)]
+                ("basis_seconds", C.c_double), ("level_seconds", C.c_double),
+                ("solve_seconds", C.c_double), ("delta_seconds", C.c_double),
+                ("batches", C.c_int64)]
 
 
 EK_RESULT_DTYPE = np.dtype([("status", np.int32), ("level", np.int32), ("dim", np.int32),
@@ -284,7 +286,10 @@ class Seed:
     # ---- online stage ----
     def workspace_bytes(self, P, opts: Optional[SolveOpts] = None) -> int:
         opts = opts or solve_opts()
-        return int(load().smw_workspace_bytes(self.h, P, C.byref(opts)))
+        nbytes = int(load().smw_workspace_bytes(self.h, P, C.byref(opts)))
+        if nbytes == 0:
+            raise LyapError(1, "smw_workspace_bytes", last_error())
+        return nbytes
 
     def solve(self, d, opts: Optional[SolveOpts] = None, stream=None):
         """smw_solve_batch for d (P x r, CUDA float64).  Returns (Y, results)."""

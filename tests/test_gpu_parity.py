@@ -313,6 +313,21 @@ def test_repeated_solves_reuse_engine_identically():
     assert np.max(rel(runs[0][2]["trace"], oracle_traces(pr))) <= 1e-10
 
 
+def test_oversized_capacitance_vector_is_an_error_not_an_abort():
+    """r * ld above the Krylov kernel's per-slot limit (16384) is reported by
+    every entry point that sizes an engine, through the status code."""
+    L, torch = lib()
+    pr = W.random_stable(1100, 16, 2, 2, 21)      # ld = 1152, r * ld = 18432
+    seed = L.Seed.from_problem(pr)
+    with pytest.raises(L.LyapError, match="16384"):
+        seed.workspace_bytes(2)
+    assert L.Engine.device_bytes(seed, 8) == 0
+    d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
+    with pytest.raises(L.LyapError):
+        seed.solve(d)
+    seed.release()
+
+
 @pytest.mark.parametrize("cfg", ["8,0,0", "8,0,1", "8,2,0", "8,2,1", "16,0,0", "16,0,1", "16,2,0",
                                  "16,2,1"])
 def test_every_gemm_launch_configuration(cfg, monkeypatch):

@@ -44,6 +44,7 @@ namespace {
 constexpr double kDeflate = 1e-10;
 constexpr int NT = 256;
 constexpr int kDeltaChunk = 1024;   // problems per batched quasi-triangular solve
+constexpr size_t kOpBytes = size_t(8) << 30;  // temporary bytes allowed for building operators
 
 // dst (rows x ldd) <- src (rows x n), pads untouched (caller zeroes them)
 __global__ void k_pad_rows_ek(double* __restrict__ dst, long ldd, const double* __restrict__ src,
@@ -121,6 +122,86 @@ k_ek_delta(const double* __restrict__ Xs, long xstride, int n, int ld,
   }
 }
 
+// out (cols x rows) = in^T (rows x cols), both row-major, 32 x 32 tiles through LDS
+__global__ void k_transpose(const double* __restrict__ in, long rows, long cols,
+                            double* __restrict__ out, long ldo) {
+  __shared__ double tile[32][33];
+  const long r0 = (long)blockIdx.y * 32, c0 = (long)blockIdx.x * 32;
+  for (int k = threadIdx.y; k < 32; k += 8) {
+    const long rr = r0 + k, cc = c0 + threadIdx.x;
+    tile[k][threadIdx.x] = (rr < rows && cc < cols) ? in[rr * cols + cc] : 0.0;
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += 8) {
+    const long cc = c0 + k, rr = r0 + threadIdx.x;
+    if (cc < cols && rr < rows) out[cc * ldo + rr] = tile[threadIdx.x][k];
+  }
+}
+
+// out[i] = sum over s < ns of part[s * stride + i]
+__global__ void k_sum_slices(const double* __restrict__ part, int ns, long stride,
+                             double* __restrict__ out) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < stride;
+       i += (long)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int s = 0; s < ns; ++s) v += part[s * stride + i];
+    out[i] = v;
+  }
+}
+
+// Backward errors from the p-independent operators: one workgroup per
+// parameter, ||L Y||^2 = sum of squares of its row of LY = W KT and
+// ||Y||^2 = <w, Mq w> with MW = W Mq.
+__global__ void __launch_bounds__(NT)
+k_ek_delta_ops(const double* __restrict__ LY, long ldly, long ncols, const double* __restrict__ Wp,
+               const double* __restrict__ MW, long ldw, int rN, const double* __restrict__ d, int r,
+               const double* __restrict__ cst, double* __restrict__ delta, double* __restrict__ nrm) {
+  const int p = blockIdx.x;
+  double sr = 0.0, sy = 0.0;
+  const double* ly = LY + (long)p * ldly;
+  for (long c = threadIdx.x; c < ncols; c += NT) sr += ly[c] * ly[c];
+  const double* w = Wp + (long)p * ldw;
+  const double* mw = MW + (long)p * ldw;
+  for (int u = threadIdx.x; u < rN; u += NT) sy += w[u] * mw[u];
+  __shared__ double red[2][NT];
+  red[0][threadIdx.x] = sy;
+  red[1][threadIdx.x] = sr;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + s];
+      red[1][threadIdx.x] += red[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double* dp = d + (long)p * r;
+    const double* H = cst + 1;
+    const double* av = H + r * r;
+    const double* Gm = av + r;
+    double a2 = cst[0];
+    for (int i = 0; i < r; ++i) {
+      a2 -= 2.0 * av[i] * dp[i];
+      for (int j = 0; j < r; ++j) a2 += dp[i] * dp[j] * H[i * r + j];
+    }
+    const int r2 = 2 * r;
+    double g2 = 0.0;
+    for (int a = 0; a < r2; ++a)
+      for (int c = 0; c < r2; ++c) {
+        const double mac = (a < r ? dp[a] * Gm[(a + r) * r2 + c] : dp[a - r] * Gm[(a - r) * r2 + c]);
+        const double mca = (c < r ? dp[c] * Gm[(c + r) * r2 + a] : dp[c - r] * Gm[(c - r) * r2 + a]);
+        g2 += mac * mca;
+      }
+    const double ny = sqrt(fmax(red[0][0], 0.0)), nr = sqrt(red[1][0]);
+    const double den = 2.0 * sqrt(fmax(a2, 0.0)) * ny + sqrt(fmax(g2, 0.0));
+    delta[p] = den > 0.0 ? sqrt(2.0) * nr / den : 0.0;
+    if (nrm) {
+      nrm[2 * p] = ny;
+      nrm[2 * p + 1] = nr;
+    }
+  }
+}
+
 }  // namespace
 }  // namespace lyap
 
@@ -134,6 +215,13 @@ struct EkLevel {
   lyap_seed_opts opts{};
   lyap_seed_s* proj = nullptr;
   DevBuf Ts, Tst, Zd, Fl, Lz;
+  // p-independent operators of the backward error (when they fit): with
+  // Ys_u the Schur-basis solution for the unit W = e_b e_k^T (u = b N + k),
+  // KT (rNp x ld q) holds (L Z) Ys_u by rows and Mq (rNp x rNp) their Gram
+  // matrix, so L Y = W KT and ||Y||^2 = w^T Mq w for every parameter.
+  bool ops = false;
+  long rNp = 0, colsK = 0;
+  DevBuf KT, Mq;
   lyap_engine_s* eng = nullptr;
   DevBuf sol;
   ~EkLevel() {
@@ -424,6 +512,67 @@ bool same_opts(const lyap_seed_opts& a, const lyap_seed_opts& b) {
   return a.basis == b.basis && a.max_eig_cond == b.max_eig_cond && a.tsvd_rank == b.tsvd_rank;
 }
 
+// The backward-error operators of a level (see EkLevel).  One batched
+// quasi-triangular solve over the r N unit right-hand sides, then two GEMMs.
+void ek_build_ops(lyap_ek_s* ek, EkLevel* lv, const std::vector<double>& Flh,
+                  const std::vector<double>& Zh, const std::vector<double>& Lzh) {
+  const long r = ek->r, N = lv->dim, ld = lv->proj->ld, q = lv->q;
+  const long rN = r * N, rNp = pad_to(rN, 128), l2 = ld * ld;
+  const size_t ybytes = (size_t)rN * l2 * sizeof(double);
+  if (q == 0 || 2 * ybytes > kOpBytes) return;  // invariant level, or too large: direct route
+  hipStream_t st = ek->st;
+  // per-problem factors: F row u = Fl row (u / N), G row u = Z row (u % N)
+  std::vector<double> Fr((size_t)rN * ld, 0.0), Gr((size_t)rN * ld, 0.0);
+  for (long u = 0; u < rN; ++u) {
+    const long b = u / N, k = u % N;
+    std::memcpy(&Fr[(size_t)u * ld], &Flh[(size_t)b * ld], sizeof(double) * ld);
+    for (long j = 0; j < N; ++j) Gr[(size_t)u * ld + j] = Zh[(size_t)k * N + j];
+  }
+  DevBuf Frd(Fr.size() * sizeof(double)), Grd(Gr.size() * sizeof(double)), Yu(ybytes);
+  LYAP_HIP(hipMemcpyAsync(Frd.p, Fr.data(), Frd.bytes, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemcpyAsync(Grd.p, Gr.data(), Grd.bytes, hipMemcpyHostToDevice, st));
+  LYAP_HIP(hipMemsetAsync(Yu.p, 0, ybytes, st));
+  trilyap_launch(lv->Ts.as<double>(), lv->Tst.as<double>(), Yu.as<double>(), l2, nullptr, 0,
+                 Frd.as<double>(), Grd.as<double>(), ld, 1, (int)N, (int)ld, (int)rN, nullptr,
+                 nullptr, st, ld);
+  // KT: rows (u, j) of Yu (column j of Ys_u) times (L Z)^T, q columns stored
+  std::vector<double> LzT((size_t)ld * 128, 0.0);
+  for (long a = 0; a < q; ++a)
+    for (long i = 0; i < N; ++i) LzT[(size_t)i * 128 + a] = Lzh[(size_t)a * ld + i];
+  DevBuf LzTd(LzT.size() * sizeof(double));
+  LYAP_HIP(hipMemcpyAsync(LzTd.p, LzT.data(), LzTd.bytes, hipMemcpyHostToDevice, st));
+  lv->colsK = ld * q;
+  lv->rNp = rNp;
+  lv->KT.alloc((size_t)rNp * lv->colsK * sizeof(double));
+  LYAP_HIP(hipMemsetAsync(lv->KT.p, 0, lv->KT.bytes, st));
+  gemm64_rm(Yu.as<double>(), ld, LzTd.as<double>(), 128, lv->KT.as<double>(), q, rN * ld, 128, ld,
+            q, st);
+  // Mq = Yflat Yflat^T with Yflat (rN x ld^2): through the transpose
+  {
+    DevBuf YT((size_t)l2 * rNp * sizeof(double));
+    LYAP_HIP(hipMemsetAsync(YT.p, 0, YT.bytes, st));
+    dim3 grid((unsigned)((l2 + 31) / 32), (unsigned)((rN + 31) / 32));
+    hipLaunchKernelGGL(k_transpose, grid, dim3(32, 8), 0, st, Yu.as<double>(), rN, l2,
+                       YT.as<double>(), rNp);
+    LYAP_HIP(hipGetLastError());
+    // K = ld^2 is long and the output has few tiles: 16 K-slices, summed after
+    constexpr int kSlices = 16;
+    const long kc = l2 / kSlices;  // ld is a multiple of 128, so kc is a multiple of the K tile
+    const size_t pe = (size_t)rNp * rNp;
+    DevBuf part(kSlices * pe * sizeof(double));
+    LYAP_HIP(hipMemsetAsync(part.p, 0, part.bytes, st));
+    for (int c = 0; c < kSlices; ++c)
+      gemm64_rm(Yu.as<double>() + c * kc, l2, YT.as<double>() + (size_t)c * kc * rNp, rNp,
+                part.as<double>() + c * pe, rNp, rN, rNp, kc, rNp, st);
+    lv->Mq.alloc(pe * sizeof(double));
+    hipLaunchKernelGGL(k_sum_slices, dim3((unsigned)std::min<size_t>((pe + 255) / 256, 65535)),
+                       dim3(256), 0, st, part.as<double>(), kSlices, (long)pe, lv->Mq.as<double>());
+    LYAP_HIP(hipGetLastError());
+    LYAP_HIP(hipStreamSynchronize(st));
+  }
+  lv->ops = true;
+}
+
 // Level m (blocks 0..m-1): the projected seed and the backward-error data.
 EkLevel* ek_build_level(lyap_ek_s* ek, int mm, const lyap_seed_opts& o) {
   const long r = ek->r;
@@ -490,6 +639,7 @@ EkLevel* ek_build_level(lyap_ek_s* ek, int mm, const lyap_seed_opts& o) {
   LYAP_HIP(hipMemcpyAsync(lv->Fl.p, Flh.data(), lv->Fl.bytes, hipMemcpyHostToDevice, st));
   LYAP_HIP(hipMemcpyAsync(lv->Lz.p, Lzh.data(), lv->Lz.bytes, hipMemcpyHostToDevice, st));
   LYAP_HIP(hipStreamSynchronize(st));
+  ek_build_ops(ek, lv.get(), Flh, Zh, Lzh);
   return lv.release();
 }
 
@@ -523,6 +673,28 @@ void ek_delta_impl(lyap_ek_s* ek, EkLevel* lv, int64_t P, const double* d_dev, c
                    double* delta_dev, double* nrm_dev) {
   const long r = ek->r, N = lv->dim, ld = lv->proj->ld;
   hipStream_t st = ek->st;
+  if (lv->ops) {
+    const long rN = r * N, rNp = lv->rNp, cols = lv->colsK;
+    const size_t wb = (size_t)P * rNp * sizeof(double);
+    if (ek->Wp.bytes < wb) ek->Wp.alloc(wb);
+    if (ek->Gs.bytes < wb) ek->Gs.alloc(wb);
+    const size_t lb = (size_t)P * cols * sizeof(double);
+    if (ek->Xs.bytes < lb) ek->Xs.alloc(lb);
+    LYAP_HIP(hipMemsetAsync(ek->Wp.p, 0, wb, st));
+    const int ub = (int)std::min<long>((rN + 255) / 256, 64);
+    hipLaunchKernelGGL(k_pad_rows_ek, dim3(ub, (unsigned)P), dim3(256), 0, st, ek->Wp.as<double>(),
+                       rNp, W_dev, rN, (int)rN);
+    LYAP_HIP(hipGetLastError());
+    gemm64_rm(ek->Wp.as<double>(), rNp, lv->KT.as<double>(), cols, ek->Xs.as<double>(), cols,
+              (long)P, cols, rNp, cols, st);
+    gemm64_rm(ek->Wp.as<double>(), rNp, lv->Mq.as<double>(), rNp, ek->Gs.as<double>(), rNp, (long)P,
+              rNp, rNp, rNp, st);
+    hipLaunchKernelGGL(k_ek_delta_ops, dim3((unsigned)P), dim3(NT), 0, st, ek->Xs.as<double>(), cols,
+                       cols, ek->Wp.as<double>(), ek->Gs.as<double>(), rNp, (int)rN, d_dev, (int)r,
+                       ek->cstd.as<double>(), delta_dev, nrm_dev);
+    LYAP_HIP(hipGetLastError());
+    return;
+  }
   for (int64_t p0 = 0; p0 < P; p0 += kDeltaChunk) {
     const int cnt = (int)std::min<int64_t>(kDeltaChunk, P - p0);
     const size_t rowsb = (size_t)cnt * r * ld * sizeof(double);

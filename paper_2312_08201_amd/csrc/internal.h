@@ -110,10 +110,12 @@ void engine_batch_run(lyap_engine_s* E, long long P, const double* d_dev, double
 
 // ---- Schur basis (schur.hip) ----
 // T Xs + Xs T^T = C per problem; C dense (Cd, row-major) or F G^T + G F^T
-// (F: k shared rows, G: k rows per problem).  X stored column by column.
+// (F: k rows, shared or fstride apart per problem; G: k rows per problem).
+// X stored column by column.
 void trilyap_launch(const double* T, const double* Tt, double* X, long xstride, const double* Cd,
                     long cstride, const double* F, const double* G, long gstride, int k, int n,
-                    int ld, int count, const int* list, const int* count_dev, hipStream_t st);
+                    int ld, int count, const int* list, const int* count_dev, hipStream_t st,
+                    long fstride = 0);
 // out_p[a] = sum_m Vt[a][m] X_p[m][:]
 void project_launch(const double* Vt, const double* X, long xstride, double* out, long ostride,
                     int r, int n, int ld, int count, const int* list, const int* count_dev,

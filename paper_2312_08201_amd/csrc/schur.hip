@@ -57,7 +57,8 @@ struct TriArgs {
   long xstride;       // elements between problems in X
   const double* Cd;   // dense right-hand side per problem (row-major, symmetric) or null
   long cstride;
-  const double* F;    // low-rank factors: k rows of length ld (shared)
+  const double* F;    // low-rank factors: k rows of length ld (shared when fstride == 0)
+  long fstride;
   const double* G;    // k rows of length ld per problem
   long gstride;
   int k;
@@ -67,8 +68,8 @@ struct TriArgs {
 };
 
 // rhs_c[i] = C[c][i] - sum_{l > j} T[c][l] X[l][i]    (C[c][i] = C[i][c])
-__device__ inline void form_rhs(const TriArgs& A, const double* Cd, const double* Gs, const double* Xp,
-                                int c, int j, double* out) {
+__device__ inline void form_rhs(const TriArgs& A, const double* Cd, const double* Fs,
+                                const double* Gs, const double* Xp, int c, int j, double* out) {
   const int n = A.n, ld = A.ld;
   const double* Trow = A.T + (long)c * ld;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -78,7 +79,7 @@ __device__ inline void form_rhs(const TriArgs& A, const double* Cd, const double
     } else {
       v = 0.0;
       for (int b = 0; b < A.k; ++b) {
-        const double* Fb = A.F + (long)b * ld;
+        const double* Fb = Fs + (long)b * ld;
         const double* Gb = Gs + (long)b * ld;
         v += Fb[c] * Gb[i] + Gb[c] * Fb[i];
       }
@@ -100,6 +101,7 @@ __global__ void __launch_bounds__(ST) k_trilyap(TriArgs A) {
   double* Xp = A.X + (long)slot * A.xstride;
   const double* Cd = A.Cd ? A.Cd + (long)slot * A.cstride : nullptr;
   const double* Gs = A.G ? A.G + (long)slot * A.gstride : nullptr;
+  const double* Fs = A.F ? A.F + (long)slot * A.fstride : nullptr;
   const double* T = A.T;
   const double* Tt = A.Tt;
 
@@ -107,7 +109,7 @@ __global__ void __launch_bounds__(ST) k_trilyap(TriArgs A) {
   while (j >= 0) {
     const bool pair = j > 0 && T[(long)j * ld + j - 1] != 0.0;
     if (!pair) {
-      form_rhs(A, Cd, Gs, Xp, j, j, b0);
+      form_rhs(A, Cd, Fs, Gs, Xp, j, j, b0);
       __syncthreads();
       const double sg = T[(long)j * ld + j];
       // (T + sg I) x = b0, back-substitution over row blocks
@@ -154,8 +156,8 @@ __global__ void __launch_bounds__(ST) k_trilyap(TriArgs A) {
       j -= 1;
     } else {
       // columns j-1, j coupled by S = T[j-1:j+1, j-1:j+1]:  T X2 + X2 S^T = B2
-      form_rhs(A, Cd, Gs, Xp, j - 1, j, b0);
-      form_rhs(A, Cd, Gs, Xp, j, j, b1);
+      form_rhs(A, Cd, Fs, Gs, Xp, j - 1, j, b0);
+      form_rhs(A, Cd, Fs, Gs, Xp, j, j, b1);
       __syncthreads();
       const double s00 = T[(long)(j - 1) * ld + j - 1], s01 = T[(long)(j - 1) * ld + j];
       const double s10 = T[(long)j * ld + j - 1], s11 = T[(long)j * ld + j];
@@ -256,8 +258,9 @@ __global__ void k_project(const double* __restrict__ Vt, const double* __restric
 
 void trilyap_launch(const double* T, const double* Tt, double* X, long xstride, const double* Cd,
                     long cstride, const double* F, const double* G, long gstride, int k, int n,
-                    int ld, int count, const int* list, const int* count_dev, hipStream_t st) {
-  TriArgs A{T, Tt, X, xstride, Cd, cstride, F, G, gstride, k, n, ld, list, count_dev};
+                    int ld, int count, const int* list, const int* count_dev, hipStream_t st,
+                    long fstride) {
+  TriArgs A{T, Tt, X, xstride, Cd, cstride, F, fstride, G, gstride, k, n, ld, list, count_dev};
   const size_t lds = 2 * (size_t)ld * sizeof(double);
   LYAP_REQUIRE(lds <= 64 * 1024, LYAP_E_INVAL, "Schur-basis solve limited to n <= 4096");
   hipLaunchKernelGGL(k_trilyap, dim3(count), dim3(ST), lds, st, A);

@@ -187,6 +187,18 @@ lyap_status smw_solve_batch(lyap_seed seed, int64_t P, const double* d_dev,
 lyap_status trace_EX(lyap_seed seed, int64_t P, const double* Y_dev, double* trace_dev,
                      void* hip_stream);
 
+/* Full solutions for functionals other than the trace (eq:Xsmalllastline in
+ * explicit form, O(n^3) per parameter): for each b < P,
+ *     X_b = X0 + L^-1(U Y_b + Y_b^T U^T),  i.e.  A0 X_b + X_b A0^T = -B B^T + U Y_b + Y_b^T U^T,
+ * with Y_b = Y_dev + b*r*n from smw_solve_batch (so X_b = X(p_b)).  Y_dev = NULL
+ * with P = 1 returns X0.  X_dev: device P x n x n row-major (symmetric).
+ * Eigen basis: block-diagonal real Lyapunov solve in the eigenbasis, then two
+ * MFMA GEMMs; Schur basis: batched quasi-triangular solve, then the same GEMMs.
+ * Work buffers of up to 3 GiB are allocated per call.  LYAP_E_UNSUPPORTED for
+ * projected seeds (they hold no B). */
+lyap_status seed_full_X(lyap_seed seed, int64_t P, const double* Y_dev, double* X_dev,
+                        void* hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* Continuous-batching engine (one seed, a fixed number of slots).            */
 /* smw_solve_batch runs on an engine; a serving loop drives engines directly. */

@@ -42,6 +42,8 @@ struct lyap_seed_s {
   lyap::DevBuf gam;     // r x ld: trace(E X) = t0 + sum_b <gam_b, rho(Yhat_b)>
   lyap::DevBuf Gam;     // r x ld: physical Gamma^T (trace = t0 + 2 <Gamma^T, Y>)
   lyap::DevBuf T, Tt;   // Schur basis only: quasi-triangular T and T^T (ld x ld)
+  lyap::DevBuf Bh;      // s x ld: B^T Tin (full solutions only)
+  bool projected = false;  // right-hand side given through V^T X0 (no B)
   // rank-pbar TSVD of the dense coupling (preconditioner of eq:prec), r*ld x 128
   int pbar = 0;
   double tsvd_sigma_ratio = 0;  // sigma_(pbar+1) / sigma_1 of the coupling
@@ -64,7 +66,7 @@ struct lyap_seed_s {
 
   size_t device_bytes() const {
     return lam.bytes + Mc.bytes + Mc32.bytes + Mcb.bytes + Tin.bytes + Tout.bytes + Uh.bytes +
-           Vh.bytes + K1.bytes + c0.bytes + gam.bytes + Gam.bytes + T.bytes + Tt.bytes +
+           Vh.bytes + K1.bytes + c0.bytes + gam.bytes + Gam.bytes + T.bytes + Tt.bytes + Bh.bytes +
            TsM.bytes + TsN.bytes + TsNt.bytes + scratch.bytes + sol_buf.bytes +
            (eng_cache && eng_cache_bytes ? eng_cache_bytes(eng_cache) : 0);
   }

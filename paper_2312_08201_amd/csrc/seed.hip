@@ -467,6 +467,7 @@ static void apply_projected_rhs(lyap_seed_s* sd, const ProjRhs* proj, hipStream_
             st);
   LYAP_HIP(hipStreamSynchronize(st));
   sd->t0 = proj->t0;
+  sd->projected = true;
 }
 
 static lyap_seed_s* factor_schur(int64_t n, int64_t r, int64_t s, const double* A0, const double* U,
@@ -562,6 +563,9 @@ static lyap_seed_s* factor_schur(int64_t n, int64_t r, int64_t s, const double* 
   gemm64(Utd.as<double>(), ld, sd->Tin.as<double>(), ld, sd->Uh.as<double>(), ld, r, ld, ld, n, st);
   gemm64(Vtd.as<double>(), ld, sd->Tin.as<double>(), ld, sd->Vh.as<double>(), ld, r, ld, ld, n, st);
   gemm64(Btd.as<double>(), ld, sd->Tin.as<double>(), ld, Bh.as<double>(), ld, s, ld, ld, n, st);
+  // kept for full solutions: rows of B^T Tin (rho(Q0^-1 B)^T, or B^T Z in the Schur basis)
+  sd->Bh.alloc(Bh.bytes);
+  LYAP_HIP(hipMemcpyAsync(sd->Bh.p, Bh.p, Bh.bytes, hipMemcpyDeviceToDevice, st));
   // -Bs/2 for the factored right-hand side -Bs Bs^T = Bs (-Bs/2)^T + (-Bs/2) Bs^T
   {
     std::vector<double> tmp((size_t)s * ld);
@@ -851,6 +855,9 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
   gemm64(Utd.as<double>(), ld, sd->Tin.as<double>(), ld, sd->Uh.as<double>(), ld, r, ld, ld, n, st);
   gemm64(Vtd.as<double>(), ld, Sd.as<double>(), ld, sd->Vh.as<double>(), ld, r, ld, ld, n, st);
   gemm64(Btd.as<double>(), ld, sd->Tin.as<double>(), ld, Bh.as<double>(), ld, s, ld, ld, n, st);
+  // kept for full solutions: rows of B^T Tin (rho(Q0^-1 B)^T, or B^T Z in the Schur basis)
+  sd->Bh.alloc(Bh.bytes);
+  LYAP_HIP(hipMemcpyAsync(sd->Bh.p, Bh.p, Bh.bytes, hipMemcpyDeviceToDevice, st));
 
   // ---- K1 = the exact block-diagonal part of the capacitance operator ----
   zeros(sd->K1, r * r);

@@ -92,7 +92,7 @@ EXPORTS = ["seed_factor", "seed_info", "seed_release", "seed_device_bytes", "lya
            "smw_workspace_bytes", "smw_solve_batch", "trace_EX", "engine_create",
            "engine_device_bytes", "engine_destroy", "engine_submit", "engine_run",
            "engine_harvest", "engine_launch", "engine_status", "lyap_status_string", "lyap_last_error", "lyap_profile_enable",
-           "lyap_profile_read", "lyap_calib_copy", "lyap_real_schur", "seed_x0v", "ek_create",
+           "lyap_profile_read", "lyap_calib_copy", "lyap_real_schur", "seed_full_X", "seed_x0v", "ek_create",
            "ek_set_level", "ek_solve", "ek_sweep", "ek_info", "ek_release"]
 
 
@@ -137,6 +137,7 @@ def load(path: str = LIB_PATH):
     lib.lyap_real_schur.argtypes = [i64, vp, vp, vp]
     lib.lyap_real_schur.restype = C.c_int
     lib.seed_x0v.argtypes = [vp, vp]
+    lib.seed_full_X.argtypes = [vp, i64, vp, vp, vp]
     lib.ek_create.argtypes = [i64, i64, vp, vp, vp, vp, C.c_double, vp, i32, vp, C.POINTER(vp)]
     lib.ek_set_level.argtypes = [vp, i32, C.POINTER(SeedOpts)]
     lib.ek_solve.argtypes = [vp, i64, vp, C.POINTER(SolveOpts), vp, vp, vp, C.POINTER(Result)]
@@ -149,7 +150,7 @@ def load(path: str = LIB_PATH):
     for name in ("seed_factor", "seed_info", "seed_release", "lyap_seed_apply", "smw_solve_batch",
                  "trace_EX", "engine_create", "engine_destroy", "engine_submit", "engine_run",
                  "engine_harvest", "engine_launch", "engine_status", "lyap_profile_read",
-                 "lyap_calib_copy", "seed_x0v", "ek_create", "ek_set_level", "ek_solve",
+                 "lyap_calib_copy", "seed_full_X", "seed_x0v", "ek_create", "ek_set_level", "ek_solve",
                  "ek_sweep", "ek_info", "ek_release"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -306,6 +307,20 @@ class Seed:
         _check(st, "smw_solve_batch")
         out = np.frombuffer(bytes(res), dtype=RESULT_DTYPE).copy()
         return Y, out
+
+    def full_X(self, Y=None, stream=None):
+        """X(p) (P x n x n) for the solutions Y of solve(); X0 when Y is None."""
+        torch = _torch()
+        if Y is None:
+            X = torch.empty((1, self.n, self.n), dtype=torch.float64, device="cuda")
+            _check(load().seed_full_X(self.h, 1, None, _dev_ptr(X), _stream(stream)), "seed_full_X")
+            return X
+        P = Y.shape[0]
+        _dev_ptr(Y, shape=(P, self.r, self.n))
+        X = torch.empty((P, self.n, self.n), dtype=torch.float64, device=Y.device)
+        _check(load().seed_full_X(self.h, P, _dev_ptr(Y), _dev_ptr(X), _stream(stream)),
+               "seed_full_X")
+        return X
 
     def trace(self, Y, stream=None):
         torch = _torch()

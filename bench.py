@@ -273,6 +273,35 @@ def ek_bench(args, L, torch, W, seed, pr, factor_s):
     ek.close()
 
 
+def full_x_bench(args, L, torch, seed, pr):
+    """Full solutions X(p) (seed_full_X) for the first K parameters of the
+    sweep.  Algorithmic work: the two basis-transform GEMMs, 4 n^3 flops per
+    parameter (the block-diagonal solve is O(n^2 (s + 2r)))."""
+    K = min(args.full_x, pr.P)
+    d = torch.tensor(pr.d[:K], dtype=torch.float64, device="cuda")
+    Y, res = seed.solve(d, L.solve_opts())
+    seed.full_X(Y)
+    torch.cuda.synchronize()
+    walls = []
+    for _ in range(args.steps):
+        t = time.perf_counter()
+        X = seed.full_X(Y)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t)
+    wall = float(np.median(walls))
+    n = pr.n
+    Et = torch.tensor(pr.E, dtype=torch.float64, device="cuda")
+    tr = torch.stack([(torch.diagonal(X[k]) * Et).sum() if pr.E.ndim == 1
+                      else (Et.T * X[k]).sum() for k in range(K)]).cpu().numpy()
+    print(json.dumps({
+        "full_x": WORKLOAD[args.config], "P": K, "n": n,
+        "ms_per_solution": 1e3 * wall / K, "solutions_per_s": K / wall,
+        "transform_gemm_tflops": 4.0 * n ** 3 * K / wall / 1e12,
+        "fp64_mfma_peak_tflops": 78.6,
+        "max_rel_diff_trace_vs_smw": float(np.max(np.abs(tr - res["trace"]) / np.abs(res["trace"])))}),
+        flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,6 +318,8 @@ def main():
     ap.add_argument("--optimize", action="store_true",
                     help="instead: the viscosity optimisation loop on the workload's seed "
                          "(Nelder-Mead from 100, tol 1e-4), without and with recycling")
+    ap.add_argument("--full-x", type=int, default=0,
+                    help="time full solutions X(p) for this many parameters of the sweep")
     ap.add_argument("--ek", action="store_true",
                     help="projection framework (Algorithm EKSM_opt) vs the exact path")
     ap.add_argument("--ek-eps", type=float, default=1e-10)
@@ -346,6 +377,9 @@ def main():
     seed = L.Seed.from_problem(pr, tsvd_rank=args.tsvd_rank)
     if args.ek:
         ek_bench(args, L, torch, W, seed, pr, time.perf_counter() - t)
+        return
+    if args.full_x:
+        full_x_bench(args, L, torch, seed, pr)
         return
     if args.optimize:
         from paper_2312_08201_amd import optimize as OPT

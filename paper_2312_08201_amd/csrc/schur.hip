@@ -68,6 +68,7 @@ struct TriArgs {
 };
 
 // rhs_c[i] = C[c][i] - sum_{l > j} T[c][l] X[l][i]    (C[c][i] = C[i][c])
+// Four independent partial sums keep several loads of X in flight.
 __device__ inline void form_rhs(const TriArgs& A, const double* Cd, const double* Fs,
                                 const double* Gs, const double* Xp, int c, int j, double* out) {
   const int n = A.n, ld = A.ld;
@@ -84,11 +85,35 @@ __device__ inline void form_rhs(const TriArgs& A, const double* Cd, const double
         v += Fb[c] * Gb[i] + Gb[c] * Fb[i];
       }
     }
-    for (int l = j + 1; l < n; ++l) v -= Trow[l] * Xp[(long)l * ld + i];
-    out[i] = v;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int l = j + 1;
+    for (; l + 3 < n; l += 4) {
+      s0 += Trow[l] * Xp[(long)l * ld + i];
+      s1 += Trow[l + 1] * Xp[(long)(l + 1) * ld + i];
+      s2 += Trow[l + 2] * Xp[(long)(l + 2) * ld + i];
+      s3 += Trow[l + 3] * Xp[(long)(l + 3) * ld + i];
+    }
+    for (; l < n; ++l) s0 += Trow[l] * Xp[(long)l * ld + i];
+    out[i] = v - ((s0 + s1) + (s2 + s3));
   }
 }
 
+// Rows q = threadIdx.x + k ST (k < NK) of column c of T (only q < c is used),
+// read from T^T so that the loads are coalesced.
+template <int NK>
+__device__ inline void load_col(const double* Tt, int ld, int c, double (&dst)[NK]) {
+#pragma unroll
+  for (int k = 0; k < NK; ++k) {
+    const int q = threadIdx.x + k * ST;
+    dst[k] = (c >= 0 && q < c) ? Tt[(long)c * ld + q] : 0.0;
+  }
+}
+
+// One workgroup per problem.  The back-substitution over the rows of a column
+// (or column pair) is sequential; each step needs the column of T above the
+// current row, which is loaded one step ahead into registers (NK per thread)
+// so that its latency overlaps the current step's barrier.
+template <int NK>
 __global__ void __launch_bounds__(ST) k_trilyap(TriArgs A) {
   extern __shared__ double sh[];
   double* b0 = sh;            // rhs of column j-1 (pairs) / j
@@ -104,10 +129,15 @@ __global__ void __launch_bounds__(ST) k_trilyap(TriArgs A) {
   const double* Fs = A.F ? A.F + (long)slot * A.fstride : nullptr;
   const double* T = A.T;
   const double* Tt = A.Tt;
+  const int tid = threadIdx.x;
 
   int j = n - 1;
   while (j >= 0) {
     const bool pair = j > 0 && T[(long)j * ld + j - 1] != 0.0;
+    // columns i and i-1 of T for the first step, prefetched
+    double Pi[NK], Pm[NK];
+    load_col<NK>(Tt, ld, n - 1, Pi);
+    load_col<NK>(Tt, ld, n - 2, Pm);
     if (!pair) {
       form_rhs(A, Cd, Fs, Gs, Xp, j, j, b0);
       __syncthreads();
@@ -117,16 +147,29 @@ __global__ void __launch_bounds__(ST) k_trilyap(TriArgs A) {
       while (i >= 0) {
         const bool rp = i > 0 && T[(long)i * ld + i - 1] != 0.0;
         if (!rp) {
-          if (threadIdx.x == 0) xs[0] = b0[i] / (T[(long)i * ld + i] + sg);
+          double Pn[NK];
+          load_col<NK>(Tt, ld, i - 2, Pn);
+          if (tid == 0) xs[0] = b0[i] / (T[(long)i * ld + i] + sg);
           __syncthreads();
           const double xi = xs[0];
-          const double* tc = Tt + (long)i * ld;  // column i of T
-          for (int q = threadIdx.x; q < i; q += blockDim.x) b0[q] -= tc[q] * xi;
-          if (threadIdx.x == 0) b0[i] = xi;
+#pragma unroll
+          for (int k = 0; k < NK; ++k) {
+            const int q = tid + k * ST;
+            if (q < i) b0[q] -= Pi[k] * xi;
+          }
+          if (tid == 0) b0[i] = xi;
           __syncthreads();
+#pragma unroll
+          for (int k = 0; k < NK; ++k) {
+            Pi[k] = Pm[k];
+            Pm[k] = Pn[k];
+          }
           i -= 1;
         } else {
-          if (threadIdx.x == 0) {
+          double Pn0[NK], Pn1[NK];
+          load_col<NK>(Tt, ld, i - 2, Pn0);
+          load_col<NK>(Tt, ld, i - 3, Pn1);
+          if (tid == 0) {
             double M[16], v[4];
             M[0] = T[(long)(i - 1) * ld + i - 1] + sg;
             M[1] = T[(long)(i - 1) * ld + i];
@@ -140,18 +183,25 @@ __global__ void __launch_bounds__(ST) k_trilyap(TriArgs A) {
           }
           __syncthreads();
           const double x0 = xs[0], x1 = xs[1];
-          const double* tc0 = Tt + (long)(i - 1) * ld;
-          const double* tc1 = Tt + (long)i * ld;
-          for (int q = threadIdx.x; q < i - 1; q += blockDim.x) b0[q] -= tc0[q] * x0 + tc1[q] * x1;
-          if (threadIdx.x == 0) {
+#pragma unroll
+          for (int k = 0; k < NK; ++k) {
+            const int q = tid + k * ST;
+            if (q < i - 1) b0[q] -= Pm[k] * x0 + Pi[k] * x1;
+          }
+          if (tid == 0) {
             b0[i - 1] = x0;
             b0[i] = x1;
           }
           __syncthreads();
+#pragma unroll
+          for (int k = 0; k < NK; ++k) {
+            Pi[k] = Pn0[k];
+            Pm[k] = Pn1[k];
+          }
           i -= 2;
         }
       }
-      for (int q = threadIdx.x; q < n; q += blockDim.x) Xp[(long)j * ld + q] = b0[q];
+      for (int q = tid; q < n; q += blockDim.x) Xp[(long)j * ld + q] = b0[q];
       __syncthreads();
       j -= 1;
     } else {
@@ -165,8 +215,10 @@ __global__ void __launch_bounds__(ST) k_trilyap(TriArgs A) {
       while (i >= 0) {
         const bool rp = i > 0 && T[(long)i * ld + i - 1] != 0.0;
         if (!rp) {
+          double Pn[NK];
+          load_col<NK>(Tt, ld, i - 2, Pn);
           // x (1x2) solves t x + x S^T = b  ->  [[t+s00, s01],[s10, t+s11]] x = b
-          if (threadIdx.x == 0) {
+          if (tid == 0) {
             const double t = T[(long)i * ld + i];
             double M[16], v[4];
             M[0] = t + s00;
@@ -181,20 +233,31 @@ __global__ void __launch_bounds__(ST) k_trilyap(TriArgs A) {
           }
           __syncthreads();
           const double xa = xs[0], xb = xs[1];
-          const double* tc = Tt + (long)i * ld;
-          for (int q = threadIdx.x; q < i; q += blockDim.x) {
-            b0[q] -= tc[q] * xa;
-            b1[q] -= tc[q] * xb;
+#pragma unroll
+          for (int k = 0; k < NK; ++k) {
+            const int q = tid + k * ST;
+            if (q < i) {
+              b0[q] -= Pi[k] * xa;
+              b1[q] -= Pi[k] * xb;
+            }
           }
-          if (threadIdx.x == 0) {
+          if (tid == 0) {
             b0[i] = xa;
             b1[i] = xb;
           }
           __syncthreads();
+#pragma unroll
+          for (int k = 0; k < NK; ++k) {
+            Pi[k] = Pm[k];
+            Pm[k] = Pn[k];
+          }
           i -= 1;
         } else {
+          double Pn0[NK], Pn1[NK];
+          load_col<NK>(Tt, ld, i - 2, Pn0);
+          load_col<NK>(Tt, ld, i - 3, Pn1);
           // 2x2 block of T at rows (i-1, i): (I2 kron T_II + S kron I2) vec(X) = vec(B)
-          if (threadIdx.x == 0) {
+          if (tid == 0) {
             const double t00 = T[(long)(i - 1) * ld + i - 1], t01 = T[(long)(i - 1) * ld + i];
             const double t10 = T[(long)i * ld + i - 1], t11 = T[(long)i * ld + i];
             double M[16] = {t00 + s00, t01, s01, 0.0,  //
@@ -210,23 +273,30 @@ __global__ void __launch_bounds__(ST) k_trilyap(TriArgs A) {
           }
           __syncthreads();
           const double a0 = xs[0], a1 = xs[1], c0 = xs[2], c1 = xs[3];
-          const double* tc0 = Tt + (long)(i - 1) * ld;
-          const double* tc1 = Tt + (long)i * ld;
-          for (int q = threadIdx.x; q < i - 1; q += blockDim.x) {
-            b0[q] -= tc0[q] * a0 + tc1[q] * a1;
-            b1[q] -= tc0[q] * c0 + tc1[q] * c1;
+#pragma unroll
+          for (int k = 0; k < NK; ++k) {
+            const int q = tid + k * ST;
+            if (q < i - 1) {
+              b0[q] -= Pm[k] * a0 + Pi[k] * a1;
+              b1[q] -= Pm[k] * c0 + Pi[k] * c1;
+            }
           }
-          if (threadIdx.x == 0) {
+          if (tid == 0) {
             b0[i - 1] = a0;
             b0[i] = a1;
             b1[i - 1] = c0;
             b1[i] = c1;
           }
           __syncthreads();
+#pragma unroll
+          for (int k = 0; k < NK; ++k) {
+            Pi[k] = Pn0[k];
+            Pm[k] = Pn1[k];
+          }
           i -= 2;
         }
       }
-      for (int q = threadIdx.x; q < n; q += blockDim.x) {
+      for (int q = tid; q < n; q += blockDim.x) {
         Xp[(long)(j - 1) * ld + q] = b0[q];
         Xp[(long)j * ld + q] = b1[q];
       }
@@ -263,7 +333,13 @@ void trilyap_launch(const double* T, const double* Tt, double* X, long xstride, 
   TriArgs A{T, Tt, X, xstride, Cd, cstride, F, fstride, G, gstride, k, n, ld, list, count_dev};
   const size_t lds = 2 * (size_t)ld * sizeof(double);
   LYAP_REQUIRE(lds <= 64 * 1024, LYAP_E_INVAL, "Schur-basis solve limited to n <= 4096");
-  hipLaunchKernelGGL(k_trilyap, dim3(count), dim3(ST), lds, st, A);
+  // rows per thread of a prefetched column: ceil(ld / ST), rounded up to a power of two
+  const int nk = (int)((ld + ST - 1) / ST);
+  if (nk <= 1) hipLaunchKernelGGL(k_trilyap<1>, dim3(count), dim3(ST), lds, st, A);
+  else if (nk <= 2) hipLaunchKernelGGL(k_trilyap<2>, dim3(count), dim3(ST), lds, st, A);
+  else if (nk <= 4) hipLaunchKernelGGL(k_trilyap<4>, dim3(count), dim3(ST), lds, st, A);
+  else if (nk <= 8) hipLaunchKernelGGL(k_trilyap<8>, dim3(count), dim3(ST), lds, st, A);
+  else hipLaunchKernelGGL(k_trilyap<16>, dim3(count), dim3(ST), lds, st, A);
   LYAP_HIP(hipGetLastError());
 }
 

@@ -310,6 +310,8 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_ir", "bf16_ir", "fp32"])
     ap.add_argument("--restart", type=int, default=40)
+    ap.add_argument("--basis", default="auto", choices=["auto", "eig", "schur"],
+                    help="seed basis (auto: eigenbasis unless ill-conditioned)")
     ap.add_argument("--tsvd-rank", type=int, default=0,
                     help="rank of the coupling TSVD in the preconditioner (0: block-diagonal part)")
     ap.add_argument("--recycle-k", type=int, default=0,
@@ -374,7 +376,7 @@ def main():
         # the multi-agent construction of workload 3 at another size
         pr = W.multiagent_problem(args.agents, 6.0, 4, 4, 512, 3, "agents%d" % args.agents)
     t = time.perf_counter()
-    seed = L.Seed.from_problem(pr, tsvd_rank=args.tsvd_rank)
+    seed = L.Seed.from_problem(pr, tsvd_rank=args.tsvd_rank, basis=args.basis)
     if args.ek:
         ek_bench(args, L, torch, W, seed, pr, time.perf_counter() - t)
         return
@@ -452,7 +454,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD[args.config], "P": P, "n": pr.n, "r": pr.r,
                    "precision": args.prec, "restart": args.restart,
-                   "recycle_k": args.recycle_k, "tsvd_rank": args.tsvd_rank},
+                   "recycle_k": args.recycle_k, "tsvd_rank": args.tsvd_rank, "basis": args.basis},
         "p50_ms": 1e3 * float(np.percentile(lat, 50)),
         "p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "all_converged": ok,

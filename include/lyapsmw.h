@@ -81,7 +81,11 @@ typedef struct {
                              completes the preconditioner of eq:prec (Section 2.1); 0 (default)
                              keeps only its exact block-diagonal part; at most 64; eigenbasis
                              seeds only (ignored in the Schur basis) */
-  int32_t reserved;       /* 0 */
+  int32_t schur_dense;    /* Schur basis only: 0 (default) assembles the capacitance operator
+                             as a dense (r ld)^2 matrix when n <= 1024 and r ld <= 8192 (one
+                             GEMM per Krylov step; assembly: r n quasi-triangular solves of
+                             size n); -1 keeps the per-slot quasi-triangular solve in every
+                             step (no (r ld)^2 memory) */
 } lyap_seed_opts;
 
 typedef struct {

@@ -870,6 +870,30 @@ k_epilogue(EngineArgs A, const HT* H, const HT* Hp, int which, int ggrid, int gn
 }
 
 // Schur basis: w = z - D out, out_s[a] = Vs_a^T Xs (projected seed solve)
+// Dense Schur operator: rows of the listed slots' z (r ld values each) into
+// consecutive rows of X, and the GEMM's rows back to the slots' rows of H.
+__global__ void k_gather_z(EngineArgs A, double* __restrict__ X) {
+  const int S = A.S;
+  const int cnt = A.lists[2 * S];
+  const long rl = (long)A.r * A.ld;
+  for (int li = blockIdx.y; li < cnt; li += gridDim.y) {
+    const int s = A.lists[li];
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < rl; e += (long)gridDim.x * blockDim.x)
+      X[(long)li * rl + e] = A.z[(long)s * A.NV + e];
+  }
+}
+
+__global__ void k_scatter_h(EngineArgs A, const double* __restrict__ Hc, double* __restrict__ H) {
+  const int S = A.S;
+  const int cnt = A.lists[2 * S];
+  const long rl = (long)A.r * A.ld;
+  for (int li = blockIdx.y; li < cnt; li += gridDim.y) {
+    const int s = A.lists[li];
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < rl; e += (long)gridDim.x * blockDim.x)
+      H[(long)s * rl + e] = Hc[(long)li * rl + e];
+  }
+}
+
 __global__ void __launch_bounds__(KT) k_epilogue_schur(EngineArgs A, const double* out) {
   const int S = A.S, r = A.r, ld = A.ld;
   const int cnt = A.lists[2 * S];
@@ -1759,7 +1783,7 @@ static EngineSizes engine_sizes(const lyap_seed_s* sd, long long S, const lyap_s
     add(S * m * (m + 1) * 8);          // unrotated Hessenberg
     add(S * (long long)kRecScratch * 8);
   }
-  if (sd->basis == LYAP_BASIS_SCHUR) add(S * ld * ld * 8);  // per-slot Schur-basis solutions
+  if (sd->basis == LYAP_BASIS_SCHUR && !sd->Kd.p) add(S * ld * ld * 8);  // per-slot Schur-basis solutions
   const bool mixed = o.prec != LYAP_PREC_FP64;
   if (mixed) {
     add(z.rows_pad * ld * 4);      // Xlo (float, or two bf16 planes)
@@ -1831,7 +1855,36 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
   }
   const int ublocks = std::max(1, std::min((nu + KT - 1) / KT, 64));
   const int egrid = 2048;  // grid-stride kernels: work proportional to the active count
-  if (sd->basis == LYAP_BASIS_SCHUR) {
+  if (sd->basis == LYAP_BASIS_SCHUR && sd->Kd.p) {
+    // dense capacitance operator: H rows of the listed slots = z rows Kd
+    const long rl = (long)r * ld;
+    const dim3 ggrid((unsigned)std::min<long>((rl + KT - 1) / KT, 16), (unsigned)std::min(S, 1024));
+    if (on(PART_PRE))
+    hipLaunchKernelGGL(k_gather_z, ggrid, dim3(KT), 0, st, A, E->X.as<double>());
+    if (on(PART_G64)) {
+    if (ev) LYAP_HIP(hipEventRecord(ev->g64[0], st));
+    GemmArgs g{};
+    g.type = GemmType::F64;
+    g.A = E->X.p;
+    g.B = sd->Kd.p;
+    g.C = E->Hp.p;
+    g.M = S;
+    g.N = rl;
+    g.K = rl;
+    g.lda = g.ldb = g.ldc = rl;
+    g.Nstore = rl;
+    g.M_dev = E->lists.as<int>() + 2 * S;
+    g.m_scale = 1;
+    gemm_launch(g, st);
+    if (ev) LYAP_HIP(hipEventRecord(ev->g64[1], st));
+    }
+    if (on(PART_MID)) {
+    hipLaunchKernelGGL(k_scatter_h, ggrid, dim3(KT), 0, st, A, E->Hp.as<double>(),
+                       E->H.as<double>());
+    hipLaunchKernelGGL(k_epilogue_schur, dim3(ublocks, S * r), dim3(KT), 0, st, A,
+                       E->H.as<double>());
+    }
+  } else if (sd->basis == LYAP_BASIS_SCHUR) {
     // seed solve in the real Schur basis for every listed slot
     const int n = (int)sd->n;
     const int* cnt = E->lists.as<int>() + 2 * S;
@@ -2296,7 +2349,7 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
     zalloc(E->Hr, S * m * (m + 1) * 8);
     zalloc(E->Fs, S * (long long)kRecScratch * 8);
   }
-  if (sd->basis == LYAP_BASIS_SCHUR) zalloc(E->XS, S * ld * ld * 8);
+  if (sd->basis == LYAP_BASIS_SCHUR && !sd->Kd.p) zalloc(E->XS, S * ld * ld * 8);
   zalloc(E->X, z.rows_pad * ld * 8);
   zalloc(E->H, z.rows_pad * ld * 8);
   zalloc(E->Hp, kPartRowsFactor * z.rows_pad * ld * 8);
@@ -2529,7 +2582,7 @@ static long long engine_harvest_impl(lyap_engine_s* E, long long max_out, long l
 
 
 static long long default_slots(const lyap_seed_s* sd, long long P) {
-  if (sd->basis == LYAP_BASIS_SCHUR) {
+  if (sd->basis == LYAP_BASIS_SCHUR && !sd->Kd.p) {
     // one n x n solution per slot: bound the buffer by 4 GiB
     const long long per = sd->ld * sd->ld * 8;
     const long long S = std::max<long long>(1, std::min<long long>(512, (4LL << 30) / per));

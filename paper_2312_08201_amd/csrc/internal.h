@@ -43,6 +43,7 @@ struct lyap_seed_s {
   lyap::DevBuf Gam;     // r x ld: physical Gamma^T (trace = t0 + 2 <Gamma^T, Y>)
   lyap::DevBuf T, Tt;   // Schur basis only: quasi-triangular T and T^T (ld x ld)
   lyap::DevBuf Bh;      // s x ld: B^T Tin (full solutions only)
+  lyap::DevBuf Kd;      // Schur basis, small n: dense capacitance operator (r ld x r ld)
   bool projected = false;  // right-hand side given through V^T X0 (no B)
   // rank-pbar TSVD of the dense coupling (preconditioner of eq:prec), r*ld x 128
   int pbar = 0;
@@ -66,7 +67,7 @@ struct lyap_seed_s {
 
   size_t device_bytes() const {
     return lam.bytes + Mc.bytes + Mc32.bytes + Mcb.bytes + Tin.bytes + Tout.bytes + Uh.bytes +
-           Vh.bytes + K1.bytes + c0.bytes + gam.bytes + Gam.bytes + T.bytes + Tt.bytes + Bh.bytes +
+           Vh.bytes + K1.bytes + c0.bytes + gam.bytes + Gam.bytes + T.bytes + Tt.bytes + Bh.bytes + Kd.bytes +
            TsM.bytes + TsN.bytes + TsNt.bytes + scratch.bytes + sol_buf.bytes +
            (eng_cache && eng_cache_bytes ? eng_cache_bytes(eng_cache) : 0);
   }
@@ -122,6 +123,8 @@ void trilyap_launch(const double* T, const double* Tt, double* X, long xstride, 
 void project_launch(const double* Vt, const double* X, long xstride, double* out, long ostride,
                     int r, int n, int ld, int count, const int* list, const int* count_dev,
                     hipStream_t st);
+// Dense capacitance operator of a Schur-basis seed (sd->Kd), see schur.hip.
+void schur_dense_operator(lyap_seed_s* sd, hipStream_t st);
 void gemm64_rm(const double* A, long lda, const double* B, long ldb, double* C, long ldc, long M,
                long N, long K, long Nstore, hipStream_t s);
 

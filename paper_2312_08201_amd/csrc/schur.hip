@@ -12,6 +12,9 @@
 // problems of a batch share T.  The right-hand side is dense (Cs given) or
 // low-rank symmetric, Cs = F G^T + G F^T with F, G stored as k rows of
 // length ld, generated on the fly (it is never stored).
+#include <algorithm>
+#include <vector>
+
 #include "internal.h"
 
 namespace lyap {
@@ -341,6 +344,37 @@ void trilyap_launch(const double* T, const double* Tt, double* X, long xstride, 
   else if (nk <= 8) hipLaunchKernelGGL(k_trilyap<8>, dim3(count), dim3(ST), lds, st, A);
   else hipLaunchKernelGGL(k_trilyap<16>, dim3(count), dim3(ST), lds, st, A);
   LYAP_HIP(hipGetLastError());
+}
+
+// Dense capacitance operator of a Schur-basis seed.  The map
+//     Ys -> Vs^T Xs,   T Xs + Xs T^T = Us Ys + Ys^T Us^T   (Ys: r x n)
+// is linear and p-independent.  Row u = b ld + k of Kd (r ld x r ld) is its
+// value on the unit input Ys = e_b e_k^T, from one quasi-triangular solve per
+// unit input in the orthogonal Schur basis; an engine step is then one GEMM
+// z Kd over the active slots.
+void schur_dense_operator(lyap_seed_s* sd, hipStream_t st) {
+  const long n = sd->n, r = sd->r, ld = sd->ld, rl = r * ld;
+  sd->Kd.alloc((size_t)rl * rl * sizeof(double));
+  LYAP_HIP(hipMemsetAsync(sd->Kd.p, 0, sd->Kd.bytes, st));
+  // unit rows e_k (k < n), the per-problem G factors
+  std::vector<double> eye_h((size_t)n * ld, 0.0);
+  for (long k = 0; k < n; ++k) eye_h[(size_t)k * ld + k] = 1.0;
+  DevBuf eye(eye_h.size() * sizeof(double));
+  LYAP_HIP(hipMemcpyAsync(eye.p, eye_h.data(), eye.bytes, hipMemcpyHostToDevice, st));
+  const long per = (long)ld * ld;
+  const long chunk = std::max<long>(1, std::min<long>(n, (long)((size_t(2) << 30) / (per * sizeof(double)))));
+  DevBuf Xb((size_t)chunk * per * sizeof(double));
+  for (long b = 0; b < r; ++b)
+    for (long k0 = 0; k0 < n; k0 += chunk) {
+      const int cnt = (int)std::min(chunk, n - k0);
+      trilyap_launch(sd->T.as<double>(), sd->Tt.as<double>(), Xb.as<double>(), per, nullptr, 0,
+                     sd->Uh.as<double>() + b * ld, eye.as<double>() + k0 * ld, ld, 1, (int)n,
+                     (int)ld, cnt, nullptr, nullptr, st);
+      project_launch(sd->Vh.as<double>(), Xb.as<double>(), per,
+                     sd->Kd.as<double>() + (size_t)(b * ld + k0) * rl, rl, (int)r, (int)n, (int)ld,
+                     cnt, nullptr, nullptr, st);
+    }
+  LYAP_HIP(hipStreamSynchronize(st));
 }
 
 void project_launch(const double* Vt, const double* X, long xstride, double* out, long ostride,

@@ -13,6 +13,11 @@
 
 namespace lyap {
 
+// Schur-basis seeds up to this size get the dense capacitance operator; its
+// assembly is r n quasi-triangular solves of size n.
+constexpr int64_t kDenseSchurMaxN = 1024;
+constexpr int64_t kDenseSchurMaxRl = 8192;
+
 namespace {
 std::mutex g_err_mu;
 std::string g_last_error;
@@ -474,7 +479,7 @@ static lyap_seed_s* factor_schur(int64_t n, int64_t r, int64_t s, const double* 
                                  const double* V, const double* B, const double* E, int E_diag,
                                  double cond, hipStream_t st,
                                  std::chrono::steady_clock::time_point t_start,
-                                 const ProjRhs* proj) {
+                                 const ProjRhs* proj, bool schur_dense) {
   LYAP_REQUIRE(n <= 4096, LYAP_E_UNSUPPORTED, "Schur-basis path limited to n <= 4096");
   const int N = (int)n;
   std::vector<double> Th((size_t)n * n), Zh((size_t)n * n);
@@ -648,6 +653,10 @@ static lyap_seed_s* factor_schur(int64_t n, int64_t r, int64_t s, const double* 
   LYAP_HIP(hipStreamSynchronize(st));
   sd->t0 = t0;
   if (proj) apply_projected_rhs(sd, proj, st);
+  // small seeds: the capacitance operator as one dense matrix (one GEMM per
+  // engine step instead of a quasi-triangular solve per slot)
+  if (schur_dense && n <= kDenseSchurMaxN && r * ld <= kDenseSchurMaxRl)
+    schur_dense_operator(sd, st);
   sd->factor_seconds =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   guard.release();
@@ -666,6 +675,7 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
   const int basis_req = opts ? opts->basis : LYAP_BASIS_AUTO;
   double max_cond = opts && opts->max_eig_cond > 0 ? opts->max_eig_cond : 1e6;
   const int tsvd_rank = opts ? opts->tsvd_rank : 0;
+  const bool schur_dense = !(opts && opts->schur_dense < 0);
   LYAP_REQUIRE(tsvd_rank >= 0 && tsvd_rank <= 64, LYAP_E_INVAL, "tsvd_rank out of [0, 64]");
   LYAP_REQUIRE(basis_req >= 0 && basis_req <= 2, LYAP_E_INVAL, "basis out of range");
   check_finite(A0, (size_t)n * n, "A0");
@@ -674,7 +684,7 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
   check_finite(B, (size_t)n * s, "B");
   check_finite(E, E_diag ? (size_t)n : (size_t)n * n, "E");
   if (basis_req == LYAP_BASIS_SCHUR)
-    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, 0.0, stream, t_start, proj);
+    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, 0.0, stream, t_start, proj, schur_dense);
 
   const LapackFns& L = lapack();
   LYAP_REQUIRE(L.dgeev && L.dgetrf && L.dgetrs, LYAP_E_UNSUPPORTED,
@@ -697,7 +707,7 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
           work.data(), &lwork, &info);
   if (info != 0) {
     LYAP_REQUIRE(basis_req == LYAP_BASIS_AUTO, LYAP_E_UNSTABLE, "dgeev failed to converge");
-    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, INFINITY, stream, t_start, proj);
+    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, INFINITY, stream, t_start, proj, schur_dense);
   }
 
   // order: conjugate pairs first (Re, Im columns), then real eigenvalues
@@ -746,7 +756,7 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
   if (info != 0) {
     LYAP_REQUIRE(basis_req == LYAP_BASIS_AUTO, LYAP_E_UNSTABLE,
                  "eigenvector matrix is singular (defective seed)");
-    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, INFINITY, stream, t_start, proj);
+    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, INFINITY, stream, t_start, proj, schur_dense);
   }
   for (int i = 0; i < N; ++i) Sinv_cm[(size_t)i * n + i] = 1.0;
   L.dgetrs("N", &N, &N, LU.data(), &N, ipiv.data(), Sinv_cm.data(), &N, &info);
@@ -762,7 +772,7 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
   };
   const double cond = norm1(Scm) * norm1(Sinv_cm);
   if (basis_req == LYAP_BASIS_AUTO && !(cond <= max_cond))
-    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, cond, stream, t_start, proj);
+    return factor_schur(n, r, s, A0, U, V, B, E, E_diag, cond, stream, t_start, proj, schur_dense);
 
   auto* sd = new lyap_seed_s();
   std::unique_ptr<lyap_seed_s> guard(sd);

@@ -33,7 +33,7 @@ class LyapError(RuntimeError):
 
 class SeedOpts(C.Structure):
     _fields_ = [("basis", C.c_int32), ("E_is_diag", C.c_int32), ("max_eig_cond", C.c_double),
-                ("tsvd_rank", C.c_int32), ("reserved", C.c_int32)]
+                ("tsvd_rank", C.c_int32), ("schur_dense", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -225,7 +225,7 @@ class Seed:
     """seed_factor: offline stage for one (A0, U, V, B, E)."""
 
     def __init__(self, A0, U, V, B, E, basis="auto", max_eig_cond=0.0, stream=None,
-                 tsvd_rank=0):
+                 tsvd_rank=0, schur_dense=True):
         lib = load()
         _torch()
         A0 = _host(A0)
@@ -242,7 +242,8 @@ class Seed:
         if (diag and E.shape != (n,)) or (not diag and E.shape != (n, n)):
             raise ValueError("E must be (n,) or (n, n)")
         self._keep = (A0, U, V, B, E)
-        opts = SeedOpts(BASIS[basis], diag, float(max_eig_cond), int(tsvd_rank), 0)
+        opts = SeedOpts(BASIS[basis], diag, float(max_eig_cond), int(tsvd_rank),
+                        0 if schur_dense else -1)
         h = C.c_void_p()
         st = lib.seed_factor(n, r, s, A0.ctypes.data, U.ctypes.data, V.ctypes.data, B.ctypes.data,
                              E.ctypes.data, C.byref(opts), _stream(stream), C.byref(h))

@@ -313,6 +313,28 @@ def test_repeated_solves_reuse_engine_identically():
     assert np.max(rel(runs[0][2]["trace"], oracle_traces(pr))) <= 1e-10
 
 
+@pytest.mark.parametrize("maker", [lambda: W.small_chain(30, (7, 22), 3, 6),
+                                   lambda: W.small_multiagent(24, 2, 3, 6)])
+def test_schur_dense_operator_matches_per_slot_solve(maker):
+    """Schur basis: the dense capacitance operator (one GEMM per step) and the
+    per-slot quasi-triangular solve give the same solutions, both at the
+    oracle's values."""
+    L, torch = lib()
+    pr = maker()
+    d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
+    out = {}
+    for dense in (True, False):
+        seed = L.Seed.from_problem(pr, basis="schur", schur_dense=dense)
+        Y, res = seed.solve(d, L.solve_opts())
+        assert np.all(res["status"] == 0)
+        out[dense] = (Y.cpu().numpy(), res["trace"].copy())
+    ref = oracle_traces(pr)
+    for dense in (True, False):
+        assert np.max(rel(out[dense][1], ref)) <= 1e-10, dense
+    Yd, Ys = out[True][0], out[False][0]
+    assert np.linalg.norm(Yd - Ys) <= 1e-11 * np.linalg.norm(Ys)
+
+
 def test_oversized_capacitance_vector_is_an_error_not_an_abort():
     """r * ld above the Krylov kernel's per-slot limit (16384) is reported by
     every entry point that sizes an engine, through the status code."""

@@ -16,15 +16,21 @@
  * seed Lyapunov solve with a low-rank right-hand side, i.e. a Cauchy-matrix
  * contraction in the eigenbasis (eq:Z(v), eq:N2M1).  The capacitance system is
  * solved in its n*r reduced form, unknown Y = D V^T X(p) (r x n), which carries
- * the same unknowns as the paper's 2nk vector w(v) (w1 = w2^T).
+ * the same unknowns as the paper's 2nk vector w(v) (w1 = w2^T).  The seed option
+ * tsvd_rank adds the low-rank part of eq:prec.
+ *
+ * Also here: full solutions X(p) for other functionals (seed_full_X), and the
+ * projection framework of Section 2.2 (ek_*), whose projected equations are
+ * solved by the same engine.
  *
  * Conventions shared by every entry point:
  *  - Host matrices are row-major (C order), float64.
  *  - Device buffers are float64 unless stated, and belong to the caller.
  *  - Calls are ordered on the HIP stream given as `void* hip_stream`
- *    (NULL = the default stream).  seed_factor and smw_solve_batch also
- *    synchronise that stream before they return (they drive the iteration
- *    from the host).  lyap_seed_apply and trace_EX only enqueue work.
+ *    (NULL = the default stream).  seed_factor, smw_solve_batch, seed_full_X
+ *    and the ek_* calls also synchronise that stream before they return (they
+ *    drive the iteration from the host).  lyap_seed_apply and trace_EX only
+ *    enqueue work.
  *  - Argument errors return synchronously, before any launch, with
  *    LYAP_E_INVAL.  No call aborts, throws or exits.
  *  - Per-parameter numerical failures are reported in lyap_result.status;
@@ -158,7 +164,8 @@ size_t seed_device_bytes(lyap_seed seed);
 /*     G_b = V^T X_b,   A0 X_b + X_b A0^T = U Y_b + Y_b^T U^T,                */
 /* written to G_dev + b*r*n.  Transform into the eigenbasis, Cauchy           */
 /* contraction (the division by lambda_i + lambda_j), transform back.          */
-/* prec: LYAP_PREC_FP64 or LYAP_PREC_FP32 (the whole chain in that precision). */
+/* prec: LYAP_PREC_FP64 (other values return LYAP_E_UNSUPPORTED; the engine's   */
+/* mixed-precision modes run inside smw_solve_batch).                         */
 /* ------------------------------------------------------------------------ */
 lyap_status lyap_seed_apply(lyap_seed seed, int64_t batch, const double* Y_dev, double* G_dev,
                             int32_t prec, void* hip_stream);

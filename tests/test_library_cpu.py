@@ -15,7 +15,7 @@ def declared_symbols():
     return sorted(set(n for n in names if n not in ("if", "while")))
 
 
-def test_header_declares_the_north_star_entry_points():
+def test_header_declares_the_boundary_entry_points():
     syms = declared_symbols()
     for s in ("seed_factor", "lyap_seed_apply", "smw_solve_batch", "trace_EX"):
         assert s in syms

@@ -69,3 +69,13 @@ def test_host_real_schur_matches_definition(n, seed):
     ref = np.linalg.eigvals(A)
     key = lambda z: (round(z.real, 8), round(z.imag, 8))
     assert np.allclose(sorted(ev, key=key), sorted(ref, key=key), atol=1e-10)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=60)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr

@@ -302,6 +302,49 @@ def full_x_bench(args, L, torch, seed, pr):
         flush=True)
 
 
+def shifted_bench(args, L, torch, seed, pr):
+    """r = 1: the shifted-family solve (one Arnoldi process for all viscosities)
+    against the batched engine on the same N log-spaced viscosities.  With
+    N = 63 k + 1 the 64-point grid of the workload is a subset, checked against
+    the stored oracle values."""
+    N = args.shifted
+    v = np.logspace(-2, 2, N)
+    _, res = seed.solve_shifted(v, max_steps=1500)          # warm-up
+    torch.cuda.synchronize()
+    walls = []
+    for _ in range(args.steps):
+        t = time.perf_counter()
+        _, res = seed.solve_shifted(v, max_steps=1500)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t)
+    wall = float(np.median(walls))
+    d = torch.tensor(v[:, None], dtype=torch.float64, device="cuda")
+    seed.solve(d)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    Y, rese = seed.solve(d)
+    torch.cuda.synchronize()
+    eng_wall = time.perf_counter() - t
+    max_rel = None
+    gold_path = os.path.join(ROOT, "tests", "golden", "oracle_traces.json")
+    if (N - 1) % 63 == 0 and os.path.exists(gold_path) and not args.chain_dof:
+        step = (N - 1) // 63
+        gold = json.load(open(gold_path)).get("c0")
+        idx = [g["index"] * step for g in gold["samples"]]
+        ref = np.array([g["trace"] for g in gold["samples"]])
+        max_rel = float(np.max(np.abs(res["trace"][idx] - ref) / np.abs(ref)))
+    print(json.dumps({
+        "shifted": WORKLOAD[args.config] if not args.chain_dof else
+        "damped chain n=%d r=1 (damper at the middle DOF), B n x 16" % pr.n,
+        "viscosities": N, "n": pr.n,
+        "evals_per_s": N / wall, "sweep_s": wall, "arnoldi_steps": int(res["iters"].max()),
+        "all_converged": bool(np.all(res["status"] == 0)),
+        "engine_evals_per_s": N / eng_wall, "engine_products_mean": float(rese["iters"].mean()),
+        "speedup_vs_engine": eng_wall / wall,
+        "max_rel_diff_vs_engine": float(np.max(np.abs(res["trace"] - rese["trace"]) / np.abs(rese["trace"]))),
+        "max_rel_err_sampled_vs_oracle": max_rel}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +363,8 @@ def main():
     ap.add_argument("--optimize", action="store_true",
                     help="instead: the viscosity optimisation loop on the workload's seed "
                          "(Nelder-Mead from 100, tol 1e-4), without and with recycling")
+    ap.add_argument("--shifted", type=int, default=0,
+                    help="r = 1 workloads: shifted-family solve over this many log-spaced viscosities")
     ap.add_argument("--full-x", type=int, default=0,
                     help="time full solutions X(p) for this many parameters of the sweep")
     ap.add_argument("--ek", action="store_true",
@@ -327,6 +372,8 @@ def main():
     ap.add_argument("--ek-eps", type=float, default=1e-10)
     ap.add_argument("--ek-mmax", type=int, default=40)
     ap.add_argument("--ek-check-every", type=int, default=1)
+    ap.add_argument("--chain-dof", type=int, default=0,
+                    help="with --shifted: the one-damper chain with this many DOF (n = 2 DOF)")
     ap.add_argument("--agents", type=int, default=0,
                     help="with --ek: the multi-agent workload with this many agents (n = 2N)")
     ap.add_argument("--stream-sweeps", type=int, default=5,
@@ -375,6 +422,10 @@ def main():
     if args.agents:
         # the multi-agent construction of workload 3 at another size
         pr = W.multiagent_problem(args.agents, 6.0, 4, 4, 512, 3, "agents%d" % args.agents)
+    if args.chain_dof:
+        # the chain of workload 0 (one damper, middle DOF) at another size, B n x 16
+        pr = W.chain_problem(args.chain_dof, [args.chain_dof // 2], 1, 16, "logspace", 64, 0,
+                             "chain%d" % (2 * args.chain_dof))
     t = time.perf_counter()
     seed = L.Seed.from_problem(pr, tsvd_rank=args.tsvd_rank, basis=args.basis)
     if args.ek:
@@ -382,6 +433,9 @@ def main():
         return
     if args.full_x:
         full_x_bench(args, L, torch, seed, pr)
+        return
+    if args.shifted:
+        shifted_bench(args, L, torch, seed, pr)
         return
     if args.optimize:
         from paper_2312_08201_amd import optimize as OPT

@@ -192,6 +192,22 @@ lyap_status smw_solve_batch(lyap_seed seed, int64_t P, const double* d_dev,
                             const lyap_solve_opts* opts, double* Y_dev, lyap_result* res_host,
                             void* workspace_dev, size_t workspace_bytes, void* hip_stream);
 
+/* Shifted-family solve for one-column parameters (r = 1 only; not in the
+ * paper).  For d != 0 the capacitance system (I - d K) y = d c0 equals
+ * (sigma I - K) y = c0 with sigma = 1/d, so one Arnoldi process on K started
+ * from c0 serves every parameter (GMRES for each shift, no preconditioner).
+ * Cost: the Arnoldi steps the hardest parameter needs, nearly independent of P.
+ *   d_host : host P doubles (finite; 0 gives y = 0).
+ *   opts   : tol (relative residual, default 1e-12) and max_iter (Arnoldi
+ *            steps, default 600, at most 2048); other fields are ignored.
+ *   Y_dev  : device P x n output or NULL.   res_host: host P results (trace;
+ *            iters = Arnoldi steps shared by all parameters).
+ * LYAP_E_UNSUPPORTED if r != 1; LYAP_E_BREAKDOWN if the Krylov space becomes
+ * invariant before every parameter has converged. */
+lyap_status smw_solve_shifted(lyap_seed seed, int64_t P, const double* d_host,
+                              const lyap_solve_opts* opts, double* Y_dev, lyap_result* res_host,
+                              void* hip_stream);
+
 /* trace(E X(p)) = t0 + 2 <Gamma, Y(p)> with Gamma = G U, A0^T G + G A0 = E
  * (the additive split of f in Section 2.1, collapsed to O(r n) per p).
  * Y_dev: device P x r x n from smw_solve_batch; trace_dev: device P doubles. */

@@ -156,6 +156,13 @@ __global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst,
 }
 
 }  // namespace
+
+// The seed Lyapunov solve with a low-rank right-hand side, FP64, for other
+// parts of the library.
+void seed_apply64(lyap_seed_s* sd, long long batch, const double* Y, double* G, hipStream_t st) {
+  apply_impl(sd, batch, Y, G, LYAP_PREC_FP64, st);
+}
+
 }  // namespace lyap
 
 using namespace lyap;

@@ -435,7 +435,13 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
   }
   const double bn = sqrt(block_sum1(acc, lds));
   if (bn == 0.0) {
-    // D = 0: y = 0 is exact, X(p) = X0
+    // D = 0: y = 0 is exact, X(p) = X0; the solution store gets the zero y
+    const long long tag0 = A.qtag[qi];
+    if (A.sol && tag0 >= 0 && tag0 < A.sol_cap) {
+      double* dst = A.sol + tag0 * (long long)N;
+      for (int e = threadIdx.x; e < N; e += blockDim.x) dst[e] = 0.0;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
       DevResult& o = A.res[qi];
       o.status = LYAP_OK;

@@ -342,6 +342,37 @@ gemm_bf16x3_kernel(const __bf16* __restrict__ A, long a_plane, const __bf16* __r
 
 }  // namespace
 
+// Few-row FP64 products (static M <= 8): C[m][c] = sum_k A[m][k] B[k][c] for
+// c < Nstore.  One workgroup per 64 output columns and row m; its four
+// wavefronts split K and combine through LDS.  Lanes own columns, so every
+// load of B is coalesced; the tiled kernel would run a handful of workgroups
+// through the whole K loop here.
+constexpr int kRowsMax = 8;
+__global__ void __launch_bounds__(256) k_gemm_rows64(const double* __restrict__ A, long lda,
+                                                     const double* __restrict__ B, long ldb,
+                                                     double* __restrict__ C, long ldc, int K,
+                                                     int Nstore) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = blockIdx.x * 64 + lane;
+  const double* a = A + (long)blockIdx.y * lda;
+  const int kc = (K + 3) / 4;
+  const int k0 = wave * kc, k1 = min(K, k0 + kc);
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  int k = k0;
+  for (; k + 3 < k1; k += 4) {
+    acc0 += a[k] * B[(long)k * ldb + col];
+    acc1 += a[k + 1] * B[(long)(k + 1) * ldb + col];
+    acc2 += a[k + 2] * B[(long)(k + 2) * ldb + col];
+    acc3 += a[k + 3] * B[(long)(k + 3) * ldb + col];
+  }
+  for (; k < k1; ++k) acc0 += a[k] * B[(long)k * ldb + col];
+  __shared__ double part[4][64];
+  part[wave][lane] = (acc0 + acc1) + (acc2 + acc3);
+  __syncthreads();
+  if (wave == 0 && col < Nstore)
+    C[(long)blockIdx.y * ldc + col] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+}
+
 void gemm_launch(const GemmArgs& g, hipStream_t s) {
   LYAP_REQUIRE(g.N % BN == 0, LYAP_E_INVAL, "gemm: N not padded");
   LYAP_REQUIRE(g.M >= 1, LYAP_E_INVAL, "gemm: M < 1");
@@ -358,6 +389,12 @@ void gemm_launch(const GemmArgs& g, hipStream_t s) {
     case GemmType::F64: {
       const int bk = gemm_bk_of(g);
       LYAP_REQUIRE(g.K % bk == 0, LYAP_E_INVAL, "gemm: K not padded");
+      if (g.M <= kRowsMax && !g.M_dev && !g.Cpart && !g.tuning) {
+        hipLaunchKernelGGL(k_gemm_rows64, dim3((unsigned)(g.N / 64), (unsigned)g.M), dim3(256), 0, s,
+                           (const double*)g.A, (long)g.lda, (const double*)g.B, (long)g.ldb,
+                           (double*)g.C, (long)g.ldc, (int)g.K, (int)g.Nstore);
+        break;
+      }
       auto kern = g.tuning ? (bk == 8 ? gemm_kernel<double, 8, true> : gemm_kernel<double, 16, true>)
                            : (bk == 8 ? gemm_kernel<double, 8> : gemm_kernel<double, 16>);
       hipLaunchKernelGGL(kern, grid, block, 0, s, (const double*)g.A, (const double*)g.B,

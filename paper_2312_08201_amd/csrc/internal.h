@@ -100,6 +100,9 @@ lyap_seed_s* factor_projected(int64_t n, int64_t r, const double* A0, const doub
                               const double* V, const double* E, const ProjRhs& proj,
                               const lyap_seed_opts* opts, hipStream_t stream);
 
+// ---- the seed apply (apply.hip): G = V^T X, A0 X + X A0^T = U Y + Y^T U^T, FP64 ----
+void seed_apply64(lyap_seed_s* sd, long long batch, const double* Y, double* G, hipStream_t st);
+
 // ---- engines owned inside the library (engine.hip) ----
 // An engine with queue and solution store for up to P_cap parameters; batches
 // of any size up to that run on it after a reset (see smw_solve_batch).

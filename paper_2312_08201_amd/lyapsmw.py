@@ -92,7 +92,8 @@ EXPORTS = ["seed_factor", "seed_info", "seed_release", "seed_device_bytes", "lya
            "smw_workspace_bytes", "smw_solve_batch", "trace_EX", "engine_create",
            "engine_device_bytes", "engine_destroy", "engine_submit", "engine_run",
            "engine_harvest", "engine_launch", "engine_status", "lyap_status_string", "lyap_last_error", "lyap_profile_enable",
-           "lyap_profile_read", "lyap_calib_copy", "lyap_real_schur", "seed_full_X", "seed_x0v", "ek_create",
+           "lyap_profile_read", "lyap_calib_copy", "lyap_real_schur", "seed_full_X", "smw_solve_shifted",
+           "seed_x0v", "ek_create",
            "ek_set_level", "ek_solve", "ek_sweep", "ek_info", "ek_release"]
 
 
@@ -138,6 +139,7 @@ def load(path: str = LIB_PATH):
     lib.lyap_real_schur.restype = C.c_int
     lib.seed_x0v.argtypes = [vp, vp]
     lib.seed_full_X.argtypes = [vp, i64, vp, vp, vp]
+    lib.smw_solve_shifted.argtypes = [vp, i64, vp, C.POINTER(SolveOpts), vp, C.POINTER(Result), vp]
     lib.ek_create.argtypes = [i64, i64, vp, vp, vp, vp, C.c_double, vp, i32, vp, C.POINTER(vp)]
     lib.ek_set_level.argtypes = [vp, i32, C.POINTER(SeedOpts)]
     lib.ek_solve.argtypes = [vp, i64, vp, C.POINTER(SolveOpts), vp, vp, vp, C.POINTER(Result)]
@@ -150,7 +152,7 @@ def load(path: str = LIB_PATH):
     for name in ("seed_factor", "seed_info", "seed_release", "lyap_seed_apply", "smw_solve_batch",
                  "trace_EX", "engine_create", "engine_destroy", "engine_submit", "engine_run",
                  "engine_harvest", "engine_launch", "engine_status", "lyap_profile_read",
-                 "lyap_calib_copy", "seed_full_X", "seed_x0v", "ek_create", "ek_set_level", "ek_solve",
+                 "lyap_calib_copy", "seed_full_X", "smw_solve_shifted", "seed_x0v", "ek_create", "ek_set_level", "ek_solve",
                  "ek_sweep", "ek_info", "ek_release"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -308,6 +310,20 @@ class Seed:
         _check(st, "smw_solve_batch")
         out = np.frombuffer(bytes(res), dtype=RESULT_DTYPE).copy()
         return Y, out
+
+    def solve_shifted(self, d, tol=1e-12, max_steps=600, want_Y=False, stream=None):
+        """r = 1: one Arnoldi process for all parameters (host d, length P).
+        Returns (Y or None, results)."""
+        torch = _torch()
+        d = _host(np.ravel(d))
+        P = d.shape[0]
+        Y = torch.empty((P, self.n), dtype=torch.float64, device="cuda") if want_Y else None
+        opts = solve_opts(tol=tol, max_iter=max_steps)
+        res = (Result * P)()
+        st = load().smw_solve_shifted(self.h, P, d.ctypes.data, C.byref(opts),
+                                      _dev_ptr(Y) if want_Y else None, res, _stream(stream))
+        _check(st, "smw_solve_shifted")
+        return Y, np.frombuffer(bytes(res), dtype=RESULT_DTYPE).copy()
 
     def full_X(self, Y=None, stream=None):
         """X(p) (P x n x n) for the solutions Y of solve(); X0 when Y is None."""

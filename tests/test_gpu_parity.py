@@ -152,6 +152,11 @@ def test_edge_cases():
     pr2 = W.Problem(pr.name, pr.A0, pr.U, pr.V, pr.B, pr.E, d)
     seed, Y, res, tr = run(pr2)
     assert res["status"][2] == 8  # LYAP_E_NONFINITE
+    # D = 0 gives Y(p) = 0 even when the solution store held an earlier solve's values
+    dd = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
+    seed.solve(dd)
+    Y2, _ = seed.solve(torch.tensor(np.nan_to_num(d), dtype=torch.float64, device="cuda"))
+    assert float(Y2[1].abs().max()) == 0.0
     ok = [0, 1, 3]
     assert np.all(res["status"][ok] == 0)
     ref = oracle_traces(pr2, ok)

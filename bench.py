@@ -226,8 +226,18 @@ def ek_bench(args, L, torch, W, seed, pr, factor_s):
         print("ek sweep %d: %.3f s" % (it, dt), file=sys.stderr, flush=True)
         if it >= args.warmup:
             walls.append(dt)
+    # continued sweeps: each starts at the level the previous one ended on (the
+    # algorithm's use inside optimisation loops keeps and extends its space)
+    walls_c = []
+    start = int(out["level"].max())
+    for it in range(args.steps):
+        t = time.perf_counter()
+        outc = ek.sweep(pr.d, eps=args.ek_eps, m_max=args.ek_mmax, check_every=args.ek_check_every,
+                        m_start=start)
+        torch.cuda.synchronize()
+        walls_c.append(time.perf_counter() - t)
     info = ek.info()
-    sweeps = args.warmup + args.steps
+    sweeps = args.warmup + 2 * args.steps
     # exact path on the same parameters
     d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
     opts = L.solve_opts()
@@ -256,6 +266,8 @@ def ek_bench(args, L, torch, W, seed, pr, factor_s):
         "P": pr.P, "n": pr.n, "r": pr.r,
         "eps": args.ek_eps, "m_max": args.ek_mmax, "check_every": args.ek_check_every,
         "evals_per_s": pr.P / wall, "sweep_s_median": wall, "create_s": create_s,
+        "continued_from_level": start, "continued_evals_per_s": pr.P / float(np.median(walls_c)),
+        "continued_all_accepted": bool(np.all(outc["status"] == 0)),
         "all_accepted": bool(np.all(out["status"] == 0)),
         "levels": {int(k): int(v) for k, v in zip(levels, counts)},
         "dim_mean": float(out["dim"].mean()), "dim_max": int(out["dim"].max()),
@@ -268,6 +280,7 @@ def ek_bench(args, L, torch, W, seed, pr, factor_s):
         "seed_factor_s": factor_s,
         "max_rel_err_sampled_vs_oracle": max_rel,
         "max_rel_diff_vs_exact_smw": float(np.max(np.abs(out["trace"] - exact) / np.abs(exact))),
+        "continued_max_rel_diff_vs_exact_smw": float(np.max(np.abs(outc["trace"] - exact) / np.abs(exact))),
         "smw_exact_evals_per_s": pr.P / smw_wall,
         "speedup_vs_smw": smw_wall / wall}), flush=True)
     ek.close()

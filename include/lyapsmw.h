@@ -336,16 +336,18 @@ lyap_status ek_set_level(lyap_ek ek, int32_t m, const lyap_seed_opts* proj_opts)
 lyap_status ek_solve(lyap_ek ek, int64_t P, const double* d_dev, const lyap_solve_opts* opts,
                      double* W_dev, double* delta_dev, double* norms_dev, lyap_result* res_host);
 
-/* Algorithm EKSM_opt for P parameters (host d, P x r), levels 1, 1 + check_every,
- * ... up to m_max.  Parameters are tested in order; the first whose backward
+/* Algorithm EKSM_opt for P parameters (host d, P x r), levels m_start,
+ * m_start + check_every, ... up to m_max (the algorithm starts at m_start = 1;
+ * a later sweep on the same space may continue from the level an earlier one
+ * reached, as in the algorithm's use inside optimisation loops).  Parameters are tested in order; the first whose backward
  * error exceeds eps (or whose projected solve fails) moves it and all after it
  * to the next level.  The queue head is solved in batches of 1, 4, 16, ...
  * parameters, keeping the accepted prefix of each batch, which reproduces the
  * sequential loop's decisions.  Levels (projected seeds, engines) are kept in
  * the handle and reused by later sweeps.  out: host P results. */
 lyap_status ek_sweep(lyap_ek ek, int64_t P, const double* d_host, const lyap_solve_opts* opts,
-                     const lyap_seed_opts* proj_opts, double eps, int32_t m_max,
-                     int32_t check_every, lyap_ek_result* out);
+                     const lyap_seed_opts* proj_opts, double eps, int32_t m_start,
+                     int32_t m_max, int32_t check_every, lyap_ek_result* out);
 
 lyap_status ek_info(lyap_ek ek, lyap_ek_info* out);
 lyap_status ek_release(lyap_ek ek);

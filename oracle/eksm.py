@@ -152,8 +152,8 @@ class EKResult:
     t0: float
 
 
-def eksm_trace(A0, U, V, B, E, d_all, eps, m_max, check_every=1) -> EKResult:
-    """Algorithm EKSM_opt with f = trace(E X)."""
+def eksm_trace(A0, U, V, B, E, d_all, eps, m_max, check_every=1, m_start=1) -> EKResult:
+    """Algorithm EKSM_opt with f = trace(E X), levels from m_start (1 in the algorithm)."""
     d_all = np.atleast_2d(np.asarray(d_all, dtype=np.float64))
     Pn = d_all.shape[0]
     X0 = seed_solution(A0, B)
@@ -165,7 +165,7 @@ def eksm_trace(A0, U, V, B, E, d_all, eps, m_max, check_every=1) -> EKResult:
     dim = np.zeros(Pn, dtype=np.int64)
     delta = np.full(Pn, np.nan)
     accepted = np.zeros(Pn, dtype=bool)
-    pos, m = 0, 1
+    pos, m = 0, m_start
     while pos < Pn and m <= m_max:
         while len(sp.blocks) < m + 1:      # the Proposition needs block m+1
             if not sp.expand():

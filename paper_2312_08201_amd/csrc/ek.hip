@@ -752,8 +752,8 @@ void ek_solve_level(lyap_ek_s* ek, EkLevel* lv, int64_t P, const double* d_dev,
 // (1, 4, 16, ...) and restart at one on a new level, so the accepted prefix is
 // the one the sequential loop finds while the solves stay batched.
 void ek_sweep_impl(lyap_ek_s* ek, int64_t P, const double* d_host, const lyap_solve_opts* opts,
-                   const lyap_seed_opts* popts, double eps, int m_max, int check_every,
-                   lyap_ek_result* out) {
+                   const lyap_seed_opts* popts, double eps, int m_start, int m_max,
+                   int check_every, lyap_ek_result* out) {
   const long r = ek->r;
   for (int64_t i = 0; i < P * r; ++i)
     LYAP_REQUIRE(std::isfinite(d_host[i]), LYAP_E_INVAL, "non-finite parameter");
@@ -765,7 +765,7 @@ void ek_sweep_impl(lyap_ek_s* ek, int64_t P, const double* d_host, const lyap_so
   std::vector<double> delta;
   std::vector<lyap_result> res;
   int64_t pos = 0, chunk = 1;
-  int m = 1;
+  int m = m_start;
   while (pos < P && m <= m_max) {
     EkLevel* lv = ek_level(ek, m, popts);
     const int64_t cnt = std::min<int64_t>(chunk, P - pos);
@@ -860,11 +860,12 @@ lyap_status ek_solve(lyap_ek ek, int64_t P, const double* d_dev, const lyap_solv
 }
 
 lyap_status ek_sweep(lyap_ek ek, int64_t P, const double* d_host, const lyap_solve_opts* opts,
-                     const lyap_seed_opts* proj_opts, double eps, int32_t m_max,
-                     int32_t check_every, lyap_ek_result* out) {
-  if (!ek || P < 1 || !d_host || !out || !(eps > 0) || m_max < 1 || check_every < 1)
+                     const lyap_seed_opts* proj_opts, double eps, int32_t m_start,
+                     int32_t m_max, int32_t check_every, lyap_ek_result* out) {
+  if (!ek || P < 1 || !d_host || !out || !(eps > 0) || m_start < 1 || m_max < m_start ||
+      check_every < 1)
     return LYAP_E_INVAL;
-  LYAP_TRY(ek_sweep_impl(ek, P, d_host, opts, proj_opts, eps, m_max, check_every, out));
+  LYAP_TRY(ek_sweep_impl(ek, P, d_host, opts, proj_opts, eps, m_start, m_max, check_every, out));
   return LYAP_OK;
 }
 

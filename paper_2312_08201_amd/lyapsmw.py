@@ -144,7 +144,7 @@ def load(path: str = LIB_PATH):
     lib.ek_set_level.argtypes = [vp, i32, C.POINTER(SeedOpts)]
     lib.ek_solve.argtypes = [vp, i64, vp, C.POINTER(SolveOpts), vp, vp, vp, C.POINTER(Result)]
     lib.ek_sweep.argtypes = [vp, i64, vp, C.POINTER(SolveOpts), C.POINTER(SeedOpts), C.c_double,
-                             i32, i32, C.POINTER(EkResult)]
+                             i32, i32, i32, C.POINTER(EkResult)]
     lib.ek_info.argtypes = [vp, C.POINTER(EkInfo)]
     lib.ek_release.argtypes = [vp]
     lib.lyap_last_error.argtypes = []
@@ -406,8 +406,9 @@ class EKSpace:
         return W, delta, norms, np.frombuffer(bytes(res), dtype=RESULT_DTYPE).copy()
 
     def sweep(self, d, eps: float, m_max: int, check_every: int = 1,
-              opts: Optional[SolveOpts] = None, basis="auto", max_eig_cond=0.0, tsvd_rank=0):
-        """Algorithm EKSM_opt over host parameters d (P x r)."""
+              opts: Optional[SolveOpts] = None, basis="auto", max_eig_cond=0.0, tsvd_rank=0,
+              m_start: int = 1):
+        """Algorithm EKSM_opt over host parameters d (P x r), from level m_start."""
         d = _host(d)
         P = d.shape[0]
         if d.shape != (P, self.r):
@@ -416,7 +417,7 @@ class EKSpace:
         po = SeedOpts(BASIS[basis], 0, float(max_eig_cond), int(tsvd_rank), 0)
         out = (EkResult * P)()
         st = load().ek_sweep(self.h, P, d.ctypes.data, C.byref(opts), C.byref(po), float(eps),
-                             int(m_max), int(check_every), out)
+                             int(m_start), int(m_max), int(check_every), out)
         _check(st, "ek_sweep")
         return np.frombuffer(bytes(out), dtype=EK_RESULT_DTYPE).copy()
 

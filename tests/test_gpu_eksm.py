@@ -176,6 +176,25 @@ def test_sweep_check_every_and_m_max(L):
     ek2.close()
 
 
+def test_sweep_continued_from_a_level(L):
+    """A later sweep may start at the level an earlier one reached (the
+    algorithm's use inside optimisation loops): same decisions as the oracle
+    started there."""
+    pr = W.small_multiagent(150, 2, 3, 8)
+    seed, ek = _space(L, pr)
+    first = ek.sweep(pr.d, eps=1e-10, m_max=60)
+    start = int(first["level"].max())
+    out = ek.sweep(pr.d, eps=1e-10, m_max=60, m_start=start)
+    ref = K.eksm_trace(pr.A0, pr.U, pr.V, pr.B, pr.E, pr.d, 1e-10, 60, m_start=start)
+    assert np.all(out["level"] >= start)
+    _compare_sweeps(pr, out, ref, 1e-10, 1e-7)
+    with pytest.raises(L.LyapError):
+        ek.sweep(pr.d, eps=1e-10, m_max=60, m_start=0)
+    with pytest.raises(L.LyapError):
+        ek.sweep(pr.d, eps=1e-10, m_max=3, m_start=5)
+    ek.close()
+
+
 def test_multiagent_workload_sampled(L):
     """The 500-agent workload (n = 1000, rank 8) at eps = 1e-10, sampled parameters."""
     pr = W.config(3).subset([0, 137, 300, 511])

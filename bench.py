@@ -440,7 +440,10 @@ def main():
         pr = W.chain_problem(args.chain_dof, [args.chain_dof // 2], 1, 16, "logspace", 64, 0,
                              "chain%d" % (2 * args.chain_dof))
     t = time.perf_counter()
+    print("factoring the seed (n=%d, r=%d, basis %s)" % (pr.n, pr.r, args.basis), file=sys.stderr,
+          flush=True)
     seed = L.Seed.from_problem(pr, tsvd_rank=args.tsvd_rank, basis=args.basis)
+    print("seed factored in %.1f s" % (time.perf_counter() - t), file=sys.stderr, flush=True)
     if args.ek:
         ek_bench(args, L, torch, W, seed, pr, time.perf_counter() - t)
         return

@@ -88,7 +88,7 @@ typedef struct {
                              keeps only its exact block-diagonal part; at most 64; eigenbasis
                              seeds only (ignored in the Schur basis) */
   int32_t schur_dense;    /* Schur basis only: 0 (default) assembles the capacitance operator
-                             as a dense (r ld)^2 matrix when n <= 1024 and r ld <= 8192 (one
+                             as a dense (r ld)^2 matrix when n <= 2048 and r ld <= 8192 (one
                              GEMM per Krylov step; assembly: r n quasi-triangular solves of
                              size n); -1 keeps the per-slot quasi-triangular solve in every
                              step (no (r ld)^2 memory) */

@@ -361,8 +361,9 @@ void schur_dense_operator(lyap_seed_s* sd, hipStream_t st) {
   for (long k = 0; k < n; ++k) eye_h[(size_t)k * ld + k] = 1.0;
   DevBuf eye(eye_h.size() * sizeof(double));
   LYAP_HIP(hipMemcpyAsync(eye.p, eye_h.data(), eye.bytes, hipMemcpyHostToDevice, st));
+  // unit problems per launch: enough workgroups to fill the chip, within 16 GiB of solutions
   const long per = (long)ld * ld;
-  const long chunk = std::max<long>(1, std::min<long>(n, (long)((size_t(2) << 30) / (per * sizeof(double)))));
+  const long chunk = std::max<long>(1, std::min<long>(n, (long)((size_t(16) << 30) / (per * sizeof(double)))));
   DevBuf Xb((size_t)chunk * per * sizeof(double));
   for (long b = 0; b < r; ++b)
     for (long k0 = 0; k0 < n; k0 += chunk) {

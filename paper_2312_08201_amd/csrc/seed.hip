@@ -15,7 +15,7 @@ namespace lyap {
 
 // Schur-basis seeds up to this size get the dense capacitance operator; its
 // assembly is r n quasi-triangular solves of size n.
-constexpr int64_t kDenseSchurMaxN = 1024;
+constexpr int64_t kDenseSchurMaxN = 2048;
 constexpr int64_t kDenseSchurMaxRl = 8192;
 
 namespace {

@@ -122,6 +122,11 @@ void trilyap_launch(const double* T, const double* Tt, double* X, long xstride, 
                     long cstride, const double* F, const double* G, long gstride, int k, int n,
                     int ld, int count, const int* list, const int* count_dev, hipStream_t st,
                     long fstride = 0);
+// One problem by the tile-blocked solver (schur.hip): X (row-major, n rows of
+// ld) with T X + X T^T = Cd + F G^T + G F^T (Cd dense symmetric or null; F, G
+// k rows of ld or null).  Synchronises the stream.
+void trilyap_blocked_one(const double* T, const double* Tt, int n, int ld, const double* Cd,
+                         const double* F, const double* G, int k, double* X, hipStream_t st);
 // out_p[a] = sum_m Vt[a][m] X_p[m][:]
 void project_launch(const double* Vt, const double* X, long xstride, double* out, long ostride,
                     int r, int n, int ld, int count, const int* list, const int* count_dev,

@@ -582,8 +582,8 @@ static lyap_seed_s* factor_schur(int64_t n, int64_t r, int64_t s, const double* 
   // Xs0: T Xs0 + Xs0 T^T = -Bs Bs^T
   DevBuf X0s(mat);
   LYAP_HIP(hipMemsetAsync(X0s.p, 0, mat, st));
-  trilyap_launch(sd->T.as<double>(), sd->Tt.as<double>(), X0s.as<double>(), 0, nullptr, 0,
-                 Bh.as<double>(), Bhm.as<double>(), 0, (int)s, N, (int)ld, 1, nullptr, nullptr, st);
+  trilyap_blocked_one(sd->T.as<double>(), sd->Tt.as<double>(), N, (int)ld, nullptr, Bh.as<double>(),
+                      Bhm.as<double>(), (int)s, X0s.as<double>(), st);
   zeros(sd->c0, r);
   project_launch(sd->Vh.as<double>(), X0s.as<double>(), 0, sd->c0.as<double>(), 0, (int)r, N,
                  (int)ld, 1, nullptr, nullptr, st);
@@ -626,14 +626,14 @@ static lyap_seed_s* factor_schur(int64_t n, int64_t r, int64_t s, const double* 
   LYAP_HIP(hipMemcpyAsync(Tftd.p, Tft.data(), mat, hipMemcpyHostToDevice, st));
   LYAP_HIP(hipMemcpyAsync(Cfd.p, Cf.data(), mat, hipMemcpyHostToDevice, st));
   LYAP_HIP(hipMemsetAsync(Gf.p, 0, mat, st));
-  trilyap_launch(Tfd.as<double>(), Tftd.as<double>(), Gf.as<double>(), 0, Cfd.as<double>(), 0, nullptr,
-                 nullptr, 0, 0, N, (int)ld, 1, nullptr, nullptr, st);
+  trilyap_blocked_one(Tfd.as<double>(), Tftd.as<double>(), N, (int)ld, Cfd.as<double>(), nullptr,
+                      nullptr, 0, Gf.as<double>(), st);
   std::vector<double> Gfh((size_t)ld * ld), Gsh((size_t)ld * ld, 0.0);
   LYAP_HIP(hipMemcpyAsync(Gfh.data(), Gf.p, mat, hipMemcpyDeviceToHost, st));
   LYAP_HIP(hipStreamSynchronize(st));
-  // Gf stored by columns: column j = Gf[j*ld + i] = G'[i][j]; Gs[i][j] = G'[n-1-i][n-1-j]
+  // Gf row-major: Gf[i*ld + j] = G'[i][j]; Gs[i][j] = G'[n-1-i][n-1-j]
   for (int i = 0; i < N; ++i)
-    for (int j = 0; j < N; ++j) Gsh[(size_t)i * ld + j] = Gfh[(size_t)(N - 1 - j) * ld + (N - 1 - i)];
+    for (int j = 0; j < N; ++j) Gsh[(size_t)i * ld + j] = Gfh[(size_t)(N - 1 - i) * ld + (N - 1 - j)];
   DevBuf Gsd(mat);
   LYAP_HIP(hipMemcpyAsync(Gsd.p, Gsh.data(), mat, hipMemcpyHostToDevice, st));
   // Gamma_s^T = Us^T Gs (Gs symmetric); trace weights 2 Gamma_s^T; physical Gamma^T = Gamma_s^T Z^T

@@ -318,14 +318,8 @@ def test_repeated_solves_reuse_engine_identically():
     assert np.max(rel(runs[0][2]["trace"], oracle_traces(pr))) <= 1e-10
 
 
-@pytest.mark.parametrize("maker", [lambda: W.small_chain(30, (7, 22), 3, 6),
-                                   lambda: W.small_multiagent(24, 2, 3, 6)])
-def test_schur_dense_operator_matches_per_slot_solve(maker):
-    """Schur basis: the dense capacitance operator (one GEMM per step) and the
-    per-slot quasi-triangular solve give the same solutions, both at the
-    oracle's values."""
+def _dense_vs_per_slot(pr):
     L, torch = lib()
-    pr = maker()
     d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
     out = {}
     for dense in (True, False):
@@ -338,6 +332,27 @@ def test_schur_dense_operator_matches_per_slot_solve(maker):
         assert np.max(rel(out[dense][1], ref)) <= 1e-10, dense
     Yd, Ys = out[True][0], out[False][0]
     assert np.linalg.norm(Yd - Ys) <= 1e-11 * np.linalg.norm(Ys)
+
+
+@pytest.mark.parametrize("maker", [lambda: W.small_chain(30, (7, 22), 3, 6),
+                                   lambda: W.small_multiagent(24, 2, 3, 6)])
+def test_schur_dense_operator_matches_per_slot_solve(maker):
+    """Schur basis: the dense capacitance operator (one GEMM per step) and the
+    per-slot quasi-triangular solve give the same solutions, both at the
+    oracle's values."""
+    _dense_vs_per_slot(maker())
+
+
+@pytest.mark.parametrize("maker", [lambda: W.small_chain(100, (23, 71), 3, 4),
+                                   lambda: W.small_multiagent(110, 2, 3, 4),
+                                   lambda: W.near_defective(150, 2, 3, 4, 3),
+                                   lambda: W.random_stable(257, 2, 3, 4, 5)])
+def test_schur_dense_operator_spans_several_tiles(maker):
+    """n = 200..300: the blocked assembly of the dense operator crosses several
+    row tiles (64 rows) and column panels (120 columns), with a ragged top tile
+    and 2x2 blocks of T beside the tile boundaries (all pairs for the agents,
+    none for the near-defective seed); same checks as above."""
+    _dense_vs_per_slot(maker())
 
 
 def test_oversized_capacitance_vector_is_an_error_not_an_abort():

@@ -198,9 +198,9 @@ void full_impl(lyap_seed_s* sd, int64_t P, const double* Y, double* X, hipStream
                          Yh.as<double>(), sd->Bh.as<double>(), G.as<double>(), (int)r, (int)s,
                          (int)ld, Y != nullptr);
       LYAP_HIP(hipGetLastError());
-      trilyap_launch(sd->T.as<double>(), sd->Tt.as<double>(), Xh.as<double>(), ld * ld, nullptr,
-                     0, F.as<double>(), G.as<double>(), k * ld, (int)k, (int)n, (int)ld, cnt,
-                     nullptr, nullptr, st);
+      trilyap_blocked(sd->T.as<double>(), sd->Tt.as<double>(), (int)n, (int)ld, nullptr,
+                      F.as<double>(), 0, G.as<double>(), k * ld, (int)k, cnt, ld, Xh.as<double>(),
+                      st);
     }
     // X = Tout^T Xh Tout: Z = Xh Tout, then X = Z^T Tout (Xh symmetric)
     gemm64_rm(Xh.as<double>(), ld, sd->Tout.as<double>(), ld, Z.as<double>(), ld, (long)cnt * ld,

@@ -122,11 +122,14 @@ void trilyap_launch(const double* T, const double* Tt, double* X, long xstride, 
                     long cstride, const double* F, const double* G, long gstride, int k, int n,
                     int ld, int count, const int* list, const int* count_dev, hipStream_t st,
                     long fstride = 0);
-// One problem by the tile-blocked solver (schur.hip): X (row-major, n rows of
-// ld) with T X + X T^T = Cd + F G^T + G F^T (Cd dense symmetric or null; F, G
-// k rows of ld or null).  Synchronises the stream.
-void trilyap_blocked_one(const double* T, const double* Tt, int n, int ld, const double* Cd,
-                         const double* F, const double* G, int k, double* X, hipStream_t st);
+// Tile-blocked solver (schur.hip) for count problems sharing T: X_b
+// (row-major, xrows >= n rows of ld, problems xrows ld apart, rows >= n
+// zero) with T X_b + X_b T^T = Cd + F_b G_b^T + G_b F_b^T (Cd dense symmetric,
+// shared, or null; F_b, G_b k rows of ld, fstride / gstride apart, 0 =
+// shared).  Allocates its workspace; synchronises the stream.
+void trilyap_blocked(const double* T, const double* Tt, int n, int ld, const double* Cd,
+                     const double* F, long fstride, const double* G, long gstride, int k,
+                     long count, long xrows, double* X, hipStream_t st);
 // out_p[a] = sum_m Vt[a][m] X_p[m][:]
 void project_launch(const double* Vt, const double* X, long xstride, double* out, long ostride,
                     int r, int n, int ld, int count, const int* list, const int* count_dev,

@@ -360,10 +360,11 @@ struct TileArgs {
   const double* G;    // k rows of ld per problem (shared when gstride == 0)
   long gstride;
   int k;
-  const double* P;    // (problems n) x 128: sum_{L > J} X_IL T_JL^T, or null
+  const double* P;    // (problems xrows) x 128: sum_{L > J} X_IL T_JL^T, or null
   const double* Q;    // ni x npad: sum_{K > I} T_IK X_KJ, column b kPanel + j, or null
   long npad;
-  double* X;          // problems n ld apart
+  double* X;          // problems xrows ld apart
+  long xrows;
   double* Panel;      // kend x npad: solved rows of the panel, column b kPanel + j
 };
 
@@ -431,30 +432,38 @@ __global__ void __launch_bounds__(kTile) k_tile_lyap(TileArgs A) {
   const int gi = I0 + (live ? q : 0);  // this lane's row of T and X
   double* xrow = Xt + q * kXs;
 
-  // right-hand side tile: C_IJ - P - Q, row by row (coalesced over the columns)
-  {
-    const double* Fb = A.F ? A.F + (long)b * A.fstride : nullptr;
-    const double* Gb = A.G ? A.G + (long)b * A.gstride : nullptr;
-#pragma unroll 4
+  // T_II into LDS (row r of the tile, column q; lanes beyond the tile read
+  // its first column instead), and the right-hand side's dense and low-rank
+  // parts into Xt (columns q and q + 64 of each row).  The GEMM products P
+  // and Q are subtracted column by column below, fetched one column step ahead.
+  const int c0 = q, c1 = q + 64;
+  const bool has0 = c0 < nj, has1 = c1 < nj;
+  const int tc = I0 + (live ? q : 0);
+#pragma unroll 8
+  for (int r = 0; r < ni; ++r) Ts[r * kTs + q] = T[(long)(I0 + r) * ld + tc];
+  for (int r = 0; r < ni; ++r) {
+    const long g = I0 + r;
+    if (has0) Xt[r * kXs + c0] = A.Cd ? A.Cd[g * ld + J0 + c0] : 0.0;
+    if (has1) Xt[r * kXs + c1] = A.Cd ? A.Cd[g * ld + J0 + c1] : 0.0;
+  }
+  for (int t = 0; t < A.k; ++t) {
+    const double* Ft = A.F + (long)b * A.fstride + (long)t * ld;
+    const double* Gt = A.G + (long)b * A.gstride + (long)t * ld;
+    const double f0 = has0 ? Ft[J0 + c0] : 0.0, g0 = has0 ? Gt[J0 + c0] : 0.0;
+    const double f1 = has1 ? Ft[J0 + c1] : 0.0, g1 = has1 ? Gt[J0 + c1] : 0.0;
+#pragma unroll 8
     for (int r = 0; r < ni; ++r) {
-      const int g = I0 + r;
-      if (q < ni) Ts[r * kTs + q] = T[(long)g * ld + I0 + q];
-#pragma unroll
-      for (int c = q; c < nj; c += kTile) {
-        const int gc = J0 + c;
-        double v = 0.0;
-        if (A.Cd) v = A.Cd[(long)g * ld + gc];
-        for (int t = 0; t < A.k; ++t) {
-          const double* Ft = Fb + (long)t * ld;
-          const double* Gt = Gb + (long)t * ld;
-          v += Ft[g] * Gt[gc] + Gt[g] * Ft[gc];
-        }
-        if (A.P) v -= A.P[((long)b * A.n + g) * 128 + c];
-        if (A.Q) v -= A.Q[(long)r * A.npad + (long)b * kPanel + c];
-        Xt[r * kXs + c] = v;
-      }
+      const double fr = Ft[I0 + r], gr = Gt[I0 + r];
+      if (has0) Xt[r * kXs + c0] += fr * g0 + gr * f0;
+      if (has1) Xt[r * kXs + c1] += fr * g1 + gr * f1;
     }
   }
+  // P + Q at column c of this lane's row, as two loads (summed where used)
+  auto load_pq = [&](int c, double& pv, double& qv) {
+    const bool ok = live && c >= 0;
+    pv = (ok && A.P) ? A.P[((long)b * A.xrows + gi) * 128 + c] : 0.0;
+    qv = (ok && A.Q) ? A.Q[(long)q * A.npad + (long)b * kPanel + c] : 0.0;
+  };
   // diagonal band of T_II (this lane's row) and of T_JJ (columns q and q + 64)
   const double dI = live ? T[(long)gi * ld + gi] : 1.0;
   const double subI = (live && q > 0) ? T[(long)gi * ld + gi - 1] : 0.0;   // T[q][q-1]
@@ -497,36 +506,56 @@ __global__ void __launch_bounds__(kTile) k_tile_lyap(TileArgs A) {
   double trA[2], trB[2];       // rows jc and j of T_JJ
   load_trow(jc, trA);
   load_trow(j, trB);
+  double pA, qA, pB, qB;       // P and Q at columns jc and j
+  load_pq(jc, pA, qA);
+  load_pq(j, pB, qB);
   while (j >= 0) {
-    // the next step's rows, loaded now so that they have arrived when needed
+    // right-hand sides: the X T_JJ^T sum over the solved columns l > j, in two
+    // ranges so that the register holding T_JJ[.][l] is fixed in each loop
+    double b0 = 0.0, b1 = 0.0;
+    {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      const int mid = nj < 64 ? nj : 64;
+      int l = j + 1;
+      for (; l + 1 < mid; l += 2) {
+        const double x0 = xrow[l], x1 = xrow[l + 1];
+        s0 += readlane_d(trA[0], l) * x0;
+        s1 += readlane_d(trA[0], l + 1) * x1;
+        s2 += readlane_d(trB[0], l) * x0;
+        s3 += readlane_d(trB[0], l + 1) * x1;
+      }
+      for (; l < mid; ++l) {
+        const double x0 = xrow[l];
+        s0 += readlane_d(trA[0], l) * x0;
+        s2 += readlane_d(trB[0], l) * x0;
+      }
+      for (; l + 1 < nj; l += 2) {
+        const double x0 = xrow[l], x1 = xrow[l + 1];
+        s0 += readlane_d(trA[1], l - 64) * x0;
+        s1 += readlane_d(trA[1], l - 63) * x1;
+        s2 += readlane_d(trB[1], l - 64) * x0;
+        s3 += readlane_d(trB[1], l - 63) * x1;
+      }
+      for (; l < nj; ++l) {
+        const double x0 = xrow[l];
+        s0 += readlane_d(trA[1], l - 64) * x0;
+        s2 += readlane_d(trB[1], l - 64) * x0;
+      }
+      if (live) {
+        b0 = ((xrow[jc] - pA) - qA) - (s0 + s1);
+        b1 = ((xrow[j] - pB) - qB) - (s2 + s3);
+      }
+    }
+    // the next step's rows, loaded now so that the substitution below hides them
     const int jn = jc - 1;
     const bool cpn = cpair_of(jn);
     const int jcn = cpn ? jn - 1 : jn;
     double tnA[2], tnB[2];
     load_trow(jcn, tnA);
     load_trow(jn, tnB);
-    // right-hand sides: the X T_JJ^T sum over the solved columns l > j
-    double b0 = 0.0, b1 = 0.0;
-    {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int l = j + 1;
-      for (; l + 1 < nj; l += 2) {
-        const double x0 = xrow[l], x1 = xrow[l + 1];
-        s0 += colv(trA, l) * x0;
-        s1 += colv(trA, l + 1) * x1;
-        s2 += colv(trB, l) * x0;
-        s3 += colv(trB, l + 1) * x1;
-      }
-      if (l < nj) {
-        const double x0 = xrow[l];
-        s0 += colv(trA, l) * x0;
-        s2 += colv(trB, l) * x0;
-      }
-      if (live) {
-        b0 = xrow[jc] - (s0 + s1);
-        b1 = xrow[j] - (s2 + s3);
-      }
-    }
+    double pAn, qAn, pBn, qBn;
+    load_pq(jcn, pAn, qAn);
+    load_pq(jn, pBn, qBn);
     // each row block's small system, inverted by the lane that ends the block
     {
       double M[16], R[16];
@@ -629,6 +658,10 @@ __global__ void __launch_bounds__(kTile) k_tile_lyap(TileArgs A) {
     j = jn;
     cpair = cpn;
     jc = jcn;
+    pA = pAn;
+    qA = qAn;
+    pB = pBn;
+    qB = qBn;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       trA[h] = tnA[h];
@@ -636,7 +669,7 @@ __global__ void __launch_bounds__(kTile) k_tile_lyap(TileArgs A) {
     }
   }
   // write the tile row by row (coalesced over the columns)
-  double* Xb = A.X + (long)b * A.n * ld;
+  double* Xb = A.X + (long)b * A.xrows * ld;
   for (int r = 0; r < ni; ++r) {
     const int g = I0 + r;
     for (int c = q; c < nj; c += kTile) {
@@ -714,17 +747,21 @@ struct BlockedLyap {
   }
 
   long npad(long count) const { return (count * kPanel + 127) / 128 * 128; }
-  // device bytes per problem: X, the panel products P and the panel rows
+  // device bytes per problem with n rows: X, the panel products P and the panel rows
   size_t bytes_per_problem() const {
     return ((size_t)n * ld + (size_t)n * 128 + (size_t)kend * kPanel + 128) * sizeof(double);
   }
 
-  // X (count x n x ld): T X_b + X_b T^T = Cd + F G_b^T + G_b F^T (Cd shared, or null)
+  // X (count problems of xrows >= n rows of ld; rows >= n are zero):
+  // T X_b + X_b T^T = Cd + F G_b^T + G_b F^T (Cd shared, or null).
+  // Workspace: P count xrows x 128, Panel kend x npad(count), Q kTile x npad(count).
   void solve(const double* Cd, const double* F, long fstride, const double* G, long gstride, int k,
-             long count, double* X, double* P, double* Panel, double* Q, hipStream_t st) const {
+             long count, long xrows, double* X, double* P, double* Panel, double* Q,
+             hipStream_t st) const {
     const long np = npad(count);
-    LYAP_REQUIRE(count * n < (1L << 31), LYAP_E_INVAL, "blocked Schur solve: batch too large");
-    LYAP_HIP(hipMemsetAsync(X, 0, (size_t)count * n * ld * sizeof(double), st));
+    LYAP_REQUIRE(xrows >= n && count * xrows < (1L << 31), LYAP_E_INVAL,
+                 "blocked Schur solve: batch too large");
+    LYAP_HIP(hipMemsetAsync(X, 0, (size_t)count * xrows * ld * sizeof(double), st));
     for (int jb = (int)cb.size() - 2; jb >= 0; --jb) {
       const int J0 = cb[jb], Jend = cb[jb + 1];
       const bool haveP = Jend < n;
@@ -734,7 +771,7 @@ struct BlockedLyap {
         g.type = GemmType::F64;
         g.A = X + ks;
         g.lda = ld;
-        g.M = count * n;
+        g.M = count * xrows;
         g.B = Ttp.as<double>() + ks * ldt + J0;
         g.ldb = ldt;
         g.N = 128;
@@ -765,7 +802,7 @@ struct BlockedLyap {
           gemm_launch(g, st);
         }
         TileArgs A{T,  Tt, n, ld, I0, Iend - I0, J0, Jend - J0, Cd, F, fstride, G, gstride, k,
-                   haveP ? P : nullptr, haveQ ? Q : nullptr, np, X, Panel};
+                   haveP ? P : nullptr, haveQ ? Q : nullptr, np, X, xrows, Panel};
         hipLaunchKernelGGL(k_tile_lyap, dim3((unsigned)count), dim3(kTile), 0, st, A);
         LYAP_HIP(hipGetLastError());
       }
@@ -775,13 +812,15 @@ struct BlockedLyap {
 
 }  // namespace
 
-void trilyap_blocked_one(const double* T, const double* Tt, int n, int ld, const double* Cd,
-                         const double* F, const double* G, int k, double* X, hipStream_t st) {
+void trilyap_blocked(const double* T, const double* Tt, int n, int ld, const double* Cd,
+                     const double* F, long fstride, const double* G, long gstride, int k,
+                     long count, long xrows, double* X, hipStream_t st) {
   BlockedLyap bl(T, Tt, n, ld, st);
-  DevBuf P((size_t)n * 128 * sizeof(double));
-  DevBuf Panel((size_t)bl.kend * bl.npad(1) * sizeof(double));
-  DevBuf Q((size_t)kTile * bl.npad(1) * sizeof(double));
-  bl.solve(Cd, F, 0, G, 0, k, 1, X, P.as<double>(), Panel.as<double>(), Q.as<double>(), st);
+  DevBuf P((size_t)count * xrows * 128 * sizeof(double));
+  DevBuf Panel((size_t)bl.kend * bl.npad(count) * sizeof(double));
+  DevBuf Q((size_t)kTile * bl.npad(count) * sizeof(double));
+  bl.solve(Cd, F, fstride, G, gstride, k, count, xrows, X, P.as<double>(), Panel.as<double>(),
+           Q.as<double>(), st);
   LYAP_HIP(hipStreamSynchronize(st));
 }
 
@@ -812,7 +851,7 @@ void schur_dense_operator(lyap_seed_s* sd, hipStream_t st) {
   for (long b = 0; b < r; ++b)
     for (long k0 = 0; k0 < n; k0 += chunk) {
       const long cnt = std::min(chunk, n - k0);
-      bl.solve(nullptr, sd->Uh.as<double>() + b * ld, 0, eye.as<double>() + k0 * ld, ld, 1, cnt,
+      bl.solve(nullptr, sd->Uh.as<double>() + b * ld, 0, eye.as<double>() + k0 * ld, ld, 1, cnt, n,
                Xb.as<double>(), P.as<double>(), Panel.as<double>(), Q.as<double>(), st);
       project_launch(sd->Vh.as<double>(), Xb.as<double>(), n * ld,
                      sd->Kd.as<double>() + (size_t)(b * ld + k0) * rl, rl, (int)r, (int)n, (int)ld,

@@ -582,8 +582,8 @@ static lyap_seed_s* factor_schur(int64_t n, int64_t r, int64_t s, const double* 
   // Xs0: T Xs0 + Xs0 T^T = -Bs Bs^T
   DevBuf X0s(mat);
   LYAP_HIP(hipMemsetAsync(X0s.p, 0, mat, st));
-  trilyap_blocked_one(sd->T.as<double>(), sd->Tt.as<double>(), N, (int)ld, nullptr, Bh.as<double>(),
-                      Bhm.as<double>(), (int)s, X0s.as<double>(), st);
+  trilyap_blocked(sd->T.as<double>(), sd->Tt.as<double>(), N, (int)ld, nullptr, Bh.as<double>(), 0,
+                  Bhm.as<double>(), 0, (int)s, 1, N, X0s.as<double>(), st);
   zeros(sd->c0, r);
   project_launch(sd->Vh.as<double>(), X0s.as<double>(), 0, sd->c0.as<double>(), 0, (int)r, N,
                  (int)ld, 1, nullptr, nullptr, st);
@@ -626,8 +626,8 @@ static lyap_seed_s* factor_schur(int64_t n, int64_t r, int64_t s, const double* 
   LYAP_HIP(hipMemcpyAsync(Tftd.p, Tft.data(), mat, hipMemcpyHostToDevice, st));
   LYAP_HIP(hipMemcpyAsync(Cfd.p, Cf.data(), mat, hipMemcpyHostToDevice, st));
   LYAP_HIP(hipMemsetAsync(Gf.p, 0, mat, st));
-  trilyap_blocked_one(Tfd.as<double>(), Tftd.as<double>(), N, (int)ld, Cfd.as<double>(), nullptr,
-                      nullptr, 0, Gf.as<double>(), st);
+  trilyap_blocked(Tfd.as<double>(), Tftd.as<double>(), N, (int)ld, Cfd.as<double>(), nullptr, 0,
+                  nullptr, 0, 0, 1, N, Gf.as<double>(), st);
   std::vector<double> Gfh((size_t)ld * ld), Gsh((size_t)ld * ld, 0.0);
   LYAP_HIP(hipMemcpyAsync(Gfh.data(), Gf.p, mat, hipMemcpyDeviceToHost, st));
   LYAP_HIP(hipStreamSynchronize(st));

@@ -231,6 +231,66 @@ def multiagent_problem(N: int, avg_degree: float, n_param_edges: int, s: int,
 # --------------------------------------------------------------------------
 # the five named workloads
 # --------------------------------------------------------------------------
+# --------------------------------------------------------------------------
+# agent-importance sweep (Section 4, the multi-agent example with identical
+# 2x2 agents): A0 blocks delta_ij A_a - l_ij B_a K_a C_a, one agent's diagonal
+# block varied by three parameters through a rank-4 update
+AGENT_A = np.array([[-10.0, 5.0], [5.0, -8.0]])
+AGENT_K = np.diag([0.3, 0.2])
+AGENT_B = np.array([[1.0, 1.0], [-1.0, 1.0]])        # C_a = B_a^T
+AGENT_BL = np.array([[1.0, 1.0, 0.0, 0.0], [0.0, 0.0, 1.0, 1.0]])
+AGENT_BR = np.array([[1.0, 0.0, 1.0, 0.0], [0.0, 1.0, 0.0, 1.0]])
+
+
+def agent_network(m: int, avg_degree: float = 4.0, seed: int = 7) -> np.ndarray:
+    """A0 (n = 2m) of m identical agents on a connected Erdos-Renyi graph
+    (unit edge weights; the paper's graph is given only as a figure).
+    Draw order: edge mask, connecting edges."""
+    rng = np.random.default_rng(seed)
+    iu, ju = np.triu_indices(m, k=1)
+    mask = rng.random(iu.shape[0]) < avg_degree / (m - 1)
+    edges = [tuple(e) for e in np.stack([iu[mask], ju[mask]], axis=1)]
+    comp = _components(m, np.array(edges, dtype=np.int64).reshape(-1, 2))
+    roots = np.unique(comp)
+    for a, b in zip(roots[:-1], roots[1:]):
+        ia = int(rng.choice(np.flatnonzero(comp == a)))
+        ib = int(rng.choice(np.flatnonzero(comp == b)))
+        edges.append((min(ia, ib), max(ia, ib)))
+    Lap = np.zeros((m, m))
+    for i, j in edges:
+        Lap[i, j] -= 1.0
+        Lap[j, i] -= 1.0
+        Lap[i, i] += 1.0
+        Lap[j, j] += 1.0
+    coup = AGENT_B @ AGENT_K @ AGENT_B.T
+    return np.kron(np.eye(m), AGENT_A) - np.kron(Lap, coup)
+
+
+def agent_grid(step: float = 1.0, lo: float = -9.9, hi: float = 10.1) -> np.ndarray:
+    """All (v1, v2, v3) on the grid lo, lo + step, ..., hi (v1 slowest), as
+    d = (v1, v2, v2, v3) rows."""
+    g = np.arange(lo, hi + 1e-9, step)
+    v = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    return np.ascontiguousarray(np.stack([v[:, 0], v[:, 1], v[:, 1], v[:, 2]], axis=1))
+
+
+def agent_problem(A0: np.ndarray, k: int, d: np.ndarray, name: str = "") -> Problem:
+    """Agent k varied: A(v) = A0 - B_l diag(v1, v2, v2, v3) B_r^T with B_l, B_r
+    nonzero in agent k's two rows; the disturbance enters agent k only
+    (B = e_k kron B_a) and E = e_k kron I_2 weighs agent k's states."""
+    n = A0.shape[0]
+    U = np.zeros((n, 4))
+    V = np.zeros((n, 4))
+    U[2 * k:2 * k + 2] = AGENT_BL
+    V[2 * k:2 * k + 2] = AGENT_BR
+    B = np.zeros((n, 2))
+    B[2 * k:2 * k + 2] = AGENT_B
+    E = np.zeros(n)
+    E[2 * k:2 * k + 2] = 1.0
+    return Problem(name or "agent%d" % k, A0, U, V, B, E, np.ascontiguousarray(d),
+                   dict(kind="agent_importance", agent=k))
+
+
 def config(i: int, P: Optional[int] = None) -> Problem:
     """Workloads c0..c3 (c4 is the request stream built by ``serving_requests``).
 

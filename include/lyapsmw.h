@@ -226,6 +226,24 @@ lyap_status trace_EX(lyap_seed seed, int64_t P, const double* Y_dev, double* tra
 lyap_status seed_full_X(lyap_seed seed, int64_t P, const double* Y_dev, double* X_dev,
                         void* hip_stream);
 
+/* Stability filter of a parameter sweep (the multi-agent importance example
+ * of Section 4 discards every sample whose A(p) = A0 - U diag(d_p) V^T has an
+ * eigenvalue with Re >= 0).  For each p < P, count_dev[p] = the number of
+ * eigenvalues of A(p) in the open right half-plane, from the argument
+ * principle applied to f(s) = det(I + D_p V^T (s I - A0)^-1 U) along the
+ * imaginary axis (A0 is stable, so those eigenvalues are the zeros of f
+ * there); V^T (i w - A0)^-1 U comes from the seed's eigenbasis on a frequency
+ * grid shared by all p.  flag_dev[p] != 0 when the grid cannot vouch for the
+ * count (bit 1: a phase step above pi/2, i.e. an eigenvalue of A(p) within
+ * about a grid step of the axis; bit 2: f not near 1 at the last frequency;
+ * bit 4: the phase total is not close to a multiple of pi; bit 8: f = 0 at a
+ * grid frequency); such samples are to be treated as not known to be stable.
+ * d_dev: device P x r; count_dev, flag_dev: device P int32.  Work buffers are
+ * allocated per call; the call synchronises the stream.  LYAP_E_UNSUPPORTED
+ * for a Schur-basis or projected seed, or r > 8. */
+lyap_status seed_unstable_count(lyap_seed seed, int64_t P, const double* d_dev, int32_t* count_dev,
+                                int32_t* flag_dev, void* hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* Continuous-batching engine (one seed, a fixed number of slots).            */
 /* smw_solve_batch runs on an engine; a serving loop drives engines directly. */

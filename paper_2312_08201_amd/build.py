@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblyapsmw.so")
-SOURCES = ["gemm.hip", "seed.hip", "engine.hip", "apply.hip", "schur.hip", "ek.hip", "full.hip", "shifted.hip", "lapack_host.cpp",
+SOURCES = ["gemm.hip", "seed.hip", "engine.hip", "apply.hip", "schur.hip", "ek.hip", "full.hip", "shifted.hip", "stability.hip", "lapack_host.cpp",
            "schur_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",

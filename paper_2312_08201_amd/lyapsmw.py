@@ -94,7 +94,7 @@ EXPORTS = ["seed_factor", "seed_info", "seed_release", "seed_device_bytes", "lya
            "engine_harvest", "engine_launch", "engine_status", "lyap_status_string", "lyap_last_error", "lyap_profile_enable",
            "lyap_profile_read", "lyap_calib_copy", "lyap_real_schur", "seed_full_X", "smw_solve_shifted",
            "seed_x0v", "ek_create",
-           "ek_set_level", "ek_solve", "ek_sweep", "ek_info", "ek_release"]
+           "ek_set_level", "ek_solve", "ek_sweep", "ek_info", "ek_release", "seed_unstable_count"]
 
 
 def load(path: str = LIB_PATH):
@@ -153,7 +153,7 @@ def load(path: str = LIB_PATH):
                  "trace_EX", "engine_create", "engine_destroy", "engine_submit", "engine_run",
                  "engine_harvest", "engine_launch", "engine_status", "lyap_profile_read",
                  "lyap_calib_copy", "seed_full_X", "smw_solve_shifted", "seed_x0v", "ek_create", "ek_set_level", "ek_solve",
-                 "ek_sweep", "ek_info", "ek_release"):
+                 "ek_sweep", "ek_info", "ek_release", "seed_unstable_count"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -324,6 +324,20 @@ class Seed:
                                       _dev_ptr(Y) if want_Y else None, res, _stream(stream))
         _check(st, "smw_solve_shifted")
         return Y, np.frombuffer(bytes(res), dtype=RESULT_DTYPE).copy()
+
+    def unstable_count(self, d, stream=None):
+        """Stability filter: for device d (P x r), the number of eigenvalues of
+        A(p) in the open right half-plane and a flag (nonzero: the frequency
+        grid cannot vouch for the count), both device int32 tensors of length P."""
+        torch = _torch()
+        P = d.shape[0]
+        _dev_ptr(d, shape=(P, self.r))
+        cnt = torch.empty(P, dtype=torch.int32, device=d.device)
+        flag = torch.empty(P, dtype=torch.int32, device=d.device)
+        _check(load().seed_unstable_count(self.h, P, _dev_ptr(d), _dev_ptr(cnt, "int32"),
+                                          _dev_ptr(flag, "int32"), _stream(stream)),
+               "seed_unstable_count")
+        return cnt, flag
 
     def full_X(self, Y=None, stream=None):
         """X(p) (P x n x n) for the solutions Y of solve(); X0 when Y is None."""

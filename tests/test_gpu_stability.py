@@ -1,0 +1,80 @@
+"""GPU parity of the stability filter (seed_unstable_count).
+
+For every sample the number of eigenvalues of A(p) = A0 - U diag(d) V^T in
+the open right half-plane must equal the oracle's count from the dense
+spectrum, wherever the sample's rightmost eigenvalue is not within 1e-6 of
+the imaginary axis and the filter did not flag the sample.  Flags are
+allowed only where the rightmost eigenvalue is within eight steps of the
+uniform frequency grid (1/2048 of the spectral radius) of the axis.
+"""
+import numpy as np
+import pytest
+
+from gen import workloads as W
+from oracle import stability as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2312_08201_amd as lib
+    lib.load()
+    return lib
+
+
+def _check(L, pr, min_unstable=0.05):
+    import torch
+    seed = L.Seed.from_problem(pr)
+    d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
+    cnt, flag = seed.unstable_count(d)
+    cnt, flag = cnt.cpu().numpy(), flag.cpu().numpy()
+    ref, rm = S.sweep(pr.A0, pr.U, pr.V, pr.d)
+    clear = (np.abs(rm) > 1e-6) & (flag == 0)
+    # flags only where an eigenvalue lies within a few grid steps of the axis
+    rho = np.max(np.abs(np.linalg.eigvals(pr.A0)))
+    near = np.abs(rm) <= 8.0 * (2.0 * rho / 4096)
+    fl = flag != 0
+    print("flagged %.3f, near-axis %.3f, max |Re| flagged %s" %
+          (np.mean(fl), np.mean(near), np.max(np.abs(rm[fl])) if fl.any() else None))
+    assert np.all(near[fl]), [(int(i), float(rm[i]), int(flag[i])) for i in np.flatnonzero(fl & ~near)[:5]]
+    bad = np.flatnonzero(clear & (cnt != ref))
+    assert bad.size == 0, [(int(i), int(cnt[i]), int(ref[i]), float(rm[i])) for i in bad[:5]]
+    assert np.mean(ref > 0) >= min_unstable and np.mean(ref == 0) > 0.05
+    return cnt, flag, ref
+
+
+@pytest.mark.parametrize("k", [0, 7, 19])
+def test_agent_example(L, k):
+    """Symmetric agents (real spectrum), rank-4 update of one agent's block."""
+    A0 = W.agent_network(20, seed=5)
+    _check(L, W.agent_problem(A0, k, W.agent_grid(step=2.0)))
+
+
+def _negative(pr, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(lo, hi, size=(300, pr.r))
+    return W.Problem(pr.name, pr.A0, pr.U, pr.V, pr.B, pr.E, d, pr.meta)
+
+
+@pytest.mark.parametrize("case", ["agents_r4", "agents_r8", "chain_r1", "chain_r2", "random_r3"])
+def test_nonsymmetric_seeds(L, case):
+    """Rotating agents (complex pairs), damped chains, a random seed; parameters
+    drawn so that a good share of the samples is unstable."""
+    pr = {"agents_r4": lambda: _negative(W.small_multiagent(30, 2, 2, 1), -2.0, 4.0, 1),
+          "agents_r8": lambda: _negative(W.small_multiagent(30, 4, 2, 1), -1.0, 4.0, 2),
+          "chain_r1": lambda: _negative(W.small_chain(30, (11,), 2, 1), -2.0, 1.0, 3),
+          "chain_r2": lambda: _negative(W.small_chain(30, (7, 22), 2, 1), -1.0, 1.0, 4),
+          "random_r3": lambda: _negative(W.random_stable(40, 3, 2, 1, 9), -1.0, 2.0, 5)}[case]()
+    _check(L, pr)
+
+
+def test_schur_seed_is_unsupported(L):
+    import torch
+    pr = W.small_chain(20, (5,), 2, 3)
+    seed = L.Seed.from_problem(pr, basis="schur")
+    with pytest.raises(L.LyapError):
+        seed.unstable_count(torch.tensor(pr.d, dtype=torch.float64, device="cuda"))

@@ -10,7 +10,11 @@ Problem statement: Section 1, equations (Ljap jdba 1) and (eq:formA).
 Damped vibrational model: Section 3.1, equations (MDK), (Cext), (Cprop) and
 the Rayleigh linearisation A0 = [[0, I], [-M^-1 K, -alpha I - beta M^-1 K]],
 B_l = [0; M^-1 B], B_r = [0; B].
-Multi-agent model: Section 3.2 (a simplified stand-in).
+Multi-agent model: Section 3.2, as a simplified stand-in: rotating 2-state
+agents on a random connected graph, parameters on chosen edge weights.
+Agent-importance model: the multi-agent example of Section 4 (identical 2x2
+agents, one agent's block varied by three parameters); its graph is given
+only as a figure, so a random connected graph stands in.
 
 All generators draw from ``numpy.random.default_rng(seed)`` in a fixed order
 so that every caller sees bit-identical inputs.

@@ -17,7 +17,7 @@ and no recycling.  The Schur factorisation is a library primitive
 (``scipy.linalg.schur``); the triangular Lyapunov back-substitution is written
 out column by column below, with no blocking.
 
-Reading (documented in the design doc): the complex Schur form A = Z T Z^H is used
+Reading: the complex Schur form A = Z T Z^H is used
 so every diagonal block is 1x1.  With X = Z Y Z^H the equation becomes
 T Y + Y T^H = Z^H C Z, and column j of Y satisfies
 

@@ -701,6 +701,12 @@ void trilyap_launch(const double* T, const double* Tt, double* X, long xstride, 
 
 namespace {
 
+// sub[i - 1] = T[i][i - 1], 0 < i < n
+__global__ void k_subdiag(const double* __restrict__ T, int ld, int n, double* __restrict__ sub) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
+  if (i < n) sub[i - 1] = T[(long)i * ld + i - 1];
+}
+
 // Tile boundaries 0 = b_0 < ... < b_m = n of nominal size nb, from the bottom
 // up, moved down by one row where a 2x2 block would straddle (sub[i - 1] =
 // T[i][i - 1]).
@@ -733,10 +739,16 @@ struct BlockedLyap {
   BlockedLyap(const double* T_, const double* Tt_, int n_, int ld_, hipStream_t st)
       : T(T_), Tt(Tt_), n(n_), ld(ld_), kend(pad16(n_)), ldt(ld_ + 128) {
     LYAP_REQUIRE(ld % 16 == 0 && kend <= ld, LYAP_E_INVAL, "blocked Schur solve: bad padding");
+    // subdiagonal of T, gathered on the device and copied back contiguously
     std::vector<double> sub(std::max(n - 1, 1), 0.0);
-    if (n > 1)
-      LYAP_HIP(hipMemcpy2DAsync(sub.data(), sizeof(double), T + ld, (ld + 1) * sizeof(double),
-                                sizeof(double), n - 1, hipMemcpyDeviceToHost, st));
+    if (n > 1) {
+      DevBuf subd(sub.size() * sizeof(double));
+      hipLaunchKernelGGL(k_subdiag, dim3((unsigned)((n - 1 + 255) / 256)), dim3(256), 0, st, T, ld,
+                         n, subd.as<double>());
+      LYAP_HIP(hipGetLastError());
+      LYAP_HIP(hipMemcpyAsync(sub.data(), subd.p, subd.bytes, hipMemcpyDeviceToHost, st));
+      LYAP_HIP(hipStreamSynchronize(st));
+    }
     Ttp.alloc((size_t)ld * ldt * sizeof(double));
     LYAP_HIP(hipMemsetAsync(Ttp.p, 0, Ttp.bytes, st));
     LYAP_HIP(hipMemcpy2DAsync(Ttp.p, ldt * sizeof(double), Tt, ld * sizeof(double),

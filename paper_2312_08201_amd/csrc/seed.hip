@@ -451,8 +451,12 @@ static void check_finite(const double* p, size_t count, const char* what) {
 
 static void upload_rows(double* dst, long dst_ld, const double* src_host_rowmajor, long rows,
                         long cols, hipStream_t s) {
-  LYAP_HIP(hipMemcpy2DAsync(dst, dst_ld * sizeof(double), src_host_rowmajor, cols * sizeof(double),
-                            cols * sizeof(double), rows, hipMemcpyHostToDevice, s));
+  // rows padded to dst_ld on the host, then one contiguous copy (the padding is zero)
+  std::vector<double> pad((size_t)rows * dst_ld, 0.0);
+  for (long i = 0; i < rows; ++i)
+    std::memcpy(&pad[(size_t)i * dst_ld], src_host_rowmajor + (size_t)i * cols, cols * sizeof(double));
+  LYAP_HIP(hipMemcpyAsync(dst, pad.data(), pad.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  LYAP_HIP(hipStreamSynchronize(s));
 }
 
 // Schur-basis seed: A0 = Z T Z^T (host Francis QR), precompute on the device.

@@ -351,7 +351,6 @@ constexpr int kXs = kPanel + 1;
 
 struct TileArgs {
   const double* T;    // n x ld row-major
-  const double* Tt;   // T^T row-major
   int n, ld;
   int I0, ni, J0, nj;
   const double* Cd;   // dense symmetric right-hand side (row-major, ld), or null
@@ -427,7 +426,6 @@ __global__ void __launch_bounds__(kTile) k_tile_lyap(TileArgs A) {
   const int b = blockIdx.x, q = threadIdx.x;
   const int ld = A.ld, I0 = A.I0, ni = A.ni, J0 = A.J0, nj = A.nj;
   const double* T = A.T;
-  const double* Tt = A.Tt;
   const bool live = q < ni;
   const int gi = I0 + (live ? q : 0);  // this lane's row of T and X
   double* xrow = Xt + q * kXs;
@@ -813,7 +811,7 @@ struct BlockedLyap {
           g.ldc = np;
           gemm_launch(g, st);
         }
-        TileArgs A{T,  Tt, n, ld, I0, Iend - I0, J0, Jend - J0, Cd, F, fstride, G, gstride, k,
+        TileArgs A{T,  n, ld, I0, Iend - I0, J0, Jend - J0, Cd, F, fstride, G, gstride, k,
                    haveP ? P : nullptr, haveQ ? Q : nullptr, np, X, xrows, Panel};
         hipLaunchKernelGGL(k_tile_lyap, dim3((unsigned)count), dim3(kTile), 0, st, A);
         LYAP_HIP(hipGetLastError());

@@ -233,9 +233,11 @@ lyap_status seed_full_X(lyap_seed seed, int64_t P, const double* Y_dev, double* 
  * principle applied to f(s) = det(I + D_p V^T (s I - A0)^-1 U) along the
  * imaginary axis (A0 is stable, so those eigenvalues are the zeros of f
  * there); V^T (i w - A0)^-1 U comes from the seed's eigenbasis on a frequency
- * grid shared by all p.  flag_dev[p] != 0 when the grid cannot vouch for the
- * count (bit 1: a phase step above pi/2, i.e. an eigenvalue of A(p) within
- * about a grid step of the axis; bit 2: f not near 1 at the last frequency;
+ * grid shared by all p, and phase steps above pi/2 (an eigenvalue of A(p) near
+ * the axis) are refined by direct evaluations in a second pass over the
+ * samples concerned.  flag_dev[p] != 0 when the count is still not certain
+ * (bit 1: a refined phase step still above pi/2, i.e. an eigenvalue of A(p)
+ * extremely close to the axis; bit 2: f not near 1 at the last frequency;
  * bit 4: the phase total is not close to a multiple of pi; bit 8: f = 0 at a
  * grid frequency); such samples are to be treated as not known to be stable.
  * d_dev: device P x r; count_dev, flag_dev: device P int32.  Work buffers are

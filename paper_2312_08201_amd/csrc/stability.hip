@@ -16,10 +16,14 @@
 // O(r^2 n) sum per frequency that every sample shares.  The phase is
 // followed on a frequency grid dense around every eigenvalue of A0 (steps of
 // |Re mu| / 4 within 4 |Re mu| of Im mu), uniform at 1/2048 of the spectral
-// radius over [0, 2 rho], and geometric out to 1000 (rho + 1).  A sample is
-// flagged when the grid cannot vouch for the count: a phase step above pi/2
-// (an eigenvalue of A(d) close to the axis), |f - 1| >= 1/2 at the last
-// frequency, or a total that is not within 1/4 of an integer multiple of pi.
+// radius over [0, 2 rho], and geometric out to 1000 (rho + 1).  A phase step
+// above pi/2 means an eigenvalue of A(d) close to the axis; the samples with
+// such a step get a second pass that splits each of those steps into 16
+// sub-steps with f evaluated directly from the eigen expansion, and splits
+// again where a sub-step still exceeds pi/2 (four levels, 16^4 times finer).
+// A sample stays flagged when that does not resolve it, when |f - 1| >= 1/2
+// at the last frequency, or when the total is not within 1/4 of an integer
+// multiple of pi.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -173,6 +177,131 @@ __global__ void __launch_bounds__(256) k_stab_phase(const double* __restrict__ G
   pflag[t] = flag;
 }
 
+// f(i w) = det(I + D G(i w)) with G evaluated directly from the eigen expansion
+// (the same sum as k_stab_G, one thread)
+template <int R>
+__device__ inline void f_direct(const double* __restrict__ lam, const double* __restrict__ Uh,
+                                const double* __restrict__ Vh, int n, int h, int ld, double w,
+                                const double (&dp)[R], double& fr, double& fi) {
+  double G[R * R * 2];
+#pragma unroll
+  for (int e = 0; e < R * R * 2; ++e) G[e] = 0.0;
+  const int units = h + (n - 2 * h);
+  for (int u = 0; u < units; ++u) {
+    if (u < h) {
+      const int q = 2 * u;
+      const double al = lam[q], be = lam[ld + q];
+      const double d1i = w - be, n1 = al * al + d1i * d1i;
+      const double d2i = w + be, n2 = al * al + d2i * d2i;
+#pragma unroll
+      for (int a = 0; a < R; ++a) {
+        const double vr = Vh[(long)a * ld + q], vi = Vh[(long)a * ld + q + 1];
+#pragma unroll
+        for (int b = 0; b < R; ++b) {
+          const double ur = Uh[(long)b * ld + q], ui = Uh[(long)b * ld + q + 1];
+          const double zr = vr * ur - vi * ui, zi = vr * ui + vi * ur;
+          G[(a * R + b) * 2] += (-zr * al + zi * d1i) / n1 + (-zr * al - zi * d2i) / n2;
+          G[(a * R + b) * 2 + 1] += (-zi * al - zr * d1i) / n1 + (zi * al - zr * d2i) / n2;
+        }
+      }
+    } else {
+      const int q = 2 * h + (u - h);
+      const double al = lam[q];
+      const double nn = al * al + w * w;
+#pragma unroll
+      for (int a = 0; a < R; ++a)
+#pragma unroll
+        for (int b = 0; b < R; ++b) {
+          const double z = Vh[(long)a * ld + q] * Uh[(long)b * ld + q];
+          G[(a * R + b) * 2] += -z * al / nn;
+          G[(a * R + b) * 2 + 1] += -z * w / nn;
+        }
+    }
+  }
+  det_l<R>(G, dp, fr, fi);
+}
+
+struct StabSeed {
+  const double* lam;
+  const double* Uh;
+  const double* Vh;
+  int n, h, ld;
+};
+
+constexpr int kRefineSplit = 16;  // sub-intervals per refinement level
+
+// Phase change of f over [wa, wb] (f known at both ends), from kRefineSplit
+// direct evaluations; a sub-step above pi/2 is split again, DEPTH more times.
+// bad is set when a sub-step at the last level still exceeds pi/2.
+template <int DEPTH, int R>
+__device__ double phase_refined(const StabSeed& S, const double (&dp)[R], double wa, double wb,
+                                double far, double fai, double fbr, double fbi, int& bad) {
+  double sum = 0.0, pr = far, pim = fai, wp = wa;
+  for (int k = 1; k <= kRefineSplit; ++k) {
+    const double w = k == kRefineSplit ? wb : wa + (wb - wa) * k / kRefineSplit;
+    double fr, fi;
+    if (k == kRefineSplit) {
+      fr = fbr;
+      fi = fbi;
+    } else {
+      f_direct<R>(S.lam, S.Uh, S.Vh, S.n, S.h, S.ld, w, dp, fr, fi);
+    }
+    double step = atan2(fi * pr - fr * pim, fr * pr + fi * pim);
+    if (fabs(step) > 0.5 * M_PI) {
+      if constexpr (DEPTH > 0) step = phase_refined<DEPTH - 1, R>(S, dp, wp, w, pr, pim, fr, fi, bad);
+      else bad = 1;
+    }
+    sum += step;
+    pr = fr;
+    pim = fi;
+    wp = w;
+  }
+  return sum;
+}
+
+// Second pass for the samples idx[0..m-1] that the grid flagged: the whole
+// phase walk again, each step above pi/2 refined by direct evaluations.
+// Writes count and flag of those samples (flag keeps bits 2, 8 of the walk).
+template <int R>
+__global__ void __launch_bounds__(64) k_stab_refine(StabSeed S, const double* __restrict__ G,
+                                                    const double* __restrict__ omega, int L,
+                                                    const double* __restrict__ d,
+                                                    const int* __restrict__ idx, int m,
+                                                    int* __restrict__ count, int* __restrict__ flag) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= m) return;
+  const long p = idx[t];
+  double dp[R];
+#pragma unroll
+  for (int a = 0; a < R; ++a) dp[a] = d[p * R + a];
+  double pr, pim;
+  det_l<R>(G, dp, pr, pim);
+  int bad = 0, f = (pr == 0.0 && pim == 0.0) ? 8 : 0;
+  double sum = 0.0;
+  for (int l = 1; l < L; ++l) {
+    double fr, fi;
+    det_l<R>(G + (long)l * R * R * 2, dp, fr, fi);
+    double step = atan2(fi * pr - fr * pim, fr * pr + fi * pim);
+    if (fabs(step) > 0.5 * M_PI)
+      step = phase_refined<3, R>(S, dp, omega[l - 1], omega[l], pr, pim, fr, fi, bad);
+    if (fr == 0.0 && fi == 0.0) f |= 8;
+    sum += step;
+    pr = fr;
+    pim = fi;
+  }
+  {
+    const double er = pr - 1.0;
+    if (er * er + pim * pim >= 0.25) f |= 2;
+    sum += -atan2(pim, pr);
+  }
+  if (bad) f |= 1;
+  const double z = -sum / M_PI;
+  const double zr = rint(z);
+  if (fabs(z - zr) > 0.25 || zr < 0.0) f |= 4;
+  count[p] = zr < 0.0 ? 0 : (int)zr;
+  flag[p] = f;
+}
+
 __global__ void k_stab_reduce(const double* __restrict__ part, const int* __restrict__ pflag,
                               long P, int nchunk, int* __restrict__ count, int* __restrict__ flag) {
   const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -261,6 +390,35 @@ void unstable_impl(lyap_seed_s* sd, int64_t P, const double* d, int* count, int*
   hipLaunchKernelGGL(k_stab_reduce, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st,
                      part.as<double>(), pflag.as<int>(), (long)P, nchunk, count, flag);
   LYAP_HIP(hipGetLastError());
+  // second pass over the flagged samples: steps above pi/2 refined by direct evaluations
+  std::vector<int> fl(P);
+  LYAP_HIP(hipMemcpyAsync(fl.data(), flag, P * sizeof(int), hipMemcpyDeviceToHost, st));
+  LYAP_HIP(hipStreamSynchronize(st));
+  std::vector<int> idx;
+  for (int64_t p = 0; p < P; ++p)
+    if (fl[p] & 1) idx.push_back((int)p);
+  if (!idx.empty()) {
+    const int m = (int)idx.size();
+    DevBuf idd(idx.size() * sizeof(int));
+    LYAP_HIP(hipMemcpyAsync(idd.p, idx.data(), idd.bytes, hipMemcpyHostToDevice, st));
+    StabSeed S{sd->lam.as<double>(), sd->Uh.as<double>(), sd->Vh.as<double>(), n, h, (int)ld};
+    const dim3 grid((unsigned)((m + 63) / 64)), block(64);
+    const double* Gp = G.as<double>();
+    const double* wp = wd.as<double>();
+    const int* ip = idd.as<int>();
+    switch (r) {
+      case 1: hipLaunchKernelGGL(k_stab_refine<1>, grid, block, 0, st, S, Gp, wp, L, d, ip, m, count, flag); break;
+      case 2: hipLaunchKernelGGL(k_stab_refine<2>, grid, block, 0, st, S, Gp, wp, L, d, ip, m, count, flag); break;
+      case 3: hipLaunchKernelGGL(k_stab_refine<3>, grid, block, 0, st, S, Gp, wp, L, d, ip, m, count, flag); break;
+      case 4: hipLaunchKernelGGL(k_stab_refine<4>, grid, block, 0, st, S, Gp, wp, L, d, ip, m, count, flag); break;
+      case 5: hipLaunchKernelGGL(k_stab_refine<5>, grid, block, 0, st, S, Gp, wp, L, d, ip, m, count, flag); break;
+      case 6: hipLaunchKernelGGL(k_stab_refine<6>, grid, block, 0, st, S, Gp, wp, L, d, ip, m, count, flag); break;
+      case 7: hipLaunchKernelGGL(k_stab_refine<7>, grid, block, 0, st, S, Gp, wp, L, d, ip, m, count, flag); break;
+      default: hipLaunchKernelGGL(k_stab_refine<8>, grid, block, 0, st, S, Gp, wp, L, d, ip, m, count, flag); break;
+    }
+    LYAP_HIP(hipGetLastError());
+    LYAP_HIP(hipStreamSynchronize(st));
+  }
   LYAP_HIP(hipStreamSynchronize(st));  // the work buffers are freed on return
 }
 

@@ -5,7 +5,9 @@ the open right half-plane must equal the oracle's count from the dense
 spectrum, wherever the sample's rightmost eigenvalue is not within 1e-6 of
 the imaginary axis and the filter did not flag the sample.  Flags are
 allowed only where the rightmost eigenvalue is within eight steps of the
-uniform frequency grid (1/2048 of the spectral radius) of the axis.
+uniform frequency grid (1/2048 of the spectral radius) of the axis, and on at
+most 1% of the samples (the refinement pass resolves the others; the lightly
+damped chains were flagged at 8-11% without it).
 """
 import numpy as np
 import pytest
@@ -41,6 +43,8 @@ def _check(L, pr, min_unstable=0.05):
     print("flagged %.3f, near-axis %.3f, max |Re| flagged %s" %
           (np.mean(fl), np.mean(near), np.max(np.abs(rm[fl])) if fl.any() else None))
     assert np.all(near[fl]), [(int(i), float(rm[i]), int(flag[i])) for i in np.flatnonzero(fl & ~near)[:5]]
+    # the refinement pass leaves few samples uncertain (none on these cases when last measured)
+    assert np.mean(fl) <= 0.01, np.mean(fl)
     bad = np.flatnonzero(clear & (cnt != ref))
     assert bad.size == 0, [(int(i), int(cnt[i]), int(ref[i]), float(rm[i])) for i in bad[:5]]
     assert np.mean(ref > 0) >= min_unstable and np.mean(ref == 0) > 0.05

@@ -240,7 +240,7 @@ lyap_status seed_full_X(lyap_seed seed, int64_t P, const double* Y_dev, double* 
  * extremely close to the axis; bit 2: f not near 1 at the last frequency;
  * bit 4: the phase total is not close to a multiple of pi; bit 8: f = 0 at a
  * grid frequency); such samples are to be treated as not known to be stable.
- * d_dev: device P x r; count_dev, flag_dev: device P int32.  Work buffers are
+ * d_dev: device P x r (P < 2^31); count_dev, flag_dev: device P int32.  Work buffers are
  * allocated per call; the call synchronises the stream.  LYAP_E_UNSUPPORTED
  * for a Schur-basis or projected seed, or r > 8. */
 lyap_status seed_unstable_count(lyap_seed seed, int64_t P, const double* d_dev, int32_t* count_dev,

@@ -353,7 +353,7 @@ void launch_phase(const double* G, int L, const double* d, long P, int nchunk, d
 
 void unstable_impl(lyap_seed_s* sd, int64_t P, const double* d, int* count, int* flag,
                    hipStream_t st) {
-  LYAP_REQUIRE(P >= 0, LYAP_E_INVAL, "P < 0");
+  LYAP_REQUIRE(P >= 0 && P < (1LL << 31), LYAP_E_INVAL, "P out of [0, 2^31)");
   if (P == 0) return;
   LYAP_REQUIRE(d && count && flag, LYAP_E_INVAL, "null pointer");
   LYAP_REQUIRE(sd->basis == LYAP_BASIS_EIG, LYAP_E_UNSUPPORTED,

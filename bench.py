@@ -339,10 +339,11 @@ def importance_bench(args, L, torch, W):
         return pr.U, pr.V, pr.B, pr.E
 
     print("importance sweep: %d agents x %d samples" % (K, d.shape[0]), file=sys.stderr, flush=True)
-    IMP.importance_sweep(A0, agents[:1], factors, d[:64])          # warm-up
+    meth = args.importance_method
+    IMP.importance_sweep(A0, agents[:1], factors, d[:64], method=meth)          # warm-up
     torch.cuda.synchronize()
     t = time.perf_counter()
-    res = IMP.importance_sweep(A0, agents, factors, d)
+    res = IMP.importance_sweep(A0, agents, factors, d, method=meth)
     wall = time.perf_counter() - t
     filt_bad = filt_n = h2_n = 0
     h2_err = 0.0
@@ -361,6 +362,7 @@ def importance_bench(args, L, torch, W):
     solved = int(np.isfinite(res.h2).sum())
     print(json.dumps({
         "importance": "196 agents (n=392), %d agents swept, 21^3 triples each" % K,
+        "method": meth,
         "samples": total, "wall_s": wall, "samples_per_s": total / wall,
         "stable_frac": solved / total, "unstable_frac": float(res.unstable.mean()),
         "uncertain_frac": float(res.uncertain.mean()),
@@ -461,6 +463,9 @@ def main():
     ap.add_argument("--importance", type=int, default=0,
                     help="instead: the agent-importance sweep (196 identical agents, n = 392, "
                          "21^3 parameter triples) over this many agents")
+    ap.add_argument("--importance-method", default="exact", choices=["exact", "ek"],
+                    help="with --importance: batched SMW solves or the projection framework "
+                         "(eps 1e-10, m_max 200, as in the paper's multi-agent example)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain copy of this many MiB (byte-counter calibration)")
     args = ap.parse_args()

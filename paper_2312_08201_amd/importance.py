@@ -9,9 +9,12 @@ paper's rightmost-eigenvalue filter; here ``Seed.unstable_count``, and samples
 it flags as uncertain are discarded as well).  For each v the agent with the
 largest H2 norm is the most important one.
 
-Each agent is one seed (A0 is shared, U_k, V_k, B_k and E_k are not); its stable
-samples are one batched SMW solve.  All arithmetic runs in the library; this
-module only drives seeds and does the bookkeeping.
+Each agent is one seed (A0 is shared, U_k, V_k, B_k and E_k are not).  Its stable
+samples are one batched SMW solve (method "exact"), or, as the paper does for this
+example, one sweep of the projection framework of Section 2.2 over an extended
+Krylov space of that agent's seed (method "ek", tolerance eps on the backward
+error, at most m_max blocks).  All arithmetic runs in the library; this module
+only drives seeds and does the bookkeeping.
 """
 from __future__ import annotations
 
@@ -38,8 +41,11 @@ class ImportanceResult:
 
 def importance_sweep(A0: np.ndarray, agents: Sequence[int],
                      factors: Callable[[int], Tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]],
-                     d: np.ndarray, opts: L.SolveOpts = None) -> ImportanceResult:
+                     d: np.ndarray, opts: L.SolveOpts = None, method: str = "exact",
+                     eps: float = 1e-10, m_max: int = 200) -> ImportanceResult:
     """factors(k) -> (U_k, V_k, B_k, E_k); d: (P, r) host parameter rows shared by all agents."""
+    if method not in ("exact", "ek"):
+        raise ValueError("method must be 'exact' or 'ek'")
     torch = L._torch()
     d = np.ascontiguousarray(d, dtype=np.float64)
     K, P = len(agents), d.shape[0]
@@ -64,11 +70,16 @@ def importance_sweep(A0: np.ndarray, agents: Sequence[int],
         uncertain[j] = (flag != 0).cpu().numpy()
         idx = torch.nonzero(keep).flatten()
         if idx.numel() > 0:
+            ii = idx.cpu().numpy()
             t = time.perf_counter()
-            _, res = seed.solve(dd.index_select(0, idx).contiguous(), opts)
+            if method == "exact":
+                _, res = seed.solve(dd.index_select(0, idx).contiguous(), opts)
+            else:
+                ek = L.EKSpace.from_seed(seed, A0, U, V, E)
+                res = ek.sweep(d[ii], eps, m_max, opts=opts)
+                ek.close()
             torch.cuda.synchronize()
             secs["solve"] += time.perf_counter() - t
-            ii = idx.cpu().numpy()
             status[j, ii] = res["status"]
             ok = res["status"] == 0
             h2[j, ii[ok]] = np.sqrt(np.maximum(res["trace"][ok], 0.0))

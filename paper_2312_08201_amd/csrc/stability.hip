@@ -16,7 +16,8 @@
 // O(r^2 n) sum per frequency that every sample shares.  The phase is
 // followed on a frequency grid dense around every eigenvalue of A0 (steps of
 // |Re mu| / 4 within 4 |Re mu| of Im mu), uniform at 1/2048 of the spectral
-// radius over [0, 2 rho], and geometric out to 1000 (rho + 1).  A phase step
+// radius over [0, 2 rho], and geometric out to 1000 (rho + 1), or further for
+// large |d| (until ||D G|| is small enough that f cannot wind).  A phase step
 // above pi/2 means an eigenvalue of A(d) close to the axis; the samples with
 // such a step get a second pass that splits each of those steps into 16
 // sub-steps with f evaluated directly from the eigen expansion, and splits
@@ -319,8 +320,10 @@ __global__ void k_stab_reduce(const double* __restrict__ part, const int* __rest
   flag[p] = f;
 }
 
-// Frequencies (ascending, from 0) for the seed's spectrum.
-std::vector<double> stability_grid(const std::vector<double>& lam_h, int n, int h, long ld) {
+// Frequencies (ascending, from 0) for the seed's spectrum; the geometric tail
+// reaches at least `reach`.
+std::vector<double> stability_grid(const std::vector<double>& lam_h, int n, int h, long ld,
+                                   double reach) {
   std::vector<double> w{0.0};
   double amin = INFINITY, rho = 0.0;
   const int units = h + (n - 2 * h);
@@ -335,7 +338,7 @@ std::vector<double> stability_grid(const std::vector<double>& lam_h, int n, int 
     }
   }
   for (int j = 1; j <= 4096; ++j) w.push_back(2.0 * rho * j / 4096.0);
-  const double top = 1000.0 * (rho + 1.0);
+  const double top = std::max(1000.0 * (rho + 1.0), reach);
   for (double x = std::max(amin / 64.0, 1e-300); x < top; x *= 1.02) w.push_back(x);
   w.push_back(top);
   std::sort(w.begin(), w.end());
@@ -366,7 +369,36 @@ void unstable_impl(lyap_seed_s* sd, int64_t P, const double* d, int* count, int*
   LYAP_HIP(hipMemcpyAsync(lam_h.data(), sd->lam.p, 2 * ld * sizeof(double), hipMemcpyDeviceToHost,
                           st));
   LYAP_HIP(hipStreamSynchronize(st));
-  const std::vector<double> w = stability_grid(lam_h, n, h, ld);
+  // Beyond w, ||D G(i w)|| <= max|d| sum_mu ||Vh_mu|| ||Uh_mu|| / (w - rho); the tail
+  // reaches the w where that is 0.04, so |det(I + D G) - 1| < 1/2 for r <= 8.
+  double reach = 0.0;
+  {
+    std::vector<double> dh((size_t)P * r), uh((size_t)r * ld), vh((size_t)r * ld);
+    LYAP_HIP(hipMemcpyAsync(dh.data(), d, dh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipMemcpyAsync(uh.data(), sd->Uh.p, uh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipMemcpyAsync(vh.data(), sd->Vh.p, vh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    LYAP_HIP(hipStreamSynchronize(st));
+    double dmax = 0.0, wsum = 0.0, rho = 0.0;
+    for (double x : dh) dmax = std::max(dmax, std::fabs(x));
+    const int units = h + (n - 2 * h);
+    for (int u = 0; u < units; ++u) {
+      const bool pair = u < h;
+      const int q = pair ? 2 * u : 2 * h + (u - h);
+      double nu = 0.0, nv = 0.0;
+      for (int a = 0; a < r; ++a) {
+        nu += uh[(size_t)a * ld + q] * uh[(size_t)a * ld + q];
+        nv += vh[(size_t)a * ld + q] * vh[(size_t)a * ld + q];
+        if (pair) {
+          nu += uh[(size_t)a * ld + q + 1] * uh[(size_t)a * ld + q + 1];
+          nv += vh[(size_t)a * ld + q + 1] * vh[(size_t)a * ld + q + 1];
+        }
+      }
+      wsum += (pair ? 2.0 : 1.0) * std::sqrt(nu * nv);
+      rho = std::max(rho, std::hypot(lam_h[q], lam_h[ld + q]));
+    }
+    reach = rho + 25.0 * dmax * wsum;
+  }
+  const std::vector<double> w = stability_grid(lam_h, n, h, ld, reach);
   const int L = (int)w.size();
   const int nchunk = (L - 1 + kStabChunk - 1) / kStabChunk;
   DevBuf wd(w.size() * sizeof(double)), G((size_t)L * r * r * 2 * sizeof(double)),

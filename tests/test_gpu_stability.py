@@ -82,3 +82,21 @@ def test_schur_seed_is_unsupported(L):
     seed = L.Seed.from_problem(pr, basis="schur")
     with pytest.raises(L.LyapError):
         seed.unstable_count(torch.tensor(pr.d, dtype=torch.float64, device="cuda"))
+
+
+def test_edge_samples(L):
+    """P = 1; d = 0 (A(p) = A0, stable); very large negative d (eigenvalues far
+    in the right half-plane, at most r of them moved); all in one call too."""
+    import torch
+    pr = W.small_multiagent(30, 2, 2, 1)
+    seed = L.Seed.from_problem(pr)
+    rows = [np.zeros(pr.r), np.full(pr.r, -1e3), np.full(pr.r, -50.0), np.full(pr.r, 1e3)]
+    D = np.stack(rows)
+    for single in rows:
+        cnt, flag = seed.unstable_count(torch.tensor(single[None, :], device="cuda"))
+        ref = S.unstable_count(pr.A0, pr.U, pr.V, single)
+        assert int(flag[0]) == 0 and int(cnt[0]) == ref, (single[0], int(cnt[0]), ref)
+    cnt, flag = seed.unstable_count(torch.tensor(D, device="cuda"))
+    ref, _ = S.sweep(pr.A0, pr.U, pr.V, D)
+    assert np.array_equal(cnt.cpu().numpy(), ref) and not flag.cpu().numpy().any()
+    assert ref[0] == 0 and 0 < ref[1] <= pr.r

@@ -73,3 +73,25 @@ def test_serving_requests():
     assert 0.15 < reused / len(reqs) < 0.45
     pr = W.request_problem(reqs[0])
     assert pr.P == reqs[0].P and pr.r == reqs[0].r
+
+
+def test_agent_importance_generator():
+    """The agent-importance workload: deterministic, A0 symmetric and stable
+    (identical symmetric agents, symmetric coupling), grid rows (v1, v2, v2, v3),
+    the update touching agent k's block only, B and E on agent k."""
+    A0 = W.agent_network(12, seed=5)
+    assert np.array_equal(A0, W.agent_network(12, seed=5))
+    assert np.allclose(A0, A0.T) and np.max(np.linalg.eigvalsh(A0)) < 0
+    d = W.agent_grid(step=5.0)
+    assert d.shape == (125, 4) and np.array_equal(d[:, 1], d[:, 2])
+    assert np.allclose(np.unique(d[:, 0]), [-9.9, -4.9, 0.1, 5.1, 10.1])
+    assert W.agent_grid().shape == (21 ** 3, 4)
+    k = 7
+    pr = W.agent_problem(A0, k, d)
+    delta = pr.A_of(3) - A0
+    mask = np.zeros_like(A0, dtype=bool)
+    mask[2 * k:2 * k + 2, 2 * k:2 * k + 2] = True
+    assert np.all(delta[~mask] == 0)
+    v1, v2, v3 = d[3, 0], d[3, 1], d[3, 3]
+    assert np.allclose(delta[mask].reshape(2, 2), -np.array([[v1, v2], [v2, v3]]))
+    assert np.count_nonzero(pr.B) == 4 and np.flatnonzero(pr.E).tolist() == [2 * k, 2 * k + 1]

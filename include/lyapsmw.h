@@ -238,7 +238,7 @@ lyap_status seed_full_X(lyap_seed seed, int64_t P, const double* Y_dev, double* 
  * samples concerned.  flag_dev[p] != 0 when the count is still not certain
  * (bit 1: a refined phase step still above pi/2, i.e. an eigenvalue of A(p)
  * extremely close to the axis; bit 2: f not near 1 at the last frequency;
- * bit 4: the phase total is not close to a multiple of pi; bit 8: f = 0 at a
+ * bit 4: the phase total is not close to a multiple of pi, or not finite; bit 8: f = 0 at a
  * grid frequency); such samples are to be treated as not known to be stable.
  * d_dev: device P x r (P < 2^31); count_dev, flag_dev: device P int32.  Work buffers are
  * allocated per call; the call synchronises the stream.  LYAP_E_UNSUPPORTED

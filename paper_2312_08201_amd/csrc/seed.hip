@@ -582,6 +582,7 @@ static lyap_seed_s* factor_schur(int64_t n, int64_t r, int64_t s, const double* 
     LYAP_HIP(hipStreamSynchronize(st));
     for (auto& v : tmp) v *= -0.5;
     LYAP_HIP(hipMemcpyAsync(Bhm.p, tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice, st));
+    LYAP_HIP(hipStreamSynchronize(st));  // tmp is read by the copy until it completes
   }
   // Xs0: T Xs0 + Xs0 T^T = -Bs Bs^T
   DevBuf X0s(mat);
@@ -653,8 +654,8 @@ static lyap_seed_s* factor_schur(int64_t n, int64_t r, int64_t s, const double* 
     for (auto& v : g) v *= 2.0;
     zeros(sd->gam, r);
     LYAP_HIP(hipMemcpyAsync(sd->gam.p, g.data(), g.size() * 8, hipMemcpyHostToDevice, st));
+    LYAP_HIP(hipStreamSynchronize(st));  // g is read by the copy until it completes
   }
-  LYAP_HIP(hipStreamSynchronize(st));
   sd->t0 = t0;
   if (proj) apply_projected_rhs(sd, proj, st);
   // small seeds: the capacitance operator as one dense matrix (one GEMM per
@@ -872,6 +873,38 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
   // kept for full solutions: rows of B^T Tin (rho(Q0^-1 B)^T, or B^T Z in the Schur basis)
   sd->Bh.alloc(Bh.bytes);
   LYAP_HIP(hipMemcpyAsync(sd->Bh.p, Bh.p, Bh.bytes, hipMemcpyDeviceToDevice, st));
+  // Self-check of the uploaded factors: the device rows of rho(Q0^-1 U), V^T S and
+  // rho(Q0^-1 B) against the same products formed on the host from the host
+  // copies.  A factor that reached the device damaged (zeros, stale data) would
+  // otherwise give wrong traces without any error.
+  {
+    auto check_rows = [&](const DevBuf& dev, const std::vector<double>& xt, long rows,
+                          const std::vector<double>& Tm, const char* what) {
+      std::vector<double> got((size_t)rows * ld), want((size_t)rows * ld, 0.0);
+      LYAP_HIP(hipMemcpyAsync(got.data(), dev.p, got.size() * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+      LYAP_HIP(hipStreamSynchronize(st));
+      for (long a = 0; a < rows; ++a)
+        for (int i = 0; i < N; ++i) {
+          const double x = xt[(size_t)a * n + i];
+          if (x == 0.0) continue;
+          const double* trow = &Tm[(size_t)i * ld];
+          double* w = &want[(size_t)a * ld];
+          for (int q = 0; q < N; ++q) w[q] += x * trow[q];
+        }
+      double num = 0.0, den = 0.0;
+      for (size_t k = 0; k < got.size(); ++k) {
+        num += (got[k] - want[k]) * (got[k] - want[k]);
+        den += want[k] * want[k];
+      }
+      LYAP_REQUIRE(std::isfinite(num) && num <= 1e-16 * den, LYAP_E_DEVICE,
+                   std::string("seed self-check failed: device ") + what +
+                       " differs from the host product");
+    };
+    check_rows(sd->Uh, Ut, r, Tin_h, "rho(Q0^-1 U)");
+    check_rows(sd->Vh, Vt, r, S_h, "V^T S");
+    check_rows(Bh, Bt, std::min<long>(s, 16), Tin_h, "rho(Q0^-1 B)");  // first rows suffice
+  }
 
   // ---- K1 = the exact block-diagonal part of the capacitance operator ----
   zeros(sd->K1, r * r);
@@ -932,6 +965,7 @@ static lyap_seed_s* factor_impl(int64_t n, int64_t r, int64_t s, const double* A
     Wrows.alloc(W_h.size() * sizeof(double));
     LYAP_HIP(hipMemcpyAsync(ES.p, ES_h.data(), ES.bytes, hipMemcpyHostToDevice, st));
     LYAP_HIP(hipMemcpyAsync(Wrows.p, W_h.data(), Wrows.bytes, hipMemcpyHostToDevice, st));
+    LYAP_HIP(hipStreamSynchronize(st));  // ES_h and W_h are read by the copies until they complete
   } else {
     // symmetric part of E, then ES = E_sym S (transform GEMM), all rows
     std::vector<double> Es_h((size_t)ld * ld, 0.0);

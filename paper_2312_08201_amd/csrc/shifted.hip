@@ -200,6 +200,7 @@ void shifted_impl(lyap_seed_s* sd, int64_t P, const double* d_host, const lyap_s
     std::vector<double> g0((size_t)P * (mmax + 1), 0.0);
     for (int64_t p = 0; p < P; ++p) g0[(size_t)p] = beta_h;  // element 0 of every shift
     LYAP_HIP(hipMemcpyAsync(g.p, g0.data(), g.bytes, hipMemcpyHostToDevice, st));
+    LYAP_HIP(hipStreamSynchronize(st));  // g0 is read by the copy until it completes
   }
   const int sgrid = (int)((P + NT - 1) / NT);
   int steps = 0;

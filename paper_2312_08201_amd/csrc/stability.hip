@@ -298,8 +298,9 @@ __global__ void __launch_bounds__(64) k_stab_refine(StabSeed S, const double* __
   if (bad) f |= 1;
   const double z = -sum / M_PI;
   const double zr = rint(z);
-  if (fabs(z - zr) > 0.25 || zr < 0.0) f |= 4;
-  count[p] = zr < 0.0 ? 0 : (int)zr;
+  // a non-finite total (NaN or Inf along the walk) fails the comparison and is flagged
+  if (!(fabs(z - zr) <= 0.25) || zr < 0.0) f |= 4;
+  count[p] = (zr >= 0.0 && zr < 2147483647.0) ? (int)zr : 0;
   flag[p] = f;
 }
 
@@ -315,8 +316,9 @@ __global__ void k_stab_reduce(const double* __restrict__ part, const int* __rest
   }
   const double z = -sum / M_PI;
   const double zr = rint(z);
-  if (fabs(z - zr) > 0.25 || zr < 0.0) f |= 4;
-  count[p] = zr < 0.0 ? 0 : (int)zr;
+  // a non-finite total (NaN or Inf along the walk) fails the comparison and is flagged
+  if (!(fabs(z - zr) <= 0.25) || zr < 0.0) f |= 4;
+  count[p] = (zr >= 0.0 && zr < 2147483647.0) ? (int)zr : 0;
   flag[p] = f;
 }
 
@@ -379,7 +381,10 @@ void unstable_impl(lyap_seed_s* sd, int64_t P, const double* d, int* count, int*
     LYAP_HIP(hipMemcpyAsync(vh.data(), sd->Vh.p, vh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     LYAP_HIP(hipStreamSynchronize(st));
     double dmax = 0.0, wsum = 0.0, rho = 0.0;
-    for (double x : dh) dmax = std::max(dmax, std::fabs(x));
+    for (double x : dh) {
+      LYAP_REQUIRE(std::isfinite(x), LYAP_E_INVAL, "d has a non-finite entry");
+      dmax = std::max(dmax, std::fabs(x));
+    }
     const int units = h + (n - 2 * h);
     for (int u = 0; u < units; ++u) {
       const bool pair = u < h;

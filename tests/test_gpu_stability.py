@@ -100,3 +100,17 @@ def test_edge_samples(L):
     ref, _ = S.sweep(pr.A0, pr.U, pr.V, D)
     assert np.array_equal(cnt.cpu().numpy(), ref) and not flag.cpu().numpy().any()
     assert ref[0] == 0 and 0 < ref[1] <= pr.r
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_non_finite_parameter_is_rejected(L, bad):
+    """A NaN or infinite parameter entry makes the whole call an argument error
+    (status LYAP_E_INVAL) instead of samples reported as certified stable."""
+    import torch
+    pr = W.small_multiagent(30, 2, 2, 1)
+    seed = L.Seed.from_problem(pr)
+    D = np.zeros((3, pr.r))
+    D[1, 0] = bad
+    with pytest.raises(L.LyapError) as e:
+        seed.unstable_count(torch.tensor(D, device="cuda"))
+    assert e.value.status == 1

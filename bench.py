@@ -1,10 +1,14 @@
 #!/usr/bin/env python3
 """Benchmark: trace(E X(p)) evaluations per second on one MI355X.
 
-Default workload (the headline configuration): damped mass-spring chain with
-d = 1000 masses (n = 2000), two grounded dampers (r = 2), the 32 x 32
-log-spaced viscosity grid (P = 1024 parameter pairs), B = n x 8 Gaussian,
-E = diag(I_d, 0), FP64.  Synthetic, seeded inputs (gen/workloads.py).
+Default workload (the headline configuration, the largest one-GPU sweep):
+damped mass-spring chain with d = 2000 masses (n = 4000), three grounded
+dampers at random DOFs (r = 3), 256 log-uniform viscosity triples on
+[1e-2, 1e2], B = n x 16 Gaussian, E = diag(I_d, 0), FP64.  The same sweep is
+also timed in the two mixed-precision modes (FP32 and split-BF16 Krylov
+products with FP64 refinement) and, as the plain baseline, one parameter per
+call (no batching across parameters).  Synthetic, seeded inputs
+(gen/workloads.py).
 
 One step = the whole online stage for one sweep: smw_solve_batch over all P
 parameters (capacitance solves, every Krylov product a Cauchy contraction on
@@ -113,22 +117,73 @@ def stored_traffic(config, prec):
             float(kv["write_kib_avg"]) * float(kv["write_scale"])) * 1024.0
 
 
+def host_cpu():
+    """CPU model and the cores this process may use (for the baseline records)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return model, int(cores)
+
+
 def cpu_baseline(pr, idx):
-    """The oracle as it stands, on this host's cores, for a few parameters of the workload."""
+    """The oracle as it stands, on this host's cores, for a few parameters of the workload
+    solved one after another with the host BLAS using every core."""
     from oracle import lyap_bs as O
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
     except Exception:
         threads = os.cpu_count()
+    model, _ = host_cpu()
     t = time.perf_counter()
     traces = [O.solve_one(pr.A0, pr.U, pr.V, pr.B, pr.E, pr.d[i], diagnostics=False).trace
               for i in idx]
     dt = time.perf_counter() - t
     return {"value": len(idx) / dt, "unit": "evals/s", "cores": int(threads), "kind": "oracle",
-            "sample": "%d parameters (indices %s) of the same workload, one after another, "
-                      "complex-Schur Bartels-Stewart, %.1f s wall, multithreaded host BLAS"
-                      % (len(idx), idx, dt)}, traces
+            "cpu_model": model,
+            "sample": "%d parameter(s) (indices %s) of the same workload, one after another, "
+                      "complex-Schur Bartels-Stewart, %.1f s wall, host BLAS on %d threads"
+                      % (len(idx), idx, dt, threads)}, traces
+
+
+def _oracle_worker(args):
+    config, i = args
+    from threadpoolctl import threadpool_limits
+    from gen import workloads as W
+    from oracle import lyap_bs as O
+    pr = W.config(config)
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        tr = O.solve_one(pr.A0, pr.U, pr.V, pr.B, pr.E, pr.d[i], diagnostics=False).trace
+        return i, tr, time.perf_counter() - t
+
+
+def cpu_baseline_per_core(config, P, workers):
+    """The oracle one parameter per core: `workers` processes, each with single-threaded
+    BLAS, over `workers` parameters spread across the sweep; evals/s = count / wall."""
+    import multiprocessing as mp
+    model, cores = host_cpu()
+    idx = sorted({(P * (2 * k + 1)) // (2 * workers) for k in range(workers)})
+    ctx = mp.get_context("spawn")
+    t = time.perf_counter()
+    with ctx.Pool(len(idx)) as pool:
+        out = pool.map(_oracle_worker, [(config, i) for i in idx])
+    wall = time.perf_counter() - t
+    return {"value": len(idx) / wall, "unit": "evals/s", "cores": len(idx), "kind": "oracle",
+            "cpu_model": model, "host_cores_visible": cores,
+            "per_solve_s": [round(o[2], 1) for o in out],
+            "sample": "%d parameters (indices %s), one per core in %d processes with "
+                      "single-threaded BLAS, %.1f s wall" % (len(idx), idx, len(idx), wall)}, \
+        {o[0]: o[1] for o in out}
 
 
 # The paper's own timings for this path (MATLAB, unstated laptop, FP64): context only,
@@ -191,25 +246,62 @@ def streamed_sweeps(L, torch, seed, pr, opts, sweeps, traces):
             "note": "sweeps queued on one engine (continuous batching); value above is isolated sweeps"}
 
 
-def per_parameter_baseline(L, torch, pr, traces, count=2):
-    """Plain FP64 per-parameter solve through the same library: each A(p) is factored as
-    its own seed (host eigendecomposition, device Cauchy solve); trace(E X(p)) is that
-    seed's t0.  No SMW correction, no Krylov iteration."""
+def per_parameter_baseline(L, torch, seed, pr, traces, count=16):
+    """The plain FP64 per-parameter solve on the same GPU: the same seed, the same
+    FP64 SMW + Krylov path, but one parameter per smw_solve_batch call, so that nothing
+    is batched across parameters.  `count` parameters spread over the sweep, one after
+    another; evals/s = count / wall."""
     P = pr.P
-    idx = [(P * (k + 1)) // (count + 1) for k in range(count)]
+    idx = [(P * (2 * k + 1)) // (2 * count) for k in range(count)]
+    dd = [torch.tensor(pr.d[i:i + 1], dtype=torch.float64, device="cuda") for i in idx]
+    opts = L.solve_opts()
+    Y, _ = seed.solve(dd[0], opts)          # warm: the one-slot engine and its graph
+    seed.trace(Y)
     torch.cuda.synchronize()
+    got, iters = [], []
     t = time.perf_counter()
-    got = []
-    for i in idx:
-        sd = L.Seed(pr.A_of(i), pr.U, pr.V, pr.B, pr.E)
-        got.append(sd.info()["t0"])
-        sd.release()
+    for d in dd:
+        Y, res = seed.solve(d, opts)
+        got.append(seed.trace(Y))
+        iters.append(int(res["iters"][0]))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
-    return {"value": len(idx) / dt, "unit": "evals/s",
-            "kind": "per-parameter seed_factor of A(p) (no SMW, no Krylov)",
-            "sample": "%d parameters (indices %s), %.2f s" % (len(idx), idx, dt),
-            "rel_diff_vs_smw": float(max(abs(g - traces[i]) / abs(g) for g, i in zip(got, idx)))}
+    got = torch.cat(got).cpu().numpy()
+    return {"value": count / dt, "unit": "evals/s",
+            "kind": "FP64 SMW + Krylov, one parameter per call (no batching across parameters)",
+            "sample": "%d parameters (indices %s..%s), %.3f s, mean %.1f Krylov products"
+                      % (count, idx[0], idx[-1], dt, float(np.mean(iters))),
+            "max_rel_diff_vs_batched": float(np.max(np.abs(got - traces[idx]) / np.abs(traces[idx])))}
+
+
+def sweep_mode(L, torch, seed, pr, d, prec, steps, gold_idx, gold_ref):
+    """Isolated sweeps of the workload in another precision mode: evals/s, the roofline
+    of its Cauchy GEMM and the sampled error against the stored oracle values."""
+    opts = L.solve_opts(prec=prec)
+    Y, res = seed.solve(d, opts)
+    seed.trace(Y)
+    torch.cuda.synchronize()
+    L.profile_enable(1)
+    t = time.perf_counter()
+    for _ in range(steps):
+        Y, res = seed.solve(d, opts)
+        tr = seed.trace(Y)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    prof = L.profile_read()
+    L.profile_enable(False)
+    traces = tr.cpu().numpy()
+    out = {"value": pr.P * steps / wall, "unit": "evals/s", "ms_per_step": 1e3 * wall / steps,
+           "all_converged": bool(np.all(res["status"] == 0)),
+           "iters_mean": float(np.mean(res["iters"])), "iters_max": int(np.max(res["iters"])),
+           "max_rel_err_sampled": float(np.max(np.abs(traces[gold_idx] - gold_ref) /
+                                               np.abs(gold_ref))) if len(gold_idx) else None}
+    if prof["gemmlo_launches"] > 0:
+        ach = prof["gemmlo_flops"] / (prof["gemmlo_ms"] * 1e-3) / 1e12
+        out["cauchy_gemm"] = {"achieved_tflops": ach, "peak_tflops": PEAK[prec],
+                              "frac": ach / PEAK[prec],
+                              "avg_launch_us": 1e3 * prof["gemmlo_ms"] / prof["gemmlo_launches"]}
+    return out, traces
 
 
 def ek_bench(args, L, torch, W, seed, pr, factor_s):
@@ -424,7 +516,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_ir", "bf16_ir", "fp32"])
     ap.add_argument("--restart", type=int, default=40)
     ap.add_argument("--basis", default="auto", choices=["auto", "eig", "schur"],
@@ -434,6 +526,13 @@ def main():
     ap.add_argument("--recycle-k", type=int, default=0,
                     help="GCRO-DR recycle space dimension (0: restarted GMRES)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-per-core", type=int, default=0,
+                    help="instead of the default CPU sample: the oracle on this many parameters, "
+                         "one per core with single-threaded BLAS (minutes at n = 4000)")
+    ap.add_argument("--modes", default="fp32_ir,bf16_ir",
+                    help="other precision modes timed on the same sweep (comma list, '' for none)")
+    ap.add_argument("--per-param", type=int, default=16,
+                    help="parameters of the one-parameter-per-call FP64 baseline (0: skip)")
     ap.add_argument("--optimize", action="store_true",
                     help="instead: the viscosity optimisation loop on the workload's seed "
                          "(Nelder-Mead from 100, tol 1e-4), without and with recycling")
@@ -571,13 +670,14 @@ def main():
 
     # error against stored oracle values (written by tests/golden/make_golden.py)
     max_rel = None
+    gidx, gref = [], np.zeros(0)
     gold_path = os.path.join(ROOT, "tests", "golden", "oracle_traces.json")
     if os.path.exists(gold_path):
         gold = json.load(open(gold_path)).get("c%d" % args.config)
         if gold:
-            idx = [g["index"] for g in gold["samples"]]
-            ref = np.array([g["trace"] for g in gold["samples"]])
-            max_rel = float(np.max(np.abs(traces[idx] - ref) / np.abs(ref)))
+            gidx = [g["index"] for g in gold["samples"]]
+            gref = np.array([g["trace"] for g in gold["samples"]])
+            max_rel = float(np.max(np.abs(traces[gidx] - gref) / np.abs(gref)))
 
     out = {
         "metric": METRIC,
@@ -599,6 +699,7 @@ def main():
         "p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "all_converged": ok,
         "max_rel_err_sampled": max_rel,
+        "oracle_samples": len(gidx),
         "iters_mean": float(np.mean(res["iters"])),
         "iters_max": int(np.max(res["iters"])),
         "seed_factor_s": factor_s,
@@ -629,13 +730,40 @@ def main():
                 "krylov": prof["krylov_ms"] / (1e3 * wall)}
     if args.stream_sweeps > 0:
         out["streamed"] = streamed_sweeps(L, torch, seed, pr, opts, args.stream_sweeps, traces)
-    # the plain per-parameter solve on the same GPU path (no SMW, no Krylov)
-    out["gpu_per_parameter_baseline"] = per_parameter_baseline(L, torch, pr, traces)
+    # the same sweep in the mixed-precision modes (FP64 refinement to the same tolerance)
+    modes = [m for m in args.modes.split(",") if m and m != args.prec]
+    if modes:
+        out["modes"] = {}
+        for m in modes:
+            print("timing mode %s" % m, file=sys.stderr, flush=True)
+            rec, mtr = sweep_mode(L, torch, seed, pr, d, m, max(1, args.steps), gidx, gref)
+            rec["max_rel_diff_vs_%s" % args.prec] = float(np.max(np.abs(mtr - traces) /
+                                                               np.abs(traces)))
+            out["modes"][m] = rec
+        best = max(out["modes"].items(), key=lambda kv: kv[1]["value"])
+        out["best_mixed"] = {"mode": best[0], "value": best[1]["value"],
+                             "vs_fp64_batched": best[1]["value"] / value}
+    # the plain FP64 per-parameter solve on the same GPU (one parameter per call)
+    if args.per_param > 0:
+        print("timing the one-parameter-per-call baseline", file=sys.stderr, flush=True)
+        pp = per_parameter_baseline(L, torch, seed, pr, traces, count=min(args.per_param, P))
+        pp["batched_fp64_over_this"] = value / pp["value"]
+        if "best_mixed" in out:
+            pp["best_mixed_over_this"] = out["best_mixed"]["value"] / pp["value"]
+        out["gpu_per_parameter_baseline"] = pp
     out["paper_context"] = PAPER_CONTEXT
-    if not args.no_cpu_baseline:
-        # about 15 s of oracle work: its time per solve grows like n^3 (about 5 s at n = 2000)
+    if args.cpu_per_core > 0:
+        print("oracle, one parameter per core on %d cores" % args.cpu_per_core, file=sys.stderr,
+              flush=True)
+        cb, ct = cpu_baseline_per_core(args.config, P, args.cpu_per_core)
+        cb["rel_diff_vs_gpu"] = float(max(abs(c - traces[i]) / abs(c) for i, c in ct.items()))
+        out["cpu_baseline"] = cb
+    elif not args.no_cpu_baseline:
+        # a bounded sample: its time per solve grows like n^3 (about 5 s at n = 2000 on all
+        # cores); at n = 4000 a single parameter already takes about a minute
         count = int(min(P, max(1, round(15.0 / (5.0 * (pr.n / 2000.0) ** 3)))))
         idx = sorted({(P // 2 + 5 + k * (P // count)) % P for k in range(count)})
+        print("oracle on %d parameter(s)" % len(idx), file=sys.stderr, flush=True)
         cb, ctraces = cpu_baseline(pr, idx)
         cb["rel_diff_vs_gpu"] = float(max(abs(c - traces[i]) / abs(c) for c, i in zip(ctraces, idx)))
         out["cpu_baseline"] = cb

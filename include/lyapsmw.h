@@ -170,6 +170,22 @@ size_t seed_device_bytes(lyap_seed seed);
 lyap_status lyap_seed_apply(lyap_seed seed, int64_t batch, const double* Y_dev, double* G_dev,
                             int32_t prec, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and results as lyap_seed_apply, which grows a work area on the
+ * seed when a batch needs more; this variant allocates nothing.  Its work
+ * area is a fixed array of 32 MiB per GPU, held from the first call on that
+ * GPU until the process ends.  The work area takes (3 r + 2 r^2) ld 8 bytes
+ * per batch entry for an eigenbasis seed and (3 r + ld) ld 8 bytes for a
+ * Schur-basis seed (ld = n rounded up to a multiple of 128); a batch that
+ * needs more returns LYAP_E_INVAL before any launch.  The seed's device must
+ * be the current device (LYAP_E_INVAL otherwise).  Every call on one GPU
+ * uses the same area: calls that overlap on one GPU (other streams, other
+ * threads) race and must be serialised by the caller.  Only enqueues work;
+ * the area is cleared by a kernel at the start of each call. */
+lyap_status lyap_seed_apply_noalloc(lyap_seed seed, int64_t batch, const double* Y_dev,
+                                    double* G_dev, int32_t prec, void* hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* Online stage (Table 1, right column).                                     */
 /* ------------------------------------------------------------------------ */

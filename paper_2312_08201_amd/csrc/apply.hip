@@ -8,6 +8,15 @@
 //   trace_EX:        trace(E X(p)) = t0 + 2 <Gamma^T, Y(p)>
 #include "internal.h"
 
+#include <mutex>
+
+// Work area of lyap_seed_apply_noalloc: one copy per GPU, alive until the
+// process ends.  Host code never passes this name to a kernel or a copy: it
+// stands for the host-side shadow, not the device address.  The device
+// address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
 namespace lyap {
 
 namespace {
@@ -90,26 +99,42 @@ void gemm64(const double* A, long lda, const double* B, long ldb, double* C, lon
   gemm_launch(g, s);
 }
 
-void apply_impl(lyap_seed_s* sd, long long batch, const double* Y, double* G, int prec,
-                hipStream_t st) {
+__global__ void k_zero(double* __restrict__ p, long count) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (long)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// Bytes of work area one call needs (pads of every row must start at zero).
+size_t apply_work_bytes(const lyap_seed_s* sd, long long batch) {
+  const long long r = sd->r, ld = sd->ld;
+  const size_t rowb = ld * sizeof(double);
+  if (sd->basis == LYAP_BASIS_SCHUR)
+    return (size_t)(3 * batch * r) * rowb + (size_t)batch * ld * rowb;
+  return (size_t)(3 * batch * r + 2 * batch * r * r) * rowb;
+}
+
+void apply_check(long long batch, const double* Y, double* G, int prec) {
   LYAP_REQUIRE(batch >= 1, LYAP_E_INVAL, "batch < 1");
   LYAP_REQUIRE(Y && G, LYAP_E_INVAL, "NULL buffer");
   LYAP_REQUIRE(prec == LYAP_PREC_FP64, LYAP_E_UNSUPPORTED, "lyap_seed_apply: only FP64");
+}
+
+// The work: `work` holds at least apply_work_bytes(sd, batch) bytes of device memory.
+void apply_core(lyap_seed_s* sd, long long batch, const double* Y, double* G, double* work,
+                hipStream_t st) {
   const long long r = sd->r, n = sd->n, ld = sd->ld, h = sd->h;
+  const size_t need = apply_work_bytes(sd, batch);
+  // pads must be zero: clear the whole area once per call (stream ordered; a fill
+  // kernel rather than a memset node, so the call can be captured in a graph)
+  hipLaunchKernelGGL(k_zero, dim3(1024), dim3(256), 0, st, work, (long)(need / sizeof(double)));
   if (sd->basis == LYAP_BASIS_SCHUR) {
     // Ys = Y Z ; T Xs + Xs T^T = Us Ys + Ys^T Us^T ; G = (Vs^T Xs) Z^T
     const long long rows1 = batch * r;
-    const size_t rowb = ld * sizeof(double);
-    const size_t need = (size_t)(3 * rows1) * rowb + (size_t)batch * ld * rowb;
-    if (sd->scratch_bytes < need) {
-      sd->scratch.alloc(need);
-      sd->scratch_bytes = need;
-    }
-    double* Yp = sd->scratch.as<double>();
+    double* Yp = work;
     double* Ys = Yp + rows1 * ld;
     double* Gs = Ys + rows1 * ld;
     double* Xs = Gs + rows1 * ld;
-    LYAP_HIP(hipMemsetAsync(Yp, 0, need, st));
     const int ub = (int)std::min<long long>((n + 255) / 256, 64);
     hipLaunchKernelGGL(k_pad_rows, dim3(ub, rows1), dim3(256), 0, st, Yp, (long)ld, Y, (long)n,
                        (int)n);
@@ -124,19 +149,11 @@ void apply_impl(lyap_seed_s* sd, long long batch, const double* Y, double* G, in
     return;
   }
   const long long rows1 = batch * r, rows2 = batch * r * r;
-  const size_t rowb = ld * sizeof(double);
-  const size_t need = (size_t)(3 * rows1 + 2 * rows2) * rowb;
-  if (sd->scratch_bytes < need) {
-    sd->scratch.alloc(need);
-    sd->scratch_bytes = need;
-  }
-  double* Yp = sd->scratch.as<double>();
+  double* Yp = work;
   double* Yh = Yp + rows1 * ld;
   double* Gh = Yh + rows1 * ld;
   double* X = Gh + rows1 * ld;
   double* H = X + rows2 * ld;
-  // pads must be zero: clear the whole area once per call (stream ordered)
-  LYAP_HIP(hipMemsetAsync(Yp, 0, need, st));
   const int ub = (int)std::min<long long>((n + 255) / 256, 64);
   hipLaunchKernelGGL(k_pad_rows, dim3(ub, rows1), dim3(256), 0, st, Yp, (long)ld, Y, (long)n, (int)n);
   gemm64(Yp, ld, sd->Tin.as<double>(), ld, Yh, ld, rows1, ld, ld, ld, st);
@@ -147,6 +164,50 @@ void apply_impl(lyap_seed_s* sd, long long batch, const double* Y, double* G, in
                      sd->K1.as<double>(), sd->Uh.as<double>(), (int)r, (int)h, (int)n, (int)ld);
   gemm64(Gh, ld, sd->Tout.as<double>(), ld, G, n, rows1, ld, ld, n, st);
   LYAP_HIP(hipGetLastError());
+}
+
+void apply_impl(lyap_seed_s* sd, long long batch, const double* Y, double* G, int prec,
+                hipStream_t st) {
+  apply_check(batch, Y, G, prec);
+  const size_t need = apply_work_bytes(sd, batch);
+  if (sd->scratch_bytes < need) {
+    sd->scratch.alloc(need);
+    sd->scratch_bytes = need;
+  }
+  apply_core(sd, batch, Y, G, sd->scratch.as<double>(), st);
+}
+
+// Device address of `scratch` on each device, taken once per device with that
+// device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+double* noalloc_scratch(int device) {
+  LYAP_REQUIRE(device >= 0 && device < kMaxDevices, LYAP_E_DEVICE, "device index out of range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    LYAP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    LYAP_REQUIRE(p != nullptr, LYAP_E_DEVICE, "no device address for the no-alloc work area");
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[device];
+}
+
+void apply_noalloc(lyap_seed_s* sd, long long batch, const double* Y, double* G, int prec,
+                   hipStream_t st) {
+  apply_check(batch, Y, G, prec);
+  const size_t need = apply_work_bytes(sd, batch);
+  LYAP_REQUIRE(need <= kNoAllocScratchBytes, LYAP_E_INVAL,
+               "lyap_seed_apply_noalloc: the batch needs " + std::to_string(need) +
+                   " bytes of work area, more than the fixed " +
+                   std::to_string(kNoAllocScratchBytes) + "; use a smaller batch");
+  int dev = -1;
+  LYAP_HIP(hipGetDevice(&dev));
+  LYAP_REQUIRE(dev == sd->device, LYAP_E_INVAL,
+               "lyap_seed_apply_noalloc: the current device is not the seed's device");
+  apply_core(sd, batch, Y, G, noalloc_scratch(dev), st);
 }
 
 __global__ void k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, long count) {
@@ -174,6 +235,13 @@ lyap_status lyap_seed_apply(lyap_seed sd, int64_t batch, const double* Y_dev, do
                             int32_t prec, void* hip_stream) {
   if (!sd) return LYAP_E_INVAL;
   LYAP_TRY(apply_impl(sd, batch, Y_dev, G_dev, prec, (hipStream_t)hip_stream));
+  return LYAP_OK;
+}
+
+lyap_status lyap_seed_apply_noalloc(lyap_seed sd, int64_t batch, const double* Y_dev,
+                                    double* G_dev, int32_t prec, void* hip_stream) {
+  if (!sd) return LYAP_E_INVAL;
+  LYAP_TRY(apply_noalloc(sd, batch, Y_dev, G_dev, prec, (hipStream_t)hip_stream));
   return LYAP_OK;
 }
 

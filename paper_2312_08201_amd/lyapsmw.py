@@ -89,6 +89,7 @@ _lib = None
 
 # exported symbols of include/lyapsmw.h (checked by the CPU tests)
 EXPORTS = ["seed_factor", "seed_info", "seed_release", "seed_device_bytes", "lyap_seed_apply",
+           "lyap_seed_apply_noalloc",
            "smw_workspace_bytes", "smw_solve_batch", "trace_EX", "engine_create",
            "engine_device_bytes", "engine_destroy", "engine_submit", "engine_run",
            "engine_harvest", "engine_launch", "engine_status", "lyap_status_string", "lyap_last_error", "lyap_profile_enable",
@@ -115,6 +116,7 @@ def load(path: str = LIB_PATH):
     lib.seed_device_bytes.argtypes = [vp]
     lib.seed_device_bytes.restype = C.c_size_t
     lib.lyap_seed_apply.argtypes = [vp, i64, vp, vp, i32, vp]
+    lib.lyap_seed_apply_noalloc.argtypes = [vp, i64, vp, vp, i32, vp]
     lib.smw_workspace_bytes.argtypes = [vp, i64, C.POINTER(SolveOpts)]
     lib.smw_workspace_bytes.restype = C.c_size_t
     lib.smw_solve_batch.argtypes = [vp, i64, vp, C.POINTER(SolveOpts), vp, C.POINTER(Result), vp,
@@ -149,7 +151,8 @@ def load(path: str = LIB_PATH):
     lib.ek_release.argtypes = [vp]
     lib.lyap_last_error.argtypes = []
     lib.lyap_last_error.restype = C.c_char_p
-    for name in ("seed_factor", "seed_info", "seed_release", "lyap_seed_apply", "smw_solve_batch",
+    for name in ("seed_factor", "seed_info", "seed_release", "lyap_seed_apply",
+                 "lyap_seed_apply_noalloc", "smw_solve_batch",
                  "trace_EX", "engine_create", "engine_destroy", "engine_submit", "engine_run",
                  "engine_harvest", "engine_launch", "engine_status", "lyap_profile_read",
                  "lyap_calib_copy", "seed_full_X", "smw_solve_shifted", "seed_x0v", "ek_create", "ek_set_level", "ek_solve",
@@ -285,6 +288,16 @@ class Seed:
         st = load().lyap_seed_apply(self.h, batch, _dev_ptr(Y), _dev_ptr(G), PREC[prec],
                                     _stream(stream))
         _check(st, "lyap_seed_apply")
+        return G
+
+    def apply_noalloc(self, Y, G, prec="fp64", stream=None):
+        """lyap_seed_apply_noalloc into the caller's G (no device allocation)."""
+        batch = Y.shape[0]
+        _dev_ptr(Y, shape=(batch, self.r, self.n))
+        _dev_ptr(G, shape=(batch, self.r, self.n))
+        st = load().lyap_seed_apply_noalloc(self.h, batch, _dev_ptr(Y), _dev_ptr(G), PREC[prec],
+                                            _stream(stream))
+        _check(st, "lyap_seed_apply_noalloc")
         return G
 
     # ---- online stage ----

@@ -280,17 +280,22 @@ def agent_grid(step: float = 1.0, lo: float = -9.9, hi: float = 10.1) -> np.ndar
 
 def agent_problem(A0: np.ndarray, k: int, d: np.ndarray, name: str = "") -> Problem:
     """Agent k varied: A(v) = A0 - B_l diag(v1, v2, v2, v3) B_r^T with B_l, B_r
-    nonzero in agent k's two rows; the disturbance enters agent k only
-    (B = e_k kron B_a) and E = e_k kron I_2 weighs agent k's states."""
+    nonzero in agent k's two rows.
+
+    The squared H2 norm of the map from the disturbance of agent k to the
+    outputs of all agents is trace(Ed Ed^T Xo) with A^T Xo + Xo A = -C^T C,
+    Ed = e_k kron I_2 and C = diag(C_1, ..., C_m) (Section 3.2).  The same
+    number is trace(C^T C Xc) with A Xc + Xc A^T = -Ed Ed^T, the form
+    A X + X A^T = -B B^T, trace(E X) used here: B = e_k kron I_2 (s = 2) and
+    E = C^T C = I_m kron (B_a B_a^T) = 2 I (the agents' C_i = B_a^T)."""
     n = A0.shape[0]
     U = np.zeros((n, 4))
     V = np.zeros((n, 4))
     U[2 * k:2 * k + 2] = AGENT_BL
     V[2 * k:2 * k + 2] = AGENT_BR
     B = np.zeros((n, 2))
-    B[2 * k:2 * k + 2] = AGENT_B
-    E = np.zeros(n)
-    E[2 * k:2 * k + 2] = 1.0
+    B[2 * k:2 * k + 2] = np.eye(2)
+    E = np.tile(np.diag(AGENT_B @ AGENT_B.T), n // 2)
     return Problem(name or "agent%d" % k, A0, U, V, B, E, np.ascontiguousarray(d),
                    dict(kind="agent_importance", agent=k))
 

@@ -94,4 +94,35 @@ def test_agent_importance_generator():
     assert np.all(delta[~mask] == 0)
     v1, v2, v3 = d[3, 0], d[3, 1], d[3, 3]
     assert np.allclose(delta[mask].reshape(2, 2), -np.array([[v1, v2], [v2, v3]]))
-    assert np.count_nonzero(pr.B) == 4 and np.flatnonzero(pr.E).tolist() == [2 * k, 2 * k + 1]
+    Bk = np.zeros_like(pr.B)
+    Bk[2 * k:2 * k + 2] = np.eye(2)
+    assert np.array_equal(pr.B, Bk) and np.allclose(pr.E, 2.0)
+
+
+def test_agent_importance_h2_is_the_output_norm_of_all_agents():
+    """The importance workload's trace(E X) is the squared H2 norm of the map
+    from agent k's disturbance to the outputs of all agents, as Section 3.2
+    defines it: trace(Ed^T Xo Ed) with A^T Xo + Xo A = -C^T C, Ed = e_k kron I_2,
+    C = diag(C_1, ..., C_m), C_i = B_a^T.  The generator uses the equal
+    controllability form; this pins it to the printed one on a small network."""
+    import scipy.linalg as sla
+    from oracle import lyap_bs as O
+    m, k = 9, 4
+    A0 = W.agent_network(m, seed=3)
+    d = W.agent_grid(step=5.0)[[10, 60]]
+    pr = W.agent_problem(A0, k, d)
+    C = np.kron(np.eye(m), W.AGENT_B.T)
+    Ed = np.zeros((2 * m, 2))
+    Ed[2 * k:2 * k + 2] = np.eye(2)
+    for i in range(d.shape[0]):
+        A = pr.A_of(i)
+        Xo = sla.solve_continuous_lyapunov(A.T, -(C.T @ C))
+        h2 = np.trace(Ed.T @ Xo @ Ed)
+        got = O.solve_one(pr.A0, pr.U, pr.V, pr.B, pr.E, pr.d[i], diagnostics=False).trace
+        assert abs(got - h2) <= 1e-12 * abs(h2), (i, got, h2)
+        # the previous reading (only agent k's own output) differs
+        Ck = C.copy()
+        Ck[:2 * k] = 0
+        Ck[2 * k + 2:] = 0
+        Xk = sla.solve_continuous_lyapunov(A.T, -(Ck.T @ Ck))
+        assert abs(np.trace(Ed.T @ Xk @ Ed) - h2) > 1e-3 * abs(h2)

@@ -152,3 +152,93 @@ def test_planted_mistakes_are_caught(monkeypatch):
     monkeypatch.setattr(O, "triangular_lyapunov", good)
     X, _ = O.lyapunov_bs(A, C)
     assert np.linalg.norm(X - Xk) <= 1e-12 * np.linalg.norm(Xk)
+
+
+def _mp_lyapunov(mp, A0, U, V, d, B):
+    """X(p) at 50 digits from the double inputs: A = A0 - U diag(d) V^T and the
+    Kronecker form of the definition, both formed in mpmath."""
+    n = A0.shape[0]
+    A = mp.matrix(A0.tolist()) - mp.matrix(U.tolist()) * mp.diag(d.tolist()) * mp.matrix(V.tolist()).T
+    K = mp.zeros(n * n, n * n)
+    for j in range(n):
+        for i in range(n):
+            for k in range(n):
+                K[j * n + i, j * n + k] += A[i, k]      # (I kron A) vec X, column-major vec
+                K[j * n + i, k * n + i] += A[j, k]      # (A kron I) vec X
+    Bm = mp.matrix(B.tolist())
+    C = -(Bm * Bm.T)
+    c = mp.matrix([C[i, j] for j in range(n) for i in range(n)])
+    x = mp.lu_solve(K, c)
+    return np.array([[float(x[j * n + i]) for j in range(n)] for i in range(n)])
+
+
+def _ill_conditioned(n=6, seed=3):
+    """A lightly damped oscillator pair (eigenvalues -1e-4 +- 5i) and other modes,
+    under a nonorthogonal similarity, with a rank-2 update of small weight: the
+    Lyapunov operator's condition number is about 1e5."""
+    rng = np.random.default_rng(seed)
+    D = np.zeros((n, n))
+    D[0:2, 0:2] = [[-1e-4, 5.0], [-5.0, -1e-4]]
+    for i in range(2, n):
+        D[i, i] = -rng.uniform(0.5, 2.0)
+    Sm = np.eye(n) + 0.3 * rng.standard_normal((n, n))
+    A0 = Sm @ D @ np.linalg.inv(Sm)
+    U = rng.standard_normal((n, 2))
+    V = rng.standard_normal((n, 2))
+    d = np.array([1e-6, -2e-6])
+    B = rng.standard_normal((n, 2))
+    return A0, U, V, d, B
+
+
+@pytest.mark.parametrize("case", ["random", "ill"])
+def test_refinement_reaches_extended_precision(case):
+    """One step of refinement with the long-double residual agrees with a
+    50-digit solve of the definition to 1e-15 (relative, Frobenius), also where
+    the plain solve is off by more."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 50
+    if case == "random":
+        pr = W.random_stable(6, 2, 3, 1, 11)
+        A0, U, V, d, B = pr.A0, pr.U, pr.V, pr.d[0], pr.B
+    else:
+        A0, U, V, d, B = _ill_conditioned()
+    Xm = _mp_lyapunov(mp, A0, U, V, d, B)
+    X0, _ = O.lyapunov_refined(A0, U, V, d, B, 0)
+    X1, _ = O.lyapunov_refined(A0, U, V, d, B, 1)
+    e0 = np.linalg.norm(X0 - Xm) / np.linalg.norm(Xm)
+    e1 = np.linalg.norm(X1 - Xm) / np.linalg.norm(Xm)
+    assert e1 <= 1e-15, (e0, e1)
+    if case == "ill":
+        assert e0 > 10 * e1, (e0, e1)   # the plain solve is measurably off here
+    # the trace through solve_one
+    E = np.ones(A0.shape[0])
+    r1 = O.solve_one(A0, U, V, B, E, d, diagnostics=False, refine=1)
+    assert abs(r1.trace - np.trace(Xm)) <= 1e-15 * abs(np.trace(Xm)) * 10
+
+
+def test_refinement_planted_mistakes_are_caught(monkeypatch):
+    """A residual without the low-rank update, with the opposite sign, or with
+    B B^T subtracted, makes the refined solution miss the 50-digit one by far
+    more than the correct step does (<= 1e-15)."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 50
+    A0, U, V, d, B = _ill_conditioned()
+    Xm = _mp_lyapunov(mp, A0, U, V, d, B)
+    good = O.extended_residual
+
+    def no_update(A0_, U_, V_, d_, BBt, X):
+        return good(A0_, U_, V_, np.zeros_like(d_), BBt, X)
+
+    def flipped(A0_, U_, V_, d_, BBt, X):
+        return -good(A0_, U_, V_, d_, BBt, X)
+
+    def rhs_sign(A0_, U_, V_, d_, BBt, X):
+        return good(A0_, U_, V_, d_, -BBt, X)
+
+    for bad in (no_update, flipped, rhs_sign):
+        monkeypatch.setattr(O, "extended_residual", bad)
+        X1, _ = O.lyapunov_refined(A0, U, V, d, B, 1)
+        assert np.linalg.norm(X1 - Xm) > 1e-12 * np.linalg.norm(Xm), bad.__name__
+    monkeypatch.setattr(O, "extended_residual", good)
+    X1, _ = O.lyapunov_refined(A0, U, V, d, B, 1)
+    assert np.linalg.norm(X1 - Xm) <= 1e-15 * np.linalg.norm(Xm)

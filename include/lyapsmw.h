@@ -82,7 +82,10 @@ typedef enum {
 typedef struct {
   int32_t basis;          /* lyap_basis */
   int32_t E_is_diag;      /* 1: E is an n-vector (diagonal); 0: E is dense n x n (symmetrised) */
-  double max_eig_cond;    /* AUTO switches to the Schur basis above this (default 1e6 if <= 0) */
+  double max_eig_cond;    /* AUTO switches to the Schur basis when the eigenbasis condition
+                             estimate ||S||_1 ||S^-1||_1 exceeds this (default 1e5 if <= 0;
+                             the refined eigenbasis route kept trace errors below 1e-12 up to
+                             1.3e5 and first exceeded 1e-10 at 5e5 on nearly defective seeds) */
   int32_t tsvd_rank;      /* rank pbar of the truncated SVD of the dense coupling block that
                              completes the preconditioner of eq:prec (Section 2.1); 0 (default)
                              keeps only its exact block-diagonal part; at most 64; eigenbasis
@@ -92,6 +95,13 @@ typedef struct {
                              GEMM per Krylov step; assembly: r n quasi-triangular solves of
                              size n); -1 keeps the per-slot quasi-triangular solve in every
                              step (no (r ld)^2 memory) */
+  int32_t seed_refine;    /* eigen basis only: steps of fixed-precision iterative refinement
+                             of the seed quantities every parameter shares -- t0, c0 and the
+                             trace weights are formed from the explicit seed solution X0 and
+                             adjoint solution G, each refined with its FP64 residual in
+                             physical coordinates (a few n x n GEMMs per step, once per seed).
+                             0 (default) = 1 step, -1 = none (quantities straight from the
+                             eigenbasis), 1..4 = that many steps */
 } lyap_seed_opts;
 
 typedef struct {
@@ -119,6 +129,15 @@ typedef struct {
   int32_t refinements;    /* FP64 refinement steps that were followed by an inner solve */
   double rel_residual;    /* final FP64 relative residual of the capacitance system */
   double trace;           /* trace(E X(p)) from the eigen-coordinate solution */
+  double err_est;         /* estimated relative error of trace, twice the first-order
+                             estimate 2 (eps_seed (max(1, |t0| / |trace|) + kappa (1 + g))
+                             + kappa rel_residual), g = ||y - D c0|| / ||D c0|| the
+                             strength of the low-rank correction (y the capacitance solution),
+                             eps_seed = the seed's measured eigenbasis error (relative
+                             change of t0 under the seed refinement), kappa = a condition
+                             estimate of the preconditioned capacitance system from the
+                             last Krylov cycle; NaN for an unrefined seed (seed_refine =
+                             -1), a Schur-basis seed, or the shifted-family solve */
 } lyap_result;
 
 typedef struct {
@@ -131,6 +150,9 @@ typedef struct {
   double min_lam_sum;     /* min |lambda_i + lambda_j| / max |lambda_i + lambda_j| */
   double max_re_lambda;   /* largest real part of the seed spectrum */
   double t0;              /* trace(E X0) of the seed equation (eq:seedLE) */
+  double t0_unrefined;    /* t0 straight from the eigenbasis, before seed_refine */
+  double eps_seed;        /* |t0_unrefined - t0| / |t0| (NaN if not refined) */
+  int32_t seed_refine;    /* refinement steps applied (0: none) */
   double factor_seconds;  /* host wall time of seed_factor */
   size_t device_bytes;
 } lyap_seed_info;
@@ -190,10 +212,12 @@ lyap_status lyap_seed_apply_noalloc(lyap_seed seed, int64_t batch, const double*
 /* Online stage (Table 1, right column).                                     */
 /* ------------------------------------------------------------------------ */
 
-/* Device workspace smw_solve_batch needs for P parameters; 0 if the seed or the
- * options are not supported by the engine (lyap_last_error says why).  The
- * Krylov kernel holds one capacitance vector per workgroup: r * ld <= 16384,
- * ld = n rounded up to a multiple of 128. */
+/* Device workspace smw_solve_batch needs for P parameters: every buffer of the
+ * batched Krylov engine (basis, iterates, preconditioner blocks, GEMM operands,
+ * device queue) plus the solution store, exactly what the call uses; 0 if the
+ * seed or the options are not supported by the engine (lyap_last_error says
+ * why).  The Krylov kernel holds one capacitance vector per workgroup:
+ * r * ld <= 16384, ld = n rounded up to a multiple of 128. */
 size_t smw_workspace_bytes(lyap_seed seed, int64_t P, const lyap_solve_opts* opts);
 
 /* Solve the capacitance system for P parameters.
@@ -201,9 +225,19 @@ size_t smw_workspace_bytes(lyap_seed seed, int64_t P, const lyap_solve_opts* opt
  *               zero is allowed (the system is used in the form (I - D K) Y = D c0).
  *   Y_dev     : device P x r x n output, Y(p) = D(p) V^T X(p) (physical coordinates).
  *   res_host  : host array of P results (status, iterations, residual, trace).
- *   workspace : device buffer of at least smw_workspace_bytes(seed, P, opts) bytes.
+ *   workspace : device buffer of at least smw_workspace_bytes(seed, P, opts) bytes,
+ *               256-byte aligned, or NULL.  Given a workspace, the call carves every
+ *               engine buffer from it and allocates no device memory of its own; the
+ *               seed keeps the engine's captured step graphs for the next call with
+ *               the same P, options and workspace, which then only resets the
+ *               engine's state (no allocation, no capture).  The workspace must stay
+ *               allocated while the seed may reuse it (until a call with another
+ *               workspace, P or options, or seed_release).  With NULL, the seed
+ *               allocates and owns the engine and the solution store
+ *               (seed_device_bytes counts them).
  * All P parameters are batched: slots of the Krylov engine are filled with
- * parameters in order and refilled as parameters converge. */
+ * parameters in order and refilled as parameters converge.  The call
+ * synchronises the stream (the host polls the engine's progress). */
 lyap_status smw_solve_batch(lyap_seed seed, int64_t P, const double* d_dev,
                             const lyap_solve_opts* opts, double* Y_dev, lyap_result* res_host,
                             void* workspace_dev, size_t workspace_bytes, void* hip_stream);

@@ -74,11 +74,20 @@ struct DevBuf {
     }
     bytes = b;
   }
+  // a view of memory owned elsewhere (e.g. a caller's workspace): never freed here
+  void view(void* ptr, size_t b) {
+    release();
+    p = ptr;
+    bytes = b;
+    owned = false;
+  }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    owned = true;
   }
+  bool owned = true;
   ~DevBuf() { release(); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
@@ -88,12 +97,15 @@ struct DevBuf {
 // Split-K factor of a dynamic-M GEMM launch: when only a few row tiles are
 // active (a tail of the sweep), idle workgroups take K-slices of the same
 // tiles; partial products go to a separate buffer and the consumer sums the
-// KS slices in fixed order.  Same formula on host and device.
+// KS slices in fixed order.  Same formula on host and device; at most
+// kMaxSplit slices.
+constexpr int kMaxSplit = 16;
 __host__ __device__ inline int splitk_of(int m_active_tiles, int ntiles, int grid, int nk) {
   const int tiles = m_active_tiles * ntiles;
   if (tiles <= 0) return 1;
   int ks = 1;
-  while (ks < 16 && tiles * ks * 2 <= grid && nk % (ks * 2) == 0 && nk / (ks * 2) >= 4) ks *= 2;
+  while (ks < kMaxSplit && tiles * ks * 2 <= grid && nk % (ks * 2) == 0 && nk / (ks * 2) >= 4)
+    ks *= 2;
   return ks;
 }
 

@@ -47,7 +47,7 @@ enum Phase : int { PH_FREE = 0, PH_ARNOLDI = 1, PH_RESTART = 2, PH_RECYC = 3, PH
 // rebuild for a new parameter, BANK: which of the two U/C banks is current)
 enum SI : int {
   SI_PHASE = 0, SI_J, SI_ITERS, SI_CYCLES, SI_REFINE, SI_QPOS, SI_KCUR, SI_RJ, SI_BANK, SI_CAPSET,
-  SI_PINV, SI_N
+  SI_PINV, SI_COMB, SI_N
 };
 constexpr int kPbarMax = 64;  // TSVD rank bound of the preconditioner
 constexpr int kTsvdGrid = 256;  // workgroup budget of the skinny TSVD GEMM (split-K)
@@ -58,12 +58,16 @@ constexpr int kTsvdGrid = 256;  // workgroup budget of the skinny TSVD GEMM (spl
 // holds twice the padded rows; the TSVD GEMM (one column tile) holds
 // kTsvdGrid row tiles.
 constexpr int kPartRowsFactor = 2;
+// Launch budget and partial-buffer rows of the engine's Cauchy GEMM (the
+// autotuned budget; at most kPartRowsFactor row tiles of partials per tile).
+inline long long cauchy_grid_min(long long tuned, long long) { return tuned; }
+inline long long cauchy_part_rows(long long rows_pad) { return kPartRowsFactor * rows_pad; }
 // per-slot double state
 enum SD : int { SD_BNORM = 0, SD_BETA, SD_N };
 
 struct DevResult {  // one per queue position
   int status, iters, cycles, refines;
-  double relres, trace;
+  double relres, trace, err_est;
   long long tag;
   int valid, pad;
 };
@@ -76,6 +80,7 @@ struct EngineArgs {
   const double* c0;
   const double* gam;
   double t0;
+  double eps_seed;  // relative forward error of the seed's eigenbasis route (NaN: unknown)
   int n, h, ld, r;
   int NV;  // per-slot vector stride: r * ld padded to a multiple of 512
   // engine
@@ -119,6 +124,13 @@ struct EngineArgs {
   double* Tpart;        // split-K partials of Tbuf
   double* Sc;           // list rows x 128: Cp^-1 Mt^T y
   double* Qc;           // list rows x Ks: Nt Cp^-1 Mt^T y
+  // split orthogonalisation (restarted GMRES): per slot and 512-element chunk
+  // of the slot vector, the chunk's partial projections and norms
+  int nchunk;           // NV / (2 x orth workgroup size)
+  double* orth1;        // S x nchunk x kPart: <v_k, w> chunk sums (k <= j), ||w||^2 last
+  double* orth1b;       // the same after the first pass
+  double* orth2;        // S x nchunk: ||w||^2 chunk sums after the second pass
+  double* ycoefs;       // S x (kMaxRestart + 1): cycle-end coefficients y (u += V y)
 };
 
 __device__ inline double* rec_u(const EngineArgs& A, int s, int bank, int l) {
@@ -173,12 +185,15 @@ __device__ inline int uslot(int u, int h, bool& pr) {
   return pr ? 2 * u : u + h;
 }
 
-// z_a[u] = sum_b P[a][b][u] o v_b[u] for one slot (all units, all a)
+// z_a[u] = sum_b P[a][b][u] o v_b[u] for one slot (all a), units u0 + threadIdx.x,
+// u0 + threadIdx.x + ustride, ... (default: all units by this workgroup)
 __device__ inline void apply_pinv(const EngineArgs& A, int s, const double* v, double* zout,
-                                  bool accumulate, const double* vscale = nullptr) {
+                                  bool accumulate, const double* vscale = nullptr, int u0 = 0,
+                                  int ustride = 0) {
   const int r = A.r, ld = A.ld, nu = A.n - A.h;
   const double* P = A.Pinv + (long)s * r * r * ld;
-  for (int u = threadIdx.x; u < nu; u += blockDim.x) {
+  if (ustride == 0) ustride = blockDim.x;
+  for (int u = u0 + threadIdx.x; u < nu; u += ustride) {
     bool pr;
     const int q = uslot(u, A.h, pr);
     for (int a = 0; a < r; ++a) {
@@ -417,6 +432,7 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
       o.iters = o.cycles = o.refines = 0;
       o.relres = NAN;
       o.trace = NAN;
+      o.err_est = NAN;
       o.tag = A.qtag[qi];
       __threadfence();
       o.valid = 1;
@@ -448,6 +464,7 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
       o.iters = o.cycles = o.refines = 0;
       o.relres = 0.0;
       o.trace = A.t0;
+      o.err_est = A.eps_seed;
       o.tag = A.qtag[qi];
       __threadfence();
       o.valid = 1;
@@ -494,14 +511,37 @@ __device__ inline int claim(const EngineArgs& A) {
   return -1;
 }
 
+// Result of slot s.  err_est, the estimated relative error of the trace:
+// twice the first-order estimate of the two error sources (the factor covers
+// the crudeness of kappa; measured errors on the parity workloads stayed below it):
+//   eps_seed (max(1, |t0| / |t|) + kappa (1 + ||D K y|| / ||b||))
+//        the seed's eigenbasis route: eps_seed is its relative forward error,
+//        measured once per seed by the refinement of t0; it enters t0 (scaled
+//        to |t|) and, through the capacitance operator that is not refined,
+//        the solve: an operator error of relative size eps_seed perturbs the
+//        system by about eps_seed ||D K y|| (= eps_seed ||y - b||), amplified by
+//        the condition number of the preconditioned system
+//   + kappa relres
+//        the capacitance residual left by the Krylov solve
+// kappa = the ratio of the largest to the smallest diagonal entry of the last
+// cycle's triangular factor (at least 1): an estimate of that condition number.
 __device__ void finish(const EngineArgs& A, int s, int status, double relres, double* lds) {
   const int r = A.r, ld = A.ld, N = r * ld;
   int* si = A.si + (long)s * SI_N;
   // the solution y = P^-1 u, formed by this step's prep for the residual
   const double* xs = A.z + (long)s * A.NV;
-  double acc = 0;
-  for (int e = threadIdx.x; e < N; e += blockDim.x) acc += A.gam[e] * xs[e];
-  const double tr = A.t0 + block_sum1(acc, lds);
+  const double* ds = A.d + (long)s * r;
+  double sums[3] = {0.0, 0.0, 0.0};  // <gam, y>, ||y - b||^2, ||b||^2 with b = D c0
+  for (int e = threadIdx.x; e < N; e += blockDim.x) {
+    const double y = xs[e], b = ds[e / ld] * A.c0[e];
+    sums[0] += A.gam[e] * y;
+    sums[1] += (y - b) * (y - b);
+    sums[2] += b * b;
+  }
+  block_sum<3>(sums, lds);
+  const double tr = A.t0 + sums[0];
+  // strength of the low-rank correction: (I - D K) y = b gives D K y = y - b
+  const double corr = sums[2] > 0.0 ? sqrt(sums[1] / sums[2]) : 0.0;
   const int qp = si[SI_QPOS];
   const int qi = qp % A.Q;
   const long long tag = A.qtag[qi];
@@ -518,6 +558,19 @@ __device__ void finish(const EngineArgs& A, int s, int status, double relres, do
     o.refines = si[SI_REFINE];
     o.relres = relres;
     o.trace = tr;
+    {
+      const int jl = si[SI_J];
+      const double* Rs = A.R + (long)s * A.m * (A.m + 1);
+      double dmax = 0.0, dmin = INFINITY;
+      for (int k = 0; k < jl && k < A.m; ++k) {
+        const double v = fabs(Rs[(long)k * (A.m + 1) + k]);
+        dmax = fmax(dmax, v);
+        dmin = fmin(dmin, v);
+      }
+      const double kappa = (jl > 0 && dmin > 0.0) ? fmax(1.0, dmax / dmin) : 1.0;
+      o.err_est = 2.0 * (A.eps_seed * (fmax(1.0, fabs(A.t0) / fabs(tr)) + kappa * (1.0 + corr)) +
+                         kappa * relres);
+    }
     o.tag = tag;
     __threadfence();
     o.valid = 1;
@@ -542,6 +595,7 @@ __global__ void __launch_bounds__(1024) k_lists(EngineArgs A) {
     const bool arn = ph == PH_ARNOLDI || ph == PH_RECYC;
     if (ph == PH_RESTART || (arn && !A.mixed)) ++n64;
     else if (arn) ++nlo;
+    A.si[(long)s * SI_N + SI_COMB] = 0;  // the previous step's cycle ends are combined
   }
   // inclusive Hillis-Steele scan of the per-thread counts
   c64[threadIdx.x] = n64;
@@ -575,7 +629,9 @@ __global__ void __launch_bounds__(1024) k_lists(EngineArgs A) {
   }
 }
 
-// z for every listed slot (both lists): workgroups stride over the entries
+// z for every listed slot (both lists): workgroups stride over the entries in
+// x; gridDim.y workgroups share one slot's units (one, with the TSVD part, whose
+// copy of y needs the whole slot)
 __global__ void __launch_bounds__(KT) k_prep(EngineArgs A) {
   const int S = A.S;
   const int c64 = A.lists[2 * S], clo = A.lists[2 * S + 1];
@@ -584,15 +640,20 @@ __global__ void __launch_bounds__(KT) k_prep(EngineArgs A) {
     const int s = li < c64 ? A.lists[li] : A.lists[S + (li - c64)];
     const int ph = A.si[(long)s * SI_N + SI_PHASE];
     double* zs = A.z + (long)s * A.NV;
-    if (threadIdx.x == 0) A.si[(long)s * SI_N + SI_PINV] = 0;  // blocks were built last step
+    // blocks were built last step; every chunk reads the phase before this
+    // launch's chunk 0 clears the flag, which no chunk reads
+    if (threadIdx.x == 0 && blockIdx.y == 0) A.si[(long)s * SI_N + SI_PINV] = 0;
     // source: the iterate u (residual step), v_j (Arnoldi) or a recycled u_rj
     const int* sis = A.si + (long)s * SI_N;
     const double* src = ph == PH_RESTART ? A.x + (long)s * A.NV
                         : ph == PH_RECYC ? rec_u(A, s, sis[SI_BANK], sis[SI_RJ])
                                          : A.V + ((long)s * (A.m + 1) + sis[SI_J]) * A.NV;
-    if (A.use_precond) apply_pinv(A, s, src, zs, false);
-    else
-      for (int e = threadIdx.x; e < N; e += blockDim.x) zs[e] = src[e];
+    if (A.use_precond) {
+      apply_pinv(A, s, src, zs, false, nullptr, blockIdx.y * blockDim.x, gridDim.y * blockDim.x);
+    } else {
+      for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < N; e += gridDim.y * blockDim.x)
+        zs[e] = src[e];
+    }
     if (A.pbar > 0) {
       __syncthreads();
       double* yc = A.Yc + (long)li * A.Ks;
@@ -1072,6 +1133,168 @@ __device__ void x_add_recycled(const EngineArgs& A, int s, int bank, int nvec, c
   store2<NE2, BT>(xs, tmp, 1.0);
 }
 
+// ---------------------------------------------------------------------------
+// Split orthogonalisation of the Arnoldi step (restarted GMRES): classical
+// Gram-Schmidt with one reorthogonalisation (CGS2).  A slot's vector is cut
+// into chunks of 512 values, one 256-thread workgroup per slot and chunk, so
+// that the streaming of the basis V_0..j uses the whole chip also when few
+// slots are active (one workgroup per slot leaves most CUs idle in a sweep's
+// tail):
+//   k_orth<0>  chunk partials of <v_k, w> (k <= j) and of ||w||^2        -> orth1
+//   k_orth<1>  h = sum of those partials (fixed order), w -= V h on the
+//              chunk; chunk partials of <v_k, w> and ||w||^2 again       -> orth1b
+//   k_orth<2>  h' = sum of the second partials, w -= V h'; chunk partial
+//              of ||w||^2                                                 -> orth2
+// k_krylov sums the same partials in the same order (projections h + h',
+// the norm), and runs a further single-workgroup pass only if the second one
+// still cancelled more than half of ||w||^2.  With the block-diagonal
+// preconditioner A P^-1 is close to the identity, so the first pass nearly
+// always cancels most of w and the second pass is the rule, not the exception.
+// ---------------------------------------------------------------------------
+// Workgroups of OT threads take chunks of 2 OT values (one double2 per thread):
+// 1024 threads (16 wavefronts, chunks of 2048) when the slot stride allows,
+// 256 for the short vectors of small seeds.
+inline int orth_threads(long long NV) { return NV % 2048 == 0 ? 1024 : 256; }
+
+// part[wave][k] (k < nvec) and part[wave][kPart - 1] for one chunk, then the
+// workgroup's sums to dst[0..nvec) and dst[kPart - 1]
+template <int OT>
+__device__ inline void chunk_dots(const double2 w, const double* V0, long NV, int nvec,
+                                  double (*part)[kPart], double* dst) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  auto vk = [&](int k) { return reinterpret_cast<const double2*>(V0 + (long)k * NV)[tid]; };
+  int k = 0;
+  // eight vectors per step: all eight loads are issued before the reductions
+  // (few slots in flight leave each workgroup latency-bound otherwise)
+  for (; k + 8 <= nvec; k += 8) {
+    double2 x[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) x[q] = vk(k + q);
+    double a[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] = wave_sum(x[q].x * w.x + x[q].y * w.y);
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) part[wave][k + q] = a[q];
+    }
+  }
+  for (; k < nvec; ++k) {
+    const double2 x0 = vk(k);
+    const double a0 = wave_sum(x0.x * w.x + x0.y * w.y);
+    if (lane == 0) part[wave][k] = a0;
+  }
+  const double ww = wave_sum(w.x * w.x + w.y * w.y);
+  if (lane == 0) part[wave][kPart - 1] = ww;
+  __syncthreads();
+  for (int t = tid; t < nvec; t += OT) {
+    double v = 0.0;
+    for (int q = 0; q < OT / 64; ++q) v += part[q][t];
+    dst[t] = v;
+  }
+  if (tid == 0) {
+    double v = 0.0;
+    for (int q = 0; q < OT / 64; ++q) v += part[q][kPart - 1];
+    dst[kPart - 1] = v;
+  }
+  __syncthreads();
+}
+
+// w -= sum_k hs[k] v_k on one chunk
+__device__ inline void chunk_update(double2& w, const double* V0, long NV, int nvec,
+                                    const double* hs) {
+  const int tid = threadIdx.x;
+  auto vk = [&](int k) { return reinterpret_cast<const double2*>(V0 + (long)k * NV)[tid]; };
+  int k = 0;
+  for (; k + 8 <= nvec; k += 8) {
+    double2 x[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) x[q] = vk(k + q);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      w.x -= hs[k + q] * x[q].x;
+      w.y -= hs[k + q] * x[q].y;
+    }
+  }
+  for (; k < nvec; ++k) {
+    const double2 x0 = vk(k);
+    const double h0 = hs[k];
+    w.x -= h0 * x0.x;
+    w.y -= h0 * x0.y;
+  }
+}
+
+// Cycle end of restarted GMRES, split like the orthogonalisation: for every
+// listed slot whose Arnoldi cycle ended in this step (SI_COMB = jn vectors),
+// u += V y on each chunk, y stored by k_krylov in ycoefs.
+template <int OT>
+__global__ void __launch_bounds__(OT) k_combine(EngineArgs A) {
+  constexpr int kChunk = 2 * OT;
+  __shared__ double ys[kMaxRestart + 1];
+  const int S = A.S, c64 = A.lists[2 * S], cnt = A.lists[2 * S + 2];
+  const int c = blockIdx.y, tid = threadIdx.x;
+  for (int li = blockIdx.x; li < cnt; li += gridDim.x) {
+    const int s = li < c64 ? A.lists[li] : A.lists[S + (li - c64)];
+    const int jn = A.si[(long)s * SI_N + SI_COMB];
+    if (jn <= 0) continue;  // uniform over the workgroup
+    for (int t = tid; t < jn; t += OT) ys[t] = A.ycoefs[(long)s * (kMaxRestart + 1) + t];
+    __syncthreads();
+    const long off = (long)c * kChunk;
+    double2* xp = reinterpret_cast<double2*>(A.x + (long)s * A.NV + off) + tid;
+    double2 x = *xp;
+    // x += V y  is  x -= V (-y): the same streaming loop as the update
+    for (int t = tid; t < jn; t += OT) ys[t] = -ys[t];
+    __syncthreads();
+    chunk_update(x, A.V + (long)s * (A.m + 1) * A.NV + off, A.NV, jn, ys);
+    *xp = x;
+    __syncthreads();  // ys is reused for the next slot
+  }
+}
+
+template <int PASS, int OT>
+__global__ void __launch_bounds__(OT) k_orth(EngineArgs A) {
+  constexpr int kChunk = 2 * OT;
+  __shared__ double part[OT / 64][kPart];
+  __shared__ double hs[kMaxBasis + 1];
+  const int S = A.S, c64 = A.lists[2 * S], cnt = A.lists[2 * S + 2];
+  const int c = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int li = blockIdx.x; li < cnt; li += gridDim.x) {
+    const int s = li < c64 ? A.lists[li] : A.lists[S + (li - c64)];
+    const int* si = A.si + (long)s * SI_N;
+    if (si[SI_PHASE] != PH_ARNOLDI) continue;  // uniform over the workgroup
+    const int nvec = si[SI_J] + 1;
+    const long off = (long)c * kChunk;
+    double2* wp = reinterpret_cast<double2*>(A.w + (long)s * A.NV + off) + tid;
+    double2 w = *wp;
+    const double* V0 = A.V + (long)s * (A.m + 1) * A.NV + off;
+    if (PASS > 0) {
+      // projections of the previous pass, summed over the chunks in fixed order
+      const double* prev = (PASS == 1 ? A.orth1 : A.orth1b) + (long)s * A.nchunk * kPart;
+      for (int t = tid; t < nvec; t += OT) {
+        double v = 0.0;
+        for (int q = 0; q < A.nchunk; ++q) v += prev[(long)q * kPart + t];
+        hs[t] = v;
+      }
+      __syncthreads();
+      chunk_update(w, V0, A.NV, nvec, hs);
+      *wp = w;
+    }
+    if (PASS < 2) {
+      double* dst = (PASS == 0 ? A.orth1 : A.orth1b) + ((long)s * A.nchunk + c) * kPart;
+      chunk_dots<OT>(w, V0, A.NV, nvec, part, dst);
+    } else {
+      const double nn = wave_sum(w.x * w.x + w.y * w.y);
+      if (lane == 0) part[wave][0] = nn;
+      __syncthreads();
+      if (tid == 0) {
+        double v = 0.0;
+        for (int q = 0; q < OT / 64; ++q) v += part[q][0];
+        A.orth2[(long)s * A.nchunk + c] = v;
+      }
+      __syncthreads();  // part and hs are reused for the next slot
+    }
+  }
+}
+
 // Per slot and step, according to the slot's phase:
 //   RESTART  w = A P^-1 u: true residual r = D c0 - w, convergence test, finish or
 //            start a new cycle (r projected off the recycle space C first)
@@ -1215,10 +1438,46 @@ __global__ void __launch_bounds__(BT) k_krylov(EngineArgs A) {
 
   // ---- Arnoldi step j: w = A P^-1 v_j, orthogonalised against [C, V_0..j] ----
   const int j = si[SI_J];
-  const double hn = cgs2<NE2, BT>(
-      w2, kc + j + 1,
-      [&](int t) { return t < kc ? cvec(t) : Vs + (long)(t - kc) * NV; }, coef, part, ytmp, lds,
-      wn0);
+  double hn;
+  if (REC) {
+    hn = cgs2<NE2, BT>(
+        w2, kc + j + 1,
+        [&](int t) { return t < kc ? cvec(t) : Vs + (long)(t - kc) * NV; }, coef, part, ytmp, lds,
+        wn0);
+  } else {
+    // two Gram-Schmidt passes done by k_orth<0..2> (w holds their result)
+    __shared__ double norms[2];
+    const double* p1 = A.orth1 + (long)s * A.nchunk * kPart;
+    const double* p2 = A.orth1b + (long)s * A.nchunk * kPart;
+    if (tid <= j) {
+      double a = 0.0, b = 0.0;
+      for (int q = 0; q < A.nchunk; ++q) {
+        a += p1[(long)q * kPart + tid];
+        b += p2[(long)q * kPart + tid];
+      }
+      coef[tid] = a + b;
+    }
+    if (tid == 0) {
+      double a = 0.0, b = 0.0;
+      for (int q = 0; q < A.nchunk; ++q) {
+        a += p2[(long)q * kPart + kPart - 1];   // ||w||^2 after the first pass
+        b += A.orth2[(long)s * A.nchunk + q];   // after the second
+      }
+      norms[0] = a;
+      norms[1] = b;
+    }
+    __syncthreads();
+    const double wn2 = norms[0], hn2 = norms[1];
+    hn = sqrt(hn2);
+    if (hn2 < 0.5 * wn2) {
+      // the second pass cancelled again: a further pass in this workgroup
+      load2<NE2, BT>(w2, ws);
+      hn = cgs2<NE2, BT>(w2, j + 1, [&](int t) { return Vs + (long)t * NV; }, ycoef, part, ytmp,
+                         lds, wn0);
+      if (tid <= j) coef[tid] += ycoef[tid];
+      __syncthreads();
+    }
+  }
   if (REC && tid < kc) A.Bk[((long)s * A.kmax + tid) * m + j] = coef[tid];
   if (tid <= j) hcol[tid] = coef[kc + tid];
   if (hn > 0) store2<NE2, BT>(Vs + (long)(j + 1) * NV, w2, 1.0 / hn);
@@ -1288,11 +1547,17 @@ __global__ void __launch_bounds__(BT) k_krylov(EngineArgs A) {
   if (next_phase != PH_ARNOLDI) {
     const int jn = j + 1;
     // u += V y - U B y  (the iterate is kept before preconditioning)
-    double* xs = A.x + (long)s * NV;
-    load2<NE2, BT>(w2, xs);
-    combine<NE2, BT>(w2, jn, [&](int t) { return Vs + (long)t * NV; }, ycoef);
-    if (REC && kc > 0) combine<NE2, BT>(w2, kc, [&](int t) { return rec_u(A, s, bank, t); }, tco);
-    store2<NE2, BT>(xs, w2, 1.0);
+    if (REC) {
+      double* xs = A.x + (long)s * NV;
+      load2<NE2, BT>(w2, xs);
+      combine<NE2, BT>(w2, jn, [&](int t) { return Vs + (long)t * NV; }, ycoef);
+      if (kc > 0) combine<NE2, BT>(w2, kc, [&](int t) { return rec_u(A, s, bank, t); }, tco);
+      store2<NE2, BT>(xs, w2, 1.0);
+    } else {
+      // done by k_combine on all chunks after this kernel
+      if (tid < jn) A.ycoefs[(long)s * (kMaxRestart + 1) + tid] = ycoef[tid];
+      if (tid == 0) si[SI_COMB] = jn;
+    }
     if (tid == 0) si[SI_PHASE] = next_phase;
   }
 }
@@ -1697,10 +1962,12 @@ struct lyap_engine_s {
   long long next_tag = 0;
   DevBuf si, sdv, d, R, g, cs, sn, V, x, z, w, Pinv, lists, X, H, Hp, Xlo, Hlo, Hplo, XS;
   DevBuf Ur, Cr, Bk, Hr, Fs;  // recycle space (GCRO-DR)
+  DevBuf orth1, orth1b, orth2, ycoefs;  // split orthogonalisation (restarted GMRES)
   DevBuf Cpinv, Tbuf, Tpart, Sc;  // low-rank preconditioner part
   DevBuf qd, qtag, qctl, res;
   double* sol = nullptr;
   long long sol_cap = 0;
+  void* ws = nullptr;        // caller workspace the buffers are carved from (or null)
   bool owns_graph = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -1758,47 +2025,75 @@ struct EngineSizes {
   long long rows_pad = 0;
 };
 
+// Every device buffer of an engine, in one fixed order: `take(buf, bytes)`
+// with buf = nullptr when only sizes are wanted.  The engine's buffers come
+// from its own allocations or are carved from a caller's workspace in this
+// order, each rounded up to 256 bytes; engine_sizes is the same walk.
+template <class F>
+static void engine_layout(const lyap_seed_s* sd, long long S, const lyap_solve_opts& o, long long Q,
+                          lyap_engine_s* E, F&& take) {
+  const long long r = sd->r, ld = sd->ld, N = slot_stride(r, ld), m = o.restart;
+  const long long rows_pad = pad_to(S * r * r, 128);
+  auto t = [&](DevBuf lyap_engine_s::*mem, long long bytes) {
+    take(E ? &(E->*mem) : nullptr, (size_t)bytes);
+  };
+  t(&lyap_engine_s::si, S * SI_N * 4);
+  t(&lyap_engine_s::sdv, S * SD_N * 8);
+  t(&lyap_engine_s::d, S * r * 8);
+  t(&lyap_engine_s::R, S * m * (m + 1) * 8);
+  t(&lyap_engine_s::g, S * (m + 1) * 8);
+  t(&lyap_engine_s::cs, S * m * 8);
+  t(&lyap_engine_s::sn, S * m * 8);
+  t(&lyap_engine_s::V, S * (m + 1) * N * 8);
+  t(&lyap_engine_s::x, S * N * 8);
+  t(&lyap_engine_s::z, S * N * 8);
+  t(&lyap_engine_s::w, S * N * 8);
+  t(&lyap_engine_s::Pinv, S * r * r * ld * 8);
+  t(&lyap_engine_s::lists, (2 * S + 3) * 4);
+  const bool tsvd = sd->pbar > 0 && o.use_precond == 1 && r <= kPrecRank;
+  if (tsvd) {
+    const long long Sp = pad_to(S, 128);
+    t(&lyap_engine_s::Cpinv, S * kPbarMax * kPbarMax * 8);
+    t(&lyap_engine_s::Tbuf, Sp * 128 * 8);
+    t(&lyap_engine_s::Sc, Sp * 128 * 8);
+    t(&lyap_engine_s::Tpart, (long long)kTsvdGrid * 128 * 128 * 8);
+  }
+  if (o.recycle_k == 0) {
+    const long long nch = N / (2 * orth_threads(N));
+    t(&lyap_engine_s::orth1, S * nch * kPart * 8);
+    t(&lyap_engine_s::orth1b, S * nch * kPart * 8);
+    t(&lyap_engine_s::orth2, S * nch * 8);
+    t(&lyap_engine_s::ycoefs, S * (kMaxRestart + 1) * 8);
+  }
+  if (o.recycle_k > 0) {
+    const long long k = o.recycle_k;
+    t(&lyap_engine_s::Ur, S * 2 * k * N * 8);
+    t(&lyap_engine_s::Cr, S * 2 * k * N * 8);
+    t(&lyap_engine_s::Bk, S * k * m * 8);
+    t(&lyap_engine_s::Hr, S * m * (m + 1) * 8);
+    t(&lyap_engine_s::Fs, S * (long long)kRecScratch * 8);
+  }
+  if (sd->basis == LYAP_BASIS_SCHUR && !sd->Kd.p) t(&lyap_engine_s::XS, S * ld * ld * 8);
+  t(&lyap_engine_s::X, rows_pad * ld * 8);
+  t(&lyap_engine_s::H, rows_pad * ld * 8);
+  t(&lyap_engine_s::Hp, cauchy_part_rows(rows_pad) * ld * 8);
+  if (o.prec != LYAP_PREC_FP64) {
+    t(&lyap_engine_s::Xlo, rows_pad * ld * 4);
+    t(&lyap_engine_s::Hlo, rows_pad * ld * 4);
+    t(&lyap_engine_s::Hplo, cauchy_part_rows(rows_pad) * ld * 4);
+  }
+  t(&lyap_engine_s::qd, Q * r * 8);
+  t(&lyap_engine_s::qtag, Q * 8);
+  t(&lyap_engine_s::qctl, 16);
+  t(&lyap_engine_s::res, Q * (long long)sizeof(DevResult));
+}
+
 static EngineSizes engine_sizes(const lyap_seed_s* sd, long long S, const lyap_solve_opts& o,
                                 long long Q) {
   EngineSizes z;
-  const long long r = sd->r, ld = sd->ld, N = slot_stride(r, ld), m = o.restart;
-  z.rows_pad = pad_to(S * r * r, 128);
-  auto add = [&](size_t b) { z.total += (b + 255) / 256 * 256; };
-  add(S * SI_N * 4);
-  add(S * SD_N * 8);
-  add(S * r * 8);
-  add(S * m * (m + 1) * 8);
-  add(S * (m + 1) * 8);
-  add(S * m * 8 * 2);
-  add(S * (m + 1) * N * 8);
-  add(S * N * 8 * 3);
-  add(S * r * r * ld * 8);
-  add((2 * S + 3) * 4);
-  const bool tsvd = sd->pbar > 0 && o.use_precond == 1 && sd->r <= kPrecRank;
-  if (tsvd) {
-    const long long Sp = pad_to(S, 128);
-    add(S * kPbarMax * kPbarMax * 8);  // Cp^-1
-    add(Sp * 128 * 8 * 2);             // Tbuf, Sc
-    add((long long)kTsvdGrid * 128 * 128 * 8);  // split-K partials
-  }
-  add(z.rows_pad * ld * 8 * (2 + kPartRowsFactor));  // X, H, split-K partials fp64
-  if (o.recycle_k > 0) {
-    const long long k = o.recycle_k;
-    add(S * 2 * k * N * 8 * 2);        // U, C (two banks each)
-    add(S * k * m * 8);                // B
-    add(S * m * (m + 1) * 8);          // unrotated Hessenberg
-    add(S * (long long)kRecScratch * 8);
-  }
-  if (sd->basis == LYAP_BASIS_SCHUR && !sd->Kd.p) add(S * ld * ld * 8);  // per-slot Schur-basis solutions
-  const bool mixed = o.prec != LYAP_PREC_FP64;
-  if (mixed) {
-    add(z.rows_pad * ld * 4);      // Xlo (float, or two bf16 planes)
-    add(z.rows_pad * ld * 4 * (1 + kPartRowsFactor));  // Hlo, split-K partials (float)
-  }
-  add(Q * r * 8);
-  add(Q * 8);
-  add(16);
-  add(Q * sizeof(DevResult));
+  z.rows_pad = pad_to(S * sd->r * sd->r, 128);
+  engine_layout(sd, S, o, Q, nullptr,
+                [&](DevBuf*, size_t b) { z.total += (std::max<size_t>(b, 16) + 255) / 256 * 256; });
   return z;
 }
 
@@ -1822,7 +2117,11 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
   const int pgrid = std::min(S, 1024);
   if (on(PART_PRE)) {
   hipLaunchKernelGGL(k_lists, dim3(1), dim3(1024), 0, st, A);
-  hipLaunchKernelGGL(k_prep, dim3(pgrid), dim3(KT), 0, st, A);
+  {
+    // units of one slot over several workgroups (full occupancy at full batch)
+    const int pch = A.pbar > 0 ? 1 : std::max(1, std::min(16, (nu + KT - 1) / KT));
+    hipLaunchKernelGGL(k_prep, dim3(pgrid, pch), dim3(KT), 0, st, A);
+  }
   }
   if (on(PART_PRE) && A.pbar > 0) {
     // low-rank preconditioner part: two skinny GEMMs over the listed slots
@@ -1926,9 +2225,9 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     g.M_dev = E->lists.as<int>() + 2 * S;
     g.m_scale = r * r;
     g.Cpart = E->Hp.p;
-    g.Cpart_rows = kPartRowsFactor * E->rows_pad;
+    g.Cpart_rows = cauchy_part_rows(E->rows_pad);
     g.bk = E->t64.bk;
-    g.grid_min = E->t64.grid_min;
+    g.grid_min = cauchy_grid_min(E->t64.grid_min, ld);
     g.xcd_off = E->t64.xcd_off;
     if (on(PART_G64)) {
     if (ev) LYAP_HIP(hipEventRecord(ev->g64[0], st));
@@ -1954,9 +2253,9 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     g.M_dev = E->lists.as<int>() + 2 * S + 1;
     g.m_scale = r * r;
     g.Cpart = E->Hplo.p;
-    g.Cpart_rows = kPartRowsFactor * E->rows_pad;
+    g.Cpart_rows = cauchy_part_rows(E->rows_pad);
     g.bk = E->tlo.bk;
-    g.grid_min = E->tlo.grid_min;
+    g.grid_min = cauchy_grid_min(E->tlo.grid_min, ld);
     g.xcd_off = E->tlo.xcd_off;
     if (E->low != GemmType::F32) {
       g.a_plane = E->rows_pad * ld;
@@ -1986,7 +2285,25 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     return;
   }
   if (ev && ev->kry[0]) LYAP_HIP(hipEventRecord(ev->kry[0], st));
+  if (A.kmax == 0) {
+    const int og = std::min(S, 1024);
+    if (orth_threads(A.NV) == 1024) {
+      hipLaunchKernelGGL((k_orth<0, 1024>), dim3(og, A.nchunk), dim3(1024), 0, st, A);
+      hipLaunchKernelGGL((k_orth<1, 1024>), dim3(og, A.nchunk), dim3(1024), 0, st, A);
+      hipLaunchKernelGGL((k_orth<2, 1024>), dim3(og, A.nchunk), dim3(1024), 0, st, A);
+    } else {
+      hipLaunchKernelGGL((k_orth<0, 256>), dim3(og, A.nchunk), dim3(256), 0, st, A);
+      hipLaunchKernelGGL((k_orth<1, 256>), dim3(og, A.nchunk), dim3(256), 0, st, A);
+      hipLaunchKernelGGL((k_orth<2, 256>), dim3(og, A.nchunk), dim3(256), 0, st, A);
+    }
+  }
   launch_krylov(A, S, (long long)A.NV, st);
+  if (A.kmax == 0) {
+    if (orth_threads(A.NV) == 1024)
+      hipLaunchKernelGGL((k_combine<1024>), dim3(std::min(S, 1024), A.nchunk), dim3(1024), 0, st, A);
+    else
+      hipLaunchKernelGGL((k_combine<256>), dim3(std::min(S, 1024), A.nchunk), dim3(256), 0, st, A);
+  }
   if (ev && ev->kry[0]) LYAP_HIP(hipEventRecord(ev->kry[1], st));
   if (A.kmax > 0) launch_krylov(A, S, (long long)A.NV, st, true);
   hipLaunchKernelGGL(k_admit, dim3(S), dim3(KT), 0, st, A);
@@ -2290,9 +2607,11 @@ static GemmTune tune_cauchy(lyap_engine_s* E, GemmType type) {
   return best;
 }
 
+// ws: optional caller workspace of at least engine_sizes(...).total bytes; the
+// engine's buffers are then carved from it (no device allocation here).
 static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lyap_solve_opts* in,
                                          hipStream_t st, long long Q, double* sol,
-                                         long long sol_cap, bool use_graph) {
+                                         long long sol_cap, bool use_graph, void* ws = nullptr) {
   LYAP_REQUIRE(sd != nullptr, LYAP_E_INVAL, "seed is NULL");
   LYAP_REQUIRE(S >= 1 && S <= 8192, LYAP_E_INVAL, "slots out of [1, 8192]");
   lyap_solve_opts o;
@@ -2322,54 +2641,20 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   const long long r = sd->r, ld = sd->ld, N = slot_stride(r, ld), m = o.restart;
   EngineSizes z = engine_sizes(sd, S, o, Q);
   E->rows_pad = z.rows_pad;
-  auto zalloc = [&](DevBuf& b, size_t bytes) {
-    b.alloc(std::max<size_t>(bytes, 16));
-    LYAP_HIP(hipMemsetAsync(b.p, 0, b.bytes, st));
-  };
-  zalloc(E->si, S * SI_N * 4);
-  zalloc(E->sdv, S * SD_N * 8);
-  zalloc(E->d, S * r * 8);
-  zalloc(E->R, S * m * (m + 1) * 8);
-  zalloc(E->g, S * (m + 1) * 8);
-  zalloc(E->cs, S * m * 8);
-  zalloc(E->sn, S * m * 8);
-  zalloc(E->V, S * (m + 1) * N * 8);
-  zalloc(E->x, S * N * 8);
-  zalloc(E->z, S * N * 8);
-  zalloc(E->w, S * N * 8);
-  zalloc(E->Pinv, S * r * r * ld * 8);
-  zalloc(E->lists, (2 * S + 3) * 4);
-  const bool tsvd = sd->pbar > 0 && o.use_precond == 1 && r <= kPrecRank;
-  if (tsvd) {
-    const long long Sp = pad_to(S, 128);
-    zalloc(E->Cpinv, S * kPbarMax * kPbarMax * 8);
-    zalloc(E->Tbuf, Sp * 128 * 8);
-    zalloc(E->Sc, Sp * 128 * 8);
-    zalloc(E->Tpart, (long long)kTsvdGrid * 128 * 128 * 8);
-  }
-  if (o.recycle_k > 0) {
-    const long long k = o.recycle_k;
-    zalloc(E->Ur, S * 2 * k * N * 8);
-    zalloc(E->Cr, S * 2 * k * N * 8);
-    zalloc(E->Bk, S * k * m * 8);
-    zalloc(E->Hr, S * m * (m + 1) * 8);
-    zalloc(E->Fs, S * (long long)kRecScratch * 8);
-  }
-  if (sd->basis == LYAP_BASIS_SCHUR && !sd->Kd.p) zalloc(E->XS, S * ld * ld * 8);
-  zalloc(E->X, z.rows_pad * ld * 8);
-  zalloc(E->H, z.rows_pad * ld * 8);
-  zalloc(E->Hp, kPartRowsFactor * z.rows_pad * ld * 8);
-  if (E->mixed) {
-    zalloc(E->Xlo, z.rows_pad * ld * 4);
-    zalloc(E->Hlo, z.rows_pad * ld * 4);
-    zalloc(E->Hplo, kPartRowsFactor * z.rows_pad * ld * 4);
-  }
-  zalloc(E->qd, Q * r * 8);
-  zalloc(E->qtag, Q * 8);
-  zalloc(E->qctl, 16);
-  zalloc(E->res, Q * sizeof(DevResult));
+  size_t carve = 0;
+  engine_layout(sd, S, o, Q, E, [&](DevBuf* b, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 16);
+    if (ws) {
+      b->view(static_cast<char*>(ws) + carve, bytes);
+      carve += (bytes + 255) / 256 * 256;
+    } else {
+      b->alloc(bytes);
+    }
+    LYAP_HIP(hipMemsetAsync(b->p, 0, b->bytes, st));
+  });
   E->sol = sol;
   E->sol_cap = sol_cap;
+  E->ws = ws;
   E->res_host.resize(Q);
   E->got.assign(Q, 0);
 
@@ -2380,6 +2665,7 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   A.c0 = sd->c0.as<double>();
   A.gam = sd->gam.as<double>();
   A.t0 = sd->t0;
+  A.eps_seed = sd->eps_seed;
   A.n = (int)sd->n;
   A.h = (int)sd->h;
   A.ld = (int)ld;
@@ -2391,6 +2677,7 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   A.max_refine = o.max_refine;
   A.use_precond = (o.use_precond && r <= kPrecRank && sd->basis != LYAP_BASIS_SCHUR) ? 1 : 0;
   // use_precond 1: all of eq:prec the seed holds; 2: its block-diagonal part only
+  const bool tsvd = sd->pbar > 0 && o.use_precond == 1 && r <= kPrecRank;
   A.pbar = tsvd ? (int)sd->pbar : 0;
   A.Ks = (int)(r * ld);
   A.TsM = sd->TsM.as<double>();
@@ -2416,6 +2703,11 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   A.z = E->z.as<double>();
   A.w = E->w.as<double>();
   A.Pinv = E->Pinv.as<double>();
+  A.nchunk = (int)(N / (2 * orth_threads(N)));
+  A.orth1 = E->orth1.as<double>();
+  A.orth1b = E->orth1b.as<double>();
+  A.ycoefs = E->ycoefs.as<double>();
+  A.orth2 = E->orth2.as<double>();
   A.lists = E->lists.as<int>();
   A.qd = E->qd.as<double>();
   A.qtag = E->qtag.as<long long>();
@@ -2572,6 +2864,7 @@ static long long engine_harvest_impl(lyap_engine_s* E, long long max_out, long l
       res_out[n].cycles = o.cycles;
       res_out[n].refinements = o.refines;
       res_out[n].rel_residual = o.relres;
+      res_out[n].err_est = o.err_est;
       res_out[n].trace = o.trace;
     }
     ++n;
@@ -2629,7 +2922,7 @@ void engine_batch_run(lyap_engine_s* E, long long P, const double* d_dev, double
   std::vector<long long> tg(P);
   std::vector<lyap_result> rr(P);
   const long long got = engine_harvest_impl(E, P, tg.data(), rr.data());
-  for (long long i = 0; i < P; ++i) res_host[i] = lyap_result{LYAP_E_NOCONV, 0, 0, 0, NAN, NAN};
+  for (long long i = 0; i < P; ++i) res_host[i] = lyap_result{LYAP_E_NOCONV, 0, 0, 0, NAN, NAN, NAN};
   for (long long i = 0; i < got; ++i)
     if (tg[i] >= 0 && tg[i] < P) res_host[tg[i]] = rr[i];
   // physical Y = rho(Yhat) Tout  (transform-out GEMM, n columns stored)
@@ -2790,18 +3083,27 @@ lyap_status smw_solve_batch(lyap_seed sd, int64_t P, const double* d_dev,
     validate_opts(o);
     hipStream_t st = (hipStream_t)hip_stream;
     const size_t need = smw_workspace_bytes(sd, P, opts);
+    LYAP_REQUIRE(need > 0, LYAP_E_INVAL, lyap_last_error());
     LYAP_REQUIRE(workspace_dev == nullptr || workspace_bytes >= need, LYAP_E_INVAL,
                  "workspace too small");
-    const long long r = sd->r, ld = sd->ld, n = sd->n;
+    LYAP_REQUIRE(workspace_dev == nullptr || ((uintptr_t)workspace_dev & 255) == 0,
+                 LYAP_E_INVAL, "workspace must be 256-byte aligned");
+    const long long r = sd->r, ld = sd->ld;
     const long long S = default_slots(sd, P);
-    // The seed keeps this call's engine (buffers, captured step graphs) for the
-    // next call with the same slots, length, options and solution store; a call
-    // that finds the cache in use by another thread builds a private engine.
+    const size_t eng_bytes = engine_sizes(sd, S, o, P).total;
+    // The engine (buffers, captured step graphs) is kept on the seed for the next
+    // call with the same slots, length, options and memory.  With a workspace,
+    // every engine buffer and the solution store are carved from it (the next
+    // call with the same workspace allocates nothing); without one, the seed
+    // allocates and owns them.  A call that finds the cache in use by another
+    // thread builds a private engine.
     std::unique_lock<std::mutex> lk(sd->cache_mu, std::try_to_lock);
     DevBuf own;
     double* sol;
+    void* ews = nullptr;
     if (workspace_dev) {
-      sol = reinterpret_cast<double*>(workspace_dev);
+      ews = workspace_dev;
+      sol = reinterpret_cast<double*>(static_cast<char*>(workspace_dev) + eng_bytes);
     } else if (lk.owns_lock()) {
       const size_t b = (size_t)P * r * ld * sizeof(double);
       if (sd->sol_buf.bytes < b) {
@@ -2820,23 +3122,23 @@ lyap_status smw_solve_batch(lyap_seed sd, int64_t P, const double* d_dev,
     lyap_engine_s* E = nullptr;
     if (lk.owns_lock()) {
       auto* C = reinterpret_cast<lyap_engine_s*>(sd->eng_cache);
-      if (C && C->S == S && C->Q == P && C->sol == sol && C->sol_cap == P &&
+      if (C && C->S == S && C->Q == P && C->sol == sol && C->sol_cap == P && C->ws == ews &&
           std::memcmp(&C->opts, &o, sizeof(o)) == 0) {
         E = C;
         engine_reset(E, st);
       } else {
         if (C) engine_destroy_impl(C);
         sd->eng_cache = nullptr;
-        E = engine_create_impl(sd, S, &o, st, P, sol, P, true);
+        E = engine_create_impl(sd, S, &o, st, P, sol, P, true, ews);
         sd->eng_cache = E;
         sd->eng_cache_free = [](void* q) { engine_destroy_impl(reinterpret_cast<lyap_engine_s*>(q)); };
         sd->eng_cache_bytes = [](const void* q) {
           const auto* e = reinterpret_cast<const lyap_engine_s*>(q);
-          return engine_sizes(e->sd, e->S, e->opts, e->Q).total;
+          return e->ws ? size_t(0) : engine_sizes(e->sd, e->S, e->opts, e->Q).total;
         };
       }
     } else {
-      E = engine_create_impl(sd, S, &o, st, P, sol, P, true);
+      E = engine_create_impl(sd, S, &o, st, P, sol, P, true, ews);
       eg.reset(E);
     }
     engine_batch_run(E, P, d_dev, Y_dev, res_host);

@@ -122,6 +122,74 @@ __global__ void k_full_blockdiag(const double* __restrict__ Uh, const double* __
     }
 }
 
+// Dense right-hand side in real eigen coordinates (no sig scaling), one thread
+// per pair of diagonal blocks (I, J), in place:
+//   adjoint = false:  Lambda_I X_IJ + X_IJ Lambda_J^T = C_IJ
+//   adjoint = true:   Lambda_I^T X_IJ + X_IJ Lambda_J = C_IJ
+__global__ void k_blockdiag_dense(double* __restrict__ C, const double* __restrict__ lam, int n,
+                                  int h, int ld, bool adjoint) {
+  const int nb = h + (n - 2 * h);
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)nb * nb) return;
+  const int I = (int)(t / nb), J = (int)(t % nb);
+  const int i0 = I < h ? 2 * I : 2 * h + (I - h), mi = I < h ? 2 : 1;
+  const int j0 = J < h ? 2 * J : 2 * h + (J - h), mj = J < h ? 2 : 1;
+  const double sgn = adjoint ? -1.0 : 1.0;  // the transposed 2x2 block flips the sign of b
+  double LI[2][2], LJ[2][2];
+  {
+    const double a = lam[i0], b = sgn * lam[ld + i0];
+    LI[0][0] = a; LI[0][1] = b; LI[1][0] = -b; LI[1][1] = a;
+  }
+  {
+    // Lambda_J^T (or, for the adjoint, Lambda_J) multiplies from the right:
+    // X Lambda_J^T has entries sum_e2 X[a][e2] Lambda_J[e][e2]
+    const double a = lam[j0], b = sgn * lam[ld + j0];
+    LJ[0][0] = a; LJ[0][1] = b; LJ[1][0] = -b; LJ[1][1] = a;
+  }
+  const int dim = mi * mj;
+  double M[16], v[4];
+  for (int q = 0; q < 16; ++q) M[q] = 0.0;
+  for (int e = 0; e < mj; ++e)
+    for (int a = 0; a < mi; ++a) {
+      const int row = e * mi + a;
+      v[row] = C[(long)(i0 + a) * ld + (j0 + e)];
+      for (int e2 = 0; e2 < mj; ++e2)
+        for (int a2 = 0; a2 < mi; ++a2) {
+          const int col = e2 * mi + a2;
+          double m = 0.0;
+          if (e == e2) m += (mi == 2 ? LI[a][a2] : (a == a2 ? LI[0][0] : 0.0));
+          if (a == a2) m += (mj == 2 ? LJ[e][e2] : (e == e2 ? LJ[0][0] : 0.0));
+          M[row * 4 + col] = m;
+        }
+    }
+  solve_small(M, v, dim);
+  for (int e = 0; e < mj; ++e)
+    for (int a = 0; a < mi; ++a) C[(long)(i0 + a) * ld + (j0 + e)] = v[e * mi + a];
+}
+
+// out = alpha (M + M^T) + beta C on the leading n x n block (C may be null);
+// entries outside it are set to zero.
+__global__ void k_sym_combine(double* __restrict__ out, const double* __restrict__ M,
+                              const double* __restrict__ C, double alpha, double beta, int n,
+                              int ld) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)ld * ld) return;
+  const int i = (int)(t / ld), j = (int)(t % ld);
+  double v = 0.0;
+  if (i < n && j < n) {
+    v = alpha * (M[(long)i * ld + j] + M[(long)j * ld + i]);
+    if (C) v += beta * C[(long)i * ld + j];
+  }
+  out[t] = v;
+}
+
+// out = a + b elementwise over ld x ld
+__global__ void k_add(double* __restrict__ out, const double* __restrict__ a,
+                      const double* __restrict__ b, long count) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) out[t] = a[t] + b[t];
+}
+
 // G rows of the Schur-basis problems: [Ys_p (r rows), -Bs/2 (s rows)]
 __global__ void k_full_schur_g(const double* __restrict__ Ys, const double* __restrict__ Bh,
                                double* __restrict__ G, int r, int s, int ld, bool with_y) {
@@ -219,6 +287,29 @@ void full_impl(lyap_seed_s* sd, int64_t P, const double* Y, double* X, hipStream
 }
 
 }  // namespace
+
+void blockdiag_dense_launch(double* C, const double* lam, int n, int h, int ld, bool adjoint,
+                            hipStream_t st) {
+  const long nb = h + (n - 2 * h);
+  hipLaunchKernelGGL(k_blockdiag_dense, dim3((unsigned)((nb * nb + 255) / 256)), dim3(256), 0, st,
+                     C, lam, n, h, ld, adjoint);
+  LYAP_HIP(hipGetLastError());
+}
+
+void sym_combine_launch(double* out, const double* M, const double* C, double alpha, double beta,
+                        int n, int ld, hipStream_t st) {
+  const long cnt = (long)ld * ld;
+  hipLaunchKernelGGL(k_sym_combine, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, out, M,
+                     C, alpha, beta, n, ld);
+  LYAP_HIP(hipGetLastError());
+}
+
+void add_launch(double* out, const double* a, const double* b, long count, hipStream_t st) {
+  hipLaunchKernelGGL(k_add, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, out, a, b,
+                     count);
+  LYAP_HIP(hipGetLastError());
+}
+
 }  // namespace lyap
 
 using namespace lyap;

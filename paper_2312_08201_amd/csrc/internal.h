@@ -25,6 +25,11 @@ struct lyap_seed_s {
   int64_t n = 0, r = 0, s = 0, h = 0, ld = 0;
   int basis = LYAP_BASIS_EIG;
   double cond_est = 0, min_lam_sum = 0, max_re = 0, t0 = 0, factor_seconds = 0;
+  double t0_unrefined = 0;  // t0 before the refinement of the right-hand-side quantities
+  int seed_refine = 0;      // refinement steps applied to t0, c0, Gamma (eigen basis)
+  // relative forward error of the eigenbasis route, |t0_unrefined - t0| / |t0|
+  // (with a floor of 4 unit roundoffs), NaN when no refinement measured it
+  double eps_seed = NAN;
   hipStream_t stream = nullptr;
   int device = 0;
 
@@ -138,5 +143,17 @@ void project_launch(const double* Vt, const double* X, long xstride, double* out
 void schur_dense_operator(lyap_seed_s* sd, hipStream_t st);
 void gemm64_rm(const double* A, long lda, const double* B, long ldb, double* C, long ldc, long M,
                long N, long K, long Nstore, hipStream_t s);
+
+// ---- dense solves in the real eigenbasis (full.hip) ----
+// In place on C (ld x ld, real eigen coordinates, no sig scaling): the
+// block-diagonal equation Lambda X + X Lambda^T = C, or with adjoint
+// Lambda^T X + X Lambda = C (Lambda from the seed's lam).
+void blockdiag_dense_launch(double* C, const double* lam, int n, int h, int ld, bool adjoint,
+                            hipStream_t st);
+// out = alpha (M + M^T) + beta C on the leading n x n block, zero outside it
+void sym_combine_launch(double* out, const double* M, const double* C, double alpha, double beta,
+                        int n, int ld, hipStream_t st);
+// out = a + b over count doubles
+void add_launch(double* out, const double* a, const double* b, long count, hipStream_t st);
 
 }  // namespace lyap

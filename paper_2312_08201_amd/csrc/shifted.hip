@@ -260,6 +260,7 @@ void shifted_impl(lyap_seed_s* sd, int64_t P, const double* d_host, const lyap_s
     o.cycles = 1;
     o.refinements = 0;
     o.rel_residual = rr;
+    o.err_est = NAN;  // no estimate for the shifted-family solve
     o.trace = tr_h[p];
   }
 }

@@ -33,7 +33,7 @@ class LyapError(RuntimeError):
 
 class SeedOpts(C.Structure):
     _fields_ = [("basis", C.c_int32), ("E_is_diag", C.c_int32), ("max_eig_cond", C.c_double),
-                ("tsvd_rank", C.c_int32), ("schur_dense", C.c_int32)]
+                ("tsvd_rank", C.c_int32), ("schur_dense", C.c_int32), ("seed_refine", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -44,7 +44,8 @@ class SolveOpts(C.Structure):
 
 class Result(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("cycles", C.c_int32),
-                ("refinements", C.c_int32), ("rel_residual", C.c_double), ("trace", C.c_double)]
+                ("refinements", C.c_int32), ("rel_residual", C.c_double), ("trace", C.c_double),
+                ("err_est", C.c_double)]
 
 
 class SeedInfo(C.Structure):
@@ -52,6 +53,7 @@ class SeedInfo(C.Structure):
                 ("ld", C.c_int64), ("basis", C.c_int32), ("tsvd_rank", C.c_int32),
                 ("cond_est", C.c_double), ("min_lam_sum", C.c_double),
                 ("max_re_lambda", C.c_double), ("t0", C.c_double),
+                ("t0_unrefined", C.c_double), ("eps_seed", C.c_double), ("seed_refine", C.c_int32),
                 ("factor_seconds", C.c_double), ("device_bytes", C.c_size_t)]
 
 
@@ -83,7 +85,7 @@ EK_RESULT_DTYPE = np.dtype([("status", np.int32), ("level", np.int32), ("dim", n
 
 RESULT_DTYPE = np.dtype([("status", np.int32), ("iters", np.int32), ("cycles", np.int32),
                          ("refinements", np.int32), ("rel_residual", np.float64),
-                         ("trace", np.float64)])
+                         ("trace", np.float64), ("err_est", np.float64)])
 
 _lib = None
 
@@ -230,7 +232,7 @@ class Seed:
     """seed_factor: offline stage for one (A0, U, V, B, E)."""
 
     def __init__(self, A0, U, V, B, E, basis="auto", max_eig_cond=0.0, stream=None,
-                 tsvd_rank=0, schur_dense=True):
+                 tsvd_rank=0, schur_dense=True, seed_refine=0):
         lib = load()
         _torch()
         A0 = _host(A0)
@@ -248,7 +250,7 @@ class Seed:
             raise ValueError("E must be (n,) or (n, n)")
         self._keep = (A0, U, V, B, E)
         opts = SeedOpts(BASIS[basis], diag, float(max_eig_cond), int(tsvd_rank),
-                        0 if schur_dense else -1)
+                        0 if schur_dense else -1, int(seed_refine))
         h = C.c_void_p()
         st = lib.seed_factor(n, r, s, A0.ctypes.data, U.ctypes.data, V.ctypes.data, B.ctypes.data,
                              E.ctypes.data, C.byref(opts), _stream(stream), C.byref(h))
@@ -270,8 +272,9 @@ class Seed:
 
     def release(self):
         if getattr(self, "h", None):
-            load().seed_release(self.h)
+            load().seed_release(self.h)   # the seed's engine may use the workspace until here
             self.h = None
+        self._ws = None
 
     def __del__(self):
         try:
@@ -316,7 +319,12 @@ class Seed:
         _dev_ptr(d, shape=(P, self.r))
         Y = torch.empty((P, self.r, self.n), dtype=torch.float64, device=d.device)
         nbytes = self.workspace_bytes(P, opts)
-        ws = torch.empty(nbytes, dtype=torch.uint8, device=d.device)
+        # one workspace kept per seed: the library keeps its engine (graphs over
+        # this memory) for the next call with the same P, options and workspace
+        ws = getattr(self, "_ws", None)
+        if ws is None or ws.numel() < nbytes or ws.device != d.device:
+            self._ws = None
+            ws = self._ws = torch.empty(nbytes, dtype=torch.uint8, device=d.device)
         res = (Result * P)()
         st = load().smw_solve_batch(self.h, P, _dev_ptr(d), C.byref(opts), _dev_ptr(Y), res,
                                     C.c_void_p(ws.data_ptr()), nbytes, _stream(stream))
@@ -411,7 +419,7 @@ class EKSpace:
         return cls(A0, U, V, seed_x0v(seed), seed.info()["t0"], E, stream=stream)
 
     def set_level(self, m: int, basis="auto", max_eig_cond=0.0, tsvd_rank=0):
-        o = SeedOpts(BASIS[basis], 0, float(max_eig_cond), int(tsvd_rank), 0)
+        o = SeedOpts(BASIS[basis], 0, float(max_eig_cond), int(tsvd_rank), 0, 0)
         _check(load().ek_set_level(self.h, int(m), C.byref(o)), "ek_set_level")
         return self.info()
 
@@ -441,7 +449,7 @@ class EKSpace:
         if d.shape != (P, self.r):
             raise ValueError("d must be P x r")
         opts = opts or solve_opts()
-        po = SeedOpts(BASIS[basis], 0, float(max_eig_cond), int(tsvd_rank), 0)
+        po = SeedOpts(BASIS[basis], 0, float(max_eig_cond), int(tsvd_rank), 0, 0)
         out = (EkResult * P)()
         st = load().ek_sweep(self.h, P, d.ctypes.data, C.byref(opts), C.byref(po), float(eps),
                              int(m_start), int(m_max), int(check_every), out)

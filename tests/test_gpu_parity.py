@@ -385,3 +385,73 @@ def test_every_gemm_launch_configuration(cfg, monkeypatch):
     assert np.all(res["status"] == 0)
     assert np.max(rel(res["trace"], oracle_traces(pr))) <= 1e-10
     seed.release()
+
+
+def test_solve_in_exactly_the_reported_workspace_allocates_nothing():
+    """smw_solve_batch with a caller workspace of exactly smw_workspace_bytes:
+    the engine is carved from it.  A second call with the same workspace
+    allocates no device memory (free device memory unchanged) and gives the
+    same results; the results equal those of a call that lets the seed
+    allocate (NULL workspace)."""
+    import ctypes as C
+    L, torch = lib()
+    pr = W.config(3, P=48)
+    seed = L.Seed.from_problem(pr)
+    lb = L.load()
+    d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
+    opts = L.solve_opts()
+    P = pr.P
+    need = seed.workspace_bytes(P, opts)
+    assert need > 0
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    out = []
+    free = []
+    for call in range(3):
+        Y = torch.empty((P, pr.r, pr.n), dtype=torch.float64, device="cuda")
+        res = (L.lyapsmw.Result * P)()
+        wsp = C.c_void_p(ws.data_ptr()) if call < 2 else None
+        torch.cuda.synchronize()
+        f0 = torch.cuda.mem_get_info()[0]
+        st = lb.smw_solve_batch(seed.h, P, C.c_void_p(d.data_ptr()), C.byref(opts),
+                                C.c_void_p(Y.data_ptr()), res, wsp, need if call < 2 else 0,
+                                C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        free.append(f0 - torch.cuda.mem_get_info()[0])
+        assert st == 0, L.last_error()
+        out.append(Y.cpu().numpy())
+        assert all(r.status == 0 for r in res)
+    print("device bytes taken by the calls:", free)
+    assert free[1] == 0                      # same workspace again: nothing allocated
+    assert np.array_equal(out[0], out[1])
+    assert np.max(np.abs(out[2] - out[0])) <= 1e-12 * np.max(np.abs(out[0]))
+    too_small = lb.smw_solve_batch(seed.h, P, C.c_void_p(d.data_ptr()), C.byref(opts),
+                                   C.c_void_p(Y.data_ptr()), (L.lyapsmw.Result * P)(),
+                                   C.c_void_p(ws.data_ptr()), need - 1,
+                                   C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert too_small == 1
+    seed.release()
+
+
+@pytest.mark.parametrize("delta,expect", [(1e-3, "eig"), (3e-4, "schur")])
+def test_basis_switch_just_below_and_above_the_default(delta, expect):
+    """Nearly defective seeds whose eigenbasis condition estimate lies just below
+    (about 5e4) and just above (about 1.7e5) the default switch of 1e5: the
+    automatic choice takes the eigenbasis and the Schur basis respectively, and
+    both meet 1e-10 against the oracle (refined values)."""
+    L, torch = lib()
+    pr = W.near_defective(60, 3, 4, 8, 11, delta=delta)
+    seed = L.Seed.from_problem(pr)
+    info = seed.info()
+    eig = L.Seed.from_problem(pr, basis="eig")
+    cond = eig.info()["cond_est"]
+    eig.release()
+    print("delta %.0e: cond %.2e, basis %d" % (delta, cond, info["basis"]), flush=True)
+    assert (cond <= 1e5) == (expect == "eig")
+    assert info["basis"] == (1 if expect == "eig" else 2)
+    d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
+    Y, res = seed.solve(d, L.solve_opts(max_iter=2000))
+    tr = seed.trace(Y).cpu().numpy()
+    ref = np.array([r.trace for r in O.solve_problem(pr, diagnostics=False, refine=1)])
+    assert np.all(res["status"] == 0)
+    assert np.max(rel(tr, ref)) <= 1e-10
+    seed.release()

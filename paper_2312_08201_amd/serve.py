@@ -50,6 +50,7 @@ class _ReqState:
     status: np.ndarray
     iters: np.ndarray
     remaining: int
+    rel_residual: Optional[np.ndarray] = None
     admitted_at: float = 0.0
     done_at: float = 0.0
 
@@ -67,7 +68,7 @@ class _SeedEntry:
 class Server:
     def __init__(self, hbm_budget: int, slots: int = 256, opts: Optional[L.SolveOpts] = None,
                  steps_per_poll: int = 8, clock: Callable[[], float] = time.perf_counter,
-                 factor_threads: int = 2):
+                 factor_threads: int = 2, seeds: Optional[dict] = None):
         self.budget = int(hbm_budget)
         self.slots = slots
         self.opts = opts or L.solve_opts()
@@ -84,6 +85,9 @@ class Server:
         self.seed_factor_seconds = 0.0
         self.pool = ThreadPoolExecutor(max_workers=factor_threads)
         self.factoring = {}   # seed_key -> future of (Seed, seconds)
+        # seeds factored before the stream starts (seed_key -> Seed): used instead of
+        # a factorisation, owned by the caller (never released here)
+        self.external = dict(seeds or {})
 
     def now(self) -> float:
         return self.clock() - self.t0
@@ -99,7 +103,8 @@ class Server:
             ent = self.cache[key]
             if ent.inflight == 0:
                 ent.engine.close()
-                ent.seed.release()
+                if key not in self.external:
+                    ent.seed.release()
                 self.used -= ent.bytes
                 del self.cache[key]
         return self.used + need <= self.budget
@@ -121,6 +126,11 @@ class Server:
 
     def _try_admit(self, req: SweepRequest) -> bool:
         ent = self.cache.get(req.seed_key)
+        if ent is None and req.seed_key in self.external and req.seed_key not in self.factoring:
+            from concurrent.futures import Future
+            fut = Future()
+            fut.set_result((self.external[req.seed_key], 0.0))
+            self.factoring[req.seed_key] = fut
         if ent is None:
             fut = self.factoring.get(req.seed_key)
             if fut is None:
@@ -135,7 +145,8 @@ class Server:
             need = seed.device_bytes() + eng_bytes
             if not self._evict_for(need):
                 if not any(e.inflight for e in self.cache.values()):
-                    seed.release()
+                    if req.seed_key not in self.external:
+                        seed.release()
                     raise MemoryError("request %d does not fit in the HBM budget" % req.rid)
                 # keep the factored seed until memory frees up
                 self.factoring[req.seed_key] = self.pool.submit(lambda s=seed, f=fs: (s, f))
@@ -155,7 +166,8 @@ class Server:
         for i, tg in enumerate(tags):
             self.tag_owner[int(tg)] = (req.rid, i)
         self.states[req.rid] = _ReqState(req, np.full(P, np.nan), np.full(P, -1, np.int32),
-                                         np.zeros(P, np.int32), P, admitted_at=self.now())
+                                         np.zeros(P, np.int32), P, np.full(P, np.nan),
+                                         admitted_at=self.now())
         ent.inflight += P
         ent.last_used = self.now()
         return True
@@ -175,6 +187,7 @@ class Server:
                 st.traces[i] = rr["trace"]
                 st.status[i] = rr["status"]
                 st.iters[i] = rr["iters"]
+                st.rel_residual[i] = rr["rel_residual"]
                 st.remaining -= 1
                 ent.inflight -= 1
                 if st.remaining == 0:
@@ -199,16 +212,18 @@ class Server:
         return self.finished
 
     def close(self):
-        for fut in self.factoring.values():
+        for key, fut in self.factoring.items():
             try:
-                fut.result()[0].release()
+                if key not in self.external:
+                    fut.result()[0].release()
             except Exception:
                 pass
         self.factoring.clear()
         self.pool.shutdown(wait=True)
-        for ent in self.cache.values():
+        for key, ent in self.cache.items():
             ent.engine.close()
-            ent.seed.release()
+            if key not in self.external:
+                ent.seed.release()
         self.cache.clear()
 
 

@@ -33,7 +33,7 @@ from oracle import lyap_bs as O  # noqa: E402
 from oracle import stability as S  # noqa: E402
 
 REFINE = 1
-SERVE_DEFAULT = dict(requests=24, rate=4.0, seed=4, sizes=[400, 1000, 2000])
+SERVE_DEFAULT = dict(requests=200, rate=1.0, seed=4, sizes=[400, 1000, 2000, 4000])
 IMPORTANCE = dict(m=196, graph_seed=7, agents=[0, 65, 130, 195], per_agent=16, sample_seed=0)
 
 SAMPLES = {

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/lyapsmw.h"
+#include "streamk.h"
 
 namespace lyap {
 
@@ -137,12 +138,22 @@ struct GemmArgs {
   int bk;             // K-tile depth (0: the type's default; F64 8 or 16, F32 16 or 32)
   int xcd_off;        // 1: plain tile order instead of the XCD-aware mapping
   int tuning;         // 1: autotuner timing launch (separate kernel symbol)
+  int streamk;        // 1: stream-K (dynamic M, Cpart holds segments; C is not
+                      // written): exactly grid_min workgroups, see sk_plan
 };
 
-constexpr int kGemmBM = 128;
-constexpr int kGemmBN = 128;
 inline int gemm_bk(GemmType t) { return t == GemmType::F64 ? 16 : 32; }
 inline int gemm_bk_of(const GemmArgs& g) { return g.bk > 0 ? g.bk : gemm_bk(g.type); }
+// K-tiles of one launch (the BF16X3 kernel's K-tile is 32)
+inline int gemm_nk_of(const GemmArgs& g) {
+  return (int)(g.K / (g.type == GemmType::BF16X3 ? 32 : gemm_bk_of(g)));
+}
+// workgroups of a launch (the consumer of split-K or stream-K partials needs it)
+inline int64_t gemm_grid_of(const GemmArgs& g) {
+  if (g.streamk) return g.grid_min;
+  const int64_t tiles = ((g.M + kGemmBM - 1) / kGemmBM) * (g.N / kGemmBN);
+  return tiles > g.grid_min ? tiles : g.grid_min;
+}
 
 void gemm_launch(const GemmArgs& g, hipStream_t s);
 

@@ -51,17 +51,26 @@ enum SI : int {
 };
 constexpr int kPbarMax = 64;  // TSVD rank bound of the preconditioner
 constexpr int kTsvdGrid = 256;  // workgroup budget of the skinny TSVD GEMM (split-K)
-// Split-K partials: a launch of G workgroups over ntiles column tiles writes
-// at most G / ntiles row tiles of partials (the doubling rule of splitk_of
-// keeps slices x active row tiles <= G / ntiles).  The Cauchy GEMM's budget is
-// at most twice its tile count (autotuner candidates), so its partial buffer
-// holds twice the padded rows; the TSVD GEMM (one column tile) holds
+// Split-K partials (the TSVD GEMM, one column tile): a launch of G
+// workgroups writes at most G row tiles of partials; its buffer holds
 // kTsvdGrid row tiles.
-constexpr int kPartRowsFactor = 2;
-// Launch budget and partial-buffer rows of the engine's Cauchy GEMM (the
-// autotuned budget; at most kPartRowsFactor row tiles of partials per tile).
-inline long long cauchy_grid_min(long long tuned, long long) { return tuned; }
-inline long long cauchy_part_rows(long long rows_pad) { return kPartRowsFactor * rows_pad; }
+// The Cauchy GEMMs run stream-K (sk_plan) on kSkGridUnit x {2, 4}
+// workgroups (two or four per CU of a 256-CU device; the autotuner picks).
+// Their partial buffers hold the segments of the largest candidate grid at
+// any active row count, for every K-tile depth a launch may use.
+constexpr int kSkGridUnit = 256;
+constexpr int kSkGridMults[2] = {2, 4};
+inline long long cauchy_part_rows(long long rows_pad, long long ld, GemmType type) {
+  const int nks[2] = {type == GemmType::F64 ? 8 : 16, type == GemmType::F64 ? 16 : 32};
+  long long rows = 0;
+  for (int mult : kSkGridMults)
+    for (int bk : nks) {
+      if (type == GemmType::BF16X3 && bk != 32) continue;
+      rows = std::max(rows, sk_part_rows(rows_pad, (int)(ld / kGemmBN), mult * kSkGridUnit,
+                                         (int)(ld / bk)));
+    }
+  return rows;
+}
 // per-slot double state
 enum SD : int { SD_BNORM = 0, SD_BETA, SD_N };
 
@@ -102,7 +111,7 @@ struct EngineArgs {
   // queue (ring of capacity Q) and results
   const double* qd;        // Q x r
   const long long* qtag;   // Q
-  int* qctl;               // [0] head, [1] tail, [2] done count
+  int* qctl;               // [0] head, [1] tail, [2] done count, [3] head after this step's claims
   DevResult* res;          // Q
   int Q;
   double* sol;             // optional: solutions by tag, stride N (rho form)
@@ -124,8 +133,8 @@ struct EngineArgs {
   double* Tpart;        // split-K partials of Tbuf
   double* Sc;           // list rows x 128: Cp^-1 Mt^T y
   double* Qc;           // list rows x Ks: Nt Cp^-1 Mt^T y
-  // split orthogonalisation (restarted GMRES): per slot and 512-element chunk
-  // of the slot vector, the chunk's partial projections and norms
+  // split orthogonalisation (restarted GMRES): per slot and chunk of the
+  // slot vector, the chunk's partial projections and norms
   int nchunk;           // NV / (2 x orth workgroup size)
   double* orth1;        // S x nchunk x kPart: <v_k, w> chunk sums (k <= j), ||w||^2 last
   double* orth1b;       // the same after the first pass
@@ -502,13 +511,28 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
 // or past the tail is given back, which keeps the head from ever falling
 // below the tail once it has reached it.  No compare-and-swap retry loop:
 // a step in which every slot claims costs one atomic per slot.
-__device__ inline int claim(const EngineArgs& A) {
-  const int tail = __atomic_load_n(&A.qctl[1], __ATOMIC_RELAXED);
-  if (__atomic_load_n(&A.qctl[0], __ATOMIC_RELAXED) >= tail) return -1;
-  const int pos = atomicAdd(&A.qctl[0], 1);
-  if (pos < tail) return pos;
-  atomicSub(&A.qctl[0], 1);
-  return -1;
+// Queue claims of one step, in slot order: free slot s takes queue position
+// head + (number of free slots before s) while positions remain.  Every
+// workgroup of k_admit computes the same ranks; the new head goes to qctl[3]
+// and becomes qctl[0] at the start of the next step (k_lists), so no
+// workgroup reads a head that another one has moved.  The slot a parameter
+// lands in (and so its rows in the Cauchy GEMM) is then a function of the
+// submissions alone.
+__device__ inline int claim_rank(const EngineArgs& A, int s, int* nfree_out, int* red) {
+  int before = 0, total = 0;
+  for (int t = threadIdx.x; t < A.S; t += blockDim.x) {
+    const int f = A.si[(long)t * SI_N + SI_PHASE] == PH_FREE ? 1 : 0;
+    total += f;
+    before += (t < s) ? f : 0;
+  }
+  // block sums (fixed order is not needed: integers)
+  if (threadIdx.x == 0) red[0] = red[1] = 0;
+  __syncthreads();
+  atomicAdd(&red[0], before);
+  atomicAdd(&red[1], total);
+  __syncthreads();
+  *nfree_out = red[1];
+  return red[0];
 }
 
 // Result of slot s.  err_est, the estimated relative error of the trace:
@@ -587,6 +611,8 @@ __global__ void __launch_bounds__(1024) k_lists(EngineArgs A) {
   // single workgroup; stable compaction in slot order
   __shared__ int c64[1024], clo[1024];
   const int S = A.S;
+  // the previous step's queue claims (k_admit) become the head
+  if (threadIdx.x == 0) A.qctl[0] = A.qctl[3];
   const int per = (S + blockDim.x - 1) / blockDim.x;
   const int s0 = threadIdx.x * per;
   int n64 = 0, nlo = 0;
@@ -888,17 +914,17 @@ __global__ void __launch_bounds__(KT) k_formX(EngineArgs A, T* X, long plane, in
   }
 }
 
-// w = z - D (sum_b z_b o K1_ab + sum_b Uh_b o H_(li,a,b)); H may be split-K partials
+// w = z - D (sum_b z_b o K1_ab + sum_b Uh_b o H_(li,a,b)); H is the sum of
+// the stream-K segments of the Cauchy GEMM (a launch of ggrid workgroups
+// over gnk K-tiles), added in segment order
 template <class HT>
 __global__ void __launch_bounds__(KT)
-k_epilogue(EngineArgs A, const HT* H, const HT* Hp, int which, int ggrid, int gnk) {
+k_epilogue(EngineArgs A, const HT* Hp, int which, int ggrid, int gnk) {
   const int S = A.S, r = A.r, ld = A.ld, h = A.h;
   const int cnt = A.lists[2 * S + which];
   const int nu = A.n - h;
-  const int mta = (cnt * r * r + kGemmBM - 1) / kGemmBM;
-  const int KS = splitk_of(mta, ld / kGemmBN, ggrid, gnk);
-  const long kstride = (long)mta * kGemmBM * ld;
-  const HT* Hsrc = KS > 1 ? Hp : H;
+  const SkPlan plan = sk_plan(cnt * r * r, ld / kGemmBN, ggrid, gnk);
+  const long segstride = (long)plan.mta * plan.bm * ld;
   const long total = (long)cnt * r * nu;
   for (long g = (long)blockIdx.x * blockDim.x + threadIdx.x; g < total;
        g += (long)gridDim.x * blockDim.x) {
@@ -916,11 +942,14 @@ k_epilogue(EngineArgs A, const HT* H, const HT* Hp, int which, int ggrid, int gn
       const double* k = A.K1 + (long)(a * r + b) * ld;
       const double* zb = zs + (long)b * ld;
       const double* ub = A.Uh + (long)b * ld;
-      const HT* hb = Hsrc + ((long)(li * r + a) * r + b) * ld;
+      const int grow = (li * r + a) * r + b;  // GEMM row; q and q + 1 share a column tile
+      int s0, ns;
+      sk_segments(plan, (q / kGemmBN) * plan.mta + grow / plan.bm, s0, ns);
+      const HT* hb = Hp + (long)grow * ld;
       double hr = 0, hi = 0;
-      for (int t = 0; t < KS; ++t) {
-        hr += (double)hb[t * kstride + q];
-        if (pr) hi += (double)hb[t * kstride + q + 1];
+      for (int t = 0; t < ns; ++t) {
+        hr += (double)hb[t * segstride + q];
+        if (pr) hi += (double)hb[t * segstride + q + 1];
       }
       if (pr) {
         const double kr = k[q], ki = k[q + 1], zr = zb[q], zi = zb[q + 1];
@@ -1136,7 +1165,7 @@ __device__ void x_add_recycled(const EngineArgs& A, int s, int bank, int nvec, c
 // ---------------------------------------------------------------------------
 // Split orthogonalisation of the Arnoldi step (restarted GMRES): classical
 // Gram-Schmidt with one reorthogonalisation (CGS2).  A slot's vector is cut
-// into chunks of 512 values, one 256-thread workgroup per slot and chunk, so
+// into chunks, one workgroup per slot and chunk (sizes below), so
 // that the streaming of the basis V_0..j uses the whole chip also when few
 // slots are active (one workgroup per slot leaves most CUs idle in a sweep's
 // tail):
@@ -1926,11 +1955,15 @@ __global__ void k_record_counts(const int* lists, int S, int* dst, int* counter)
 // queue), so a slot freed in this step starts its next parameter in the next.
 __global__ void __launch_bounds__(KT) k_admit(EngineArgs A) {
   __shared__ double lds[4 * 9];
-  __shared__ int qp;
+  __shared__ int red[2];
   const int s = blockIdx.x;
-  if (A.si[(long)s * SI_N + SI_PHASE] != PH_FREE) return;
-  if (threadIdx.x == 0) qp = claim(A);
-  __syncthreads();
+  int nfree;
+  const int rank = claim_rank(A, s, &nfree, red);
+  const int head = __atomic_load_n(&A.qctl[0], __ATOMIC_RELAXED);
+  const int tail = __atomic_load_n(&A.qctl[1], __ATOMIC_RELAXED);
+  if (s == 0 && threadIdx.x == 0) A.qctl[3] = head + min(nfree, max(tail - head, 0));
+  if (A.si[(long)s * SI_N + SI_PHASE] != PH_FREE) return;  // uniform over the workgroup
+  const int qp = head + rank < tail ? head + rank : -1;
   if (qp >= 0) admit(A, s, qp, lds);
 }
 
@@ -1944,8 +1977,8 @@ using namespace lyap;
 // Launch configuration of the Cauchy GEMM chosen by the autotuner.
 struct GemmTune {
   int bk = 0;               // K-tile depth (0: default)
-  long long grid_min = 0;   // workgroup budget for split-K (0: one per output tile)
-  int xcd_off = 0;          // plain tile order instead of the XCD-aware mapping
+  long long grid_min = 0;   // stream-K grid (workgroups)
+  int xcd_off = 0;          // plain range order instead of the XCD-aware one
 };
 
 struct lyap_engine_s {
@@ -2076,11 +2109,12 @@ static void engine_layout(const lyap_seed_s* sd, long long S, const lyap_solve_o
   if (sd->basis == LYAP_BASIS_SCHUR && !sd->Kd.p) t(&lyap_engine_s::XS, S * ld * ld * 8);
   t(&lyap_engine_s::X, rows_pad * ld * 8);
   t(&lyap_engine_s::H, rows_pad * ld * 8);
-  t(&lyap_engine_s::Hp, cauchy_part_rows(rows_pad) * ld * 8);
+  t(&lyap_engine_s::Hp, cauchy_part_rows(rows_pad, ld, GemmType::F64) * ld * 8);
   if (o.prec != LYAP_PREC_FP64) {
+    const GemmType lo = o.prec == LYAP_PREC_BF16_IR ? GemmType::BF16X3 : GemmType::F32;
     t(&lyap_engine_s::Xlo, rows_pad * ld * 4);
     t(&lyap_engine_s::Hlo, rows_pad * ld * 4);
-    t(&lyap_engine_s::Hplo, cauchy_part_rows(rows_pad) * ld * 4);
+    t(&lyap_engine_s::Hplo, cauchy_part_rows(rows_pad, ld, lo) * ld * 4);
   }
   t(&lyap_engine_s::qd, Q * r * 8);
   t(&lyap_engine_s::qtag, Q * 8);
@@ -2225,19 +2259,19 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     g.M_dev = E->lists.as<int>() + 2 * S;
     g.m_scale = r * r;
     g.Cpart = E->Hp.p;
-    g.Cpart_rows = cauchy_part_rows(E->rows_pad);
+    g.Cpart_rows = cauchy_part_rows(E->rows_pad, ld, GemmType::F64);
     g.bk = E->t64.bk;
-    g.grid_min = cauchy_grid_min(E->t64.grid_min, ld);
+    g.grid_min = E->t64.grid_min;
     g.xcd_off = E->t64.xcd_off;
+    g.streamk = 1;
     if (on(PART_G64)) {
     if (ev) LYAP_HIP(hipEventRecord(ev->g64[0], st));
     gemm_launch(g, st);
     if (ev) LYAP_HIP(hipEventRecord(ev->g64[1], st));
     }
-    const int ggrid = (int)std::max<long long>((E->rows_pad / kGemmBM) * (ld / kGemmBN), g.grid_min);
     if (on(PART_MID))
-    hipLaunchKernelGGL((k_epilogue<double>), dim3(egrid), dim3(KT), 0, st, A, E->H.as<double>(),
-                       E->Hp.as<double>(), 0, ggrid, ld / gemm_bk_of(g));
+    hipLaunchKernelGGL((k_epilogue<double>), dim3(egrid), dim3(KT), 0, st, A, E->Hp.as<double>(),
+                       0, (int)gemm_grid_of(g), gemm_nk_of(g));
   }
   if (E->mixed) {
     GemmArgs g{};
@@ -2253,10 +2287,11 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     g.M_dev = E->lists.as<int>() + 2 * S + 1;
     g.m_scale = r * r;
     g.Cpart = E->Hplo.p;
-    g.Cpart_rows = cauchy_part_rows(E->rows_pad);
+    g.Cpart_rows = cauchy_part_rows(E->rows_pad, ld, E->low);
     g.bk = E->tlo.bk;
-    g.grid_min = cauchy_grid_min(E->tlo.grid_min, ld);
+    g.grid_min = E->tlo.grid_min;
     g.xcd_off = E->tlo.xcd_off;
+    g.streamk = 1;
     if (E->low != GemmType::F32) {
       g.a_plane = E->rows_pad * ld;
       g.b_plane = (long long)ld * ld;
@@ -2274,10 +2309,9 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     gemm_launch(g, st);
     if (ev) LYAP_HIP(hipEventRecord(ev->glo[1], st));
     }
-    const int ggrid = (int)std::max<long long>((E->rows_pad / kGemmBM) * (ld / kGemmBN), g.grid_min);
     if (on(PART_POST))
-    hipLaunchKernelGGL((k_epilogue<float>), dim3(egrid), dim3(KT), 0, st, A, E->Hlo.as<float>(),
-                       E->Hplo.as<float>(), 1, ggrid, ld / gemm_bk_of(g));
+    hipLaunchKernelGGL((k_epilogue<float>), dim3(egrid), dim3(KT), 0, st, A,
+                       E->Hplo.as<float>(), 1, (int)gemm_grid_of(g), gemm_nk_of(g));
   }
   }  // eigen basis
   if (!on(PART_POST)) {
@@ -2483,16 +2517,17 @@ static void profiled_steps(lyap_engine_s* E, long long k, int level) {
 }
 
 // ---- launch autotuner of the Cauchy GEMM ----
-// For the engine's GEMM shape (rows_pad x ld x ld) every candidate launch
-// configuration (K-tile depth x split-K workgroup budget x tile order) is
-// timed with HIP events at three active-row counts that stand for a sweep:
-// the full batch, an eighth of it and one row tile (the tail), weighted by
-// the share of steps spent in each (0.15, 0.15, 0.7); each figure is the
-// median of 5 timings of 2 launches.  A candidate replaces the default launch
-// (K-tile 16/32, one workgroup per tile, XCD-aware order) only when it is
-// more than 3% faster, so that timing noise does not flip the choice.  The
-// result is kept for the process, per (precision, rows, ld).  The engine's
-// own GEMM buffers serve as operands before its first step.
+// The Cauchy GEMMs run stream-K.  For the engine's GEMM shape (rows_pad x ld
+// x ld) every candidate launch configuration (K-tile depth x grid of 2 or 4
+// workgroups per CU x range order) is timed with HIP events at three
+// active-row counts that stand for a sweep: the full batch, an eighth of it
+// and 32 rows (the tail), weighted by the share of steps spent in each
+// (0.15, 0.15, 0.7); each figure is the median of 5 timings of 2 launches.
+// A candidate replaces the default launch (K-tile 16/32, two workgroups per
+// CU, plain range order) only when it is more than 3% faster, so that timing
+// noise does not flip the choice.  The result is kept for the process, per
+// (precision, rows, ld).  The engine's own GEMM buffers serve as operands
+// before its first step.  The split-BF16 GEMM is not tuned (default launch).
 // LYAP_GEMM_TUNE_LOG=1 prints the candidate table to stderr.
 namespace {
 std::mutex g_tune_mu;
@@ -2501,20 +2536,21 @@ GemmTune g_last_tune;
 }  // namespace
 
 static GemmTune tune_cauchy(lyap_engine_s* E, GemmType type) {
-  if (type == GemmType::BF16X3) return GemmTune{};
   const long long ld = E->sd->ld, rows = E->rows_pad;
-  const long long sgrid0 = (rows / kGemmBM) * (ld / kGemmBN);
+  const GemmTune dflt{type == GemmType::F64 ? 16 : 32, (long long)kSkGridMults[0] * kSkGridUnit, 1};
+  if (type == GemmType::BF16X3) return dflt;
   // LYAP_GEMM_CONFIG="bk,grid_mult,xcd_off" fixes the configuration (tests,
-  // diagnostics); bk must be one of the candidates of the precision
+  // diagnostics): bk one of the precision's K-tile depths, grid_mult 2 or 4
+  // (workgroups per CU of a 256-CU device)
   if (const char* env = std::getenv("LYAP_GEMM_CONFIG")) {
     int bk = 0, mult = 0, xoff = 0;
     LYAP_REQUIRE(std::sscanf(env, "%d,%d,%d", &bk, &mult, &xoff) == 3, LYAP_E_INVAL,
                  "LYAP_GEMM_CONFIG must be bk,grid_mult,xcd_off");
     const bool ok_bk = type == GemmType::F64 ? (bk == 8 || bk == 16) : (bk == 16 || bk == 32);
-    LYAP_REQUIRE(ok_bk && (mult == 0 || mult == kPartRowsFactor) && (xoff == 0 || xoff == 1),
-                 LYAP_E_INVAL,
+    const bool ok_mult = mult == kSkGridMults[0] || mult == kSkGridMults[1];
+    LYAP_REQUIRE(ok_bk && ok_mult && (xoff == 0 || xoff == 1), LYAP_E_INVAL,
                  "LYAP_GEMM_CONFIG out of the candidate set");
-    return GemmTune{bk, mult * sgrid0, xoff};
+    return GemmTune{bk, (long long)mult * kSkGridUnit, xoff};
   }
   const auto key = std::make_tuple((int)type, rows, ld);
   {
@@ -2523,18 +2559,20 @@ static GemmTune tune_cauchy(lyap_engine_s* E, GemmType type) {
     if (it != g_tune.end()) return it->second;
   }
   hipStream_t st = E->stream;
-  const long long sgrid = (rows / kGemmBM) * (ld / kGemmBN);
   const int bks[2] = {type == GemmType::F64 ? 8 : 16, type == GemmType::F64 ? 16 : 32};
   std::vector<GemmTune> cand;
-  cand.push_back(GemmTune{bks[1], 0, 0});  // the default launch comes first
+  cand.push_back(dflt);  // the default launch comes first
   for (int bk : bks)
-    for (long long gm : {0LL, (long long)kPartRowsFactor * sgrid})
-      for (int x : {0, 1})
-        if (!(bk == bks[1] && gm == 0 && x == 0)) cand.push_back(GemmTune{bk, gm, x});
+    for (int mult : kSkGridMults)
+      for (int x : {0, 1}) {
+        const GemmTune c{bk, (long long)mult * kSkGridUnit, x};
+        if (!(c.bk == dflt.bk && c.grid_min == dflt.grid_min && c.xcd_off == dflt.xcd_off))
+          cand.push_back(c);
+      }
   const bool log = std::getenv("LYAP_GEMM_TUNE_LOG") != nullptr;
   const long long full = rows;
   const long long regimes[3] = {full, std::max<long long>(kGemmBM, (full / 8) / kGemmBM * kGemmBM),
-                                std::min<long long>(full, kGemmBM)};
+                                std::min<long long>(full, 32)};
   const double weight[3] = {0.15, 0.15, 0.7};
   DevBuf mdev(sizeof(int));
   hipEvent_t e0, e1;
@@ -2558,11 +2596,12 @@ static GemmTune tune_cauchy(lyap_engine_s* E, GemmType type) {
       g.M_dev = mdev.as<int>();
       g.m_scale = 1;
       g.Cpart = type == GemmType::F64 ? E->Hp.p : E->Hplo.p;
-      g.Cpart_rows = kPartRowsFactor * rows;
+      g.Cpart_rows = cauchy_part_rows(rows, ld, type);
       g.bk = c.bk;
       g.grid_min = c.grid_min;
       g.xcd_off = c.xcd_off;
       g.tuning = 1;
+      g.streamk = 1;
       double tot = 0, per[3];
       for (int q = 0; q < 3; ++q) {
         const int m = (int)regimes[q];

@@ -370,12 +370,13 @@ def test_oversized_capacitance_vector_is_an_error_not_an_abort():
     seed.release()
 
 
-@pytest.mark.parametrize("cfg", ["8,0,0", "8,0,1", "8,2,0", "8,2,1", "16,0,0", "16,0,1", "16,2,0",
-                                 "16,2,1"])
+@pytest.mark.parametrize("cfg", ["8,2,0", "8,2,1", "8,4,0", "8,4,1", "16,2,0", "16,2,1", "16,4,0",
+                                 "16,4,1"])
 def test_every_gemm_launch_configuration(cfg, monkeypatch):
-    """Each configuration the GEMM autotuner can choose (K-tile depth, split-K
-    workgroup budget, tile order), forced, gives oracle-exact traces: a full
-    batch and a ragged tail (one slow parameter) so split-K slices occur."""
+    """Each configuration the GEMM autotuner can choose (K-tile depth, stream-K
+    grid of 2 or 4 workgroups per CU, range order), forced, gives oracle-exact
+    traces: a full batch and a ragged tail (one slow parameter), so tiles are
+    split over several workgroups at every active row count."""
     L, torch = lib()
     monkeypatch.setenv("LYAP_GEMM_CONFIG", cfg)
     pr = W.small_chain(150, (20, 75, 130), 4, 24, seed=8)   # n = 300, ld = 384

@@ -260,8 +260,13 @@ def cpu_baseline_per_core(config, P, workers):
     idx = sorted({(P * (2 * k + 1)) // (2 * workers) for k in range(workers)})
     ctx = mp.get_context("spawn")
     t = time.perf_counter()
+    out = []
     with ctx.Pool(len(idx)) as pool:
-        out = pool.map(_oracle_worker, [(config, i) for i in idx])
+        for o in pool.imap_unordered(_oracle_worker, [(config, i) for i in idx]):
+            out.append(o)
+            print("  oracle parameter %d done in %.1f s (%d of %d)" % (o[0], o[2], len(out), len(idx)),
+                  file=sys.stderr, flush=True)
+    out.sort()
     wall = time.perf_counter() - t
     return {"value": len(idx) / wall, "unit": "evals/s", "cores": len(idx), "kind": "oracle",
             "cpu_model": model, "host_cores_visible": cores,

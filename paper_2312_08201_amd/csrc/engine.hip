@@ -47,7 +47,7 @@ enum Phase : int { PH_FREE = 0, PH_ARNOLDI = 1, PH_RESTART = 2, PH_RECYC = 3, PH
 // rebuild for a new parameter, BANK: which of the two U/C banks is current)
 enum SI : int {
   SI_PHASE = 0, SI_J, SI_ITERS, SI_CYCLES, SI_REFINE, SI_QPOS, SI_KCUR, SI_RJ, SI_BANK, SI_CAPSET,
-  SI_PINV, SI_COMB, SI_N
+  SI_PINV, SI_COMB, SI_PASSB, SI_N
 };
 constexpr int kPbarMax = 64;  // TSVD rank bound of the preconditioner
 constexpr int kTsvdGrid = 256;  // workgroup budget of the skinny TSVD GEMM (split-K)
@@ -140,6 +140,13 @@ struct EngineArgs {
   double* orth1b;       // the same after the first pass
   double* orth2;        // S x nchunk: ||w||^2 chunk sums after the second pass
   double* ycoefs;       // S x (kMaxRestart + 1): cycle-end coefficients y (u += V y)
+  // delayed reorthogonalisation (dcgs = 1, see k_orth_a): chunk partials of
+  // the one projection pass, the update coefficients of the second pass and
+  // the unrotated Hessenberg columns
+  int dcgs;
+  double* orthA;        // S x nchunk x kPartA
+  double* coefB;        // S x kPartA: a (m), b (m), 1 / beta, z
+  double* Hu;           // S x m x (m + 1)
 };
 
 __device__ inline double* rec_u(const EngineArgs& A, int s, int bank, int l) {
@@ -1014,6 +1021,7 @@ __global__ void __launch_bounds__(KT) k_epilogue_schur(EngineArgs A, const doubl
 // products of a pass are reduced with a single barrier.
 // ---------------------------------------------------------------------------
 constexpr int kPart = kMaxBasis + 2;
+constexpr int kPartA = 2 * kMaxRestart + 2;  // a (m), b (m), c, d
 
 // Orthogonalise w against the unit vectors vec(0..nvec-1): classical
 // Gram-Schmidt, with a second pass only when the first one cancelled more
@@ -1324,6 +1332,263 @@ __global__ void __launch_bounds__(OT) k_orth(EngineArgs A) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Arnoldi with delayed reorthogonalisation (CGS2 with one projection pass per
+// step; after Swirydowicz, Langou, Ananthan, Yang and Thomas, "Low
+// synchronization Gram-Schmidt and GMRES algorithms", 2020, DCGS2).  At step
+// j the basis holds q_0..q_{j-1} (orthonormal) and u_j, the next direction
+// after ONE Gram-Schmidt pass, not normalised; the operator gave
+// w = A P^-1 u_j.  One pass over [q_0..q_{j-1}, u_j, w] (k_orth_a) yields
+//   a = Q^T u_j, b = Q^T w, c = u_j^T u_j, d = u_j^T w,
+// from which k_krylov forms, without touching the vectors:
+//   beta = sqrt(c - a^T a)           u_j = Q a + beta q_j (the second pass)
+//   column j of H:  (A P^-1 q_j = (w - A P^-1 Q a) / beta, A P^-1 Q = Q H)
+//     h_top = (b - (H a)_top) / beta,
+//     h_jj  = ((d - a^T b) / beta - beta a_{j-1}) / beta,
+//   and one update pass (k_orth_b) writes
+//     q_j     = (u_j - Q a) / beta                      (into V_j)
+//     u_{j+1} = (w - Q b) / beta - z q_j,  z = a_{j-1} + h_jj   (into V_{j+1})
+//   with the chunk partials of ||u_{j+1}||^2, the subdiagonal h_{j+1,j}
+//   (k_krylov_post: Givens rotation, convergence, cycle end).
+// The basis is read twice per step instead of four times (classical CGS2 in
+// three passes).  Column j-1 keeps h_{j,j-1} = ||u_j|| and its first-pass
+// projections: the second pass changes them by O(eps ||w_{j-1}||), the size
+// of the rounding already in the Arnoldi relation.
+// ---------------------------------------------------------------------------
+// Sum over the wavefront of eight values per lane (a butterfly that halves the
+// values at each of the first three exchanges: 10 exchanges instead of 48).
+// Lane L ends with the total of value 4 b5 + 2 b4 + b3 (the bits 5, 4, 3 of L);
+// all eight lanes of its group hold it.  Fixed order: deterministic.
+__device__ inline double wave_sum8(const double (&v)[8]) {
+  const int lane = threadIdx.x & 63;
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  double t4[4], t2[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double send = b5 ? v[i] : v[i + 4];
+    t4[i] = (b5 ? v[i + 4] : v[i]) + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double send = b4 ? t4[i] : t4[i + 2];
+    t2[i] = (b4 ? t4[i + 2] : t4[i]) + __shfl_xor(send, 16, 64);
+  }
+  const double send = b3 ? t2[0] : t2[1];
+  double t = (b3 ? t2[1] : t2[0]) + __shfl_xor(send, 8, 64);
+  t += __shfl_xor(t, 4, 64);
+  t += __shfl_xor(t, 2, 64);
+  t += __shfl_xor(t, 1, 64);
+  return t;
+}
+
+template <int OT>
+__global__ void __launch_bounds__(OT) k_orth_a(EngineArgs A) {
+  constexpr int kChunk = 2 * OT;
+  __shared__ double part[OT / 64][kPartA];
+  const int S = A.S, c64 = A.lists[2 * S], cnt = A.lists[2 * S + 2];
+  const int c = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = A.m;
+  for (int li = blockIdx.x; li < cnt; li += gridDim.x) {
+    const int s = li < c64 ? A.lists[li] : A.lists[S + (li - c64)];
+    const int* si = A.si + (long)s * SI_N;
+    if (si[SI_PHASE] != PH_ARNOLDI) continue;  // uniform over the workgroup
+    const int j = si[SI_J];
+    const long off = (long)c * kChunk;
+    const double* V0 = A.V + (long)s * (m + 1) * A.NV + off;
+    const double2 w = reinterpret_cast<const double2*>(A.w + (long)s * A.NV + off)[tid];
+    const double2 u = reinterpret_cast<const double2*>(V0 + (long)j * A.NV)[tid];
+    auto vk = [&](int k) { return reinterpret_cast<const double2*>(V0 + (long)k * A.NV)[tid]; };
+    // four basis vectors per group: <v, u> as values 0..3, <v, w> as 4..7
+    const int grp = lane >> 3;  // the value this lane's group of eight ends with
+    for (int k = 0; k < j; k += 4) {
+      double2 x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = k + q < j ? vk(k + q) : make_double2(0.0, 0.0);
+      double v[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        v[q] = x[q].x * u.x + x[q].y * u.y;
+        v[4 + q] = x[q].x * w.x + x[q].y * w.y;
+      }
+      const double t = wave_sum8(v);
+      if ((lane & 7) == 0 && k + (grp & 3) < j)
+        part[wave][(grp < 4 ? 0 : m) + k + (grp & 3)] = t;
+    }
+    {
+      double v[8] = {u.x * u.x + u.y * u.y, u.x * w.x + u.y * w.y, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      const double t = wave_sum8(v);
+      if ((lane & 7) == 0 && grp < 2) part[wave][2 * m + grp] = t;
+    }
+    __syncthreads();
+    double* dst = A.orthA + ((long)s * A.nchunk + c) * kPartA;
+    for (int t = tid; t < 2 * m + 2; t += OT) {
+      if (t < 2 * m && (t % m) >= j) continue;
+      double v = 0.0;
+      for (int q = 0; q < OT / 64; ++q) v += part[q][t];
+      dst[t] = v;
+    }
+    __syncthreads();  // part is reused for the next slot
+  }
+}
+
+// The update pass of the delayed reorthogonalisation (see k_orth_a): q_j into
+// V_j, u_{j+1} into V_{j+1}, chunk partials of ||u_{j+1}||^2 -> orth2.
+template <int OT>
+__global__ void __launch_bounds__(OT) k_orth_b(EngineArgs A) {
+  constexpr int kChunk = 2 * OT;
+  __shared__ double cf[kPartA];
+  __shared__ double part[OT / 64];
+  const int S = A.S, c64 = A.lists[2 * S], cnt = A.lists[2 * S + 2];
+  const int c = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = A.m;
+  for (int li = blockIdx.x; li < cnt; li += gridDim.x) {
+    const int s = li < c64 ? A.lists[li] : A.lists[S + (li - c64)];
+    const int* si = A.si + (long)s * SI_N;
+    if (!si[SI_PASSB]) continue;  // uniform over the workgroup
+    const int j = si[SI_J];
+    const double* cb = A.coefB + (long)s * kPartA;
+    for (int t = tid; t < 2 * m + 2; t += OT) cf[t] = cb[t];
+    __syncthreads();
+    const long off = (long)c * kChunk;
+    double* V0 = A.V + (long)s * (m + 1) * A.NV + off;
+    const double2 w = reinterpret_cast<const double2*>(A.w + (long)s * A.NV + off)[tid];
+    double2* up = reinterpret_cast<double2*>(V0 + (long)j * A.NV) + tid;
+    const double2 u = *up;
+    double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
+    auto vk = [&](int k) { return reinterpret_cast<const double2*>(V0 + (long)k * A.NV)[tid]; };
+    int k = 0;
+    for (; k + 4 <= j; k += 4) {
+      double2 x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = vk(k + q);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        sa.x += cf[k + q] * x[q].x;
+        sa.y += cf[k + q] * x[q].y;
+        sb.x += cf[m + k + q] * x[q].x;
+        sb.y += cf[m + k + q] * x[q].y;
+      }
+    }
+    for (; k < j; ++k) {
+      const double2 x0 = vk(k);
+      sa.x += cf[k] * x0.x;
+      sa.y += cf[k] * x0.y;
+      sb.x += cf[m + k] * x0.x;
+      sb.y += cf[m + k] * x0.y;
+    }
+    const double ib = cf[2 * m], z = cf[2 * m + 1];
+    double2 qv, un;
+    qv.x = (u.x - sa.x) * ib;
+    qv.y = (u.y - sa.y) * ib;
+    un.x = (w.x - sb.x) * ib - z * qv.x;
+    un.y = (w.y - sb.y) * ib - z * qv.y;
+    *up = qv;
+    reinterpret_cast<double2*>(V0 + (long)(j + 1) * A.NV)[tid] = un;
+    const double nn = wave_sum(un.x * un.x + un.y * un.y);
+    if (lane == 0) part[wave] = nn;
+    __syncthreads();
+    if (tid == 0) {
+      double v = 0.0;
+      for (int q = 0; q < OT / 64; ++q) v += part[q];
+      A.orth2[(long)s * A.nchunk + c] = v;
+    }
+    __syncthreads();  // cf and part are reused for the next slot
+  }
+}
+
+// Arnoldi step j of the delayed reorthogonalisation, after the update pass:
+// h_{j+1,j} = ||u_{j+1}||, Givens rotation of column j, residual estimate,
+// end of the cycle (back substitution, coefficients for k_combine).
+__global__ void __launch_bounds__(64) k_krylov_post(EngineArgs A) {
+  __shared__ double hcol[kMaxRestart + 2];
+  __shared__ double cs_l[kMaxRestart], sn_l[kMaxRestart];
+  __shared__ double Rl[kMaxRestart][kMaxRestart + 1];  // R[l][k]: column l, row k
+  __shared__ double gl[kMaxRestart + 1];
+  __shared__ double y[kMaxRestart];
+  __shared__ int end_sh;
+  const int s = blockIdx.x, tid = threadIdx.x;
+  int* si = A.si + (long)s * SI_N;
+  if (!si[SI_PASSB]) return;  // uniform over the workgroup
+  const int m = A.m;
+  const double* sdv = A.sdv + (long)s * SD_N;
+  double* gs = A.g + (long)s * (m + 1);
+  double* Rs = A.R + (long)s * m * (m + 1);
+  double* css = A.cs + (long)s * m;
+  double* sns = A.sn + (long)s * m;
+  const double bn = sdv[SD_BNORM];
+  const int j = si[SI_J];
+  const double* hu = A.Hu + ((long)s * m + j) * (m + 1);
+  for (int k = tid; k <= j; k += 64) hcol[k] = hu[k];
+  for (int k = tid; k < j; k += 64) {
+    cs_l[k] = css[k];
+    sn_l[k] = sns[k];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double n2 = 0.0;
+    for (int q = 0; q < A.nchunk; ++q) n2 += A.orth2[(long)s * A.nchunk + q];
+    const double hn = sqrt(n2);
+    hcol[j + 1] = hn;
+    A.Hu[((long)s * m + j) * (m + 1) + j + 1] = hn;
+    for (int k = 0; k < j; ++k) {
+      const double a = hcol[k], b = hcol[k + 1];
+      hcol[k] = cs_l[k] * a + sn_l[k] * b;
+      hcol[k + 1] = -sn_l[k] * a + cs_l[k] * b;
+    }
+    const double a = hcol[j], b = hcol[j + 1];
+    double cr, sg;
+    if (b == 0.0) {
+      cr = 1.0;
+      sg = 0.0;
+    } else {
+      const double t = hypot(a, b);
+      cr = a / t;
+      sg = b / t;
+    }
+    css[j] = cr;
+    sns[j] = sg;
+    hcol[j] = cr * a + sg * b;
+    const double gj = gs[j];
+    gs[j] = cr * gj;
+    gs[j + 1] = -sg * gj;
+    const double est = fabs(gs[j + 1]);
+    const int iters = si[SI_ITERS] + 1;
+    si[SI_ITERS] = iters;
+    si[SI_J] = j + 1;
+    si[SI_PASSB] = 0;
+    double target = 0.5 * A.tol * bn;
+    if (A.mixed) target = fmax(target, A.inner_tol * sdv[SD_BETA]);
+    end_sh = est <= target || j + 1 >= m || !(hn > 1e-300 * bn) || iters >= A.max_iter ||
+             !isfinite(est);
+  }
+  __syncthreads();
+  for (int k = tid; k <= j; k += 64) Rs[(long)j * (m + 1) + k] = hcol[k];
+  if (!end_sh) return;  // uniform
+  // end of the cycle: back substitution R y = g (R from columns 0..j), then
+  // u += V y by k_combine
+  const int jn = j + 1;
+  for (int e = tid; e < j * jn; e += 64) {  // columns 0..j-1 (column j is in hcol)
+    const int l = e / jn, k = e - l * jn;
+    Rl[l][k] = Rs[(long)l * (m + 1) + k];
+  }
+  for (int k = tid; k < jn; k += 64) {
+    Rl[j][k] = hcol[k];
+    gl[k] = gs[k];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    for (int k = jn - 1; k >= 0; --k) {
+      double v = gl[k];
+      for (int l = k + 1; l < jn; ++l) v -= Rl[l][k] * y[l];
+      y[k] = v / Rl[k][k];
+    }
+    si[SI_COMB] = jn;
+    si[SI_PHASE] = PH_RESTART;
+  }
+  __syncthreads();
+  for (int k = tid; k < jn; k += 64) A.ycoefs[(long)s * (kMaxRestart + 1) + k] = y[k];
+}
+
 // Per slot and step, according to the slot's phase:
 //   RESTART  w = A P^-1 u: true residual r = D c0 - w, convergence test, finish or
 //            start a new cycle (r projected off the recycle space C first)
@@ -1364,7 +1629,7 @@ __global__ void __launch_bounds__(BT) k_krylov(EngineArgs A) {
   const double* d = A.d + (long)s * r;
 
   double2 w2[NE2];
-  load2<NE2, BT>(w2, ws);
+  if (REC || ph != PH_ARNOLDI || !A.dcgs) load2<NE2, BT>(w2, ws);
   double wn0 = 0.0;
 
   if (REC && ph == PH_RECYC) {
@@ -1467,6 +1732,59 @@ __global__ void __launch_bounds__(BT) k_krylov(EngineArgs A) {
 
   // ---- Arnoldi step j: w = A P^-1 v_j, orthogonalised against [C, V_0..j] ----
   const int j = si[SI_J];
+  if (!REC && A.dcgs) {
+    // delayed reorthogonalisation (see k_orth_a): sums of the chunk partials,
+    // beta, column j of H (unrotated, to Hu) and the update coefficients
+    __shared__ double sa[kPartA];  // a (0..m-1), b (m..2m-1), c, d
+    __shared__ double Hl[kMaxRestart][kMaxRestart + 1];  // H[k][i], k < j, i < j
+    __shared__ double sbeta;
+    double* cb = A.coefB + (long)s * kPartA;
+    const double* pa = A.orthA + (long)s * A.nchunk * kPartA;
+    for (int t = tid; t < 2 * m + 2; t += BT) {
+      if (t < 2 * m && (t % m) >= j) continue;
+      double v = 0.0;
+      for (int q = 0; q < A.nchunk; ++q) v += pa[(long)q * kPartA + t];
+      sa[t] = v;
+    }
+    // the unrotated columns 0..j-1, rows 0..j-1
+    const double* Hg = A.Hu + (long)s * m * (m + 1);
+    for (int e = tid; e < j * j; e += BT) {
+      const int k = e / j, i = e - k * j;
+      Hl[k][i] = Hg[(long)k * (m + 1) + i];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double aa = 0.0;
+      for (int k = 0; k < j; ++k) aa += sa[k] * sa[k];
+      const double cc = sa[2 * m];
+      const double b2 = cc - aa;
+      sbeta = b2 > 0.0 ? sqrt(b2) : sqrt(fmax(cc, 0.0));
+    }
+    __syncthreads();
+    const double beta = sbeta;
+    double* hu = A.Hu + ((long)s * m + j) * (m + 1);
+    // h_i = (b_i - (H a)_i) / beta for i < j; H upper Hessenberg (H[k][i] = 0 for i > k + 1)
+    for (int i = tid; i < j; i += BT) {
+      double v = 0.0;
+      for (int k = (i > 0 ? i - 1 : 0); k < j; ++k) v += Hl[k][i] * sa[k];
+      hu[i] = (sa[m + i] - v) / beta;
+      cb[i] = sa[i];
+      cb[m + i] = sa[m + i];
+    }
+    if (tid == 0) {
+      double ab = 0.0;
+      for (int k = 0; k < j; ++k) ab += sa[k] * sa[m + k];
+      const double dd = sa[2 * m + 1];
+      const double ajm1 = j > 0 ? sa[j - 1] : 0.0;
+      const double hjj = ((dd - ab) / beta - beta * ajm1) / beta;
+      hu[j] = hjj;
+      cb[2 * m] = 1.0 / beta;
+      cb[2 * m + 1] = ajm1 + hjj;
+      if (j == 0) gs[0] *= beta;  // r = ||r|| u_0 = ||r|| beta q_0
+      si[SI_PASSB] = 1;
+    }
+    return;
+  }
   double hn;
   if (REC) {
     hn = cgs2<NE2, BT>(
@@ -1996,6 +2314,7 @@ struct lyap_engine_s {
   DevBuf si, sdv, d, R, g, cs, sn, V, x, z, w, Pinv, lists, X, H, Hp, Xlo, Hlo, Hplo, XS;
   DevBuf Ur, Cr, Bk, Hr, Fs;  // recycle space (GCRO-DR)
   DevBuf orth1, orth1b, orth2, ycoefs;  // split orthogonalisation (restarted GMRES)
+  DevBuf orthA, coefB, Hu;              // its delayed-reorthogonalisation form
   DevBuf Cpinv, Tbuf, Tpart, Sc;  // low-rank preconditioner part
   DevBuf qd, qtag, qctl, res;
   double* sol = nullptr;
@@ -2097,6 +2416,9 @@ static void engine_layout(const lyap_seed_s* sd, long long S, const lyap_solve_o
     t(&lyap_engine_s::orth1b, S * nch * kPart * 8);
     t(&lyap_engine_s::orth2, S * nch * 8);
     t(&lyap_engine_s::ycoefs, S * (kMaxRestart + 1) * 8);
+    t(&lyap_engine_s::orthA, S * nch * kPartA * 8);
+    t(&lyap_engine_s::coefB, S * kPartA * 8);
+    t(&lyap_engine_s::Hu, S * m * (m + 1) * 8);
   }
   if (o.recycle_k > 0) {
     const long long k = o.recycle_k;
@@ -2319,19 +2641,34 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     return;
   }
   if (ev && ev->kry[0]) LYAP_HIP(hipEventRecord(ev->kry[0], st));
-  if (A.kmax == 0) {
-    const int og = std::min(S, 1024);
-    if (orth_threads(A.NV) == 1024) {
-      hipLaunchKernelGGL((k_orth<0, 1024>), dim3(og, A.nchunk), dim3(1024), 0, st, A);
-      hipLaunchKernelGGL((k_orth<1, 1024>), dim3(og, A.nchunk), dim3(1024), 0, st, A);
-      hipLaunchKernelGGL((k_orth<2, 1024>), dim3(og, A.nchunk), dim3(1024), 0, st, A);
-    } else {
-      hipLaunchKernelGGL((k_orth<0, 256>), dim3(og, A.nchunk), dim3(256), 0, st, A);
-      hipLaunchKernelGGL((k_orth<1, 256>), dim3(og, A.nchunk), dim3(256), 0, st, A);
-      hipLaunchKernelGGL((k_orth<2, 256>), dim3(og, A.nchunk), dim3(256), 0, st, A);
+  const int og = std::min(S, 1024);
+  const bool big = orth_threads(A.NV) == 1024;
+  if (A.kmax == 0 && A.dcgs) {
+    // delayed reorthogonalisation: projections, coefficients, update, Givens
+    if (big)
+      hipLaunchKernelGGL((k_orth_a<1024>), dim3(og, A.nchunk), dim3(1024), 0, st, A);
+    else
+      hipLaunchKernelGGL((k_orth_a<256>), dim3(og, A.nchunk), dim3(256), 0, st, A);
+    launch_krylov(A, S, (long long)A.NV, st);
+    if (big)
+      hipLaunchKernelGGL((k_orth_b<1024>), dim3(og, A.nchunk), dim3(1024), 0, st, A);
+    else
+      hipLaunchKernelGGL((k_orth_b<256>), dim3(og, A.nchunk), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_krylov_post, dim3(S), dim3(64), 0, st, A);
+  } else {
+    if (A.kmax == 0) {
+      if (big) {
+        hipLaunchKernelGGL((k_orth<0, 1024>), dim3(og, A.nchunk), dim3(1024), 0, st, A);
+        hipLaunchKernelGGL((k_orth<1, 1024>), dim3(og, A.nchunk), dim3(1024), 0, st, A);
+        hipLaunchKernelGGL((k_orth<2, 1024>), dim3(og, A.nchunk), dim3(1024), 0, st, A);
+      } else {
+        hipLaunchKernelGGL((k_orth<0, 256>), dim3(og, A.nchunk), dim3(256), 0, st, A);
+        hipLaunchKernelGGL((k_orth<1, 256>), dim3(og, A.nchunk), dim3(256), 0, st, A);
+        hipLaunchKernelGGL((k_orth<2, 256>), dim3(og, A.nchunk), dim3(256), 0, st, A);
+      }
     }
+    launch_krylov(A, S, (long long)A.NV, st);
   }
-  launch_krylov(A, S, (long long)A.NV, st);
   if (A.kmax == 0) {
     if (orth_threads(A.NV) == 1024)
       hipLaunchKernelGGL((k_combine<1024>), dim3(std::min(S, 1024), A.nchunk), dim3(1024), 0, st, A);
@@ -2746,6 +3083,14 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   A.orth1 = E->orth1.as<double>();
   A.orth1b = E->orth1b.as<double>();
   A.ycoefs = E->ycoefs.as<double>();
+  A.orthA = E->orthA.as<double>();
+  A.coefB = E->coefB.as<double>();
+  A.Hu = E->Hu.as<double>();
+  // LYAP_ORTH=cgs2 selects classical CGS2 in three passes (measurements)
+  {
+    const char* env = std::getenv("LYAP_ORTH");
+    A.dcgs = (env && std::string(env) == "cgs2") ? 0 : 1;
+  }
   A.orth2 = E->orth2.as<double>();
   A.lists = E->lists.as<int>();
   A.qd = E->qd.as<double>();

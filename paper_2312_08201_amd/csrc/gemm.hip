@@ -193,9 +193,10 @@ gemm_kernel(const T* __restrict__ A, const T* __restrict__ B, T* __restrict__ C,
       sk_segments(p, t, s0, ns);
       T* dst = Cpart + (long)(v - s0) * segstride;
       const int row0 = (t % p.mta) * p.bm, col0 = (t / p.mta) * BN;
-      if (p.bm == 32)
+      const int hb = sk_tile_height(p, t % p.mta, Meff);
+      if (hb == 32)
         mac_tile<T, BK, PAD, 32>(A, B, dst, M, Meff, row0, col0, k0, k1, lda, ldb, ldc, Nstore, As, Bs);
-      else if (p.bm == 64)
+      else if (hb == 64)
         mac_tile<T, BK, PAD, 64>(A, B, dst, M, Meff, row0, col0, k0, k1, lda, ldb, ldc, Nstore, As, Bs);
       else
         mac_tile<T, BK, PAD>(A, B, dst, M, Meff, row0, col0, k0, k1, lda, ldb, ldc, Nstore, As, Bs);
@@ -385,10 +386,11 @@ gemm_bf16x3_kernel(const __bf16* __restrict__ A, long a_plane, const __bf16* __r
       sk_segments(p, t, s0, ns);
       float* dst = Cpart + (long)(v - s0) * segstride;
       const int row0 = (t % p.mta) * p.bm, col0 = (t / p.mta) * BN;
-      if (p.bm == 32)
+      const int hb = sk_tile_height(p, t % p.mta, Meff);
+      if (hb == 32)
         mac_tile_bf16<32>(A, a_plane, Bt, b_plane, dst, M, Meff, row0, col0, k0, k1, lda, ldb, ldc,
                           Nstore, Ash, Bsh);
-      else if (p.bm == 64)
+      else if (hb == 64)
         mac_tile_bf16<64>(A, a_plane, Bt, b_plane, dst, M, Meff, row0, col0, k0, k1, lda, ldb, ldc,
                           Nstore, Ash, Bsh);
       else

@@ -56,6 +56,14 @@ LYAP_HD inline void sk_segments(const SkPlan& p, int t, int& s0, int& ns) {
   s0 = (int)(a / p.per);
   ns = (int)((a + p.nk - 1) / p.per) - s0 + 1;
 }
+// Rows computed for row tile mt: bm, except that the last row tile of a
+// 128-row plan takes 32 or 64 rows when the active rows end within them (the
+// partial layout keeps the bm-row stride, so consumers are unaffected).
+LYAP_HD inline int sk_tile_height(const SkPlan& p, int mt, int Meff) {
+  if (p.bm != kGemmBM || mt < p.mta - 1) return p.bm;
+  const int rem = Meff - mt * p.bm;
+  return rem <= 32 ? 32 : (rem <= 64 ? 64 : kGemmBM);
+}
 // the iteration range [first, end) of range index v
 LYAP_HD inline void sk_range(const SkPlan& p, int v, long long& first, long long& end) {
   const long long total = (long long)p.mta * p.ntiles * p.nk;

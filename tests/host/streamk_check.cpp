@@ -53,6 +53,12 @@ static void check(long long M, int Meff, int ntiles, int grid, int nk, int xcd) 
             (long long)(seg + 1) * p.mta * p.bm, rows_avail, M, Meff, grid, nk);
       CHECK((t % p.mta) * p.bm < Meff, "tile row %d beyond the active rows %d", (t % p.mta) * p.bm,
             Meff);
+      {
+        const int mt = t % p.mta, hb = sk_tile_height(p, mt, Meff);
+        const int need = Meff - mt * p.bm < p.bm ? Meff - mt * p.bm : p.bm;
+        CHECK(hb >= need && hb <= p.bm && (hb == 32 || hb == 64 || hb == kGemmBM),
+              "tile %d height %d for %d rows", mt, hb, need);
+      }
       it += k1 - k0;
     }
   }

@@ -364,10 +364,10 @@ def per_parameter_baseline(L, torch, seed, pr, traces, count=16):
             "max_rel_diff_vs_batched": float(np.max(np.abs(got - traces[idx]) / np.abs(traces[idx])))}
 
 
-def sweep_mode(L, torch, seed, pr, d, prec, steps, gold_idx, gold_ref):
+def sweep_mode(L, torch, seed, pr, d, prec, steps, gold_idx, gold_ref, restart=None, inner_tol=1e-4):
     """Isolated sweeps of the workload in another precision mode: evals/s, the roofline
     of its Cauchy GEMM and the sampled error against the stored oracle values."""
-    opts = L.solve_opts(prec=prec)
+    opts = L.solve_opts(prec=prec, restart=restart, inner_tol=inner_tol)
     Y, res = seed.solve(d, opts)
     seed.trace(Y)
     torch.cuda.synchronize()
@@ -608,7 +608,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32_ir", "bf16_ir", "fp32"])
-    ap.add_argument("--restart", type=int, default=40)
+    ap.add_argument("--restart", type=int, default=None,
+                    help="Krylov cycle length (default: the library's, 64 or 40 with recycling)")
+    ap.add_argument("--inner-tol", type=float, default=1e-4,
+                    help="relative residual reduction of an inner (low-precision) cycle")
     ap.add_argument("--basis", default="auto", choices=["auto", "eig", "schur"],
                     help="seed basis (auto: eigenbasis unless ill-conditioned)")
     ap.add_argument("--tsvd-rank", type=int, default=0,
@@ -729,7 +732,8 @@ def main():
     factor_s = time.perf_counter() - t
     info = seed.info()
     d = torch.tensor(pr.d, dtype=torch.float64, device="cuda")
-    opts = L.solve_opts(prec=args.prec, restart=args.restart, recycle_k=args.recycle_k)
+    opts = L.solve_opts(prec=args.prec, restart=args.restart, recycle_k=args.recycle_k,
+                        inner_tol=args.inner_tol)
 
     def step():
         Y, res = seed.solve(d, opts)
@@ -785,7 +789,8 @@ def main():
         "dtype": {"fp64": "f64", "fp32_ir": "f32+f64", "bf16_ir": "bf16+f64", "fp32": "f32"}[args.prec],
         "data": "synthetic",
         "config": {"workload": WORKLOAD[args.config], "P": P, "n": pr.n, "r": pr.r,
-                   "precision": args.prec, "restart": args.restart,
+                   "precision": args.prec,
+                   "restart": args.restart or (40 if args.recycle_k else 64),
                    "recycle_k": args.recycle_k, "tsvd_rank": args.tsvd_rank, "basis": args.basis},
         "p50_ms": 1e3 * float(np.percentile(lat, 50)),
         "p99_ms": 1e3 * float(np.percentile(lat, 99)),
@@ -830,7 +835,8 @@ def main():
         out["modes"] = {}
         for m in modes:
             print("timing mode %s" % m, file=sys.stderr, flush=True)
-            rec, mtr = sweep_mode(L, torch, seed, pr, d, m, max(1, args.steps), gidx, gref)
+            rec, mtr = sweep_mode(L, torch, seed, pr, d, m, max(1, args.steps), gidx, gref,
+                                  restart=args.restart, inner_tol=args.inner_tol)
             rec["max_rel_diff_vs_%s" % args.prec] = float(np.max(np.abs(mtr - traces) /
                                                                np.abs(traces)))
             out["modes"][m] = rec

@@ -107,7 +107,8 @@ typedef struct {
 typedef struct {
   int32_t prec;           /* lyap_prec */
   int32_t max_iter;       /* total matrix-vector products per parameter (default 600) */
-  int32_t restart;        /* Krylov dimension per cycle m (default 40, at most 64) */
+  int32_t restart;        /* Krylov dimension per cycle m (0: default, 64 for restarted
+                             GMRES and 40 with recycle_k > 0; at most 64) */
   int32_t use_precond;    /* right preconditioner of eq:prec: 1 (default) = its exact
                              block-diagonal part plus the seed's coupling TSVD if it holds one
                              (lyap_seed_opts.tsvd_rank), 2 = block-diagonal part only,

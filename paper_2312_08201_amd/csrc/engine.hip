@@ -144,6 +144,8 @@ struct EngineArgs {
   // the one projection pass, the update coefficients of the second pass and
   // the unrotated Hessenberg columns
   int dcgs;
+  int vf32;             // 1: the basis is stored in FP32 (Vf), see basis_f32
+  float* Vf;            // S x (m+1) x NV when vf32
   double* orthA;        // S x nchunk x kPartA
   double* coefB;        // S x kPartA: a (m), b (m), 1 / beta, z
   double* Hu;           // S x m x (m + 1)
@@ -203,7 +205,8 @@ __device__ inline int uslot(int u, int h, bool& pr) {
 
 // z_a[u] = sum_b P[a][b][u] o v_b[u] for one slot (all a), units u0 + threadIdx.x,
 // u0 + threadIdx.x + ustride, ... (default: all units by this workgroup)
-__device__ inline void apply_pinv(const EngineArgs& A, int s, const double* v, double* zout,
+template <class ST = double>
+__device__ inline void apply_pinv(const EngineArgs& A, int s, const ST* v, double* zout,
                                   bool accumulate, const double* vscale = nullptr, int u0 = 0,
                                   int ustride = 0) {
   const int r = A.r, ld = A.ld, nu = A.n - A.h;
@@ -216,14 +219,15 @@ __device__ inline void apply_pinv(const EngineArgs& A, int s, const double* v, d
       double sr = 0, si = 0;
       for (int b = 0; b < r; ++b) {
         const double* pb = P + (long)(a * r + b) * ld;
-        const double* vb = v + (long)b * ld;
+        const ST* vb = v + (long)b * ld;
         if (pr) {
           const double f = vscale ? vscale[b] : 1.0;
-          const double pr_ = pb[q], pi_ = pb[q + 1], vr = f * vb[q], vi = f * vb[q + 1];
+          const double pr_ = pb[q], pi_ = pb[q + 1], vr = f * (double)vb[q],
+                       vi = f * (double)vb[q + 1];
           sr += pr_ * vr - pi_ * vi;
           si += pr_ * vi + pi_ * vr;
         } else {
-          sr += pb[q] * (vscale ? vscale[b] : 1.0) * vb[q];
+          sr += pb[q] * (vscale ? vscale[b] : 1.0) * (double)vb[q];
         }
       }
       double* za = zout + (long)a * ld;
@@ -462,7 +466,6 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
   double acc = 0;
   for (int e = threadIdx.x; e < N; e += blockDim.x) {
     const double v = dsh[e / ld] * A.c0[e];
-    V0[e] = v;
     acc += v * v;
   }
   const double bn = sqrt(block_sum1(acc, lds));
@@ -490,8 +493,15 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
     __syncthreads();
     return;
   }
+  // v_0 = b / ||b|| (the FP32 basis of the low-precision modes, else FP64)
   const double inv = 1.0 / bn;
-  for (int e = threadIdx.x; e < N; e += blockDim.x) V0[e] *= inv;
+  if (A.vf32) {
+    float* V0f = A.Vf + (long)s * (A.m + 1) * NV;
+    for (int e = threadIdx.x; e < N; e += blockDim.x)
+      V0f[e] = (float)(dsh[e / ld] * A.c0[e] * inv);
+  } else {
+    for (int e = threadIdx.x; e < N; e += blockDim.x) V0[e] = dsh[e / ld] * A.c0[e] * inv;
+  }
   if (threadIdx.x == 0) {
     // a slot that kept a recycle space from its previous parameter first
     // rebuilds C = A(p) P(p)^-1 U for the new parameter
@@ -678,6 +688,16 @@ __global__ void __launch_bounds__(KT) k_prep(EngineArgs A) {
     if (threadIdx.x == 0 && blockIdx.y == 0) A.si[(long)s * SI_N + SI_PINV] = 0;
     // source: the iterate u (residual step), v_j (Arnoldi) or a recycled u_rj
     const int* sis = A.si + (long)s * SI_N;
+    if (ph == PH_ARNOLDI && A.vf32) {
+      const float* srcf = A.Vf + ((long)s * (A.m + 1) + sis[SI_J]) * A.NV;
+      if (A.use_precond) {
+        apply_pinv(A, s, srcf, zs, false, nullptr, blockIdx.y * blockDim.x,
+                   gridDim.y * blockDim.x);
+      } else {
+        for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < N; e += gridDim.y * blockDim.x)
+          zs[e] = srcf[e];
+      }
+    } else {
     const double* src = ph == PH_RESTART ? A.x + (long)s * A.NV
                         : ph == PH_RECYC ? rec_u(A, s, sis[SI_BANK], sis[SI_RJ])
                                          : A.V + ((long)s * (A.m + 1) + sis[SI_J]) * A.NV;
@@ -686,6 +706,7 @@ __global__ void __launch_bounds__(KT) k_prep(EngineArgs A) {
     } else {
       for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < N; e += gridDim.y * blockDim.x)
         zs[e] = src[e];
+    }
     }
     if (A.pbar > 0) {
       __syncthreads();
@@ -1260,10 +1281,31 @@ __device__ inline void chunk_update(double2& w, const double* V0, long NV, int n
   }
 }
 
+// a chunk element pair of a basis vector stored as VT (double or float)
+template <class VT> struct Pair2;
+template <> struct Pair2<double> {
+  typedef double2 type;
+  __device__ static double2 load(const double* p, int i) { return reinterpret_cast<const double2*>(p)[i]; }
+  __device__ static void store(double* p, int i, double2 v) { reinterpret_cast<double2*>(p)[i] = v; }
+};
+template <> struct Pair2<float> {
+  typedef float2 type;
+  __device__ static double2 load(const float* p, int i) {
+    const float2 v = reinterpret_cast<const float2*>(p)[i];
+    return make_double2(v.x, v.y);
+  }
+  __device__ static void store(float* p, int i, double2 v) {
+    reinterpret_cast<float2*>(p)[i] = make_float2((float)v.x, (float)v.y);
+  }
+};
+template <class VT> __device__ inline const VT* basis(const EngineArgs& A);
+template <> __device__ inline const double* basis<double>(const EngineArgs& A) { return A.V; }
+template <> __device__ inline const float* basis<float>(const EngineArgs& A) { return A.Vf; }
+
 // Cycle end of restarted GMRES, split like the orthogonalisation: for every
 // listed slot whose Arnoldi cycle ended in this step (SI_COMB = jn vectors),
 // u += V y on each chunk, y stored by k_krylov in ycoefs.
-template <int OT>
+template <int OT, class VT = double>
 __global__ void __launch_bounds__(OT) k_combine(EngineArgs A) {
   constexpr int kChunk = 2 * OT;
   __shared__ double ys[kMaxRestart + 1];
@@ -1281,7 +1323,27 @@ __global__ void __launch_bounds__(OT) k_combine(EngineArgs A) {
     // x += V y  is  x -= V (-y): the same streaming loop as the update
     for (int t = tid; t < jn; t += OT) ys[t] = -ys[t];
     __syncthreads();
-    chunk_update(x, A.V + (long)s * (A.m + 1) * A.NV + off, A.NV, jn, ys);
+    if (sizeof(VT) == 8) {
+      chunk_update(x, A.V + (long)s * (A.m + 1) * A.NV + off, A.NV, jn, ys);
+    } else {
+      const VT* V0 = basis<VT>(A) + (long)s * (A.m + 1) * A.NV + off;
+      int k = 0;
+      for (; k + 8 <= jn; k += 8) {
+        double2 v8[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v8[q] = Pair2<VT>::load(V0 + (long)(k + q) * A.NV, tid);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          x.x -= ys[k + q] * v8[q].x;
+          x.y -= ys[k + q] * v8[q].y;
+        }
+      }
+      for (; k < jn; ++k) {
+        const double2 v0 = Pair2<VT>::load(V0 + (long)k * A.NV, tid);
+        x.x -= ys[k] * v0.x;
+        x.y -= ys[k] * v0.y;
+      }
+    }
     *xp = x;
     __syncthreads();  // ys is reused for the next slot
   }
@@ -1381,7 +1443,7 @@ __device__ inline double wave_sum8(const double (&v)[8]) {
   return t;
 }
 
-template <int OT>
+template <int OT, class VT = double>
 __global__ void __launch_bounds__(OT) k_orth_a(EngineArgs A) {
   constexpr int kChunk = 2 * OT;
   __shared__ double part[OT / 64][kPartA];
@@ -1394,10 +1456,10 @@ __global__ void __launch_bounds__(OT) k_orth_a(EngineArgs A) {
     if (si[SI_PHASE] != PH_ARNOLDI) continue;  // uniform over the workgroup
     const int j = si[SI_J];
     const long off = (long)c * kChunk;
-    const double* V0 = A.V + (long)s * (m + 1) * A.NV + off;
+    const VT* V0 = basis<VT>(A) + (long)s * (m + 1) * A.NV + off;
     const double2 w = reinterpret_cast<const double2*>(A.w + (long)s * A.NV + off)[tid];
-    const double2 u = reinterpret_cast<const double2*>(V0 + (long)j * A.NV)[tid];
-    auto vk = [&](int k) { return reinterpret_cast<const double2*>(V0 + (long)k * A.NV)[tid]; };
+    const double2 u = Pair2<VT>::load(V0 + (long)j * A.NV, tid);
+    auto vk = [&](int k) { return Pair2<VT>::load(V0 + (long)k * A.NV, tid); };
     // four basis vectors per group: <v, u> as values 0..3, <v, w> as 4..7
     const int grp = lane >> 3;  // the value this lane's group of eight ends with
     for (int k = 0; k < j; k += 4) {
@@ -1433,7 +1495,7 @@ __global__ void __launch_bounds__(OT) k_orth_a(EngineArgs A) {
 
 // The update pass of the delayed reorthogonalisation (see k_orth_a): q_j into
 // V_j, u_{j+1} into V_{j+1}, chunk partials of ||u_{j+1}||^2 -> orth2.
-template <int OT>
+template <int OT, class VT = double>
 __global__ void __launch_bounds__(OT) k_orth_b(EngineArgs A) {
   constexpr int kChunk = 2 * OT;
   __shared__ double cf[kPartA];
@@ -1450,12 +1512,11 @@ __global__ void __launch_bounds__(OT) k_orth_b(EngineArgs A) {
     for (int t = tid; t < 2 * m + 2; t += OT) cf[t] = cb[t];
     __syncthreads();
     const long off = (long)c * kChunk;
-    double* V0 = A.V + (long)s * (m + 1) * A.NV + off;
+    VT* V0 = const_cast<VT*>(basis<VT>(A)) + (long)s * (m + 1) * A.NV + off;
     const double2 w = reinterpret_cast<const double2*>(A.w + (long)s * A.NV + off)[tid];
-    double2* up = reinterpret_cast<double2*>(V0 + (long)j * A.NV) + tid;
-    const double2 u = *up;
+    const double2 u = Pair2<VT>::load(V0 + (long)j * A.NV, tid);
     double2 sa = make_double2(0.0, 0.0), sb = make_double2(0.0, 0.0);
-    auto vk = [&](int k) { return reinterpret_cast<const double2*>(V0 + (long)k * A.NV)[tid]; };
+    auto vk = [&](int k) { return Pair2<VT>::load(V0 + (long)k * A.NV, tid); };
     int k = 0;
     for (; k + 4 <= j; k += 4) {
       double2 x[4];
@@ -1482,8 +1543,8 @@ __global__ void __launch_bounds__(OT) k_orth_b(EngineArgs A) {
     qv.y = (u.y - sa.y) * ib;
     un.x = (w.x - sb.x) * ib - z * qv.x;
     un.y = (w.y - sb.y) * ib - z * qv.y;
-    *up = qv;
-    reinterpret_cast<double2*>(V0 + (long)(j + 1) * A.NV)[tid] = un;
+    Pair2<VT>::store(V0 + (long)j * A.NV, tid, qv);
+    Pair2<VT>::store(V0 + (long)(j + 1) * A.NV, tid, un);
     const double nn = wave_sum(un.x * un.x + un.y * un.y);
     if (lane == 0) part[wave] = nn;
     __syncthreads();
@@ -1714,6 +1775,12 @@ __global__ void __launch_bounds__(BT) k_krylov(EngineArgs A) {
           if (tid == 0) si[SI_PHASE] = PH_RESTART;
           return;
         }
+      } else if (A.vf32) {
+        float2* d2 = reinterpret_cast<float2*>(A.Vf + (long)s * (m + 1) * NV);
+        const double sc = 1.0 / rn;
+#pragma unroll
+        for (int i = 0; i < NE2; ++i)
+          d2[threadIdx.x + BT * i] = make_float2((float)(w2[i].x * sc), (float)(w2[i].y * sc));
       } else {
         store2<NE2, BT>(Vs, w2, 1.0 / rn);
       }
@@ -2302,6 +2369,10 @@ struct GemmTune {
 struct lyap_engine_s {
   lyap_seed sd = nullptr;
   GemmTune t64, tlo;  // Cauchy GEMM launch configurations (FP64, low precision)
+  // workgroups of the grid-stride element kernels (k_formX, k_epilogue) and slot
+  // workgroups per chunk of the orthogonalisation kernels (LYAP_EPI_GRID and
+  // LYAP_ORTH_GRID override them for measurements)
+  int egrid = 2048, og_cap = 1024;
   int S = 0, m = 40;
   lyap_solve_opts opts{};
   hipStream_t stream = nullptr;  // private non-blocking stream (graph capture needs one)
@@ -2315,6 +2386,7 @@ struct lyap_engine_s {
   DevBuf Ur, Cr, Bk, Hr, Fs;  // recycle space (GCRO-DR)
   DevBuf orth1, orth1b, orth2, ycoefs;  // split orthogonalisation (restarted GMRES)
   DevBuf orthA, coefB, Hu;              // its delayed-reorthogonalisation form
+  DevBuf Vf;                            // FP32 basis of the low-precision modes
   DevBuf Cpinv, Tbuf, Tpart, Sc;  // low-rank preconditioner part
   DevBuf qd, qtag, qctl, res;
   double* sol = nullptr;
@@ -2343,7 +2415,7 @@ namespace lyap {
 static void fill_defaults(lyap_solve_opts& o, const lyap_solve_opts* in) {
   o.prec = LYAP_PREC_FP64;
   o.max_iter = 600;
-  o.restart = 40;
+  o.restart = 64;
   o.use_precond = 1;
   o.recycle_k = 0;
   o.max_refine = 30;
@@ -2352,12 +2424,30 @@ static void fill_defaults(lyap_solve_opts& o, const lyap_solve_opts* in) {
   if (!in) return;
   o.prec = in->prec;
   if (in->max_iter > 0) o.max_iter = in->max_iter;
-  if (in->restart > 0) o.restart = in->restart;
   o.use_precond = in->use_precond;
   o.recycle_k = in->recycle_k;
+  // default cycle: 64 for restarted GMRES, 40 with a recycle space (restart +
+  // recycle_k <= 64)
+  o.restart = in->restart > 0 ? in->restart : (o.recycle_k > 0 ? 40 : 64);
   if (in->max_refine > 0) o.max_refine = in->max_refine;
   if (in->tol > 0) o.tol = in->tol;
   if (in->inner_tol > 0) o.inner_tol = in->inner_tol;
+}
+
+// Arnoldi with delayed reorthogonalisation unless LYAP_ORTH=cgs2
+static bool orth_dcgs() {
+  const char* env = std::getenv("LYAP_ORTH");
+  return !(env && std::string(env) == "cgs2");
+}
+// The Krylov basis of the low-precision modes is stored in FP32: their inner
+// cycles only reduce the residual by inner_tol before an FP64 restart, so an
+// FP32 basis (orthogonal to about 1e-7) halves the basis traffic at no cost in
+// the refined result.  Restarted GMRES with the delayed reorthogonalisation
+// only; LYAP_KRYLOV_F64=1 keeps FP64 (measurements).
+static bool basis_f32(const lyap_solve_opts& o) {
+  if (o.prec == LYAP_PREC_FP64 || o.recycle_k > 0 || !orth_dcgs()) return false;
+  const char* env = std::getenv("LYAP_KRYLOV_F64");
+  return !(env && std::string(env) == "1");
 }
 
 static void validate_opts(const lyap_solve_opts& o) {
@@ -2396,7 +2486,9 @@ static void engine_layout(const lyap_seed_s* sd, long long S, const lyap_solve_o
   t(&lyap_engine_s::g, S * (m + 1) * 8);
   t(&lyap_engine_s::cs, S * m * 8);
   t(&lyap_engine_s::sn, S * m * 8);
-  t(&lyap_engine_s::V, S * (m + 1) * N * 8);
+  const bool vf32 = basis_f32(o);
+  t(&lyap_engine_s::V, vf32 ? 256 : S * (m + 1) * N * 8);
+  t(&lyap_engine_s::Vf, vf32 ? S * (m + 1) * N * 4 : 256);
   t(&lyap_engine_s::x, S * N * 8);
   t(&lyap_engine_s::z, S * N * 8);
   t(&lyap_engine_s::w, S * N * 8);
@@ -2515,7 +2607,8 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     hipLaunchKernelGGL(k_prep2, dim3(pgrid), dim3(KT), 0, st, A);
   }
   const int ublocks = std::max(1, std::min((nu + KT - 1) / KT, 64));
-  const int egrid = 2048;  // grid-stride kernels: work proportional to the active count
+  // grid-stride kernels: work proportional to the active count
+  const int egrid = E->egrid;
   if (sd->basis == LYAP_BASIS_SCHUR && sd->Kd.p) {
     // dense capacitance operator: H rows of the listed slots = z rows Kd
     const long rl = (long)r * ld;
@@ -2641,19 +2734,34 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     return;
   }
   if (ev && ev->kry[0]) LYAP_HIP(hipEventRecord(ev->kry[0], st));
-  const int og = std::min(S, 1024);
+  const int og = std::min(S, E->og_cap);
   const bool big = orth_threads(A.NV) == 1024;
   if (A.kmax == 0 && A.dcgs) {
     // delayed reorthogonalisation: projections, coefficients, update, Givens
-    if (big)
-      hipLaunchKernelGGL((k_orth_a<1024>), dim3(og, A.nchunk), dim3(1024), 0, st, A);
-    else
-      hipLaunchKernelGGL((k_orth_a<256>), dim3(og, A.nchunk), dim3(256), 0, st, A);
+    const dim3 og2(og, A.nchunk);
+    if (A.vf32) {
+      if (big)
+        hipLaunchKernelGGL((k_orth_a<1024, float>), og2, dim3(1024), 0, st, A);
+      else
+        hipLaunchKernelGGL((k_orth_a<256, float>), og2, dim3(256), 0, st, A);
+    } else {
+      if (big)
+        hipLaunchKernelGGL((k_orth_a<1024>), og2, dim3(1024), 0, st, A);
+      else
+        hipLaunchKernelGGL((k_orth_a<256>), og2, dim3(256), 0, st, A);
+    }
     launch_krylov(A, S, (long long)A.NV, st);
-    if (big)
-      hipLaunchKernelGGL((k_orth_b<1024>), dim3(og, A.nchunk), dim3(1024), 0, st, A);
-    else
-      hipLaunchKernelGGL((k_orth_b<256>), dim3(og, A.nchunk), dim3(256), 0, st, A);
+    if (A.vf32) {
+      if (big)
+        hipLaunchKernelGGL((k_orth_b<1024, float>), og2, dim3(1024), 0, st, A);
+      else
+        hipLaunchKernelGGL((k_orth_b<256, float>), og2, dim3(256), 0, st, A);
+    } else {
+      if (big)
+        hipLaunchKernelGGL((k_orth_b<1024>), og2, dim3(1024), 0, st, A);
+      else
+        hipLaunchKernelGGL((k_orth_b<256>), og2, dim3(256), 0, st, A);
+    }
     hipLaunchKernelGGL(k_krylov_post, dim3(S), dim3(64), 0, st, A);
   } else {
     if (A.kmax == 0) {
@@ -2670,10 +2778,18 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
     launch_krylov(A, S, (long long)A.NV, st);
   }
   if (A.kmax == 0) {
-    if (orth_threads(A.NV) == 1024)
-      hipLaunchKernelGGL((k_combine<1024>), dim3(std::min(S, 1024), A.nchunk), dim3(1024), 0, st, A);
-    else
-      hipLaunchKernelGGL((k_combine<256>), dim3(std::min(S, 1024), A.nchunk), dim3(256), 0, st, A);
+    const bool big = orth_threads(A.NV) == 1024;
+    if (A.vf32) {
+      if (big)
+        hipLaunchKernelGGL((k_combine<1024, float>), dim3(og, A.nchunk), dim3(1024), 0, st, A);
+      else
+        hipLaunchKernelGGL((k_combine<256, float>), dim3(og, A.nchunk), dim3(256), 0, st, A);
+    } else {
+      if (big)
+        hipLaunchKernelGGL((k_combine<1024>), dim3(og, A.nchunk), dim3(1024), 0, st, A);
+      else
+        hipLaunchKernelGGL((k_combine<256>), dim3(og, A.nchunk), dim3(256), 0, st, A);
+    }
   }
   if (ev && ev->kry[0]) LYAP_HIP(hipEventRecord(ev->kry[1], st));
   if (A.kmax > 0) launch_krylov(A, S, (long long)A.NV, st, true);
@@ -3086,11 +3202,12 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   A.orthA = E->orthA.as<double>();
   A.coefB = E->coefB.as<double>();
   A.Hu = E->Hu.as<double>();
+  if (const char* env = std::getenv("LYAP_EPI_GRID")) E->egrid = std::max(1, std::atoi(env));
+  if (const char* env = std::getenv("LYAP_ORTH_GRID")) E->og_cap = std::max(1, std::atoi(env));
   // LYAP_ORTH=cgs2 selects classical CGS2 in three passes (measurements)
-  {
-    const char* env = std::getenv("LYAP_ORTH");
-    A.dcgs = (env && std::string(env) == "cgs2") ? 0 : 1;
-  }
+  A.dcgs = orth_dcgs() ? 1 : 0;
+  A.vf32 = basis_f32(o) ? 1 : 0;
+  A.Vf = E->Vf.as<float>();
   A.orth2 = E->orth2.as<double>();
   A.lists = E->lists.as<int>();
   A.qd = E->qd.as<double>();

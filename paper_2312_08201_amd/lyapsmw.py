@@ -221,11 +221,12 @@ def _precond_mode(v) -> int:
     return int(v)
 
 
-def solve_opts(prec="fp64", tol=1e-12, max_iter=600, restart=40, use_precond=True,
+def solve_opts(prec="fp64", tol=1e-12, max_iter=600, restart=None, use_precond=True,
                max_refine=30, inner_tol=1e-4, recycle_k=0) -> SolveOpts:
+    """restart None: the library's default cycle (64, or 40 with recycle_k > 0)."""
     return SolveOpts(PREC[prec] if isinstance(prec, str) else int(prec), int(max_iter),
-                     int(restart), _precond_mode(use_precond), int(recycle_k), int(max_refine),
-                     float(tol), float(inner_tol))
+                     0 if restart is None else int(restart), _precond_mode(use_precond),
+                     int(recycle_k), int(max_refine), float(tol), float(inner_tol))
 
 
 class Seed:

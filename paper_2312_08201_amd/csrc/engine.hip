@@ -47,7 +47,7 @@ enum Phase : int { PH_FREE = 0, PH_ARNOLDI = 1, PH_RESTART = 2, PH_RECYC = 3, PH
 // rebuild for a new parameter, BANK: which of the two U/C banks is current)
 enum SI : int {
   SI_PHASE = 0, SI_J, SI_ITERS, SI_CYCLES, SI_REFINE, SI_QPOS, SI_KCUR, SI_RJ, SI_BANK, SI_CAPSET,
-  SI_PINV, SI_COMB, SI_PASSB, SI_N
+  SI_PINV, SI_COMB, SI_PASSB, SI_CLAIM, SI_N
 };
 constexpr int kPbarMax = 64;  // TSVD rank bound of the preconditioner
 constexpr int kTsvdGrid = 256;  // workgroup budget of the skinny TSVD GEMM (split-K)
@@ -111,7 +111,7 @@ struct EngineArgs {
   // queue (ring of capacity Q) and results
   const double* qd;        // Q x r
   const long long* qtag;   // Q
-  int* qctl;               // [0] head, [1] tail, [2] done count, [3] head after this step's claims
+  int* qctl;               // [0] head, [1] tail, [2] done count
   DevResult* res;          // Q
   int Q;
   double* sol;             // optional: solutions by tag, stride N (rho form)
@@ -528,28 +528,39 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
 // or past the tail is given back, which keeps the head from ever falling
 // below the tail once it has reached it.  No compare-and-swap retry loop:
 // a step in which every slot claims costs one atomic per slot.
-// Queue claims of one step, in slot order: free slot s takes queue position
-// head + (number of free slots before s) while positions remain.  Every
-// workgroup of k_admit computes the same ranks; the new head goes to qctl[3]
-// and becomes qctl[0] at the start of the next step (k_lists), so no
-// workgroup reads a head that another one has moved.  The slot a parameter
-// lands in (and so its rows in the Cauchy GEMM) is then a function of the
-// submissions alone.
-__device__ inline int claim_rank(const EngineArgs& A, int s, int* nfree_out, int* red) {
-  int before = 0, total = 0;
-  for (int t = threadIdx.x; t < A.S; t += blockDim.x) {
-    const int f = A.si[(long)t * SI_N + SI_PHASE] == PH_FREE ? 1 : 0;
-    total += f;
-    before += (t < s) ? f : 0;
+// Queue claims of one step, in slot order (one workgroup, after every slot's
+// phase for the step is final): free slot s takes queue position head + (the
+// number of free slots before s) while positions remain, written to
+// si[SI_CLAIM] (-1: none); the head moves past the claimed positions.  The
+// slot a parameter lands in (and so its rows in the Cauchy GEMM) is then a
+// function of the submissions alone.  k_admit admits the claims.
+__global__ void __launch_bounds__(1024) k_claim(EngineArgs A) {
+  __shared__ int cnt[1024];
+  const int S = A.S, tid = threadIdx.x;
+  const int per = (S + blockDim.x - 1) / blockDim.x;
+  const int s0 = tid * per;
+  int n = 0;
+  for (int t = s0; t < min(S, s0 + per); ++t) n += A.si[(long)t * SI_N + SI_PHASE] == PH_FREE;
+  cnt[tid] = n;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {  // inclusive scan
+    const int v = tid >= off ? cnt[tid - off] : 0;
+    __syncthreads();
+    cnt[tid] += v;
+    __syncthreads();
   }
-  // block sums (fixed order is not needed: integers)
-  if (threadIdx.x == 0) red[0] = red[1] = 0;
-  __syncthreads();
-  atomicAdd(&red[0], before);
-  atomicAdd(&red[1], total);
-  __syncthreads();
-  *nfree_out = red[1];
-  return red[0];
+  const int head = A.qctl[0], tail = A.qctl[1];
+  int pos = head + cnt[tid] - n;
+  for (int t = s0; t < min(S, s0 + per); ++t) {
+    int* si = A.si + (long)t * SI_N;
+    if (si[SI_PHASE] != PH_FREE) continue;
+    si[SI_CLAIM] = pos < tail ? pos : -1;
+    ++pos;
+  }
+  if (tid == blockDim.x - 1) {
+    const int total = cnt[tid];
+    A.qctl[0] = head + min(total, max(tail - head, 0));
+  }
 }
 
 // Result of slot s.  err_est, the estimated relative error of the trace:
@@ -628,8 +639,6 @@ __global__ void __launch_bounds__(1024) k_lists(EngineArgs A) {
   // single workgroup; stable compaction in slot order
   __shared__ int c64[1024], clo[1024];
   const int S = A.S;
-  // the previous step's queue claims (k_admit) become the head
-  if (threadIdx.x == 0) A.qctl[0] = A.qctl[3];
   const int per = (S + blockDim.x - 1) / blockDim.x;
   const int s0 = threadIdx.x * per;
   int n64 = 0, nlo = 0;
@@ -2340,15 +2349,10 @@ __global__ void k_record_counts(const int* lists, int S, int* dst, int* counter)
 // queue), so a slot freed in this step starts its next parameter in the next.
 __global__ void __launch_bounds__(KT) k_admit(EngineArgs A) {
   __shared__ double lds[4 * 9];
-  __shared__ int red[2];
   const int s = blockIdx.x;
-  int nfree;
-  const int rank = claim_rank(A, s, &nfree, red);
-  const int head = __atomic_load_n(&A.qctl[0], __ATOMIC_RELAXED);
-  const int tail = __atomic_load_n(&A.qctl[1], __ATOMIC_RELAXED);
-  if (s == 0 && threadIdx.x == 0) A.qctl[3] = head + min(nfree, max(tail - head, 0));
-  if (A.si[(long)s * SI_N + SI_PHASE] != PH_FREE) return;  // uniform over the workgroup
-  const int qp = head + rank < tail ? head + rank : -1;
+  const int* si = A.si + (long)s * SI_N;
+  if (si[SI_PHASE] != PH_FREE) return;  // uniform over the workgroup
+  const int qp = si[SI_CLAIM];          // k_claim
   if (qp >= 0) admit(A, s, qp, lds);
 }
 
@@ -2793,6 +2797,7 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
   }
   if (ev && ev->kry[0]) LYAP_HIP(hipEventRecord(ev->kry[1], st));
   if (A.kmax > 0) launch_krylov(A, S, (long long)A.NV, st, true);
+  hipLaunchKernelGGL(k_claim, dim3(1), dim3(1024), 0, st, A);
   hipLaunchKernelGGL(k_admit, dim3(S), dim3(KT), 0, st, A);
   if (A.use_precond)
     hipLaunchKernelGGL(k_pinv, dim3(S, pinv_chunks(r, nu)), dim3(KT), 0, st, A);

@@ -180,7 +180,8 @@ def stored_traffic(config, prec):
     """HBM bytes per launch of the dominant kernel from stored rocprofv3 --pmc runs.
 
     Returns None unless the figures were taken on this workload and precision
-    with the current GEMM source (its hash is stored beside the counters).
+    with the current GEMM sources (the hash of the listed files, concatenated
+    in order, is stored beside the counters).
     """
     import hashlib
     path = os.path.join(ROOT, "profiles", "cauchy_gemm_c%d_%s_traffic.txt" % (config, prec))
@@ -192,11 +193,13 @@ def stored_traffic(config, prec):
         if line and not line.startswith("#") and "=" in line:
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    src = os.path.join(ROOT, kv.get("source", ""))
-    if not os.path.exists(src):
-        return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if sha != kv.get("source_sha256_16"):
+    h = hashlib.sha256()
+    for name in kv.get("source", "").split(","):
+        src = os.path.join(ROOT, name.strip())
+        if not name.strip() or not os.path.exists(src):
+            return None
+        h.update(open(src, "rb").read())
+    if h.hexdigest()[:16] != kv.get("source_sha256_16"):
         return None
     return (float(kv["fetch_kib_avg"]) * float(kv["fetch_scale"]) +
             float(kv["write_kib_avg"]) * float(kv["write_scale"])) * 1024.0

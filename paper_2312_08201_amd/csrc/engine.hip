@@ -923,82 +923,133 @@ template <> __device__ inline void put<__bf16>(__bf16* X, long off, long plane, 
   X[off + plane] = (__bf16)(f - (float)hi);
 }
 
+// one unit u of X row li * r * r + a * r + b
+template <class T>
+__device__ inline void formx_unit(const EngineArgs& A, T* X, long plane, int which, int row,
+                                  int u) {
+  const int r = A.r, ld = A.ld;
+  const int ab = row % (r * r), li = row / (r * r);
+  const int a = ab / r, b = ab - a * r;
+  const int s = A.lists[which * A.S + li];
+  const double* va = A.Vh + (long)a * ld;
+  const double* zb = A.z + (long)s * A.NV + (long)b * ld;
+  const long base = (long)row * ld;
+  bool pr;
+  const int q = uslot(u, A.h, pr);
+  if (pr) {
+    const double ar = va[q], ai = va[q + 1], br = zb[q], bi = zb[q + 1];
+    put<T>(X, base + q, plane, ar * br - ai * bi);
+    put<T>(X, base + q + 1, plane, ar * bi + ai * br);
+  } else {
+    put<T>(X, base + q, plane, va[q] * zb[q]);
+  }
+}
+
 template <class T>
 __global__ void __launch_bounds__(KT) k_formX(EngineArgs A, T* X, long plane, int which) {
-  const int S = A.S, r = A.r, ld = A.ld, h = A.h;
-  const int cnt = A.lists[2 * S + which];
-  const int nu = A.n - h;
+  const int r = A.r;
+  const int cnt = A.lists[2 * A.S + which];
+  const int nu = A.n - A.h;
   const long total = (long)cnt * r * r * nu;
-  for (long g = (long)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-       g += (long)gridDim.x * blockDim.x) {
-    const int row = (int)(g / nu);  // li * r * r + a * r + b
-    const int u = (int)(g - (long)row * nu);
-    const int li = row / (r * r);
-    const int a = (row / r) % r, b = row % r;
-    const int s = A.lists[which * S + li];
-    const double* va = A.Vh + (long)a * ld;
-    const double* zb = A.z + (long)s * A.NV + (long)b * ld;
-    const long base = (long)row * ld;
-    bool pr;
-    const int q = uslot(u, h, pr);
-    if (pr) {
-      const double ar = va[q], ai = va[q + 1], br = zb[q], bi = zb[q + 1];
-      put<T>(X, base + q, plane, ar * br - ai * bi);
-      put<T>(X, base + q + 1, plane, ar * bi + ai * br);
-    } else {
-      put<T>(X, base + q, plane, va[q] * zb[q]);
+  const long stride = (long)gridDim.x * blockDim.x;
+  const long g0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (total + stride < 0x7fffffffL) {  // 32-bit index arithmetic (every practical size)
+    for (int g = (int)g0; g < (int)total; g += (int)stride) {
+      const int row = g / nu;
+      formx_unit(A, X, plane, which, row, g - row * nu);
+    }
+  } else {
+    for (long g = g0; g < total; g += stride) {
+      const int row = (int)(g / nu);
+      formx_unit(A, X, plane, which, row, (int)(g - (long)row * nu));
     }
   }
 }
 
 // w = z - D (sum_b z_b o K1_ab + sum_b Uh_b o H_(li,a,b)); H is the sum of
 // the stream-K segments of the Cauchy GEMM (a launch of ggrid workgroups
-// over gnk K-tiles), added in segment order
+// over gnk K-tiles), added in segment order.  One unit u of row li * r + a.
+template <class HT>
+__device__ inline void epilogue_unit(const EngineArgs& A, const HT* __restrict__ Hp,
+                                     const SkPlan& plan, int bshift, long segstride, int which,
+                                     int row, int u) {
+  const int S = A.S, r = A.r, ld = A.ld;
+  const int li = row / r, a = row - li * r;
+  const int s = A.lists[which * S + li];
+  const double* zs = A.z + (long)s * A.NV;
+  double* ws = A.w + (long)s * A.NV + (long)a * ld;
+  const double da = A.d[(long)s * r + a];
+  bool pr;
+  const int q = uslot(u, A.h, pr);
+  const int ct = q / kGemmBN;  // q and q + 1 share a column tile
+  double sr = 0, si = 0;
+  int rt_seg = -1, s0 = 0, ns = 0;
+  for (int b = 0; b < r; ++b) {
+    const double* k = A.K1 + (long)(a * r + b) * ld;
+    const double* zb = zs + (long)b * ld;
+    const double* ub = A.Uh + (long)b * ld;
+    const int grow = row * r + b;  // GEMM row
+    const int rt = grow >> bshift;
+    if (rt != rt_seg) {  // the r rows of one (li, a) mostly share a row tile
+      // sk_segments in 32-bit arithmetic (the launch bounds t * nk below 2^31)
+      const unsigned a0 = (unsigned)(ct * plan.mta + rt) * (unsigned)plan.nk;
+      s0 = (int)(a0 / (unsigned)plan.per);
+      ns = (int)((a0 + (unsigned)plan.nk - 1u) / (unsigned)plan.per) - s0 + 1;
+      rt_seg = rt;
+    }
+    const HT* hb = Hp + (long)grow * ld + q;
+    // segments in order, two loads issued before their adds (a sweep's
+    // tail has up to 16 segments per tile)
+    double hr = 0, hi = 0;
+    int t = 0;
+    for (; t + 2 <= ns; t += 2) {
+      const HT* h0 = hb + t * segstride;
+      const double r0 = (double)h0[0], r1 = (double)h0[segstride];
+      const double i0 = pr ? (double)h0[1] : 0.0, i1 = pr ? (double)h0[segstride + 1] : 0.0;
+      hr += r0;
+      hr += r1;
+      hi += i0;
+      hi += i1;
+    }
+    if (t < ns) {
+      hr += (double)hb[t * segstride];
+      if (pr) hi += (double)hb[t * segstride + 1];
+    }
+    if (pr) {
+      const double kr = k[q], ki = k[q + 1], zr = zb[q], zi = zb[q + 1];
+      const double ur = ub[q], ui = ub[q + 1];
+      sr += zr * kr - zi * ki + ur * hr - ui * hi;
+      si += zr * ki + zi * kr + ur * hi + ui * hr;
+    } else {
+      sr += zb[q] * k[q] + ub[q] * hr;
+    }
+  }
+  ws[q] = zs[(long)a * ld + q] - da * sr;
+  if (pr) ws[q + 1] = zs[(long)a * ld + q + 1] - da * si;
+}
+
 template <class HT>
 __global__ void __launch_bounds__(KT)
 k_epilogue(EngineArgs A, const HT* Hp, int which, int ggrid, int gnk) {
-  const int S = A.S, r = A.r, ld = A.ld, h = A.h;
+  const int S = A.S, r = A.r, ld = A.ld;
   const int cnt = A.lists[2 * S + which];
-  const int nu = A.n - h;
+  const int nu = A.n - A.h;
   const SkPlan plan = sk_plan(cnt * r * r, ld / kGemmBN, ggrid, gnk);
+  const int bshift = plan.bm == 32 ? 5 : (plan.bm == 64 ? 6 : 7);
   const long segstride = (long)plan.mta * plan.bm * ld;
   const long total = (long)cnt * r * nu;
-  for (long g = (long)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-       g += (long)gridDim.x * blockDim.x) {
-    const int row = (int)(g / nu);  // li * r + a
-    const int u = (int)(g - (long)row * nu);
-    const int li = row / r, a = row % r;
-    const int s = A.lists[which * S + li];
-    const double* zs = A.z + (long)s * A.NV;
-    double* ws = A.w + (long)s * A.NV + (long)a * ld;
-    const double da = A.d[(long)s * r + a];
-    bool pr;
-    const int q = uslot(u, h, pr);
-    double sr = 0, si = 0;
-    for (int b = 0; b < r; ++b) {
-      const double* k = A.K1 + (long)(a * r + b) * ld;
-      const double* zb = zs + (long)b * ld;
-      const double* ub = A.Uh + (long)b * ld;
-      const int grow = (li * r + a) * r + b;  // GEMM row; q and q + 1 share a column tile
-      int s0, ns;
-      sk_segments(plan, (q / kGemmBN) * plan.mta + grow / plan.bm, s0, ns);
-      const HT* hb = Hp + (long)grow * ld;
-      double hr = 0, hi = 0;
-      for (int t = 0; t < ns; ++t) {
-        hr += (double)hb[t * segstride + q];
-        if (pr) hi += (double)hb[t * segstride + q + 1];
-      }
-      if (pr) {
-        const double kr = k[q], ki = k[q + 1], zr = zb[q], zi = zb[q + 1];
-        const double ur = ub[q], ui = ub[q + 1];
-        sr += zr * kr - zi * ki + ur * hr - ui * hi;
-        si += zr * ki + zi * kr + ur * hi + ui * hr;
-      } else {
-        sr += zb[q] * k[q] + ub[q] * hr;
-      }
+  const long stride = (long)gridDim.x * blockDim.x;
+  const long g0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (total + stride < 0x7fffffffL) {  // 32-bit index arithmetic (every practical size)
+    for (int g = (int)g0; g < (int)total; g += (int)stride) {
+      const int row = g / nu;  // li * r + a
+      epilogue_unit(A, Hp, plan, bshift, segstride, which, row, g - row * nu);
     }
-    ws[q] = zs[(long)a * ld + q] - da * sr;
-    if (pr) ws[q + 1] = zs[(long)a * ld + q + 1] - da * si;
+  } else {
+    for (long g = g0; g < total; g += stride) {
+      const int row = (int)(g / nu);
+      epilogue_unit(A, Hp, plan, bshift, segstride, which, row, (int)(g - (long)row * nu));
+    }
   }
 }
 
@@ -3137,6 +3188,10 @@ static lyap_engine_s* engine_create_impl(lyap_seed_s* sd, long long S, const lya
   E->Q = (int)Q;
   const long long r = sd->r, ld = sd->ld, N = slot_stride(r, ld), m = o.restart;
   EngineSizes z = engine_sizes(sd, S, o, Q);
+  // the consumers of the Cauchy GEMM's stream-K partials index its
+  // (tile, K-tile) iterations in 32 bits
+  LYAP_REQUIRE((z.rows_pad / kGemmBM + 1) * (ld / kGemmBN) * (ld / 8) < (1LL << 31), LYAP_E_INVAL,
+               "Cauchy GEMM too large for 32-bit stream-K indices");
   E->rows_pad = z.rows_pad;
   size_t carve = 0;
   engine_layout(sd, S, o, Q, E, [&](DevBuf* b, size_t bytes) {

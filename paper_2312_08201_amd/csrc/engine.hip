@@ -203,6 +203,23 @@ __device__ inline int uslot(int u, int h, bool& pr) {
   return pr ? 2 * u : u + h;
 }
 
+// at(0) + at(1) + ... + at(n - 1), added in index order, with eight loads in
+// flight at a time (per-chunk partials of one slot: n is small, and a plain
+// loop would wait for every load before issuing the next)
+template <class F>
+__device__ inline double chunk_sum(int n, F&& at) {
+  double acc = 0.0;
+  for (int q0 = 0; q0 < n; q0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = q0 + e < n ? at(q0 + e) : 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if (q0 + e < n) acc += v[e];
+  }
+  return acc;
+}
+
 // z_a[u] = sum_b P[a][b][u] o v_b[u] for one slot (all a), units u0 + threadIdx.x,
 // u0 + threadIdx.x + ustride, ... (default: all units by this workgroup)
 template <class ST = double>
@@ -1428,11 +1445,8 @@ __global__ void __launch_bounds__(OT) k_orth(EngineArgs A) {
     if (PASS > 0) {
       // projections of the previous pass, summed over the chunks in fixed order
       const double* prev = (PASS == 1 ? A.orth1 : A.orth1b) + (long)s * A.nchunk * kPart;
-      for (int t = tid; t < nvec; t += OT) {
-        double v = 0.0;
-        for (int q = 0; q < A.nchunk; ++q) v += prev[(long)q * kPart + t];
-        hs[t] = v;
-      }
+      for (int t = tid; t < nvec; t += OT)
+        hs[t] = chunk_sum(A.nchunk, [&](int q) { return prev[(long)q * kPart + t]; });
       __syncthreads();
       chunk_update(w, V0, A.NV, nvec, hs);
       *wp = w;
@@ -1625,7 +1639,6 @@ __global__ void __launch_bounds__(64) k_krylov_post(EngineArgs A) {
   __shared__ double cs_l[kMaxRestart], sn_l[kMaxRestart];
   __shared__ double Rl[kMaxRestart][kMaxRestart + 1];  // R[l][k]: column l, row k
   __shared__ double gl[kMaxRestart + 1];
-  __shared__ double y[kMaxRestart];
   __shared__ int end_sh;
   const int s = blockIdx.x, tid = threadIdx.x;
   int* si = A.si + (long)s * SI_N;
@@ -1646,17 +1659,19 @@ __global__ void __launch_bounds__(64) k_krylov_post(EngineArgs A) {
   }
   __syncthreads();
   if (tid == 0) {
-    double n2 = 0.0;
-    for (int q = 0; q < A.nchunk; ++q) n2 += A.orth2[(long)s * A.nchunk + q];
+    const double n2 = chunk_sum(A.nchunk, [&](int q) { return A.orth2[(long)s * A.nchunk + q]; });
     const double hn = sqrt(n2);
     hcol[j + 1] = hn;
     A.Hu[((long)s * m + j) * (m + 1) + j + 1] = hn;
+    // the rotated entry k + 1 is carried in a register, so the loads of the
+    // next rotation do not wait for the previous one
+    double carry = hcol[0];
     for (int k = 0; k < j; ++k) {
-      const double a = hcol[k], b = hcol[k + 1];
-      hcol[k] = cs_l[k] * a + sn_l[k] * b;
-      hcol[k + 1] = -sn_l[k] * a + cs_l[k] * b;
+      const double b = hcol[k + 1], c = cs_l[k], sk = sn_l[k];
+      hcol[k] = c * carry + sk * b;
+      carry = -sk * carry + c * b;
     }
-    const double a = hcol[j], b = hcol[j + 1];
+    const double a = carry, b = hcol[j + 1];
     double cr, sg;
     if (b == 0.0) {
       cr = 1.0;
@@ -1697,17 +1712,20 @@ __global__ void __launch_bounds__(64) k_krylov_post(EngineArgs A) {
     gl[k] = gs[k];
   }
   __syncthreads();
+  // column-oriented back substitution over the wave: lane i keeps the
+  // right-hand side entry i (jn <= 64 lanes) and subtracts column k's
+  // contribution once y_k is known
+  double v = tid < jn ? gl[tid] : 0.0, yv = 0.0;
+  for (int k = jn - 1; k >= 0; --k) {
+    const double yk = __shfl(v, k) / Rl[k][k];
+    if (tid == k) yv = yk;
+    if (tid < k) v -= Rl[k][tid] * yk;
+  }
+  if (tid < jn) A.ycoefs[(long)s * (kMaxRestart + 1) + tid] = yv;
   if (tid == 0) {
-    for (int k = jn - 1; k >= 0; --k) {
-      double v = gl[k];
-      for (int l = k + 1; l < jn; ++l) v -= Rl[l][k] * y[l];
-      y[k] = v / Rl[k][k];
-    }
     si[SI_COMB] = jn;
     si[SI_PHASE] = PH_RESTART;
   }
-  __syncthreads();
-  for (int k = tid; k < jn; k += 64) A.ycoefs[(long)s * (kMaxRestart + 1) + k] = y[k];
 }
 
 // Per slot and step, according to the slot's phase:
@@ -1869,9 +1887,7 @@ __global__ void __launch_bounds__(BT) k_krylov(EngineArgs A) {
     const double* pa = A.orthA + (long)s * A.nchunk * kPartA;
     for (int t = tid; t < 2 * m + 2; t += BT) {
       if (t < 2 * m && (t % m) >= j) continue;
-      double v = 0.0;
-      for (int q = 0; q < A.nchunk; ++q) v += pa[(long)q * kPartA + t];
-      sa[t] = v;
+      sa[t] = chunk_sum(A.nchunk, [&](int q) { return pa[(long)q * kPartA + t]; });
     }
     // the unrotated columns 0..j-1, rows 0..j-1
     const double* Hg = A.Hu + (long)s * m * (m + 1);
@@ -1880,12 +1896,17 @@ __global__ void __launch_bounds__(BT) k_krylov(EngineArgs A) {
       Hl[k][i] = Hg[(long)k * (m + 1) + i];
     }
     __syncthreads();
-    if (tid == 0) {
-      double aa = 0.0;
-      for (int k = 0; k < j; ++k) aa += sa[k] * sa[k];
-      const double cc = sa[2 * m];
-      const double b2 = cc - aa;
-      sbeta = b2 > 0.0 ? sqrt(b2) : sqrt(fmax(cc, 0.0));
+    // sum_k a_k^2 and sum_k a_k b_k over the first wave (j <= 64 terms)
+    __shared__ double sab;
+    if (tid < 64) {
+      const double ak = tid < j ? sa[tid] : 0.0, bk = tid < j ? sa[m + tid] : 0.0;
+      const double aa = wave_sum(ak * ak), ab = wave_sum(ak * bk);
+      if (tid == 0) {
+        const double cc = sa[2 * m];
+        const double b2 = cc - aa;
+        sbeta = b2 > 0.0 ? sqrt(b2) : sqrt(fmax(cc, 0.0));
+        sab = ab;
+      }
     }
     __syncthreads();
     const double beta = sbeta;
@@ -1899,8 +1920,7 @@ __global__ void __launch_bounds__(BT) k_krylov(EngineArgs A) {
       cb[m + i] = sa[m + i];
     }
     if (tid == 0) {
-      double ab = 0.0;
-      for (int k = 0; k < j; ++k) ab += sa[k] * sa[m + k];
+      const double ab = sab;
       const double dd = sa[2 * m + 1];
       const double ajm1 = j > 0 ? sa[j - 1] : 0.0;
       const double hjj = ((dd - ab) / beta - beta * ajm1) / beta;
@@ -1924,21 +1944,14 @@ __global__ void __launch_bounds__(BT) k_krylov(EngineArgs A) {
     const double* p1 = A.orth1 + (long)s * A.nchunk * kPart;
     const double* p2 = A.orth1b + (long)s * A.nchunk * kPart;
     if (tid <= j) {
-      double a = 0.0, b = 0.0;
-      for (int q = 0; q < A.nchunk; ++q) {
-        a += p1[(long)q * kPart + tid];
-        b += p2[(long)q * kPart + tid];
-      }
+      const double a = chunk_sum(A.nchunk, [&](int q) { return p1[(long)q * kPart + tid]; });
+      const double b = chunk_sum(A.nchunk, [&](int q) { return p2[(long)q * kPart + tid]; });
       coef[tid] = a + b;
     }
     if (tid == 0) {
-      double a = 0.0, b = 0.0;
-      for (int q = 0; q < A.nchunk; ++q) {
-        a += p2[(long)q * kPart + kPart - 1];   // ||w||^2 after the first pass
-        b += A.orth2[(long)s * A.nchunk + q];   // after the second
-      }
-      norms[0] = a;
-      norms[1] = b;
+      // ||w||^2 after the first pass and after the second
+      norms[0] = chunk_sum(A.nchunk, [&](int q) { return p2[(long)q * kPart + kPart - 1]; });
+      norms[1] = chunk_sum(A.nchunk, [&](int q) { return A.orth2[(long)s * A.nchunk + q]; });
     }
     __syncthreads();
     const double wn2 = norms[0], hn2 = norms[1];

@@ -32,6 +32,7 @@
 #include <memory>
 #include <tuple>
 #include <mutex>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -220,20 +221,54 @@ __device__ inline double chunk_sum(int n, F&& at) {
   return acc;
 }
 
+// out(e, in(e)) for e = threadIdx.x, threadIdx.x + blockDim.x, ... < n, with
+// the loads of eight consecutive steps issued before their stores (a plain
+// loop waits for each load, since the compiler cannot move a load above a
+// store that may alias it)
+template <class In, class Out>
+__device__ inline void strided_map(int n, In&& in, Out&& out) {
+  const int bd = (int)blockDim.x;
+  for (int e0 = threadIdx.x; e0 < n; e0 += 8 * bd) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = e0 + q * bd < n ? in(e0 + q * bd) : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (e0 + q * bd < n) out(e0 + q * bd, v[q]);
+  }
+}
+
+// f(std::integral_constant<int, R>) with R = r for r <= 4 and R = 0 (r read at
+// run time) otherwise: per-unit loops over r unroll, so their loads issue
+// together instead of one round trip per loop step.
+template <class F>
+__device__ inline void dispatch_r(int r, F&& f) {
+  switch (r) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    default: f(std::integral_constant<int, 0>{}); break;
+  }
+}
+
 // z_a[u] = sum_b P[a][b][u] o v_b[u] for one slot (all a), units u0 + threadIdx.x,
-// u0 + threadIdx.x + ustride, ... (default: all units by this workgroup)
-template <class ST = double>
+// u0 + threadIdx.x + ustride, ... (default: all units by this workgroup);
+// RT: r at compile time (0: read from A)
+template <int RT = 0, class ST = double>
 __device__ inline void apply_pinv(const EngineArgs& A, int s, const ST* v, double* zout,
                                   bool accumulate, const double* vscale = nullptr, int u0 = 0,
                                   int ustride = 0) {
-  const int r = A.r, ld = A.ld, nu = A.n - A.h;
+  const int r = RT > 0 ? RT : A.r, ld = A.ld, nu = A.n - A.h;
   const double* P = A.Pinv + (long)s * r * r * ld;
   if (ustride == 0) ustride = blockDim.x;
   for (int u = u0 + threadIdx.x; u < nu; u += ustride) {
     bool pr;
     const int q = uslot(u, A.h, pr);
+#pragma unroll
     for (int a = 0; a < r; ++a) {
       double sr = 0, si = 0;
+#pragma unroll
       for (int b = 0; b < r; ++b) {
         const double* pb = P + (long)(a * r + b) * ld;
         const ST* vb = v + (long)b * ld;
@@ -481,6 +516,7 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
   }
   // b = D c0 ; ||b||  (the preconditioner blocks follow in k_pinv)
   double acc = 0;
+#pragma unroll 8
   for (int e = threadIdx.x; e < N; e += blockDim.x) {
     const double v = dsh[e / ld] * A.c0[e];
     acc += v * v;
@@ -514,10 +550,11 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
   const double inv = 1.0 / bn;
   if (A.vf32) {
     float* V0f = A.Vf + (long)s * (A.m + 1) * NV;
-    for (int e = threadIdx.x; e < N; e += blockDim.x)
-      V0f[e] = (float)(dsh[e / ld] * A.c0[e] * inv);
+    strided_map(N, [&](int e) { return A.c0[e]; },
+                [&](int e, double c) { V0f[e] = (float)(dsh[e / ld] * c * inv); });
   } else {
-    for (int e = threadIdx.x; e < N; e += blockDim.x) V0[e] = dsh[e / ld] * A.c0[e] * inv;
+    strided_map(N, [&](int e) { return A.c0[e]; },
+                [&](int e, double c) { V0[e] = dsh[e / ld] * c * inv; });
   }
   if (threadIdx.x == 0) {
     // a slot that kept a recycle space from its previous parameter first
@@ -601,6 +638,7 @@ __device__ void finish(const EngineArgs& A, int s, int status, double relres, do
   const double* xs = A.z + (long)s * A.NV;
   const double* ds = A.d + (long)s * r;
   double sums[3] = {0.0, 0.0, 0.0};  // <gam, y>, ||y - b||^2, ||b||^2 with b = D c0
+#pragma unroll 8
   for (int e = threadIdx.x; e < N; e += blockDim.x) {
     const double y = xs[e], b = ds[e / ld] * A.c0[e];
     sums[0] += A.gam[e] * y;
@@ -616,7 +654,25 @@ __device__ void finish(const EngineArgs& A, int s, int status, double relres, do
   const long long tag = A.qtag[qi];
   if (A.sol && tag >= 0 && tag < A.sol_cap) {
     double* dst = A.sol + tag * (long long)N;
-    for (int e = threadIdx.x; e < N; e += blockDim.x) dst[e] = xs[e];
+    strided_map(N, [&](int e) { return xs[e]; }, [&](int e, double v) { dst[e] = v; });
+  }
+  // largest and smallest |R_kk| of the last cycle over the first wave
+  __shared__ double kap_sh;
+  if (threadIdx.x < 64) {
+    const int jl = min(si[SI_J], A.m);
+    const double* Rs = A.R + (long)s * A.m * (A.m + 1);
+    double dmax = 0.0, dmin = INFINITY;
+    for (int k = threadIdx.x; k < jl; k += 64) {
+      const double v = fabs(Rs[(long)k * (A.m + 1) + k]);
+      dmax = fmax(dmax, v);
+      dmin = fmin(dmin, v);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      dmax = fmax(dmax, __shfl_xor(dmax, o, 64));
+      dmin = fmin(dmin, __shfl_xor(dmin, o, 64));
+    }
+    if (threadIdx.x == 0) kap_sh = (jl > 0 && dmin > 0.0) ? fmax(1.0, dmax / dmin) : 1.0;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -628,15 +684,7 @@ __device__ void finish(const EngineArgs& A, int s, int status, double relres, do
     o.relres = relres;
     o.trace = tr;
     {
-      const int jl = si[SI_J];
-      const double* Rs = A.R + (long)s * A.m * (A.m + 1);
-      double dmax = 0.0, dmin = INFINITY;
-      for (int k = 0; k < jl && k < A.m; ++k) {
-        const double v = fabs(Rs[(long)k * (A.m + 1) + k]);
-        dmax = fmax(dmax, v);
-        dmin = fmin(dmin, v);
-      }
-      const double kappa = (jl > 0 && dmin > 0.0) ? fmax(1.0, dmax / dmin) : 1.0;
+      const double kappa = kap_sh;
       o.err_est = 2.0 * (A.eps_seed * (fmax(1.0, fabs(A.t0) / fabs(tr)) + kappa * (1.0 + corr)) +
                          kappa * relres);
     }
@@ -717,8 +765,10 @@ __global__ void __launch_bounds__(KT) k_prep(EngineArgs A) {
     if (ph == PH_ARNOLDI && A.vf32) {
       const float* srcf = A.Vf + ((long)s * (A.m + 1) + sis[SI_J]) * A.NV;
       if (A.use_precond) {
-        apply_pinv(A, s, srcf, zs, false, nullptr, blockIdx.y * blockDim.x,
-                   gridDim.y * blockDim.x);
+        dispatch_r(A.r, [&](auto R) {
+          apply_pinv<decltype(R)::value>(A, s, srcf, zs, false, nullptr, blockIdx.y * blockDim.x,
+                                         gridDim.y * blockDim.x);
+        });
       } else {
         for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < N; e += gridDim.y * blockDim.x)
           zs[e] = srcf[e];
@@ -728,7 +778,10 @@ __global__ void __launch_bounds__(KT) k_prep(EngineArgs A) {
                         : ph == PH_RECYC ? rec_u(A, s, sis[SI_BANK], sis[SI_RJ])
                                          : A.V + ((long)s * (A.m + 1) + sis[SI_J]) * A.NV;
     if (A.use_precond) {
-      apply_pinv(A, s, src, zs, false, nullptr, blockIdx.y * blockDim.x, gridDim.y * blockDim.x);
+      dispatch_r(A.r, [&](auto R) {
+        apply_pinv<decltype(R)::value>(A, s, src, zs, false, nullptr, blockIdx.y * blockDim.x,
+                                       gridDim.y * blockDim.x);
+      });
     } else {
       for (int e = blockIdx.y * blockDim.x + threadIdx.x; e < N; e += gridDim.y * blockDim.x)
         zs[e] = src[e];
@@ -986,11 +1039,11 @@ __global__ void __launch_bounds__(KT) k_formX(EngineArgs A, T* X, long plane, in
 // w = z - D (sum_b z_b o K1_ab + sum_b Uh_b o H_(li,a,b)); H is the sum of
 // the stream-K segments of the Cauchy GEMM (a launch of ggrid workgroups
 // over gnk K-tiles), added in segment order.  One unit u of row li * r + a.
-template <class HT>
+template <int RT, class HT>
 __device__ inline void epilogue_unit(const EngineArgs& A, const HT* __restrict__ Hp,
                                      const SkPlan& plan, int bshift, long segstride, int which,
                                      int row, int u) {
-  const int S = A.S, r = A.r, ld = A.ld;
+  const int S = A.S, r = RT > 0 ? RT : A.r, ld = A.ld;
   const int li = row / r, a = row - li * r;
   const int s = A.lists[which * S + li];
   const double* zs = A.z + (long)s * A.NV;
@@ -1001,6 +1054,7 @@ __device__ inline void epilogue_unit(const EngineArgs& A, const HT* __restrict__
   const int ct = q / kGemmBN;  // q and q + 1 share a column tile
   double sr = 0, si = 0;
   int rt_seg = -1, s0 = 0, ns = 0;
+#pragma unroll
   for (int b = 0; b < r; ++b) {
     const double* k = A.K1 + (long)(a * r + b) * ld;
     const double* zb = zs + (long)b * ld;
@@ -1057,17 +1111,20 @@ k_epilogue(EngineArgs A, const HT* Hp, int which, int ggrid, int gnk) {
   const long total = (long)cnt * r * nu;
   const long stride = (long)gridDim.x * blockDim.x;
   const long g0 = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (total + stride < 0x7fffffffL) {  // 32-bit index arithmetic (every practical size)
-    for (int g = (int)g0; g < (int)total; g += (int)stride) {
-      const int row = g / nu;  // li * r + a
-      epilogue_unit(A, Hp, plan, bshift, segstride, which, row, g - row * nu);
+  dispatch_r(r, [&](auto R) {
+    constexpr int RT = decltype(R)::value;
+    if (total + stride < 0x7fffffffL) {  // 32-bit index arithmetic (every practical size)
+      for (int g = (int)g0; g < (int)total; g += (int)stride) {
+        const int row = g / nu;  // li * r + a
+        epilogue_unit<RT>(A, Hp, plan, bshift, segstride, which, row, g - row * nu);
+      }
+    } else {
+      for (long g = g0; g < total; g += stride) {
+        const int row = (int)(g / nu);
+        epilogue_unit<RT>(A, Hp, plan, bshift, segstride, which, row, (int)(g - (long)row * nu));
+      }
     }
-  } else {
-    for (long g = g0; g < total; g += stride) {
-      const int row = (int)(g / nu);
-      epilogue_unit(A, Hp, plan, bshift, segstride, which, row, (int)(g - (long)row * nu));
-    }
-  }
+  });
 }
 
 // Schur basis: w = z - D out, out_s[a] = Vs_a^T Xs (projected seed solve)
@@ -1703,10 +1760,9 @@ __global__ void __launch_bounds__(64) k_krylov_post(EngineArgs A) {
   // end of the cycle: back substitution R y = g (R from columns 0..j), then
   // u += V y by k_combine
   const int jn = j + 1;
-  for (int e = tid; e < j * jn; e += 64) {  // columns 0..j-1 (column j is in hcol)
-    const int l = e / jn, k = e - l * jn;
-    Rl[l][k] = Rs[(long)l * (m + 1) + k];
-  }
+  // columns 0..j-1 (column j is in hcol)
+  strided_map(j * jn, [&](int e) { const int l = e / jn; return Rs[(long)l * (m + 1) + (e - l * jn)]; },
+              [&](int e, double v) { const int l = e / jn; Rl[l][e - l * jn] = v; });
   for (int k = tid; k < jn; k += 64) {
     Rl[j][k] = hcol[k];
     gl[k] = gs[k];
@@ -1891,10 +1947,8 @@ __global__ void __launch_bounds__(BT) k_krylov(EngineArgs A) {
     }
     // the unrotated columns 0..j-1, rows 0..j-1
     const double* Hg = A.Hu + (long)s * m * (m + 1);
-    for (int e = tid; e < j * j; e += BT) {
-      const int k = e / j, i = e - k * j;
-      Hl[k][i] = Hg[(long)k * (m + 1) + i];
-    }
+    strided_map(j * j, [&](int e) { const int k = e / j; return Hg[(long)k * (m + 1) + (e - k * j)]; },
+                [&](int e, double v) { const int k = e / j; Hl[k][e - k * j] = v; });
     __syncthreads();
     // sum_k a_k^2 and sum_k a_k b_k over the first wave (j <= 64 terms)
     __shared__ double sab;

@@ -198,6 +198,14 @@ __device__ inline double block_sum1(double v, double* lds) {
   return a[0];
 }
 
+// a slot's phase and Arnoldi index in one load (adjacent, 8-byte aligned), so
+// that the index does not wait for the phase test
+static_assert(SI_J == SI_PHASE + 1 && SI_PHASE % 2 == 0 && (SI_N * 4) % 8 == 0,
+              "phase and index load as one int2");
+__device__ inline int2 phase_j(const int* si_slot) {
+  return *reinterpret_cast<const int2*>(si_slot + SI_PHASE);
+}
+
 // unit u: conjugate pair u < h (slots 2u, 2u+1) or real eigenvalue (slot u + h)
 __device__ inline int uslot(int u, int h, bool& pr) {
   pr = u < h;
@@ -755,15 +763,16 @@ __global__ void __launch_bounds__(KT) k_prep(EngineArgs A) {
   const int N = A.r * A.ld;
   for (int li = blockIdx.x; li < c64 + clo; li += gridDim.x) {
     const int s = li < c64 ? A.lists[li] : A.lists[S + (li - c64)];
-    const int ph = A.si[(long)s * SI_N + SI_PHASE];
+    const int* sis = A.si + (long)s * SI_N;
+    const int2 pj = phase_j(sis);
+    const int ph = pj.x;
     double* zs = A.z + (long)s * A.NV;
     // blocks were built last step; every chunk reads the phase before this
     // launch's chunk 0 clears the flag, which no chunk reads
     if (threadIdx.x == 0 && blockIdx.y == 0) A.si[(long)s * SI_N + SI_PINV] = 0;
     // source: the iterate u (residual step), v_j (Arnoldi) or a recycled u_rj
-    const int* sis = A.si + (long)s * SI_N;
     if (ph == PH_ARNOLDI && A.vf32) {
-      const float* srcf = A.Vf + ((long)s * (A.m + 1) + sis[SI_J]) * A.NV;
+      const float* srcf = A.Vf + ((long)s * (A.m + 1) + pj.y) * A.NV;
       if (A.use_precond) {
         dispatch_r(A.r, [&](auto R) {
           apply_pinv<decltype(R)::value>(A, s, srcf, zs, false, nullptr, blockIdx.y * blockDim.x,
@@ -776,7 +785,7 @@ __global__ void __launch_bounds__(KT) k_prep(EngineArgs A) {
     } else {
     const double* src = ph == PH_RESTART ? A.x + (long)s * A.NV
                         : ph == PH_RECYC ? rec_u(A, s, sis[SI_BANK], sis[SI_RJ])
-                                         : A.V + ((long)s * (A.m + 1) + sis[SI_J]) * A.NV;
+                                         : A.V + ((long)s * (A.m + 1) + pj.y) * A.NV;
     if (A.use_precond) {
       dispatch_r(A.r, [&](auto R) {
         apply_pinv<decltype(R)::value>(A, s, src, zs, false, nullptr, blockIdx.y * blockDim.x,
@@ -1053,39 +1062,25 @@ __device__ inline void epilogue_unit(const EngineArgs& A, const HT* __restrict__
   const int q = uslot(u, A.h, pr);
   const int ct = q / kGemmBN;  // q and q + 1 share a column tile
   double sr = 0, si = 0;
-  int rt_seg = -1, s0 = 0, ns = 0;
-#pragma unroll
-  for (int b = 0; b < r; ++b) {
+  // segment range of GEMM row grow (sk_segments in 32-bit arithmetic: the
+  // engine bounds t * nk below 2^31); the r rows of one (li, a) mostly share a
+  // row tile, so it is worked out again only when the row tile changes
+  int rt_seg = -1, s0 = 0, nseg = 0;
+  auto segments = [&](int grow) {
+    const int rt = grow >> bshift;
+    if (rt != rt_seg) {
+      const unsigned a0 = (unsigned)(ct * plan.mta + rt) * (unsigned)plan.nk;
+      s0 = (int)(a0 / (unsigned)plan.per);
+      nseg = (int)((a0 + (unsigned)plan.nk - 1u) / (unsigned)plan.per) - s0 + 1;
+      rt_seg = rt;
+    }
+    return nseg;
+  };
+  // the r rows' contributions, added in b order
+  auto add_row = [&](int b, double hr, double hi) {
     const double* k = A.K1 + (long)(a * r + b) * ld;
     const double* zb = zs + (long)b * ld;
     const double* ub = A.Uh + (long)b * ld;
-    const int grow = row * r + b;  // GEMM row
-    const int rt = grow >> bshift;
-    if (rt != rt_seg) {  // the r rows of one (li, a) mostly share a row tile
-      // sk_segments in 32-bit arithmetic (the launch bounds t * nk below 2^31)
-      const unsigned a0 = (unsigned)(ct * plan.mta + rt) * (unsigned)plan.nk;
-      s0 = (int)(a0 / (unsigned)plan.per);
-      ns = (int)((a0 + (unsigned)plan.nk - 1u) / (unsigned)plan.per) - s0 + 1;
-      rt_seg = rt;
-    }
-    const HT* hb = Hp + (long)grow * ld + q;
-    // segments in order, two loads issued before their adds (a sweep's
-    // tail has up to 16 segments per tile)
-    double hr = 0, hi = 0;
-    int t = 0;
-    for (; t + 2 <= ns; t += 2) {
-      const HT* h0 = hb + t * segstride;
-      const double r0 = (double)h0[0], r1 = (double)h0[segstride];
-      const double i0 = pr ? (double)h0[1] : 0.0, i1 = pr ? (double)h0[segstride + 1] : 0.0;
-      hr += r0;
-      hr += r1;
-      hi += i0;
-      hi += i1;
-    }
-    if (t < ns) {
-      hr += (double)hb[t * segstride];
-      if (pr) hi += (double)hb[t * segstride + 1];
-    }
     if (pr) {
       const double kr = k[q], ki = k[q + 1], zr = zb[q], zi = zb[q + 1];
       const double ur = ub[q], ui = ub[q + 1];
@@ -1093,6 +1088,68 @@ __device__ inline void epilogue_unit(const EngineArgs& A, const HT* __restrict__
       si += zr * ki + zi * kr + ur * hi + ui * hr;
     } else {
       sr += zb[q] * k[q] + ub[q] * hr;
+    }
+  };
+  if constexpr (RT > 0) {
+    // the partial sums of the r rows advance together, two segments at a
+    // time, so the loads of all r rows are in flight at once (each row's sum
+    // keeps segment order; a sweep's tail has up to 16 segments per tile)
+    const HT* hb[RT];
+    int ns[RT], nsmax = 0;
+#pragma unroll
+    for (int b = 0; b < RT; ++b) {
+      const int grow = row * RT + b;  // GEMM row
+      ns[b] = segments(grow);
+      nsmax = ns[b] > nsmax ? ns[b] : nsmax;
+      hb[b] = Hp + (long)grow * ld + q;
+    }
+    double hr[RT], hi[RT];
+#pragma unroll
+    for (int b = 0; b < RT; ++b) hr[b] = hi[b] = 0.0;
+    for (int t = 0; t < nsmax; t += 2) {
+      double vr[RT][2], vi[RT][2];
+#pragma unroll
+      for (int b = 0; b < RT; ++b)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const bool ok = t + e < ns[b];
+          const HT* h = hb[b] + (t + e) * segstride;
+          vr[b][e] = ok ? (double)h[0] : 0.0;
+          vi[b][e] = ok && pr ? (double)h[1] : 0.0;
+        }
+#pragma unroll
+      for (int b = 0; b < RT; ++b)
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+          if (t + e < ns[b]) {
+            hr[b] += vr[b][e];
+            hi[b] += vi[b][e];
+          }
+    }
+#pragma unroll
+    for (int b = 0; b < RT; ++b) add_row(b, hr[b], hi[b]);
+  } else {
+    for (int b = 0; b < r; ++b) {
+      const int grow = row * r + b;
+      const int ns = segments(grow);
+      const HT* hb = Hp + (long)grow * ld + q;
+      // segments in order, two loads issued before their adds
+      double hr = 0, hi = 0;
+      int t = 0;
+      for (; t + 2 <= ns; t += 2) {
+        const HT* h0 = hb + t * segstride;
+        const double r0 = (double)h0[0], r1 = (double)h0[segstride];
+        const double i0 = pr ? (double)h0[1] : 0.0, i1 = pr ? (double)h0[segstride + 1] : 0.0;
+        hr += r0;
+        hr += r1;
+        hi += i0;
+        hi += i1;
+      }
+      if (t < ns) {
+        hr += (double)hb[t * segstride];
+        if (pr) hi += (double)hb[t * segstride + 1];
+      }
+      add_row(b, hr, hi);
     }
   }
   ws[q] = zs[(long)a * ld + q] - da * sr;
@@ -1583,9 +1640,9 @@ __global__ void __launch_bounds__(OT) k_orth_a(EngineArgs A) {
   const int m = A.m;
   for (int li = blockIdx.x; li < cnt; li += gridDim.x) {
     const int s = li < c64 ? A.lists[li] : A.lists[S + (li - c64)];
-    const int* si = A.si + (long)s * SI_N;
-    if (si[SI_PHASE] != PH_ARNOLDI) continue;  // uniform over the workgroup
-    const int j = si[SI_J];
+    const int2 pj = phase_j(A.si + (long)s * SI_N);
+    if (pj.x != PH_ARNOLDI) continue;  // uniform over the workgroup
+    const int j = pj.y;
     const long off = (long)c * kChunk;
     const VT* V0 = basis<VT>(A) + (long)s * (m + 1) * A.NV + off;
     const double2 w = reinterpret_cast<const double2*>(A.w + (long)s * A.NV + off)[tid];
@@ -1637,8 +1694,8 @@ __global__ void __launch_bounds__(OT) k_orth_b(EngineArgs A) {
   for (int li = blockIdx.x; li < cnt; li += gridDim.x) {
     const int s = li < c64 ? A.lists[li] : A.lists[S + (li - c64)];
     const int* si = A.si + (long)s * SI_N;
-    if (!si[SI_PASSB]) continue;  // uniform over the workgroup
-    const int j = si[SI_J];
+    const int passb = si[SI_PASSB], j = si[SI_J];  // both loads before the test
+    if (!passb) continue;  // uniform over the workgroup
     const double* cb = A.coefB + (long)s * kPartA;
     for (int t = tid; t < 2 * m + 2; t += OT) cf[t] = cb[t];
     __syncthreads();
@@ -1699,7 +1756,8 @@ __global__ void __launch_bounds__(64) k_krylov_post(EngineArgs A) {
   __shared__ int end_sh;
   const int s = blockIdx.x, tid = threadIdx.x;
   int* si = A.si + (long)s * SI_N;
-  if (!si[SI_PASSB]) return;  // uniform over the workgroup
+  const int passb = si[SI_PASSB], j = si[SI_J];  // both loads before the test
+  if (!passb) return;  // uniform over the workgroup
   const int m = A.m;
   const double* sdv = A.sdv + (long)s * SD_N;
   double* gs = A.g + (long)s * (m + 1);
@@ -1707,7 +1765,6 @@ __global__ void __launch_bounds__(64) k_krylov_post(EngineArgs A) {
   double* css = A.cs + (long)s * m;
   double* sns = A.sn + (long)s * m;
   const double bn = sdv[SD_BNORM];
-  const int j = si[SI_J];
   const double* hu = A.Hu + ((long)s * m + j) * (m + 1);
   for (int k = tid; k <= j; k += 64) hcol[k] = hu[k];
   for (int k = tid; k < j; k += 64) {
@@ -1807,7 +1864,8 @@ __global__ void __launch_bounds__(BT) k_krylov(EngineArgs A) {
   const int r = A.r, ld = A.ld, N = r * ld, NV = A.NV, m = A.m;
   int* si = A.si + (long)s * SI_N;
   double* sdv = A.sdv + (long)s * SD_N;
-  const int ph = si[SI_PHASE];
+  const int2 pj = phase_j(si);
+  const int ph = pj.x;
   if (ph != PH_ARNOLDI && ph != PH_RESTART && !(REC && ph == PH_RECYC)) return;
 
   double* Vs = A.V + (long)s * (m + 1) * NV;
@@ -1932,7 +1990,7 @@ __global__ void __launch_bounds__(BT) k_krylov(EngineArgs A) {
   }
 
   // ---- Arnoldi step j: w = A P^-1 v_j, orthogonalised against [C, V_0..j] ----
-  const int j = si[SI_J];
+  const int j = pj.y;  // the Arnoldi path does not write it before here
   if (!REC && A.dcgs) {
     // delayed reorthogonalisation (see k_orth_a): sums of the chunk partials,
     // beta, column j of H (unrotated, to Hu) and the update coefficients

@@ -3,8 +3,6 @@
 // Every busy slot holds one parameter sample p and advances one Krylov step
 // per engine step.  A step is a fixed sequence of launches (captured once as
 // a HIP graph):
-//   k_lists     compact the slots that need an FP64 or a low-precision
-//               matrix-vector product into two lists (device counts)
 //   k_prep      z = P^-1 v_j (Arnoldi step) or z = P^-1 u (residual step);
 //               the iterate u is kept before preconditioning, y = P^-1 u
 //   k_formX     rows (p, a, b) of the Cauchy GEMM: Vh_a o z_b
@@ -14,6 +12,9 @@
 //               wavefront reductions, Givens update in FP64, restart with a
 //               true FP64 residual, convergence, result write-out and
 //               admission of the next queued parameter (device-side queue).
+//   k_claim_lists  queue claims of the free slots and the compacted lists of
+//               the slots that need an FP64 or a low-precision product in the
+//               next step (device counts), then k_admit
 //
 // The capacitance system is the n*r reduced form of eq:SMW_linearsystem,
 // scaled by D so that d = 0 is allowed:  (I - D K) y = D c0,
@@ -584,25 +585,37 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
   __syncthreads();
 }
 
-// claim the next queue position, or -1.  The tail only moves between
-// launches (host submissions are ordered on the engine stream), so one
-// fetch-add hands out each position below the tail exactly once; a claim at
-// or past the tail is given back, which keeps the head from ever falling
-// below the tail once it has reached it.  No compare-and-swap retry loop:
-// a step in which every slot claims costs one atomic per slot.
-// Queue claims of one step, in slot order (one workgroup, after every slot's
-// phase for the step is final): free slot s takes queue position head + (the
-// number of free slots before s) while positions remain, written to
-// si[SI_CLAIM] (-1: none); the head moves past the claimed positions.  The
-// slot a parameter lands in (and so its rows in the Cauchy GEMM) is then a
-// function of the submissions alone.  k_admit admits the claims.
-__global__ void __launch_bounds__(1024) k_claim(EngineArgs A) {
-  __shared__ int cnt[1024];
+// The last launch before the admission, in one workgroup, after every slot's
+// phase for the step is final:
+// * queue claims in slot order: free slot s takes queue position head + (the
+//   number of free slots before s) while positions remain, written to
+//   si[SI_CLAIM] (-1: none); the head moves past the claimed positions.  The
+//   slot a parameter lands in (and so its rows in the Cauchy GEMM) is then a
+//   function of the submissions alone.  k_admit admits the claims.
+// * the slot lists of the next step (stable compaction in slot order): the
+//   slots that need an FP64 product (a restart, or any product in FP64 mode)
+//   and those that need a low-precision one.  A claimed slot is listed with
+//   the phase its admission gives it (Arnoldi, or the recycle rebuild when it
+//   keeps a recycle space).  An admission that fails (a non-finite or zero
+//   parameter) leaves its slot free but listed for that one step: the step
+//   kernels test the phase and skip it, and its Cauchy GEMM rows are wasted
+//   work, nothing else.
+// Building the lists here saves a launch per step; the counts therefore
+// describe the coming step, and the buffer holds empty lists at creation and
+// after a reset.
+__device__ inline int claim_phase(const EngineArgs& A, const int* si) {
+  const int ph = si[SI_PHASE];
+  if (ph != PH_FREE || si[SI_CLAIM] < 0) return ph;
+  return A.kmax > 0 && si[SI_KCUR] > 0 ? PH_RECYC : PH_ARNOLDI;
+}
+
+__global__ void __launch_bounds__(1024) k_claim_lists(EngineArgs A) {
+  __shared__ int cnt[1024], c64[1024], clo[1024];
   const int S = A.S, tid = threadIdx.x;
   const int per = (S + blockDim.x - 1) / blockDim.x;
-  const int s0 = tid * per;
+  const int s0 = tid * per, s1 = min(S, s0 + per);
   int n = 0;
-  for (int t = s0; t < min(S, s0 + per); ++t) n += A.si[(long)t * SI_N + SI_PHASE] == PH_FREE;
+  for (int t = s0; t < s1; ++t) n += A.si[(long)t * SI_N + SI_PHASE] == PH_FREE;
   cnt[tid] = n;
   __syncthreads();
   for (int off = 1; off < (int)blockDim.x; off <<= 1) {  // inclusive scan
@@ -613,15 +626,46 @@ __global__ void __launch_bounds__(1024) k_claim(EngineArgs A) {
   }
   const int head = A.qctl[0], tail = A.qctl[1];
   int pos = head + cnt[tid] - n;
-  for (int t = s0; t < min(S, s0 + per); ++t) {
+  int n64 = 0, nlo = 0;
+  for (int t = s0; t < s1; ++t) {
     int* si = A.si + (long)t * SI_N;
-    if (si[SI_PHASE] != PH_FREE) continue;
-    si[SI_CLAIM] = pos < tail ? pos : -1;
-    ++pos;
+    if (si[SI_PHASE] == PH_FREE) {
+      si[SI_CLAIM] = pos < tail ? pos : -1;
+      ++pos;
+    }
+    si[SI_COMB] = 0;  // this step's cycle ends are combined
+    const int ph = claim_phase(A, si);
+    const bool arn = ph == PH_ARNOLDI || ph == PH_RECYC;
+    if (ph == PH_RESTART || (arn && !A.mixed)) ++n64;
+    else if (arn) ++nlo;
   }
   if (tid == blockDim.x - 1) {
     const int total = cnt[tid];
     A.qctl[0] = head + min(total, max(tail - head, 0));
+  }
+  // inclusive scan of the per-thread list counts
+  c64[tid] = n64;
+  clo[tid] = nlo;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const int a = tid >= off ? c64[tid - off] : 0;
+    const int b = tid >= off ? clo[tid - off] : 0;
+    __syncthreads();
+    c64[tid] += a;
+    clo[tid] += b;
+    __syncthreads();
+  }
+  if (tid == blockDim.x - 1) {
+    A.lists[2 * S] = c64[tid];
+    A.lists[2 * S + 1] = clo[tid];
+    A.lists[2 * S + 2] = c64[tid] + clo[tid];
+  }
+  int o64 = c64[tid] - n64, olo = clo[tid] - nlo;
+  for (int t = s0; t < s1; ++t) {
+    const int ph = claim_phase(A, A.si + (long)t * SI_N);
+    const bool arn = ph == PH_ARNOLDI || ph == PH_RECYC;
+    if (ph == PH_RESTART || (arn && !A.mixed)) A.lists[o64++] = t;
+    else if (arn) A.lists[S + olo++] = t;
   }
 }
 
@@ -708,52 +752,6 @@ __device__ void finish(const EngineArgs& A, int s, int status, double relres, do
 // ---------------------------------------------------------------------------
 // step kernels
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) k_lists(EngineArgs A) {
-  // single workgroup; stable compaction in slot order
-  __shared__ int c64[1024], clo[1024];
-  const int S = A.S;
-  const int per = (S + blockDim.x - 1) / blockDim.x;
-  const int s0 = threadIdx.x * per;
-  int n64 = 0, nlo = 0;
-  for (int s = s0; s < min(S, s0 + per); ++s) {
-    const int ph = A.si[(long)s * SI_N + SI_PHASE];
-    const bool arn = ph == PH_ARNOLDI || ph == PH_RECYC;
-    if (ph == PH_RESTART || (arn && !A.mixed)) ++n64;
-    else if (arn) ++nlo;
-    A.si[(long)s * SI_N + SI_COMB] = 0;  // the previous step's cycle ends are combined
-  }
-  // inclusive Hillis-Steele scan of the per-thread counts
-  c64[threadIdx.x] = n64;
-  clo[threadIdx.x] = nlo;
-  __syncthreads();
-  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-    const int a = threadIdx.x >= (unsigned)off ? c64[threadIdx.x - off] : 0;
-    const int b = threadIdx.x >= (unsigned)off ? clo[threadIdx.x - off] : 0;
-    __syncthreads();
-    c64[threadIdx.x] += a;
-    clo[threadIdx.x] += b;
-    __syncthreads();
-  }
-  if (threadIdx.x == blockDim.x - 1) {
-    A.lists[2 * S] = c64[threadIdx.x];
-    A.lists[2 * S + 1] = clo[threadIdx.x];
-    A.lists[2 * S + 2] = c64[threadIdx.x] + clo[threadIdx.x];
-  }
-  // exclusive offsets
-  const int ex64 = c64[threadIdx.x] - n64, exlo = clo[threadIdx.x] - nlo;
-  __syncthreads();
-  c64[threadIdx.x] = ex64;
-  clo[threadIdx.x] = exlo;
-  __syncthreads();
-  int o64 = c64[threadIdx.x], olo = clo[threadIdx.x];
-  for (int s = s0; s < min(S, s0 + per); ++s) {
-    const int ph = A.si[(long)s * SI_N + SI_PHASE];
-    const bool arn = ph == PH_ARNOLDI || ph == PH_RECYC;
-    if (ph == PH_RESTART || (arn && !A.mixed)) A.lists[o64++] = s;
-    else if (arn) A.lists[S + olo++] = s;
-  }
-}
-
 // z for every listed slot (both lists): workgroups stride over the entries in
 // x; gridDim.y workgroups share one slot's units (one, with the TSVD part, whose
 // copy of y needs the whole slot)
@@ -2528,7 +2526,7 @@ __global__ void __launch_bounds__(KT) k_admit(EngineArgs A) {
   const int s = blockIdx.x;
   const int* si = A.si + (long)s * SI_N;
   if (si[SI_PHASE] != PH_FREE) return;  // uniform over the workgroup
-  const int qp = si[SI_CLAIM];          // k_claim
+  const int qp = si[SI_CLAIM];          // k_claim_lists
   if (qp >= 0) admit(A, s, qp, lds);
 }
 
@@ -2581,6 +2579,7 @@ struct lyap_engine_s {
   std::vector<hipEvent_t> pev;
   DevBuf pcounts;
   bool prof_graph_ok = true;
+  bool prof_rec = false;  // while the profiled step segments are captured
   int prof_level = 0;        // level the profiling segments were captured with
   long long prof_step = 0;     // steps run while profiling (sampling)
   EngineArgs args{};
@@ -2744,7 +2743,6 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
   if (part != PART_ALL) ev = nullptr;
   const int pgrid = std::min(S, 1024);
   if (on(PART_PRE)) {
-  hipLaunchKernelGGL(k_lists, dim3(1), dim3(1024), 0, st, A);
   {
     // units of one slot over several workgroups (full occupancy at full batch)
     const int pch = A.pbar > 0 ? 1 : std::max(1, std::min(16, (nu + KT - 1) / KT));
@@ -2973,7 +2971,10 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
   }
   if (ev && ev->kry[0]) LYAP_HIP(hipEventRecord(ev->kry[1], st));
   if (A.kmax > 0) launch_krylov(A, S, (long long)A.NV, st, true);
-  hipLaunchKernelGGL(k_claim, dim3(1), dim3(1024), 0, st, A);
+  if (E->prof_rec)  // profiled steps: this step's list counts, before the next step's
+    hipLaunchKernelGGL(k_record_counts, dim3(1), dim3(1), 0, st, E->lists.as<int>(), E->S,
+                       E->pcounts.as<int>() + 1, E->pcounts.as<int>());
+  hipLaunchKernelGGL(k_claim_lists, dim3(1), dim3(1024), 0, st, A);
   hipLaunchKernelGGL(k_admit, dim3(S), dim3(KT), 0, st, A);
   if (A.use_precond)
     hipLaunchKernelGGL(k_pinv, dim3(S, pinv_chunks(r, nu)), dim3(KT), 0, st, A);
@@ -3067,11 +3068,11 @@ static void prof_segments_build(lyap_engine_s* E) {
   for (int q = 0; q < 3; ++q) {
     LYAP_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     try {
+      E->prof_rec = parts[q] == PART_POST;  // counts recorded inside the step
       launch_step(E, st, nullptr, parts[q]);
-      if (parts[q] == PART_POST)
-        hipLaunchKernelGGL(k_record_counts, dim3(1), dim3(1), 0, st, E->lists.as<int>(), E->S,
-                           E->pcounts.as<int>() + 1, E->pcounts.as<int>());
+      E->prof_rec = false;
     } catch (...) {
+      E->prof_rec = false;
       hipGraph_t tmp;
       (void)hipStreamEndCapture(st, &tmp);
       throw;
@@ -3138,9 +3139,10 @@ static void profiled_steps(lyap_engine_s* E, long long k, int level) {
   int* counts = nullptr;
   LYAP_HIP(hipHostMalloc((void**)&counts, sizeof(int) * 2 * k, hipHostMallocDefault));
   for (long long i = 0; i < k; ++i) {
-    launch_step(E, st, &evs[i]);
+    // the lists of step i were built at the end of the step before it
     LYAP_HIP(hipMemcpyAsync(counts + 2 * i, E->lists.as<int>() + 2 * S, 2 * sizeof(int),
                             hipMemcpyDeviceToHost, st));
+    launch_step(E, st, &evs[i]);
   }
   LYAP_HIP(hipStreamSynchronize(st));
   prof_accumulate(E, evs, counts, k, false);
@@ -3457,6 +3459,7 @@ static void engine_reset(lyap_engine_s* E, hipStream_t user) {
   LYAP_HIP(hipStreamWaitEvent(st, ev, 0));
   LYAP_HIP(hipEventDestroy(ev));
   LYAP_HIP(hipMemsetAsync(E->si.p, 0, E->si.bytes, st));
+  LYAP_HIP(hipMemsetAsync(E->lists.p, 0, E->lists.bytes, st));  // no slot listed
   LYAP_HIP(hipMemsetAsync(E->qctl.p, 0, E->qctl.bytes, st));
   LYAP_HIP(hipMemsetAsync(E->res.p, 0, E->res.bytes, st));
   E->submitted = E->harvested = E->next_tag = 0;

@@ -484,6 +484,30 @@ static int pinv_chunks(int r, int nu) {
   return r <= 4 ? (nu + KT - 1) / KT : (nu + kPinvUnitsWave - 1) / kPinvUnitsWave;
 }
 
+// With r <= 4 and no TSVD part, the blocks of a newly admitted slot are built
+// by the next step's k_prep, each thread for the units it then applies them
+// to, instead of by k_pinv right after the admission (one launch fewer per
+// step).  The TSVD capacitance set up at the admission needs the blocks at
+// once, and r > 4 inverts per wavefront: both keep k_pinv.
+__host__ __device__ inline bool lazy_pinv(const EngineArgs& A) {
+  return A.use_precond && A.r <= 4 && A.pbar == 0;
+}
+__device__ inline void build_pinv(const EngineArgs& A, int s, int u0, int ustride) {
+  const int r = A.r, nu = A.n - A.h;
+  const double* d = A.d + (long)s * r;
+  double* P = A.Pinv + (long)s * r * r * A.ld;
+  for (int u = u0 + threadIdx.x; u < nu; u += ustride) {
+    bool pr;
+    const int q = uslot(u, A.h, pr);
+    switch (r) {
+      case 1: block_inverse<1>(A, d, q, pr, P); break;
+      case 2: block_inverse<2>(A, d, q, pr, P); break;
+      case 3: block_inverse<3>(A, d, q, pr, P); break;
+      default: block_inverse<4>(A, d, q, pr, P); break;
+    }
+  }
+}
+
 // Admission of queue entry qp into slot s (whole workgroup): preconditioner
 // blocks (I - D K1_j)^-1, right-hand side b = D c0, v0 = b / ||b||.
 __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
@@ -634,6 +658,7 @@ __global__ void __launch_bounds__(1024) k_claim_lists(EngineArgs A) {
       ++pos;
     }
     si[SI_COMB] = 0;  // this step's cycle ends are combined
+    if (lazy_pinv(A)) si[SI_PINV] = 0;  // this step's k_prep built the blocks
     const int ph = claim_phase(A, si);
     const bool arn = ph == PH_ARNOLDI || ph == PH_RECYC;
     if (ph == PH_RESTART || (arn && !A.mixed)) ++n64;
@@ -765,9 +790,10 @@ __global__ void __launch_bounds__(KT) k_prep(EngineArgs A) {
     const int2 pj = phase_j(sis);
     const int ph = pj.x;
     double* zs = A.z + (long)s * A.NV;
-    // blocks were built last step; every chunk reads the phase before this
-    // launch's chunk 0 clears the flag, which no chunk reads
-    if (threadIdx.x == 0 && blockIdx.y == 0) A.si[(long)s * SI_N + SI_PINV] = 0;
+    // a slot admitted in the last step: its preconditioner blocks, for the
+    // units this thread applies them to below (k_claim_lists clears the flag)
+    if (lazy_pinv(A) && sis[SI_PINV])
+      build_pinv(A, s, blockIdx.y * blockDim.x, gridDim.y * blockDim.x);
     // source: the iterate u (residual step), v_j (Arnoldi) or a recycled u_rj
     if (ph == PH_ARNOLDI && A.vf32) {
       const float* srcf = A.Vf + ((long)s * (A.m + 1) + pj.y) * A.NV;
@@ -2976,7 +3002,7 @@ static void launch_step(lyap_engine_s* E, hipStream_t st, StepEvents* ev = nullp
                        E->pcounts.as<int>() + 1, E->pcounts.as<int>());
   hipLaunchKernelGGL(k_claim_lists, dim3(1), dim3(1024), 0, st, A);
   hipLaunchKernelGGL(k_admit, dim3(S), dim3(KT), 0, st, A);
-  if (A.use_precond)
+  if (A.use_precond && !lazy_pinv(A))  // else the next step's k_prep builds the blocks
     hipLaunchKernelGGL(k_pinv, dim3(S, pinv_chunks(r, nu)), dim3(KT), 0, st, A);
   if (A.pbar > 0) hipLaunchKernelGGL(k_capsetup, dim3(S), dim3(KT), 0, st, A);
   LYAP_HIP(hipGetLastError());

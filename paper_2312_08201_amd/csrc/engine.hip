@@ -658,7 +658,7 @@ __global__ void __launch_bounds__(1024) k_claim_lists(EngineArgs A) {
       ++pos;
     }
     si[SI_COMB] = 0;  // this step's cycle ends are combined
-    if (lazy_pinv(A)) si[SI_PINV] = 0;  // this step's k_prep built the blocks
+    si[SI_PINV] = 0;  // the blocks of this step's admissions are built (k_prep or k_pinv)
     const int ph = claim_phase(A, si);
     const bool arn = ph == PH_ARNOLDI || ph == PH_RECYC;
     if (ph == PH_RESTART || (arn && !A.mixed)) ++n64;

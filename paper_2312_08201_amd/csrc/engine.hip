@@ -508,8 +508,9 @@ __device__ inline void build_pinv(const EngineArgs& A, int s, int u0, int ustrid
   }
 }
 
-// Admission of queue entry qp into slot s (whole workgroup): preconditioner
-// blocks (I - D K1_j)^-1, right-hand side b = D c0, v0 = b / ||b||.
+// Admission of queue entry qp into slot s (whole workgroup): d(p), right-hand
+// side b = D c0, v0 = b / ||b||.  The preconditioner blocks (I - D K1_j)^-1
+// follow: in the next step's k_prep (see lazy_pinv) or in k_pinv.
 __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
   const int r = A.r, ld = A.ld, N = r * ld, NV = A.NV, nu = A.n - A.h;
   int* si = A.si + (long)s * SI_N;
@@ -547,7 +548,7 @@ __device__ void admit(const EngineArgs& A, int s, int qp, double* lds) {
     __syncthreads();
     return;
   }
-  // b = D c0 ; ||b||  (the preconditioner blocks follow in k_pinv)
+  // b = D c0 ; ||b||
   double acc = 0;
 #pragma unroll 8
   for (int e = threadIdx.x; e < N; e += blockDim.x) {
